@@ -1,0 +1,234 @@
+"""Reconstruction algorithm (RA, paper Sec. 3) and independent-sets algorithm (ISA,
+paper Sec. 4), step by step as the paper lists them, on top of the FP64 SL solver.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Readings of the paper used here:
+  * the coarse grid K is "partially superimposed" on the fine grid G: every s-th
+    fine node (stride ``prob.coarse_stride``); K inherits speed, cost, drift and
+    targets at the coincident nodes; a component with no coincident node gets the
+    coarse node nearest its lowest-index fine node; the SL step on K is h*s;
+  * the auxiliary problem i (RA step 1, "T_i with boundary X_i") keeps component i
+    at g and holds every other component's target nodes at the ghost value, a
+    boundary datum larger than g ((gcond));
+  * RA step 2: the (H2) check is skipped (every problem here is a control
+    problem, whose Hamiltonian is convex, Remark 2.1), then V = min_i V_i;
+  * RA step 3 threshold delta = 2 (C dx^q + M dx) (Proposition 3.1), dx the coarse
+    grid spacing (largest over axes);
+  * ISA step 2, Con(.): a fine node belongs to the projected set iff some closed
+    coarse cell containing it has all 2^d corners in the coarse set; a fine node
+    left in no set receives every set present at a corner of its cells (so the
+    sets cover the grid);
+  * labels: the coarse argmin of V_i (lowest index on ties), pulled to the fine
+    grid from the nearest coarse node (ties rounded up);
+  * ISA step 3 solves T on each projected set, non-members reading the ghost value;
+    ISA step 4 takes the minimum over the sets containing each node (owner = the
+    lowest minimising index).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+from . import initial_values, fixed_mask, solve
+
+
+@dataclass
+class Reconstruction:
+    member_K: np.ndarray      # uint8 bitmask on K
+    label_K: np.ndarray       # uint8 argmin label on K
+    V_aux: List[np.ndarray]   # auxiliary values V_i on K
+    V_K: np.ndarray           # min_i V_i on K
+    delta: float
+    nK: tuple
+    member: np.ndarray        # uint8 bitmask on the fine grid (after projection)
+    label: np.ndarray         # uint8 label on the fine grid
+    sweeps: List[int]
+
+
+def coarse_problem(prob):
+    """The superimposed coarse grid K (every s-th node) and its problem data."""
+    s = int(prob.coarse_stride)
+    shp = prob.shape()
+    nK = tuple((prob.n[d] - 1) // s + 1 for d in range(prob.dim))
+    for d in range(prob.dim):
+        if (prob.n[d] - 1) % s:
+            raise ValueError("coarse stride must divide n-1 on every axis")
+    sl = tuple(slice(None, None, s) for _ in range(prob.dim))
+
+    def sub(a):
+        return None if a is None else np.ascontiguousarray(
+            np.asarray(a).reshape(shp)[sl]).reshape(-1)
+
+    tid = sub(prob.target).copy()
+    g = sub(prob.g)
+    ftid = np.asarray(prob.target)
+    for i in range(prob.n_comp):
+        if (tid == i).any():
+            continue
+        nodes = np.flatnonzero(ftid == i)
+        if nodes.size == 0:
+            continue
+        j = int(nodes[0])
+        ij = []
+        rem = j
+        for d in range(prob.dim):
+            ij.append(rem % prob.n[d])
+            rem //= prob.n[d]
+        kk = [min((ij[d] + s // 2) // s, nK[d] - 1) for d in range(prob.dim)]
+        jk = 0
+        stride = 1
+        for d in range(prob.dim):
+            jk += kk[d] * stride
+            stride *= nK[d]
+        if tid[jk] < 0:
+            tid[jk] = i
+            if g is not None:
+                g = g.copy()
+                g[jk] = np.asarray(prob.g)[j]
+    drift = None
+    if prob.drift is not None:
+        dr = np.asarray(prob.drift).reshape(shp + (prob.dim,))
+        drift = np.ascontiguousarray(dr[sl]).reshape(-1, prob.dim)
+    return prob.with_(name=prob.name + "_K", n=nK, target=tid, speed=sub(prob.speed),
+                      cost=sub(prob.cost), g=g, drift=drift, h=prob.step * s,
+                      coarse_stride=1)
+
+
+def ra_delta(probK) -> float:
+    """RA threshold 2 (C dx^q + M dx) of Proposition 3.1 on grid ``probK``."""
+    dx = max(probK.dx)
+    return 2.0 * (probK.ra_C * math.pow(dx, probK.ra_q) + probK.ra_M * dx)
+
+
+def reconstruct_on(probK, delta: Optional[float] = None, tol: float = 0.0,
+                   max_sweeps: int = 10**7):
+    """RA steps 1-3 on the grid of ``probK``: auxiliary solves, min, threshold.
+    Returns (member bitmask, label, V_aux list, V, delta, sweeps)."""
+    if delta is None:
+        delta = ra_delta(probK)
+    fixed = fixed_mask(probK)
+    V_aux, sweeps = [], []
+    for i in range(probK.n_comp):                          # step 1
+        Vi, _, s, _ = solve(probK, V0=initial_values(probK, comp=i), fixed=fixed, tol=tol,
+                            max_sweeps=max_sweeps)
+        V_aux.append(Vi)
+        sweeps.append(s)
+    V = V_aux[0].copy()                                    # step 2
+    for Vi in V_aux[1:]:
+        V = np.minimum(V, Vi)
+    tid = np.asarray(probK.target)
+    member = np.zeros(probK.N, dtype=np.uint8)             # step 3
+    label = np.full(probK.N, 255, dtype=np.uint8)
+    for i, Vi in enumerate(V_aux):
+        sel = (tid == i) | (np.abs(Vi - V) <= delta)
+        member |= (sel.astype(np.uint8) << i)
+    for i in reversed(range(probK.n_comp)):                # lowest index wins ties
+        label[V_aux[i] == V] = i
+    return member, label, V_aux, V, delta, sweeps
+
+
+def project(member_K: np.ndarray, label_K: np.ndarray, nK: tuple, n: tuple, s: int):
+    """ISA step 2: Con(.) projection of the coarse sets to the fine grid (integer
+    only), orphan repair, and the nearest-coarse-node label."""
+    dim = len(n)
+    mK = member_K.reshape(tuple(reversed(nK)))
+    lK = label_K.reshape(tuple(reversed(nK)))
+    # per coarse cell: AND and OR of the member bits of its 2^d corners
+    cells_and = None
+    cells_or = None
+    for corner in range(1 << dim):
+        sl = []
+        for d in reversed(range(dim)):                     # numpy axis order
+            b = (corner >> d) & 1
+            sl.append(slice(b, nK[d] - 1 + b))
+        v = mK[tuple(sl)]
+        cells_and = v.copy() if cells_and is None else (cells_and & v)
+        cells_or = v.copy() if cells_or is None else (cells_or | v)
+    # per fine index and axis: the (up to two) coarse cells whose closure holds it
+    cand = []
+    for d in range(dim):
+        j = np.arange(n[d])
+        hi_c = np.minimum(j // s, nK[d] - 2)
+        lo_c = np.where(j % s == 0, np.maximum(j // s - 1, 0), hi_c)
+        cand.append((lo_c, hi_c))
+    mem = np.zeros(tuple(reversed(n)), dtype=np.uint8)
+    orf = np.zeros_like(mem)
+    for choice in range(1 << dim):
+        idx = [cand[d][(choice >> d) & 1] for d in range(dim)]
+        ix = np.ix_(*reversed(idx))
+        mem |= cells_and[ix]
+        orf |= cells_or[ix]
+    mem = np.where(mem == 0, orf, mem).astype(np.uint8)
+    near = [np.minimum((np.arange(n[d]) + s // 2) // s, nK[d] - 1) for d in range(dim)]
+    lab = lK[np.ix_(*reversed(near))]
+    return mem.reshape(-1), np.ascontiguousarray(lab).reshape(-1)
+
+
+def reconstruct(prob, delta: Optional[float] = None, max_sweeps: int = 10**7) -> Reconstruction:
+    """ISA steps 1-2: RA on the coarse grid K, projection to the fine grid."""
+    probK = coarse_problem(prob)
+    mK, lK, V_aux, VK, delta, sweeps = reconstruct_on(probK, delta, max_sweeps=max_sweeps)
+    mem, lab = project(mK, lK, probK.n, prob.n, prob.coarse_stride)
+    return Reconstruction(mK, lK, V_aux, VK, delta, probK.n, mem, lab, sweeps)
+
+
+def solve_subdomains(prob, member: np.ndarray, tol: float = 0.0, max_sweeps: int = 10**7,
+                     want_policy: bool = False):
+    """ISA step 3: V_i = T(V_i) on each projected set (non-members are ghosts)."""
+    fixed = fixed_mask(prob)
+    out, pols, sweeps = [], [], []
+    for i in range(prob.n_comp):
+        dom = ((member >> i) & 1).astype(np.uint8)
+        Vi, pol, s, _ = solve(prob, V0=initial_values(prob), fixed=fixed, dom=dom, tol=tol,
+                              max_sweeps=max_sweeps)
+        out.append(Vi)
+        pols.append(pol)
+        sweeps.append(s)
+    return (out, pols, sweeps) if want_policy else (out, sweeps)
+
+
+def assemble(V_sub: List[np.ndarray], member: np.ndarray, G: float):
+    """ISA step 4: Vbar(j) = min over the sets containing j; owner = lowest argmin."""
+    N = member.size
+    Vbar = np.full(N, np.inf)
+    owner = np.full(N, 255, dtype=np.uint8)
+    for i, Vi in enumerate(V_sub):
+        on = ((member >> i) & 1).astype(bool)
+        better = on & (Vi < Vbar)
+        Vbar[better] = Vi[better]
+        owner[better] = i
+    Vbar[np.isinf(Vbar)] = G
+    return Vbar, owner
+
+
+def isa(prob, delta: Optional[float] = None, max_sweeps: int = 10**7):
+    """The whole ISA: returns (Vbar, owner, Reconstruction, V_sub, sweeps)."""
+    rec = reconstruct(prob, delta, max_sweeps=max_sweeps)
+    V_sub, sweeps = solve_subdomains(prob, rec.member, max_sweeps=max_sweeps)
+    Vbar, owner = assemble(V_sub, rec.member, prob.v_ghost)
+    return Vbar, owner, rec, V_sub, sweeps
+
+
+def adjoint_isa(prob, member: np.ndarray, pols: List[np.ndarray], owner: np.ndarray,
+                gV: np.ndarray, tol: float = 0.0, max_iters: int = 10**7):
+    """Gradient of a loss on the assembled value Vbar with respect to the running
+    cost l, with the sets (``member``) and every set's policy frozen.  Vbar(j) is
+    the owner set's value, so dL/dVbar is routed to the owner; each set then runs
+    its own adjoint (non-members are ghosts, i.e. constants), and the per-set
+    dL/dl add up.  Returns (dLdl, per-set adjoint states)."""
+    from . import adjoint
+    fixed = fixed_mask(prob)
+    total = np.zeros(prob.N)
+    lams = []
+    for i in range(prob.n_comp):
+        dom = ((member >> i) & 1).astype(np.uint8)
+        gi = np.where(owner == i, gV, 0.0)
+        lam_i, dLdl_i, _, _ = adjoint(prob, pols[i], gi, fixed=fixed, dom=dom, tol=tol,
+                                      max_iters=max_iters)
+        total += dLdl_i
+        lams.append(lam_i)
+    return total, lams

@@ -1,0 +1,410 @@
+/*
+ * FP64 CPU oracle for the semi-Lagrangian (SL) value iteration of the discounted
+ * exit-time Hamilton-Jacobi-Bellman problem, and for its adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code with the
+ * HIP library: it is written from the paper's definitions, plainly and slowly.
+ *
+ * What it computes (paper, Section 3, scheme (SL) and operator (Tdef)):
+ *   for a free node x_j of the solve domain
+ *     [T(V)]_j = min_k { beta * I[V](x_j + h f(x_j, a_k)) + w * l(x_j) }
+ *   fixed (target) nodes keep their value, nodes outside the box or outside the
+ *   solve domain read the ghost value G (the paper's ghost nodes, finite here).
+ *   I is tensor-product linear (Q1) interpolation on the Cartesian grid.
+ *   The fixed point is found by the plain (Jacobi) iteration V <- T(V) (Sec. 3,
+ *   "the fixed point ... is found through the iterative map", a contraction).
+ *
+ * Readings of the paper used here (each is listed in the design notes):
+ *   - foot at x + h f and cost added with +, minimum over the discrete controls
+ *     (the printed signs of (Tdef) are inconsistent with the Hamiltonian (HJ));
+ *   - discount: "exp"   beta = exp(-lam h),  w = (1 - beta)/lam   (default),
+ *               "paper" beta = 1/(1 + lam h), w = h               ((Tdef) as printed);
+ *   - dynamics f(x, a_k) = c(x) b_k (+ drift(x)), evaluated in grid-index units:
+ *       disp_d = (h/dx_d * b_kd) * c_j  (+ h/dx_d * drift_jd),   u_d = i_d + disp_d;
+ *   - interpolation in a fixed operation order (weights are products of 1-tau / tau
+ *     in axis order; accumulation by fused multiply-add in corner order), so an
+ *     implementation that follows the same order gets bit-identical FP64 results.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_CORNERS 8
+
+typedef struct {
+    int dim;
+    long n[3];
+    long N;
+    int m;
+    double *e;            /* m*dim: (h/dx_d) * b_kd                  */
+    double *q;            /* N*dim: (h/dx_d) * drift_jd, or NULL     */
+    const double *c;      /* speed per node, or NULL (= 1)           */
+    double *wl;           /* w * l_j per node                        */
+    double beta;
+    double G;
+    const uint8_t *fixed; /* 1: value fixed (target node)            */
+    const uint8_t *dom;   /* NULL (whole box) or 1: node in domain   */
+} orc_prob;
+
+/* Discount beta and cost weight w of one SL step of length h. */
+int orc_scheme_constants(double lam, double h, int disc, double *beta, double *w)
+{
+    if (!(lam > 0.0) || !(h > 0.0) || !beta || !w) return -1;
+    if (disc == 0) {                 /* exact integral of e^{-lam s} over [0, h] */
+        *beta = exp(-lam * h);
+        *w = -expm1(-lam * h) / lam;
+    } else if (disc == 1) {          /* the printed (Tdef): 1/(1+lam h) and h    */
+        *beta = 1.0 / (1.0 + lam * h);
+        *w = h;
+    } else {
+        return -1;
+    }
+    return 0;
+}
+
+static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const double *hi,
+                     double h, int m, const double *b, const double *c, const double *l,
+                     const double *drift, double lam, int disc, double G,
+                     const uint8_t *fixed, const uint8_t *dom)
+{
+    double beta, w, t[3];
+    memset(P, 0, sizeof(*P));
+    if (dim < 1 || dim > 3 || m < 1) return -1;
+    P->dim = dim;
+    P->N = 1;
+    for (int d = 0; d < 3; ++d) P->n[d] = 1;
+    for (int d = 0; d < dim; ++d) {
+        if (n[d] < 2) return -1;
+        P->n[d] = n[d];
+        P->N *= n[d];
+        t[d] = h / ((hi[d] - lo[d]) / (double)(n[d] - 1));
+    }
+    if (orc_scheme_constants(lam, h, disc, &beta, &w)) return -1;
+    P->m = m;
+    P->e = (double *)malloc(sizeof(double) * (size_t)m * dim);
+    P->wl = (double *)malloc(sizeof(double) * (size_t)P->N);
+    if (!P->e || !P->wl) return -2;
+    for (int k = 0; k < m; ++k)
+        for (int d = 0; d < dim; ++d) P->e[k * dim + d] = t[d] * b[k * dim + d];
+    if (drift) {
+        P->q = (double *)malloc(sizeof(double) * (size_t)P->N * dim);
+        if (!P->q) return -2;
+        for (long j = 0; j < P->N; ++j)
+            for (int d = 0; d < dim; ++d) P->q[j * dim + d] = t[d] * drift[j * dim + d];
+    }
+    for (long j = 0; j < P->N; ++j) P->wl[j] = w * (l ? l[j] : 1.0);
+    P->c = c;
+    P->beta = beta;
+    P->G = G;
+    P->fixed = fixed;
+    P->dom = dom;
+    return 0;
+}
+
+static void prob_free(orc_prob *P)
+{
+    free(P->e);
+    free(P->q);
+    free(P->wl);
+}
+
+static inline void node_index(const orc_prob *P, long j, long *ij)
+{
+    ij[0] = j % P->n[0];
+    ij[1] = (j / P->n[0]) % P->n[1];
+    ij[2] = j / (P->n[0] * P->n[1]);
+}
+
+/* Q1 stencil at the foot of control k from node j: corner node indices (-1 = ghost:
+ * outside the box or outside the domain) and weights.  Returns the corner count. */
+static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx, double *wt)
+{
+    const int dim = P->dim;
+    double tau[3];
+    long p[3];
+    const double cj = P->c ? P->c[j] : 1.0;
+    for (int d = 0; d < dim; ++d) {
+        double disp = P->e[k * dim + d] * cj;
+        if (P->q) disp = disp + P->q[j * dim + d];
+        double u = (double)ij[d] + disp;
+        double fl = floor(u);
+        tau[d] = u - fl;
+        p[d] = (long)fl;
+    }
+    const int K = 1 << dim;
+    for (int s = 0; s < K; ++s) {
+        double w = 0.0;
+        long idx = 0, stride = 1;
+        int inside = 1;
+        for (int d = 0; d < dim; ++d) {
+            int bit = (s >> d) & 1;
+            double f = bit ? tau[d] : 1.0 - tau[d];
+            w = (d == 0) ? f : w * f;
+            long pd = p[d] + bit;
+            if (pd < 0 || pd >= P->n[d]) inside = 0;
+            idx += pd * stride;
+            stride *= P->n[d];
+        }
+        if (inside && P->dom && !P->dom[idx]) inside = 0;
+        cidx[s] = inside ? idx : -1;
+        wt[s] = w;
+    }
+    return K;
+}
+
+/* One application of T at node j; returns the minimum, *arg = first minimising k. */
+static double apply_node(const orc_prob *P, long j, const double *V, int *arg)
+{
+    long ij[3], cidx[ORC_MAX_CORNERS];
+    double wt[ORC_MAX_CORNERS];
+    node_index(P, j, ij);
+    double best = 0.0;
+    int bk = -1;
+    for (int k = 0; k < P->m; ++k) {
+        int K = stencil(P, j, ij, k, cidx, wt);
+        double r = 0.0;
+        for (int s = 0; s < K; ++s) {
+            double v = cidx[s] >= 0 ? V[cidx[s]] : P->G;
+            r = (s == 0) ? wt[0] * v : fma(wt[s], v, r);
+        }
+        double cand = fma(P->beta, r, P->wl[j]);
+        if (bk < 0 || cand < best) {
+            best = cand;
+            bk = k;
+        }
+    }
+    *arg = bk;
+    return best;
+}
+
+static inline int is_free(const orc_prob *P, long j)
+{
+    return !(P->fixed && P->fixed[j]) && !(P->dom && !P->dom[j]);
+}
+
+/* One Jacobi sweep Vn = T(V); returns max |Vn - V| over free domain nodes. */
+static double sweep(const orc_prob *P, const double *V, double *Vn, int32_t *policy)
+{
+    double res = 0.0;
+    const long N = P->N;
+#pragma omp parallel for schedule(static) reduction(max : res)
+    for (long j = 0; j < N; ++j) {
+        if (P->dom && !P->dom[j]) {
+            Vn[j] = P->G;
+            if (policy) policy[j] = -1;
+            continue;
+        }
+        if (P->fixed && P->fixed[j]) {
+            Vn[j] = V[j];
+            if (policy) policy[j] = -1;
+            continue;
+        }
+        int arg;
+        double v = apply_node(P, j, V, &arg);
+        Vn[j] = v;
+        if (policy) policy[j] = arg;
+        double dv = fabs(v - V[j]);
+        if (dv > res) res = dv;
+    }
+    return res;
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Apply T once: TV = T(V), policy (first minimising control, -1 on fixed or
+ * non-domain nodes) optional.  Returns 0 or a negative error. */
+int orc_apply(int dim, const int *n, const double *lo, const double *hi, double h, int m,
+              const double *b, const double *c, const double *l, const double *drift, double lam,
+              int disc, double G, const uint8_t *fixed, const uint8_t *dom, const double *V,
+              double *TV, int32_t *policy, int nthreads)
+{
+    orc_prob P;
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, l, drift, lam, disc, G, fixed, dom);
+    if (rc) { prob_free(&P); return rc; }
+    set_threads(nthreads);
+    (void)sweep(&P, V, TV, policy);
+    prob_free(&P);
+    return 0;
+}
+
+/* Jacobi iteration V <- T(V) from the caller's V (fixed nodes hold their values)
+ * until max|V_new - V| <= tol (tol = 0: until nothing changes) or max_sweeps.
+ * Returns the number of sweeps done (the last one's residual in *residual), or a
+ * negative error.  On return V holds the last iterate, policy (optional) the
+ * first minimising control of the last sweep. */
+long orc_solve(int dim, const int *n, const double *lo, const double *hi, double h, int m,
+               const double *b, const double *c, const double *l, const double *drift,
+               double lam, int disc, double G, const uint8_t *fixed, const uint8_t *dom,
+               double *V, int32_t *policy, double tol, long max_sweeps, double *residual,
+               int nthreads)
+{
+    orc_prob P;
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, l, drift, lam, disc, G, fixed, dom);
+    if (rc) { prob_free(&P); return rc; }
+    set_threads(nthreads);
+    double *W = (double *)malloc(sizeof(double) * (size_t)P.N);
+    if (!W) { prob_free(&P); return -2; }
+    for (long j = 0; j < P.N; ++j)
+        if (P.dom && !P.dom[j]) V[j] = G;
+    double res = INFINITY;
+    long s = 0;
+    while (s < max_sweeps) {
+        res = sweep(&P, V, W, policy);
+        memcpy(V, W, sizeof(double) * (size_t)P.N);
+        ++s;
+        if (res <= tol) break;
+    }
+    if (residual) *residual = res;
+    free(W);
+    prob_free(&P);
+    return s;
+}
+
+/* Interpolation stencil of the frozen policy: for every node j with policy[j] >= 0,
+ * corner indices (-1 = ghost) and weights of I at its foot, 2^dim per node. */
+int orc_policy_stencil(int dim, const int *n, const double *lo, const double *hi, double h, int m,
+                       const double *b, const double *c, const double *drift, const uint8_t *dom,
+                       const int32_t *policy, int64_t *cidx, double *wts)
+{
+    orc_prob P;
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, NULL, drift, 1.0, 0, 0.0, NULL, dom);
+    if (rc) { prob_free(&P); return rc; }
+    const int K = 1 << dim;
+    for (long j = 0; j < P.N; ++j) {
+        long ij[3], ci[ORC_MAX_CORNERS];
+        double wt[ORC_MAX_CORNERS];
+        if (policy[j] < 0) {
+            for (int s = 0; s < K; ++s) { cidx[j * K + s] = -1; wts[j * K + s] = 0.0; }
+            continue;
+        }
+        node_index(&P, j, ij);
+        stencil(&P, j, ij, policy[j], ci, wt);
+        for (int s = 0; s < K; ++s) { cidx[j * K + s] = ci[s]; wts[j * K + s] = wt[s]; }
+    }
+    prob_free(&P);
+    return 0;
+}
+
+/* Adjoint of the policy-frozen scheme.  With the policy frozen, on free domain
+ * nodes V = beta P V + w l + (constants from fixed and ghost corners), so for a
+ * loss with gradient gV = dL/dV the adjoint state solves
+ *     lambda = gV + beta P^T lambda      (free domain nodes only)
+ * and dL/dl_j = w lambda_j.  Plain Jacobi iteration from lambda = gV, scattering
+ * beta * weight * lambda_j to the free corners of node j's foot, until
+ * max|lambda_new - lambda| <= tol.  Output: lam_out (N, zero off free nodes) and,
+ * if dLdl != NULL, w * lambda.  Returns iterations or a negative error. */
+long orc_adjoint(int dim, const int *n, const double *lo, const double *hi, double h, int m,
+                 const double *b, const double *c, const double *drift, double lam, int disc,
+                 const uint8_t *fixed, const uint8_t *dom, const int32_t *policy,
+                 const double *gV, double *lam_out, double *dLdl, double tol, long max_iters,
+                 double *residual)
+{
+    orc_prob P;
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, NULL, drift, lam, disc, 0.0, fixed, dom);
+    if (rc) { prob_free(&P); return rc; }
+    double beta = P.beta, w;
+    orc_scheme_constants(lam, h, disc, &beta, &w);
+    const long N = P.N;
+    const int K = 1 << dim;
+    double *X = (double *)calloc((size_t)N, sizeof(double));
+    double *Y = (double *)calloc((size_t)N, sizeof(double));
+    if (!X || !Y) { free(X); free(Y); prob_free(&P); return -2; }
+    for (long j = 0; j < N; ++j) X[j] = is_free(&P, j) ? gV[j] : 0.0;
+    long it = 0;
+    double res = INFINITY;
+    while (it < max_iters) {
+        for (long j = 0; j < N; ++j) Y[j] = is_free(&P, j) ? gV[j] : 0.0;
+        for (long j = 0; j < N; ++j) {
+            if (!is_free(&P, j) || X[j] == 0.0) continue;
+            long ij[3], ci[ORC_MAX_CORNERS];
+            double wt[ORC_MAX_CORNERS];
+            node_index(&P, j, ij);
+            stencil(&P, j, ij, policy[j], ci, wt);
+            for (int s = 0; s < K; ++s)
+                if (ci[s] >= 0 && is_free(&P, ci[s])) Y[ci[s]] += beta * wt[s] * X[j];
+        }
+        res = 0.0;
+        for (long j = 0; j < N; ++j) {
+            double dv = fabs(Y[j] - X[j]);
+            if (dv > res) res = dv;
+        }
+        double *T = X; X = Y; Y = T;
+        ++it;
+        if (res <= tol) break;
+    }
+    memcpy(lam_out, X, sizeof(double) * (size_t)N);
+    if (dLdl)
+        for (long j = 0; j < N; ++j) dLdl[j] = w * X[j];
+    if (residual) *residual = res;
+    free(X); free(Y);
+    prob_free(&P);
+    return it;
+}
+
+/* Tangent of the policy-frozen scheme: Vdot = beta P Vdot + w * dl on free domain
+ * nodes (zero elsewhere), plain Jacobi from zero.  Used for the dot-product test
+ * <lambda, w dl> = <gV, Vdot>.  Returns iterations or a negative error. */
+long orc_tangent(int dim, const int *n, const double *lo, const double *hi, double h, int m,
+                 const double *b, const double *c, const double *drift, double lam, int disc,
+                 const uint8_t *fixed, const uint8_t *dom, const int32_t *policy,
+                 const double *dl, double *Vdot, double tol, long max_iters, double *residual)
+{
+    orc_prob P;
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, dl, drift, lam, disc, 0.0, fixed, dom);
+    if (rc) { prob_free(&P); return rc; }
+    const long N = P.N;
+    const int K = 1 << dim;
+    double *X = (double *)calloc((size_t)N, sizeof(double));
+    double *Y = (double *)calloc((size_t)N, sizeof(double));
+    if (!X || !Y) { free(X); free(Y); prob_free(&P); return -2; }
+    long it = 0;
+    double res = INFINITY;
+    while (it < max_iters) {
+        res = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : res)
+        for (long j = 0; j < N; ++j) {
+            if (!is_free(&P, j)) { Y[j] = 0.0; continue; }
+            long ij[3], ci[ORC_MAX_CORNERS];
+            double wt[ORC_MAX_CORNERS];
+            node_index(&P, j, ij);
+            stencil(&P, j, ij, policy[j], ci, wt);
+            double r = 0.0;
+            for (int s = 0; s < K; ++s)
+                if (ci[s] >= 0 && is_free(&P, ci[s])) r += wt[s] * X[ci[s]];
+            Y[j] = P.beta * r + P.wl[j];
+            double dv = fabs(Y[j] - X[j]);
+            if (dv > res) res = dv;
+        }
+        double *T = X; X = Y; Y = T;
+        ++it;
+        if (res <= tol) break;
+    }
+    memcpy(Vdot, X, sizeof(double) * (size_t)N);
+    if (residual) *residual = res;
+    free(X); free(Y);
+    prob_free(&P);
+    return it;
+}
