@@ -1,0 +1,156 @@
+/*
+ * slhjb.h -- C ABI of the MI355X semi-Lagrangian HJB solver with independent
+ * sub-domains (Festa, "Reconstruction of independent sub-domains for a class of
+ * Hamilton-Jacobi equations and its application to parallel computing").
+ *
+ * Problem (paper Sec. 2, exit-time problem (P1) and equation (HJ), control case):
+ *   dynamics   f(x, a_k) = c(x) * b_k   (+ drift(x))   on a discrete control set
+ *   running cost l(x) > 0, discount lambda > 0, target set Gamma = union of
+ *   components Gamma_i (nodes with target id i), exit cost g on Gamma.
+ * Scheme (Sec. 3, (SL) and (Tdef), read as: foot x + h f, cost added, min over
+ * controls):  for a free node x_j
+ *   V(j) = min_k { beta * I[V](x_j + h f(x_j, a_k)) + w * l(x_j) }
+ *   I = Q1 (bi/trilinear) interpolation on the Cartesian grid; corners outside
+ *   the box or outside the current sub-domain read the ghost value v_ghost;
+ *   target nodes keep g.  Discount: SL_DISC_EXP beta = exp(-lambda h),
+ *   w = (1 - beta)/lambda;  SL_DISC_PAPER beta = 1/(1 + lambda h), w = h.
+ * Fixed point by value iteration from V = v_ghost (a supersolution), which the
+ * paper notes is a contraction (Sec. 3).
+ *
+ * Conventions (all entry points):
+ *   - Array arguments marked DEVICE are device pointers owned by the caller; the
+ *     library never frees or keeps them past the call.  HOST arrays are read
+ *     during the call only.
+ *   - Node fields are flat, row-major, x fastest: j = i0 + n0*(i1 + n1*i2).
+ *   - Every device operation is ordered on the caller's HIP stream `stream`
+ *     (NULL = default stream).  A call returns after its work has completed
+ *     (it synchronizes the stream once at the end to fill the stats).
+ *   - Scratch memory is a caller-provided DEVICE workspace of at least the size
+ *     the matching *_workspace_size query returns; it may be reused between calls.
+ *   - Functions return an sl_status.  No C++ exception crosses the ABI.  Errors
+ *     are not sticky: the next call starts clean.  On SL_NOT_CONVERGED the outputs
+ *     are written with the last iterate.
+ */
+#ifndef SLHJB_H
+#define SLHJB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLHJB_ABI_VERSION 1
+#define SL_MAX_COMP 8
+#define SL_MAX_CONTROLS 256
+
+typedef enum {
+    SL_OK = 0,
+    SL_NOT_CONVERGED = 1,     /* max_sweeps reached before the tolerance           */
+    SL_ERR_INVALID_ARG = -1,  /* bad size, pointer, value or too small workspace    */
+    SL_ERR_NO_TARGET = -2,    /* no target node (checked on the device)            */
+    SL_ERR_UNSUPPORTED = -3,  /* dim, control count or component count out of range */
+    SL_ERR_HIP = -4,          /* a HIP runtime call failed                          */
+    SL_ERR_WORKSPACE = -5     /* workspace smaller than the query says              */
+} sl_status;
+
+typedef enum { SL_F32 = 0, SL_F64 = 1 } sl_dtype;
+typedef enum { SL_DISC_EXP = 0, SL_DISC_PAPER = 1 } sl_disc;
+
+/* One exit-time problem on a uniform box grid (paper Sec. 2-3). */
+typedef struct sl_problem {
+    int dim;                  /* 2 or 3                                              */
+    int n[3];                 /* nodes per axis (>= 3 on used axes)                  */
+    double lo[3], hi[3];      /* box corners; dx_d = (hi_d - lo_d)/(n_d - 1)         */
+    int m;                    /* number of discrete controls, 1..SL_MAX_CONTROLS     */
+    const double *velocity;   /* HOST, m*dim: b_k with f(x, a_k) = c(x) b_k           */
+    const void *speed;        /* DEVICE, N values of c(x) >= 0 in `dtype`; NULL = 1   */
+    const void *cost;         /* DEVICE, N values of l(x) > 0 in `dtype`; NULL = 1    */
+    const void *drift;        /* DEVICE, N*dim drift b(x) in `dtype` (node-major); NULL = 0 */
+    const int8_t *target;     /* DEVICE, N: -1 free node, i in [0, n_comp) target of component i */
+    const void *g;            /* DEVICE, N exit costs (read on target nodes) in `dtype`; NULL = 0 */
+    int n_comp;               /* number of target components, 1..SL_MAX_COMP          */
+    double lambda;            /* discount rate > 0                                    */
+    double h;                 /* fictitious time step > 0                             */
+    double v_ghost;           /* value read outside the box / sub-domain; should be >= max(l)/lambda */
+    int disc;                 /* sl_disc                                              */
+    int dtype;                /* sl_dtype of fields and values                        */
+} sl_problem;
+
+/* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */
+typedef struct sl_ra_opts {
+    int coarse_stride;        /* s >= 1 dividing n_d - 1: coarse grid K = every s-th node */
+    double C, M, q;           /* threshold delta = 2 (C dx_K^q + M dx_K) (Prop. 3.1)  */
+    double delta_override;    /* > 0: use this delta instead                          */
+    double tol;               /* coarse stopping tolerance on max|V_new - V| (0 = until nothing changes) */
+    long max_sweeps;          /* coarse sweep cap                                     */
+} sl_ra_opts;
+
+/* Value-iteration options. */
+typedef struct sl_solve_opts {
+    double tol;               /* stop when max|V_new - V| <= tol over the sub-domain (0: no change) */
+    long max_sweeps;          /* sweep cap (>= 1)                                     */
+    int want_policy;          /* write the first minimising control index per node   */
+    int check_every;          /* sweeps between host convergence polls (0 = default 32) */
+    int profile;              /* 1: time the sweep launches with HIP events (stats.ms_sweeps) */
+} sl_solve_opts;
+
+/* Per-call statistics (HOST struct filled at the end of a call). */
+typedef struct sl_stats {
+    long sweeps_max;          /* most sweeps done by one sub-domain                   */
+    long sweeps_total;        /* sum over sub-domains                                 */
+    double residual;          /* largest final residual over sub-domains              */
+    double node_control_updates; /* node*control evaluations actually computed        */
+    double ms_ra, ms_fine, ms_total; /* wall times of the phases (HIP events)         */
+    int n_subdomains;         /* sub-domains solved                                   */
+    int n_unreachable;        /* reserved (0)                                         */
+    double set_fraction_max;  /* max_i |Sigma_i| / N on the fine grid (ISA calls)     */
+    double ms_sweeps;         /* profile: HIP-event time spanning the sweep launches  */
+    long sweep_launches;      /* profile: number of sweep launches timed              */
+} sl_stats;
+
+const char *sl_status_string(int status);
+int sl_abi_version(void);
+
+/* Workspace bytes needed by sl_solve for problem `p` (0 if `p` is invalid). */
+size_t sl_solve_workspace_size(const sl_problem *p);
+
+/* Global solve ("no decomposition"): value iteration of T on the whole grid
+ * (paper Sec. 3, (SL)).  Outputs: V (DEVICE, N in p->dtype), policy (DEVICE, N
+ * uint8, 255 on target nodes; may be NULL).  Targets start at g, free nodes at
+ * v_ghost. */
+int sl_solve(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_bytes,
+             void *V, uint8_t *policy, sl_stats *stats, void *stream);
+
+/* Workspace bytes needed by sl_reconstruct / sl_solve_isa. */
+size_t sl_isa_workspace_size(const sl_problem *p, const sl_ra_opts *ra);
+
+/* Reconstruction of the independent sub-domains (paper Sec. 3, RA steps 1-3, on
+ * the coarse grid K of ISA step 1; Sec. 4, ISA step 2 projection to the fine
+ * grid).  The coarse auxiliary solves run in FP64 whatever p->dtype is, with the
+ * operation order of the scheme fixed (products of 1-tau / tau in axis order,
+ * fused multiply-add accumulation in corner order, candidate fma(beta, I, w l)),
+ * so the labels are reproducible bit for bit.
+ * Outputs (DEVICE, N uint8 each): member = bitmask of the sets containing each
+ * fine node; label = coarse argmin component at the nearest coarse node.
+ * member_K, label_K (DEVICE, N_K uint8 each) may be NULL. */
+int sl_reconstruct(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t ws_bytes,
+                   uint8_t *member, uint8_t *label, uint8_t *member_K, uint8_t *label_K,
+                   sl_stats *stats, void *stream);
+
+/* ISA steps 3-4 (paper Sec. 4): value iteration of T on every set i (nodes with
+ * bit i of `member`; non-members read v_ghost), all sets in one launch per
+ * sweep, then V(j) = min over the sets containing j.  Inputs: member (DEVICE, N
+ * uint8).  Outputs: V (DEVICE, N in p->dtype), owner (DEVICE, N uint8, lowest
+ * minimising set; may be NULL), policy (DEVICE, n_comp*N uint8 per set, 255 on
+ * target and non-member nodes; may be NULL), V_sets (DEVICE, n_comp*N values per
+ * set, v_ghost off the set; may be NULL). */
+int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
+                 const sl_solve_opts *o, void *ws, size_t ws_bytes, void *V, uint8_t *owner,
+                 uint8_t *policy, void *V_sets, sl_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLHJB_H */

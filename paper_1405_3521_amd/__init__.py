@@ -1,0 +1,330 @@
+"""MI355X semi-Lagrangian HJB solver with independent sub-domains.
+
+Thin Python binding of the C-ABI library ``libslhjb.so`` (declared in
+``include/slhjb.h``).  PyTorch provides device memory and streams; every step of
+the solver runs in the library's HIP kernels.  This module only marshals
+arguments (ctypes) and allocates the output tensors and workspaces.
+
+If the library is not built, or no HIP device is present, the functions raise:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "DeviceProblem", "RaOpts", "SolveOpts", "lib", "lib_path", "to_device", "solve",
+    "reconstruct", "solve_isa", "isa", "SlError",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_lib", "libslhjb.so")
+_LIB = None
+
+SL_OK, SL_NOT_CONVERGED = 0, 1
+DISC = {"exp": 0, "paper": 1}
+
+
+class SlError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = lib().sl_status_string(status).decode()
+        super().__init__(f"{fn} failed: {msg} ({status})")
+        self.status = status
+
+
+class SlProblem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("n", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("m", C.c_int), ("velocity", C.POINTER(C.c_double)), ("speed", C.c_void_p),
+        ("cost", C.c_void_p), ("drift", C.c_void_p), ("target", C.c_void_p), ("g", C.c_void_p),
+        ("n_comp", C.c_int), ("lambda_", C.c_double), ("h", C.c_double),
+        ("v_ghost", C.c_double), ("disc", C.c_int), ("dtype", C.c_int),
+    ]
+
+
+class SlRaOpts(C.Structure):
+    _fields_ = [("coarse_stride", C.c_int), ("C", C.c_double), ("M", C.c_double),
+                ("q", C.c_double), ("delta_override", C.c_double), ("tol", C.c_double),
+                ("max_sweeps", C.c_long)]
+
+
+class SlSolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_sweeps", C.c_long), ("want_policy", C.c_int),
+                ("check_every", C.c_int), ("profile", C.c_int)]
+
+
+class SlStats(C.Structure):
+    _fields_ = [("sweeps_max", C.c_long), ("sweeps_total", C.c_long), ("residual", C.c_double),
+                ("node_control_updates", C.c_double), ("ms_ra", C.c_double),
+                ("ms_fine", C.c_double), ("ms_total", C.c_double), ("n_subdomains", C.c_int),
+                ("n_unreachable", C.c_int), ("set_fraction_max", C.c_double),
+                ("ms_sweeps", C.c_double), ("sweep_launches", C.c_long)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libslhjb.so (raises if it is not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is not built: run `python -m paper_1405_3521_amd.build`")
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        L.sl_status_string.argtypes = [C.c_int]
+        L.sl_status_string.restype = C.c_char_p
+        L.sl_abi_version.restype = C.c_int
+        L.sl_solve_workspace_size.argtypes = [P(SlProblem)]
+        L.sl_solve_workspace_size.restype = C.c_size_t
+        L.sl_solve.argtypes = [P(SlProblem), P(SlSolveOpts), C.c_void_p, C.c_size_t, C.c_void_p,
+                               C.c_void_p, P(SlStats), C.c_void_p]
+        L.sl_solve.restype = C.c_int
+        L.sl_isa_workspace_size.argtypes = [P(SlProblem), P(SlRaOpts)]
+        L.sl_isa_workspace_size.restype = C.c_size_t
+        L.sl_reconstruct.argtypes = [P(SlProblem), P(SlRaOpts), C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(SlStats),
+                                     C.c_void_p]
+        L.sl_reconstruct.restype = C.c_int
+        L.sl_solve_isa.argtypes = [P(SlProblem), P(SlRaOpts), C.c_void_p, P(SlSolveOpts),
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, P(SlStats), C.c_void_p]
+        L.sl_solve_isa.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+# ------------------------------------------------------------------ problem data
+@dataclass
+class DeviceProblem:
+    """A problem whose node fields are device tensors (see include/slhjb.h)."""
+    dim: int
+    n: tuple
+    lo: tuple
+    hi: tuple
+    velocity: np.ndarray            # host (m, dim) float64
+    target: "object"                # torch.int8 device tensor (N,)
+    n_comp: int
+    speed: Optional[object] = None  # torch tensor (N,) of `dtype` or None
+    cost: Optional[object] = None
+    g: Optional[object] = None
+    lam: float = 1.0
+    h: float = 0.0
+    v_ghost: float = 1.0
+    disc: str = "exp"
+    dtype: "object" = None          # torch.float32 / torch.float64
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def m(self) -> int:
+        return int(self.velocity.shape[0])
+
+    @property
+    def step(self) -> float:
+        return self.h if self.h > 0 else (self.hi[0] - self.lo[0]) / (self.n[0] - 1)
+
+
+@dataclass
+class RaOpts:
+    coarse_stride: int = 1
+    C: float = 0.5
+    M: float = 0.5
+    q: float = 1.0
+    delta_override: float = 0.0
+    tol: float = 0.0
+    max_sweeps: int = 10_000_000
+
+
+@dataclass
+class SolveOpts:
+    tol: float = 0.0
+    max_sweeps: int = 10_000_000
+    want_policy: bool = False
+    check_every: int = 0
+    profile: bool = False
+
+
+def to_device(prob, dtype=None, device: str = "cuda:0") -> DeviceProblem:
+    """Copy a host problem description (any object with the attributes of
+    ``DeviceProblem``, fields as numpy arrays) to device tensors of ``dtype``."""
+    import torch
+    dtype = dtype or torch.float32
+
+    def dev(a, dt):
+        return None if a is None else torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+
+    return DeviceProblem(
+        dim=prob.dim, n=tuple(prob.n), lo=tuple(prob.lo), hi=tuple(prob.hi),
+        velocity=np.ascontiguousarray(prob.velocity, dtype=np.float64),
+        target=dev(prob.target, torch.int8), n_comp=int(prob.n_comp),
+        speed=dev(getattr(prob, "speed", None), dtype), cost=dev(getattr(prob, "cost", None), dtype),
+        g=dev(getattr(prob, "g", None), dtype), lam=float(prob.lam),
+        h=float(getattr(prob, "step", 0.0) or prob.h), v_ghost=float(prob.v_ghost),
+        disc=prob.disc, dtype=dtype)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, dtype, numel, name):
+    import torch
+    if t is None:
+        return
+    if not t.is_cuda or t.dtype != dtype or t.numel() != numel or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} device tensor with {numel} elements")
+
+
+def _cproblem(p: DeviceProblem):
+    import torch
+    N = p.N
+    _check_tensor(p.target, torch.int8, N, "target")
+    for name in ("speed", "cost", "g"):
+        _check_tensor(getattr(p, name), p.dtype, N, name)
+    vel = np.ascontiguousarray(p.velocity, dtype=np.float64)
+    if vel.ndim != 2 or vel.shape[1] != p.dim:
+        raise ValueError("velocity must have shape (m, dim)")
+    cp = SlProblem()
+    cp.dim = p.dim
+    for d in range(3):
+        cp.n[d] = int(p.n[d]) if d < p.dim else 1
+        cp.lo[d] = float(p.lo[d]) if d < p.dim else 0.0
+        cp.hi[d] = float(p.hi[d]) if d < p.dim else 1.0
+    cp.m = vel.shape[0]
+    cp.velocity = vel.ctypes.data_as(C.POINTER(C.c_double))
+    cp.speed = _ptr(p.speed)
+    cp.cost = _ptr(p.cost)
+    cp.drift = None
+    cp.target = _ptr(p.target)
+    cp.g = _ptr(p.g)
+    cp.n_comp = p.n_comp
+    cp.lambda_ = p.lam
+    cp.h = p.step
+    cp.v_ghost = p.v_ghost
+    cp.disc = DISC[p.disc]
+    cp.dtype = 0 if p.dtype == torch.float32 else 1
+    return cp, vel           # keep vel alive
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ra(o: RaOpts) -> SlRaOpts:
+    return SlRaOpts(o.coarse_stride, o.C, o.M, o.q, o.delta_override, o.tol, o.max_sweeps)
+
+
+def _so(o: SolveOpts) -> SlSolveOpts:
+    return SlSolveOpts(o.tol, o.max_sweeps, int(bool(o.want_policy)), o.check_every,
+                       int(bool(o.profile)))
+
+
+def _workspace(nbytes: int, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def solve(p: DeviceProblem, opts: SolveOpts = SolveOpts(), out=None, policy=None,
+          workspace=None):
+    """Global value iteration (no decomposition).  Returns (V, policy or None, stats)."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    ws_bytes = L.sl_solve_workspace_size(C.byref(cp))
+    if ws_bytes == 0:
+        raise ValueError("invalid problem")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    V = out if out is not None else torch.empty(p.N, dtype=p.dtype, device=dev)
+    pol = policy
+    if opts.want_policy and pol is None:
+        pol = torch.full((p.N,), 255, dtype=torch.uint8, device=dev)
+    st = SlStats()
+    rc = L.sl_solve(C.byref(cp), C.byref(_so(opts)), _ptr(ws), ws.numel(), _ptr(V), _ptr(pol),
+                    C.byref(st), _stream())
+    if rc < 0:
+        raise SlError("sl_solve", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    return V, pol, d
+
+
+def reconstruct(p: DeviceProblem, ra: RaOpts, want_coarse: bool = False, workspace=None):
+    """RA on the coarse grid + projection.  Returns (member, label, stats[, mK, lK])."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    cra = _ra(ra)
+    ws_bytes = L.sl_isa_workspace_size(C.byref(cp), C.byref(cra))
+    if ws_bytes == 0:
+        raise ValueError("invalid problem or RA options")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    member = torch.empty(p.N, dtype=torch.uint8, device=dev)
+    label = torch.empty(p.N, dtype=torch.uint8, device=dev)
+    NK = 1
+    for d in range(p.dim):
+        NK *= (p.n[d] - 1) // ra.coarse_stride + 1
+    mK = torch.empty(NK, dtype=torch.uint8, device=dev) if want_coarse else None
+    lK = torch.empty(NK, dtype=torch.uint8, device=dev) if want_coarse else None
+    st = SlStats()
+    rc = L.sl_reconstruct(C.byref(cp), C.byref(cra), _ptr(ws), ws.numel(), _ptr(member),
+                          _ptr(label), _ptr(mK), _ptr(lK), C.byref(st), _stream())
+    if rc < 0:
+        raise SlError("sl_reconstruct", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    if want_coarse:
+        return member, label, d, mK, lK
+    return member, label, d
+
+
+def solve_isa(p: DeviceProblem, ra: RaOpts, member, opts: SolveOpts = SolveOpts(),
+              want_owner: bool = True, want_sets: bool = False, workspace=None):
+    """ISA steps 3-4 on given sets.  Returns (V, owner, policy, V_sets, stats)."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    _check_tensor(member, torch.uint8, p.N, "member")
+    cra = _ra(ra)
+    ws_bytes = L.sl_isa_workspace_size(C.byref(cp), C.byref(cra))
+    if ws_bytes == 0:
+        raise ValueError("invalid problem or RA options")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    V = torch.empty(p.N, dtype=p.dtype, device=dev)
+    owner = torch.empty(p.N, dtype=torch.uint8, device=dev) if want_owner else None
+    pol = (torch.full((p.n_comp * p.N,), 255, dtype=torch.uint8, device=dev)
+           if opts.want_policy else None)
+    Vs = torch.empty(p.n_comp * p.N, dtype=p.dtype, device=dev) if want_sets else None
+    st = SlStats()
+    rc = L.sl_solve_isa(C.byref(cp), C.byref(cra), _ptr(member), C.byref(_so(opts)), _ptr(ws),
+                        ws.numel(), _ptr(V), _ptr(owner), _ptr(pol), _ptr(Vs), C.byref(st),
+                        _stream())
+    if rc < 0:
+        raise SlError("sl_solve_isa", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    return V, owner, pol, Vs, d
+
+
+def isa(p: DeviceProblem, ra: RaOpts, opts: SolveOpts = SolveOpts(), want_sets: bool = False):
+    """The whole independent-sets algorithm: reconstruct, then solve the sets."""
+    member, label, st_ra = reconstruct(p, ra)
+    V, owner, pol, Vs, st = solve_isa(p, ra, member, opts, want_sets=want_sets)
+    st["ms_ra"] = st_ra["ms_total"]
+    st["ra_sweeps_max"] = st_ra["sweeps_max"]
+    return V, owner, member, label, pol, Vs, st

@@ -1,0 +1,162 @@
+// Internal declarations of the slhjb HIP library (not part of the C ABI).
+//
+// Execution model
+//   A "sub-domain" (sd) is one value-iteration problem on one box grid: the
+//   whole grid (global solve), one auxiliary problem of the reconstruction
+//   algorithm on the coarse grid, one reconstructed set on the fine grid, or one
+//   problem of a batch.  Every sweep is ONE launch over a device-built list of
+//   (sd, tile) work items; each work item stages its tile plus a halo of H nodes
+//   in LDS and applies the SL operator to its free member nodes (Jacobi: read
+//   buffer s%2, write 1-s%2).  Per-sd residuals are max-reduced on the device
+//   (FP64, atomicMax on the bit pattern); a converged sd is skipped by later
+//   sweeps, so no host round trip is needed per sweep.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/slhjb.h"
+
+namespace slhjb {
+
+constexpr int kMaxHalo = 8;            // largest supported halo (cells)
+constexpr int kThreads = 256;          // threads per sweep work-group (4 waves)
+
+// Per-sub-domain description (device memory, read-only during a sweep).
+template <typename T>
+struct SdDesc {
+    T *V[2];                    // Jacobi double buffer
+    const T *speed;             // per-node speed c(x) or nullptr (= 1)
+    const T *wl;                // per-node w*l(x) or nullptr (= wl_const)
+    const T *drift;             // per-node (h/dx)*drift, dim values per node, or nullptr
+    const int8_t *target;       // per-node target id (>= 0: fixed node)
+    const uint8_t *member;      // per-node set bitmask or nullptr (whole box)
+    uint8_t *policy;            // per-node first minimising control (policy pass only)
+    const T *ctrl;              // m*dim control displacements e_kd = (h/dx_d) b_kd
+    T wl_const, beta, G;
+    int n[3];
+    int m;
+    int bit;                    // member bit of this sd
+    int tiles[3];               // tiles per axis
+    int tile_offset;            // first global tile id of this sd
+    int halo;                   // halo this sd needs (<= launch halo)
+};
+
+// Per-sub-domain convergence state (device memory).
+struct SdState {
+    unsigned long long res[3];  // residual slots (FP64 bit patterns, >= 0)
+    int conv_at;                // sweep whose residual first met tol, -1 if none
+    int final_buf;              // buffer holding the latest iterate
+    int done_sweeps;            // sweeps applied to this sd
+    int pad;
+    unsigned long long final_res;  // residual of the last sweep (set by bookkeeping)
+};
+
+struct WorkItem {
+    int sd;
+    int t[3];                   // tile coordinates
+};
+
+// Counters shared by a launch sequence (device memory).
+struct ExecCounters {
+    int n_items;                // valid work items
+    int n_active;               // sds not yet converged (after the last bookkeeping)
+    unsigned long long nc_updates;  // node*control evaluations (only in stats mode)
+};
+
+// Input statistics gathered on the device in one pass (see launch_field_stats).
+struct FieldStats {
+    unsigned long long speed_max;   // FP64 bit patterns of non-negative maxima
+    unsigned long long cost_max;
+    unsigned long long drift_max;
+    int bad_speed;                  // speed < 0 or non-finite, drift non-finite
+    int bad_cost;                   // cost <= 0 or non-finite
+    int n_target;                   // nodes with target id >= 0
+    int bad_target;                 // target ids >= n_comp
+    int first_node[SL_MAX_COMP];    // lowest node index per component (INT_MAX: none)
+};
+
+struct LaunchCfg {
+    int dim;
+    int dtype;                  // SL_F32 / SL_F64
+    int tile[3];                // tile shape
+    int halo;                   // H
+    int variant;                // kernel variant id (autotuner)
+};
+
+// ---- launchers (sweep.hip) -------------------------------------------------
+// One Jacobi sweep over all work items.  `sweep` is the global sweep index.
+hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
+                        const WorkItem *items, const ExecCounters *cnt, int max_items,
+                        int sweep, double tol, int want_policy, hipStream_t s);
+// Bookkeeping before sweep `sweep` (marks sds converged, resets slots, counts
+// active sds); `final_pass` also settles final_buf of unconverged sds.
+hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep, double tol,
+                           ExecCounters *cnt, int final_pass, hipStream_t s);
+// Supported tile shapes per (dim) for the autotuner; returns count.
+int sweep_variants(int dim, LaunchCfg *out, int cap);
+
+// ---- launchers (ops.hip) ----------------------------------------------------
+template <typename T>
+hipError_t launch_fill(T *dst, T v, size_t n, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_convert(const Tin *src, Tout *dst, size_t n, Tout scale, hipStream_t s);
+// dst[j] = scale * (src ? src[j] : 1)
+template <typename Tin, typename Tout>
+hipError_t launch_scale_field(const Tin *src, Tout *dst, size_t n, double scale, hipStream_t s);
+// max over a field (non-negative values), result as double bits in *out (pre-zeroed)
+template <typename T>
+hipError_t launch_absmax(const T *src, size_t n, unsigned long long *out, hipStream_t s);
+// count of nodes with target >= 0 (int atomic) and per-component presence bits
+hipError_t launch_target_scan(const int8_t *target, size_t n, int n_comp, int *count,
+                              int *first_node, hipStream_t s);
+// V init for a solve: fixed (target) nodes -> g (or G if comp >= 0 and id != comp),
+// others -> G.  member/bit: non-members -> G.
+template <typename T>
+hipError_t launch_init_values(T *V, const int8_t *target, const T *g, T G, int comp,
+                              size_t n, hipStream_t s);
+// Build work items for sds whose grids are tiled with cfg.tile; sds with member
+// masks only get tiles that contain a member node.
+template <typename T>
+hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, int n_sd,
+                              int total_tiles, const int *tile_prefix_dev, WorkItem *items,
+                              ExecCounters *cnt, hipStream_t s);
+// Coarse grid gather: dst[k] = src[k*s per axis]
+template <typename T>
+hipError_t launch_gather_coarse(const T *src, T *dst, const int *n, const int *nK, int dim,
+                                int stride, int comps, hipStream_t s);
+hipError_t launch_gather_coarse_i8(const int8_t *src, int8_t *dst, const int *n,
+                                   const int *nK, int dim, int stride, hipStream_t s);
+// Place components without a coincident coarse node (single thread, in order).
+template <typename T>
+hipError_t launch_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,
+                                const int *firstK, const int *n, const int *nK, int dim,
+                                int stride, int n_comp, hipStream_t s);
+// One-pass input statistics (fs must be pre-initialised: zeros, first_node = INT_MAX).
+template <typename T>
+hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
+                              const int8_t *target, size_t n, int n_comp, FieldStats *fs,
+                              hipStream_t s);
+// Flip final_buf of every sd (after a policy pass).
+hipError_t launch_flip(SdState *st, int n_sd, hipStream_t s);
+// RA steps 2-3 on K: V = min_i V_i, member bits, argmin label.
+hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
+                             double delta, uint8_t *memberK, uint8_t *labelK, hipStream_t s);
+// ISA step 2: Con(.) projection + orphan repair + nearest-node label.
+hipError_t launch_project(const uint8_t *memberK, const uint8_t *labelK, const int *nK,
+                          const int *n, int dim, int stride, uint8_t *member, uint8_t *label,
+                          hipStream_t s);
+// ISA step 4: V = min over member sets (final buffers from SdState), owner.
+template <typename T>
+hipError_t launch_assemble(const SdDesc<T> *sds_dev, const SdState *st, int n_comp,
+                           const uint8_t *member, size_t N, T G, T *V, uint8_t *owner,
+                           hipStream_t s);
+// Copy the final buffer of sd `i` to dst.
+template <typename T>
+hipError_t launch_copy_final(const SdDesc<T> *sds_dev, const SdState *st, int i, T *dst,
+                             size_t N, hipStream_t s);
+// member popcounts per bit (for set fractions)
+hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long long *counts8,
+                                hipStream_t s);
+
+}  // namespace slhjb

@@ -1,0 +1,485 @@
+// Element-wise and integer kernels around the sweeps: initial values, coarse-grid
+// gathers, the reconstruction algorithm's combine/threshold step, the Con(.)
+// projection to the fine grid, the min-assembly of the sub-domain values and the
+// construction of the (sub-domain, tile) work list.  All are streaming kernels
+// (HBM/L2 bound); grid-stride loops with 256-thread work-groups.
+#include "internal.h"
+
+namespace slhjb {
+
+namespace {
+
+constexpr int kOpThreads = 256;
+
+inline int grid_for(size_t n) {
+    size_t g = (n + kOpThreads - 1) / kOpThreads;
+    if (g > 65536) g = 65536;
+    return g > 0 ? (int)g : 1;
+}
+
+template <typename T>
+__global__ void k_fill(T *dst, T v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = v;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_scale_field(const Tin *src, Tout *dst, size_t n, double scale) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double v = src ? (double)src[i] : 1.0;
+        dst[i] = (Tout)(scale * v);
+    }
+}
+
+template <typename T>
+__global__ void k_absmax(const T *src, size_t n, unsigned long long *out) {
+    double m = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double v = __builtin_fabs((double)src[i]);
+        if (!(v == v)) v = INFINITY;             // NaN -> reported as +inf
+        m = v > m ? v : m;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m > 0.0)
+        atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// Input statistics in one pass: max |speed| and |drift|, max cost, counts of bad
+// values (speed < 0, cost <= 0, non-finite), target counts, lowest node index per
+// target component, target ids out of range.
+template <typename T>
+__global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int dim,
+                              const int8_t *target, size_t n, int n_comp, FieldStats *fs) {
+    double smax = 0.0, cmax = 0.0, dmax = 0.0;
+    int bad_s = 0, bad_c = 0, ntar = 0, bad_t = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (speed) {
+            const double v = (double)speed[i];
+            if (!(v >= 0.0) || !(v < INFINITY)) ++bad_s; else smax = v > smax ? v : smax;
+        }
+        if (cost) {
+            const double v = (double)cost[i];
+            if (!(v > 0.0) || !(v < INFINITY)) ++bad_c; else cmax = v > cmax ? v : cmax;
+        }
+        if (drift) {
+            for (int d = 0; d < dim; ++d) {
+                const double v = __builtin_fabs((double)drift[i * dim + d]);
+                if (!(v < INFINITY)) ++bad_s; else dmax = v > dmax ? v : dmax;
+            }
+        }
+        const int t = target[i];
+        if (t >= 0) {
+            ++ntar;
+            if (t < n_comp) atomicMin(&fs->first_node[t], (int)i); else ++bad_t;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(smax, off, 64); smax = o > smax ? o : smax;
+        o = __shfl_xor(cmax, off, 64); cmax = o > cmax ? o : cmax;
+        o = __shfl_xor(dmax, off, 64); dmax = o > dmax ? o : dmax;
+        bad_s += __shfl_xor(bad_s, off, 64);
+        bad_c += __shfl_xor(bad_c, off, 64);
+        ntar += __shfl_xor(ntar, off, 64);
+        bad_t += __shfl_xor(bad_t, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (smax > 0.0) atomicMax(&fs->speed_max, (unsigned long long)__double_as_longlong(smax));
+        if (cmax > 0.0) atomicMax(&fs->cost_max, (unsigned long long)__double_as_longlong(cmax));
+        if (dmax > 0.0) atomicMax(&fs->drift_max, (unsigned long long)__double_as_longlong(dmax));
+        if (bad_s) atomicAdd(&fs->bad_speed, bad_s);
+        if (bad_c) atomicAdd(&fs->bad_cost, bad_c);
+        if (ntar) atomicAdd(&fs->n_target, ntar);
+        if (bad_t) atomicAdd(&fs->bad_target, bad_t);
+    }
+}
+
+__global__ void k_target_scan(const int8_t *target, size_t n, int n_comp, int *count,
+                              int *first_node) {
+    int local = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int t = target[i];
+        if (t >= 0) {
+            ++local;
+            if (t < n_comp) atomicMin(&first_node[t], (int)i);
+        }
+    }
+    if (local) atomicAdd(count, local);
+}
+
+template <typename T>
+__global__ void k_init_values(T *V, const int8_t *target, const T *g, T G, int comp,
+                              size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int t = target[i];
+        T v = G;
+        if (t >= 0 && (comp < 0 || t == comp)) v = g ? g[i] : T(0);
+        V[i] = v;
+    }
+}
+
+// One work-group per (sd, tile): OR-reduce the member bit over the tile's nodes.
+template <typename T>
+__global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
+                              const int *tile_prefix, int tx, int ty, int tz,
+                              WorkItem *items, ExecCounters *cnt) {
+    __shared__ int hit;
+    const int g = blockIdx.x;
+    if (g >= total_tiles) return;
+    // binary search the sd owning tile g
+    int lo = 0, hi = n_sd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const int sd = lo;
+    const SdDesc<T> &d = sds[sd];
+    const int local = g - tile_prefix[sd];
+    const int t0 = local % d.tiles[0];
+    const int t1 = (local / d.tiles[0]) % d.tiles[1];
+    const int t2 = local / (d.tiles[0] * d.tiles[1]);
+    if (threadIdx.x == 0) hit = d.member ? 0 : 1;
+    __syncthreads();
+    if (d.member) {
+        const int cnt_nodes = tx * ty * tz;
+        int mine = 0;
+        for (int q = threadIdx.x; q < cnt_nodes; q += blockDim.x) {
+            const int lx = q % tx, ly = (q / tx) % ty, lz = q / (tx * ty);
+            const int gx = t0 * tx + lx, gy = t1 * ty + ly, gz = t2 * tz + lz;
+            if (gx < d.n[0] && gy < d.n[1] && gz < d.n[2]) {
+                const size_t j = ((size_t)gz * d.n[1] + gy) * d.n[0] + gx;
+                mine |= (d.member[j] >> d.bit) & 1;
+            }
+        }
+        if (__any(mine) && (threadIdx.x & 63) == 0) hit = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && hit) {
+        const int slot = atomicAdd(&cnt->n_items, 1);
+        WorkItem w;
+        w.sd = sd;
+        w.t[0] = t0;
+        w.t[1] = t1;
+        w.t[2] = t2;
+        items[slot] = w;
+    }
+}
+
+template <typename T>
+__global__ void k_gather_coarse(const T *src, T *dst, int n0, int n1, int k0, int k1, int k2,
+                                int stride, int comps) {
+    const size_t NK = (size_t)k0 * k1 * k2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < NK;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int a = (int)(i % k0);
+        const int b = (int)((i / k0) % k1);
+        const int c = (int)(i / ((size_t)k0 * k1));
+        const size_t j = ((size_t)c * stride * n1 + (size_t)b * stride) * n0 + (size_t)a * stride;
+        for (int q = 0; q < comps; ++q) dst[i * comps + q] = src[j * comps + q];
+    }
+}
+
+// Components with no coincident coarse node get the coarse node nearest to
+// their lowest-index fine node (components in index order; an occupied coarse
+// node is not taken over).  firstK: lowest coarse node per component (or INT_MAX).
+template <typename T>
+__global__ void k_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,
+                                const int *firstK, int n0, int n1, int k0, int k1, int k2,
+                                int dim, int stride, int n_comp) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < n_comp; ++i) {
+        if (firstK[i] != 0x7fffffff) continue;
+        const int j = first_fine[i];
+        if (j == 0x7fffffff) continue;
+        const int a = j % n0, b = (j / n0) % n1, c = j / (n0 * n1);
+        int ka = (a + stride / 2) / stride, kb = (b + stride / 2) / stride,
+            kc = (c + stride / 2) / stride;
+        ka = ka < k0 - 1 ? ka : k0 - 1;
+        kb = kb < k1 - 1 ? kb : k1 - 1;
+        kc = kc < k2 - 1 ? kc : k2 - 1;
+        if (dim < 3) kc = 0;
+        const size_t jk = ((size_t)kc * k1 + kb) * k0 + ka;
+        if (tK[jk] < 0) {
+            tK[jk] = (int8_t)i;
+            if (gK) gK[jk] = g ? g[j] : T(0);
+        }
+    }
+}
+
+__global__ void k_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
+                             double delta, uint8_t *memberK, uint8_t *labelK) {
+    for (size_t z = blockIdx.x * (size_t)blockDim.x + threadIdx.x; z < NK;
+         z += (size_t)gridDim.x * blockDim.x) {
+        double V = Vaux[z];
+        for (int i = 1; i < n_comp; ++i) {
+            const double v = Vaux[(size_t)i * NK + z];
+            V = v < V ? v : V;
+        }
+        const int t = tK[z];
+        unsigned bits = 0;
+        int label = 255;
+        for (int i = n_comp - 1; i >= 0; --i) {
+            const double v = Vaux[(size_t)i * NK + z];
+            if (t == i || __builtin_fabs(v - V) <= delta) bits |= 1u << i;
+            if (v == V) label = i;
+        }
+        memberK[z] = (uint8_t)bits;
+        labelK[z] = (uint8_t)label;
+    }
+}
+
+// Per fine index along one axis: the coarse cells whose closure holds it.
+__device__ __forceinline__ void cells_of(int j, int s, int nK, int &lo, int &hi) {
+    hi = j / s;
+    hi = hi < nK - 2 ? hi : nK - 2;
+    if (j % s == 0) {
+        lo = j / s - 1;
+        lo = lo > 0 ? lo : 0;
+    } else {
+        lo = hi;
+    }
+}
+
+__global__ void k_project(const uint8_t *mK, const uint8_t *lK, int k0, int k1, int k2,
+                          int n0, int n1, int n2, int dim, int s, uint8_t *member,
+                          uint8_t *label) {
+    const size_t N = (size_t)n0 * n1 * n2;
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
+         j += (size_t)gridDim.x * blockDim.x) {
+        const int a = (int)(j % n0);
+        const int b = (int)((j / n0) % n1);
+        const int c = (int)(j / ((size_t)n0 * n1));
+        int lo[3], hi[3];
+        cells_of(a, s, k0, lo[0], hi[0]);
+        cells_of(b, s, k1, lo[1], hi[1]);
+        if (dim == 3) cells_of(c, s, k2, lo[2], hi[2]);
+        else { lo[2] = hi[2] = 0; }
+        unsigned full = 0, anyb = 0;
+        const int ncell = 1 << dim;
+        for (int ch = 0; ch < ncell; ++ch) {
+            const int ca = (ch & 1) ? hi[0] : lo[0];
+            const int cb = (ch & 2) ? hi[1] : lo[1];
+            const int cc = (ch & 4) ? hi[2] : lo[2];
+            unsigned andb = 0xFFu;
+            for (int q = 0; q < (1 << dim); ++q) {
+                const int xa = ca + (q & 1), xb = cb + ((q >> 1) & 1), xc = cc + ((q >> 2) & 1);
+                const unsigned v = mK[((size_t)xc * k1 + xb) * k0 + xa];
+                andb &= v;
+                anyb |= v;
+            }
+            full |= andb;
+        }
+        member[j] = (uint8_t)(full ? full : anyb);
+        int na = (a + s / 2) / s, nb = (b + s / 2) / s, nc = (c + s / 2) / s;
+        na = na < k0 - 1 ? na : k0 - 1;
+        nb = nb < k1 - 1 ? nb : k1 - 1;
+        nc = nc < k2 - 1 ? nc : k2 - 1;
+        if (dim < 3) nc = 0;
+        label[j] = lK[((size_t)nc * k1 + nb) * k0 + na];
+    }
+}
+
+template <typename T>
+__global__ void k_assemble(const SdDesc<T> *sds, const SdState *st, int n_comp,
+                           const uint8_t *member, size_t N, T G, T *V, uint8_t *owner) {
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
+         j += (size_t)gridDim.x * blockDim.x) {
+        const unsigned bits = member[j];
+        T best = (T)INFINITY;
+        int arg = 255;
+        for (int i = 0; i < n_comp; ++i) {
+            if (!((bits >> i) & 1)) continue;
+            const T v = sds[i].V[st[i].final_buf][j];
+            if (v < best) {
+                best = v;
+                arg = i;
+            }
+        }
+        V[j] = arg == 255 ? G : best;
+        if (owner) owner[j] = (uint8_t)arg;
+    }
+}
+
+template <typename T>
+__global__ void k_copy_final(const SdDesc<T> *sds, const SdState *st, int i, T *dst, size_t N) {
+    const T *src = sds[i].V[st[i].final_buf];
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
+         j += (size_t)gridDim.x * blockDim.x)
+        dst[j] = src[j];
+}
+
+__global__ void k_member_counts(const uint8_t *member, size_t N, unsigned long long *counts) {
+    __shared__ unsigned c[8];
+    if (threadIdx.x < 8) c[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned loc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
+         j += (size_t)gridDim.x * blockDim.x) {
+        const unsigned b = member[j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) loc[i] += (b >> i) & 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (loc[i]) atomicAdd(&c[i], loc[i]);
+    __syncthreads();
+    if (threadIdx.x < 8 && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)c[threadIdx.x]);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fill(T *dst, T v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kOpThreads), 0, s, dst, v, n);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<float>(float *, float, size_t, hipStream_t);
+template hipError_t launch_fill<double>(double *, double, size_t, hipStream_t);
+
+template <typename Tin, typename Tout>
+hipError_t launch_scale_field(const Tin *src, Tout *dst, size_t n, double scale, hipStream_t s) {
+    hipLaunchKernelGGL((k_scale_field<Tin, Tout>), dim3(grid_for(n)), dim3(kOpThreads), 0, s,
+                       src, dst, n, scale);
+    return hipGetLastError();
+}
+template hipError_t launch_scale_field<float, float>(const float *, float *, size_t, double, hipStream_t);
+template hipError_t launch_scale_field<float, double>(const float *, double *, size_t, double, hipStream_t);
+template hipError_t launch_scale_field<double, double>(const double *, double *, size_t, double, hipStream_t);
+template hipError_t launch_scale_field<double, float>(const double *, float *, size_t, double, hipStream_t);
+
+template <typename T>
+hipError_t launch_absmax(const T *src, size_t n, unsigned long long *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_absmax<T>, dim3(grid_for(n) < 2048 ? grid_for(n) : 2048),
+                       dim3(kOpThreads), 0, s, src, n, out);
+    return hipGetLastError();
+}
+template hipError_t launch_absmax<float>(const float *, size_t, unsigned long long *, hipStream_t);
+template hipError_t launch_absmax<double>(const double *, size_t, unsigned long long *, hipStream_t);
+
+hipError_t launch_target_scan(const int8_t *target, size_t n, int n_comp, int *count,
+                              int *first_node, hipStream_t s) {
+    hipLaunchKernelGGL(k_target_scan, dim3(grid_for(n) < 2048 ? grid_for(n) : 2048),
+                       dim3(kOpThreads), 0, s, target, n, n_comp, count, first_node);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_values(T *V, const int8_t *target, const T *g, T G, int comp, size_t n,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_init_values<T>, dim3(grid_for(n)), dim3(kOpThreads), 0, s, V, target, g,
+                       G, comp, n);
+    return hipGetLastError();
+}
+template hipError_t launch_init_values<float>(float *, const int8_t *, const float *, float, int, size_t, hipStream_t);
+template hipError_t launch_init_values<double>(double *, const int8_t *, const double *, double, int, size_t, hipStream_t);
+
+template <typename T>
+hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, int n_sd,
+                              int total_tiles, const int *tile_prefix_dev, WorkItem *items,
+                              ExecCounters *cnt, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_items<T>, dim3(total_tiles), dim3(kOpThreads), 0, s, sds_dev,
+                       n_sd, total_tiles, tile_prefix_dev, cfg.tile[0], cfg.tile[1],
+                       cfg.tile[2], items, cnt);
+    return hipGetLastError();
+}
+template hipError_t launch_build_items<float>(const LaunchCfg &, const SdDesc<float> *, int, int, const int *, WorkItem *, ExecCounters *, hipStream_t);
+template hipError_t launch_build_items<double>(const LaunchCfg &, const SdDesc<double> *, int, int, const int *, WorkItem *, ExecCounters *, hipStream_t);
+
+template <typename T>
+hipError_t launch_gather_coarse(const T *src, T *dst, const int *n, const int *nK, int dim,
+                                int stride, int comps, hipStream_t s) {
+    const size_t NK = (size_t)nK[0] * nK[1] * (dim == 3 ? nK[2] : 1);
+    hipLaunchKernelGGL(k_gather_coarse<T>, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, src, dst,
+                       n[0], n[1], nK[0], nK[1], dim == 3 ? nK[2] : 1, stride, comps);
+    return hipGetLastError();
+}
+template hipError_t launch_gather_coarse<float>(const float *, float *, const int *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_gather_coarse<double>(const double *, double *, const int *, const int *, int, int, int, hipStream_t);
+
+hipError_t launch_gather_coarse_i8(const int8_t *src, int8_t *dst, const int *n, const int *nK,
+                                   int dim, int stride, hipStream_t s) {
+    const size_t NK = (size_t)nK[0] * nK[1] * (dim == 3 ? nK[2] : 1);
+    hipLaunchKernelGGL(k_gather_coarse<int8_t>, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, src,
+                       dst, n[0], n[1], nK[0], nK[1], dim == 3 ? nK[2] : 1, stride, 1);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,
+                                const int *firstK, const int *n, const int *nK, int dim,
+                                int stride, int n_comp, hipStream_t s) {
+    hipLaunchKernelGGL(k_place_missing<T>, dim3(1), dim3(64), 0, s, tK, gK, g, first_fine, firstK,
+                       n[0], n[1], nK[0], nK[1], dim == 3 ? nK[2] : 1, dim, stride, n_comp);
+    return hipGetLastError();
+}
+template hipError_t launch_place_missing<float>(int8_t *, float *, const float *, const int *, const int *, const int *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_place_missing<double>(int8_t *, double *, const double *, const int *, const int *, const int *, const int *, int, int, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
+                              const int8_t *target, size_t n, int n_comp, FieldStats *fs,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_field_stats<T>, dim3(grid_for(n) < 2048 ? grid_for(n) : 2048),
+                       dim3(kOpThreads), 0, s, speed, cost, drift, dim, target, n, n_comp, fs);
+    return hipGetLastError();
+}
+template hipError_t launch_field_stats<float>(const float *, const float *, const float *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
+template hipError_t launch_field_stats<double>(const double *, const double *, const double *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
+
+hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
+                             double delta, uint8_t *memberK, uint8_t *labelK, hipStream_t s) {
+    hipLaunchKernelGGL(k_ra_combine, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, Vaux, n_comp,
+                       NK, tK, delta, memberK, labelK);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const uint8_t *memberK, const uint8_t *labelK, const int *nK,
+                          const int *n, int dim, int stride, uint8_t *member, uint8_t *label,
+                          hipStream_t s) {
+    const size_t N = (size_t)n[0] * n[1] * (dim == 3 ? n[2] : 1);
+    hipLaunchKernelGGL(k_project, dim3(grid_for(N)), dim3(kOpThreads), 0, s, memberK, labelK,
+                       nK[0], nK[1], dim == 3 ? nK[2] : 1, n[0], n[1], dim == 3 ? n[2] : 1, dim,
+                       stride, member, label);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_assemble(const SdDesc<T> *sds_dev, const SdState *st, int n_comp,
+                           const uint8_t *member, size_t N, T G, T *V, uint8_t *owner,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble<T>, dim3(grid_for(N)), dim3(kOpThreads), 0, s, sds_dev, st,
+                       n_comp, member, N, G, V, owner);
+    return hipGetLastError();
+}
+template hipError_t launch_assemble<float>(const SdDesc<float> *, const SdState *, int, const uint8_t *, size_t, float, float *, uint8_t *, hipStream_t);
+template hipError_t launch_assemble<double>(const SdDesc<double> *, const SdState *, int, const uint8_t *, size_t, double, double *, uint8_t *, hipStream_t);
+
+template <typename T>
+hipError_t launch_copy_final(const SdDesc<T> *sds_dev, const SdState *st, int i, T *dst,
+                             size_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_final<T>, dim3(grid_for(N)), dim3(kOpThreads), 0, s, sds_dev, st, i,
+                       dst, N);
+    return hipGetLastError();
+}
+template hipError_t launch_copy_final<float>(const SdDesc<float> *, const SdState *, int, float *, size_t, hipStream_t);
+template hipError_t launch_copy_final<double>(const SdDesc<double> *, const SdState *, int, double *, size_t, hipStream_t);
+
+hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long long *counts8,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_member_counts, dim3(grid_for(N) < 1024 ? grid_for(N) : 1024),
+                       dim3(kOpThreads), 0, s, member, N, counts8);
+    return hipGetLastError();
+}
+
+}  // namespace slhjb

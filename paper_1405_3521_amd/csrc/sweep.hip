@@ -1,0 +1,560 @@
+// Semi-Lagrangian sweep kernels for gfx950 (CDNA4).
+//
+// One sweep applies the SL operator (paper Sec. 3, (SL)/(Tdef), control case)
+//     V_new(j) = min_k  fma(beta, I[V](foot_jk), w l_j)
+// to every free member node of every active (sub-domain, tile) work item.
+//
+// Mapping to the hardware
+//   * one work-group (4 wave64) per work item; the tile plus an H-cell halo
+//     (all the corners a foot can reach) is staged in LDS with coalesced row
+//     loads, ghost and non-member nodes already replaced by the ghost value, so
+//     the inner loop has no branches;
+//   * lanes of a wave own consecutive x nodes, so the four (eight) corner reads
+//     of neighbouring lanes hit neighbouring LDS banks;
+//   * the control loop is uniform across the wave: the displacement table is
+//     read through the scalar cache and every lane carries NPT nodes (ILP);
+//   * no MFMA: this is a gather + min, not a dense contraction;
+//   * FP32 values use tile-local foot coordinates (exact fractional parts, small
+//     magnitudes); the FP64 variant uses global grid-index coordinates and the
+//     fixed operation order of the scheme, so its results are reproducible bit
+//     for bit by any IEEE implementation of the same order.
+//   * the per-sd residual max|V_new - V| is reduced in FP64 (wave shuffles, LDS,
+//     one 64-bit atomicMax per work-group on the bit pattern).
+#include "internal.h"
+
+namespace slhjb {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T fma_(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fma_<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fma_<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T min_(T a, T b) { return a < b ? a : b; }
+template <>
+__device__ __forceinline__ float min_<float>(float a, float b) { return __builtin_fminf(a, b); }
+template <>
+__device__ __forceinline__ double min_<double>(double a, double b) { return __builtin_fmin(a, b); }
+
+// Split a foot coordinate into the integer cell index (tile-local, >= 0) and the
+// fractional part.  FP32: local coordinate u > 0, so truncation is the floor and
+// the fractional part is exact.  FP64: global coordinate (may be < 0 near the
+// box), floor and subtraction exactly as the scheme's reference order.
+template <typename T>
+struct Foot;
+template <>
+struct Foot<float> {
+    static __device__ __forceinline__ void split(float u, int origin, int &i, float &t) {
+        (void)origin;
+        i = (int)u;
+        t = __builtin_amdgcn_fractf(u);
+    }
+};
+template <>
+struct Foot<double> {
+    static __device__ __forceinline__ void split(double u, int origin, int &i, double &t) {
+        double f = __builtin_floor(u);
+        t = u - f;
+        i = (int)f - origin;
+    }
+};
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(v, off, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void block_max_to(double v, unsigned long long *dst) {
+    __shared__ double red[kThreads / 64];
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int i = 1; i < kThreads / 64; ++i) m = red[i] > m ? red[i] : m;
+        if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__device__ __forceinline__ void block_sum_to(unsigned v, unsigned long long *dst) {
+    __shared__ unsigned red[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < kThreads / 64; ++i) s += red[i];
+        if (s) atomicAdd(dst, s);
+    }
+}
+
+// Convergence bookkeeping before sweep `sweep` (one work-group).
+__device__ void bookkeep_block(SdState *st, int n_sd, int sweep, double tol,
+                               ExecCounters *cnt, int final_pass) {
+    __shared__ int active;
+    if (threadIdx.x == 0) active = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_sd; i += blockDim.x) {
+        SdState &s = st[i];
+        if (s.conv_at < 0) {
+            const double r = __longlong_as_double((long long)s.res[(sweep + 2) % 3]);
+            if (sweep > 0 && r <= tol) {
+                s.conv_at = sweep - 1;
+                s.final_buf = sweep & 1;
+                s.done_sweeps = sweep;
+                s.final_res = s.res[(sweep + 2) % 3];
+            } else {
+                if (final_pass) {
+                    s.final_buf = sweep & 1;
+                    s.done_sweeps = sweep;
+                    s.final_res = s.res[(sweep + 2) % 3];
+                }
+                atomicAdd(&active, 1);
+            }
+        }
+        s.res[(sweep + 1) % 3] = 0ull;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) cnt->n_active = active;
+}
+
+// Should work items of this sd be skipped at `sweep`?  Reads only data finished
+// before this launch started.
+__device__ __forceinline__ bool sd_skip(const SdState *s, int sweep, double tol) {
+    if (s->conv_at >= 0) return true;
+    if (sweep > 0) {
+        const double r = __longlong_as_double((long long)s->res[(sweep + 2) % 3]);
+        if (r <= tol) return true;
+    }
+    return false;
+}
+
+// ------------------------------------------------------------------ 2D kernel
+template <typename T, int TX, int TY, int H, bool POLICY>
+__global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
+                                                      SdState *__restrict__ st, int n_sd,
+                                                      const WorkItem *__restrict__ items,
+                                                      ExecCounters *__restrict__ cnt,
+                                                      int sweep, double tol) {
+    constexpr int LW = TX + 2 * H;
+    constexpr int LH = TY + 2 * H;
+    constexpr int RSTEP = kThreads / TX;
+    constexpr int NPT = TY / RSTEP;
+    static_assert(kThreads % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
+    __shared__ T lds[LW * LH];
+
+    if (!POLICY && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
+    if ((int)blockIdx.x >= cnt->n_items) return;
+    const WorkItem it = items[blockIdx.x];
+    SdState *sst = st + it.sd;
+    if (!POLICY && sd_skip(sst, sweep, tol)) return;
+    const SdDesc<T> &d = sds[it.sd];
+    const int n0 = d.n[0], n1 = d.n[1];
+    const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
+    const int src = POLICY ? sst->final_buf : (sweep & 1);
+    const T *__restrict__ Vin = d.V[src];
+    T *__restrict__ Vout = d.V[src ^ 1];
+    const uint8_t *__restrict__ mem = d.member;
+    const int bit = d.bit;
+    const T G = d.G;
+
+    for (int q = threadIdx.x; q < LW * LH; q += kThreads) {
+        const int ly = q / LW;
+        const int lx = q - ly * LW;
+        const int gx = x0 - H + lx, gy = y0 - H + ly;
+        T v = G;
+        if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1) {
+            const size_t j = (size_t)gy * n0 + gx;
+            if (!mem || ((mem[j] >> bit) & 1)) v = Vin[j];
+        }
+        lds[q] = v;
+    }
+    __syncthreads();
+
+    const int tx = threadIdx.x % TX;
+    const int ty0 = threadIdx.x / TX;
+    const int gx = x0 + tx;
+    T c[NPT], ux0[NPT], uy0[NPT], wl[NPT], best[NPT];
+    int arg[NPT];
+    bool act[NPT];
+    int any = 0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int ty = ty0 + r * RSTEP;
+        const int gy = y0 + ty;
+        act[r] = false;
+        c[r] = T(0);                        // inactive lanes: foot = own node
+        wl[r] = d.wl_const;
+        if (gx < n0 && gy < n1) {
+            const size_t j = (size_t)gy * n0 + gx;
+            const bool inset = !mem || ((mem[j] >> bit) & 1);
+            act[r] = inset && d.target[j] < 0;
+            if (act[r]) {
+                c[r] = d.speed ? d.speed[j] : T(1);
+                if (d.wl) wl[r] = d.wl[j];
+            }
+        }
+        any |= act[r];
+        if (sizeof(T) == 4) {
+            ux0[r] = (T)(tx + H);
+            uy0[r] = (T)(ty + H);
+        } else {
+            ux0[r] = (T)gx;
+            uy0[r] = (T)gy;
+        }
+        best[r] = (T)INFINITY;
+        arg[r] = 0;
+    }
+    const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
+    const T beta = d.beta;
+    const T *__restrict__ ctrl = d.ctrl;
+    const int m = d.m;
+    if (__any(any)) {
+        for (int k = 0; k < m; ++k) {
+            const T ex = ctrl[2 * k], ey = ctrl[2 * k + 1];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                T ux, uy;
+                if (sizeof(T) == 4) {
+                    ux = fma_(c[r], ex, ux0[r]);
+                    uy = fma_(c[r], ey, uy0[r]);
+                } else {
+                    ux = ux0[r] + ex * c[r];
+                    uy = uy0[r] + ey * c[r];
+                }
+                int ix, iy;
+                T fx, fy;
+                Foot<T>::split(ux, ox, ix, fx);
+                Foot<T>::split(uy, oy, iy, fy);
+                const int base = iy * LW + ix;
+                const T v00 = lds[base], v10 = lds[base + 1];
+                const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
+                const T ax = T(1) - fx, ay = T(1) - fy;
+                const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
+                T acc = w00 * v00;
+                acc = fma_(w10, v10, acc);
+                acc = fma_(w01, v01, acc);
+                acc = fma_(w11, v11, acc);
+                const T cand = fma_(beta, acc, wl[r]);
+                if (POLICY) {
+                    if (cand < best[r]) {
+                        best[r] = cand;
+                        arg[r] = k;
+                    }
+                } else {
+                    best[r] = min_(best[r], cand);
+                }
+            }
+        }
+    }
+    double rmax = 0.0;
+    unsigned nact = 0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        if (!act[r]) continue;
+        const int ty = ty0 + r * RSTEP;
+        const size_t j = (size_t)(y0 + ty) * n0 + gx;
+        Vout[j] = best[r];
+        if (POLICY) d.policy[j] = (uint8_t)arg[r];
+        const double dv = __builtin_fabs((double)best[r] - (double)lds[(ty + H) * LW + tx + H]);
+        rmax = dv > rmax ? dv : rmax;
+        ++nact;
+    }
+    if (!POLICY) {
+        block_max_to(rmax, &sst->res[sweep % 3]);
+        block_sum_to(nact * (unsigned)m, &cnt->nc_updates);
+    }
+}
+
+// ------------------------------------------------------------------ 3D kernel
+template <typename T, int TX, int TY, int TZ, int H, bool POLICY>
+__global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restrict__ sds,
+                                                      SdState *__restrict__ st, int n_sd,
+                                                      const WorkItem *__restrict__ items,
+                                                      ExecCounters *__restrict__ cnt,
+                                                      int sweep, double tol) {
+    constexpr int LW = TX + 2 * H;
+    constexpr int LH = TY + 2 * H;
+    constexpr int LD = TZ + 2 * H;
+    constexpr int PL = LW * LH;
+    constexpr int TXY = TX * TY;
+    static_assert(kThreads % TXY == 0 || TXY % kThreads == 0, "tile/thread mismatch");
+    constexpr int ZSTEP = kThreads / TXY;              // z planes covered per pass
+    constexpr int NPT = TZ / ZSTEP;
+    static_assert(ZSTEP >= 1 && TZ % ZSTEP == 0, "tile/thread mismatch");
+    extern __shared__ unsigned char lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+
+    if (!POLICY && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
+    if ((int)blockIdx.x >= cnt->n_items) return;
+    const WorkItem it = items[blockIdx.x];
+    SdState *sst = st + it.sd;
+    if (!POLICY && sd_skip(sst, sweep, tol)) return;
+    const SdDesc<T> &d = sds[it.sd];
+    const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+    const int x0 = it.t[0] * TX, y0 = it.t[1] * TY, z0 = it.t[2] * TZ;
+    const int src = POLICY ? sst->final_buf : (sweep & 1);
+    const T *__restrict__ Vin = d.V[src];
+    T *__restrict__ Vout = d.V[src ^ 1];
+    const uint8_t *__restrict__ mem = d.member;
+    const int bit = d.bit;
+    const T G = d.G;
+
+    for (int q = threadIdx.x; q < PL * LD; q += kThreads) {
+        const int lz = q / PL;
+        const int rem = q - lz * PL;
+        const int ly = rem / LW;
+        const int lx = rem - ly * LW;
+        const int gx = x0 - H + lx, gy = y0 - H + ly, gz = z0 - H + lz;
+        T v = G;
+        if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+            (unsigned)gz < (unsigned)n2) {
+            const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+            if (!mem || ((mem[j] >> bit) & 1)) v = Vin[j];
+        }
+        lds[q] = v;
+    }
+    __syncthreads();
+
+    const int tx = threadIdx.x % TX;
+    const int ty = (threadIdx.x / TX) % TY;
+    const int tz0 = threadIdx.x / TXY;
+    const int gx = x0 + tx, gy = y0 + ty;
+    T c[NPT], ux0[NPT], uy0[NPT], uz0[NPT], wl[NPT], best[NPT];
+    int arg[NPT];
+    bool act[NPT];
+    int any = 0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int tz = tz0 + r * ZSTEP;
+        const int gz = z0 + tz;
+        act[r] = false;
+        c[r] = T(0);                        // inactive lanes: foot = own node
+        wl[r] = d.wl_const;
+        if (gx < n0 && gy < n1 && gz < n2) {
+            const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+            const bool inset = !mem || ((mem[j] >> bit) & 1);
+            act[r] = inset && d.target[j] < 0;
+            if (act[r]) {
+                c[r] = d.speed ? d.speed[j] : T(1);
+                if (d.wl) wl[r] = d.wl[j];
+            }
+        }
+        any |= act[r];
+        if (sizeof(T) == 4) {
+            ux0[r] = (T)(tx + H);
+            uy0[r] = (T)(ty + H);
+            uz0[r] = (T)(tz + H);
+        } else {
+            ux0[r] = (T)gx;
+            uy0[r] = (T)gy;
+            uz0[r] = (T)gz;
+        }
+        best[r] = (T)INFINITY;
+        arg[r] = 0;
+    }
+    const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
+    const T beta = d.beta;
+    const T *__restrict__ ctrl = d.ctrl;
+    const int m = d.m;
+    if (__any(any)) {
+        for (int k = 0; k < m; ++k) {
+            const T ex = ctrl[3 * k], ey = ctrl[3 * k + 1], ez = ctrl[3 * k + 2];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                T ux, uy, uz;
+                if (sizeof(T) == 4) {
+                    ux = fma_(c[r], ex, ux0[r]);
+                    uy = fma_(c[r], ey, uy0[r]);
+                    uz = fma_(c[r], ez, uz0[r]);
+                } else {
+                    ux = ux0[r] + ex * c[r];
+                    uy = uy0[r] + ey * c[r];
+                    uz = uz0[r] + ez * c[r];
+                }
+                int ix, iy, iz;
+                T fx, fy, fz;
+                Foot<T>::split(ux, ox, ix, fx);
+                Foot<T>::split(uy, oy, iy, fy);
+                Foot<T>::split(uz, oz, iz, fz);
+                const int base = (iz * LH + iy) * LW + ix;
+                const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
+                const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
+                T acc = (w00 * az) * lds[base];
+                acc = fma_(w10 * az, lds[base + 1], acc);
+                acc = fma_(w01 * az, lds[base + LW], acc);
+                acc = fma_(w11 * az, lds[base + LW + 1], acc);
+                acc = fma_(w00 * fz, lds[base + PL], acc);
+                acc = fma_(w10 * fz, lds[base + PL + 1], acc);
+                acc = fma_(w01 * fz, lds[base + PL + LW], acc);
+                acc = fma_(w11 * fz, lds[base + PL + LW + 1], acc);
+                const T cand = fma_(beta, acc, wl[r]);
+                if (POLICY) {
+                    if (cand < best[r]) {
+                        best[r] = cand;
+                        arg[r] = k;
+                    }
+                } else {
+                    best[r] = min_(best[r], cand);
+                }
+            }
+        }
+    }
+    double rmax = 0.0;
+    unsigned nact = 0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        if (!act[r]) continue;
+        const int tz = tz0 + r * ZSTEP;
+        const size_t j = ((size_t)(z0 + tz) * n1 + gy) * n0 + gx;
+        Vout[j] = best[r];
+        if (POLICY) d.policy[j] = (uint8_t)arg[r];
+        const double dv = __builtin_fabs(
+            (double)best[r] - (double)lds[((tz + H) * LH + ty + H) * LW + tx + H]);
+        rmax = dv > rmax ? dv : rmax;
+        ++nact;
+    }
+    if (!POLICY) {
+        block_max_to(rmax, &sst->res[sweep % 3]);
+        block_sum_to(nact * (unsigned)m, &cnt->nc_updates);
+    }
+}
+
+__global__ void k_flip(SdState *st, int n_sd) {
+    for (int i = threadIdx.x; i < n_sd; i += blockDim.x) st[i].final_buf ^= 1;
+}
+
+__global__ void k_bookkeep(SdState *st, int n_sd, int sweep, double tol, ExecCounters *cnt,
+                           int final_pass) {
+    bookkeep_block(st, n_sd, sweep, tol, cnt, final_pass);
+}
+
+// ------------------------------------------------------------ dispatch tables
+using SweepFn = void (*)(const void *, SdState *, int, const WorkItem *, ExecCounters *, int,
+                         double);
+
+struct Variant {
+    int dim, dtype, tile[3];
+    const void *fn[kMaxHalo + 1][2];    // [H][policy]
+    size_t lds_bytes[kMaxHalo + 1];     // dynamic LDS (3D only)
+};
+
+template <typename T, int TX, int TY, int H>
+void fill2d(Variant &v) {
+    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false>;
+    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true>;
+    v.lds_bytes[H] = 0;
+}
+template <typename T, int TX, int TY, int TZ, int H>
+void fill3d(Variant &v) {
+    v.fn[H][0] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, false>;
+    v.fn[H][1] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, true>;
+    v.lds_bytes[H] = sizeof(T) * (size_t)(TX + 2 * H) * (TY + 2 * H) * (TZ + 2 * H);
+}
+
+template <typename T, int TX, int TY>
+Variant make2d() {
+    Variant v{};
+    v.dim = 2;
+    v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
+    v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = 1;
+    fill2d<T, TX, TY, 1>(v); fill2d<T, TX, TY, 2>(v); fill2d<T, TX, TY, 3>(v);
+    fill2d<T, TX, TY, 4>(v); fill2d<T, TX, TY, 5>(v); fill2d<T, TX, TY, 6>(v);
+    fill2d<T, TX, TY, 7>(v); fill2d<T, TX, TY, 8>(v);
+    return v;
+}
+template <typename T, int TX, int TY, int TZ>
+Variant make3d() {
+    Variant v{};
+    v.dim = 3;
+    v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
+    v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = TZ;
+    fill3d<T, TX, TY, TZ, 1>(v); fill3d<T, TX, TY, TZ, 2>(v); fill3d<T, TX, TY, TZ, 3>(v);
+    fill3d<T, TX, TY, TZ, 4>(v); fill3d<T, TX, TY, TZ, 5>(v); fill3d<T, TX, TY, TZ, 6>(v);
+    fill3d<T, TX, TY, TZ, 7>(v); fill3d<T, TX, TY, TZ, 8>(v);
+    return v;
+}
+
+const Variant *variants(int *count) {
+    static const Variant table[] = {
+        make2d<float, 64, 16>(),   // 0: default FP32 2D
+        make2d<float, 64, 8>(),    // 1
+        make2d<float, 64, 4>(),    // 2
+        make2d<float, 32, 16>(),   // 3
+        make2d<double, 64, 8>(),   // 4: FP64 2D
+        make3d<float, 32, 8, 8>(), // 5: default FP32 3D
+        make3d<float, 32, 8, 4>(), // 6
+        make3d<float, 16, 16, 4>(),// 7
+        make3d<double, 16, 8, 8>(),// 8: FP64 3D
+    };
+    *count = (int)(sizeof(table) / sizeof(table[0]));
+    return table;
+}
+
+}  // namespace
+
+int sweep_variants(int dim, LaunchCfg *out, int cap) {
+    int nv = 0, k = 0;
+    const Variant *v = variants(&nv);
+    for (int i = 0; i < nv; ++i) {
+        if (v[i].dim != dim) continue;
+        if (k < cap) {
+            out[k].dim = v[i].dim;
+            out[k].dtype = v[i].dtype;
+            out[k].tile[0] = v[i].tile[0];
+            out[k].tile[1] = v[i].tile[1];
+            out[k].tile[2] = v[i].tile[2];
+            out[k].halo = 0;
+            out[k].variant = i;
+        }
+        ++k;
+    }
+    return k;
+}
+
+hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
+                        const WorkItem *items, const ExecCounters *cnt, int max_items,
+                        int sweep, double tol, int want_policy, hipStream_t s) {
+    int nv = 0;
+    const Variant *vt = variants(&nv);
+    if (cfg.variant < 0 || cfg.variant >= nv || cfg.halo < 1 || cfg.halo > kMaxHalo)
+        return hipErrorInvalidValue;
+    const Variant &v = vt[cfg.variant];
+    const void *fn = v.fn[cfg.halo][want_policy ? 1 : 0];
+    const size_t lds = v.lds_bytes[cfg.halo];
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int grid = max_items > 0 ? max_items : 1;
+    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items,
+                    (void *)&cnt, (void *)&sweep, (void *)&tol};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s);
+}
+
+hipError_t launch_flip(SdState *st, int n_sd, hipStream_t s) {
+    hipLaunchKernelGGL(k_flip, dim3(1), dim3(kThreads), 0, s, st, n_sd);
+    return hipGetLastError();
+}
+
+hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep, double tol, ExecCounters *cnt,
+                           int final_pass, hipStream_t s) {
+    hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(kThreads), 0, s, st, n_sd, sweep, tol, cnt,
+                       final_pass);
+    return hipGetLastError();
+}
+
+}  // namespace slhjb
