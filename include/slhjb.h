@@ -150,6 +150,28 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
                  const sl_solve_opts *o, void *ws, size_t ws_bytes, void *V, uint8_t *owner,
                  uint8_t *policy, void *V_sets, sl_stats *stats, void *stream);
 
+/* Workspace bytes needed by sl_adjoint (n_sets = n_comp with sets, 1 without). */
+size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
+
+/* Gradient of a loss on V with respect to the running cost l, with the argmin
+ * controls frozen (the fixed point is then linear in l: V = beta P V + w l + c on
+ * free nodes).  Solves lambda = g + beta P^T lambda by Jacobi iteration with a
+ * scatter of beta * (Q1 weight) * lambda to the free corners of each node's foot
+ * (float atomics, so the summation order varies run to run), until the test
+ * below holds or max_iters; then dLdl = w * sum over sets of
+ * lambda.  Because the summation order varies between iterations, the state
+ * settles only to within a few ulps, so the stopping test is
+ * max|lambda_new - lambda| <= tol + 16 eps max|lambda_new| (eps of p->dtype);
+ * tol = 0 therefore means "until the change is at rounding level".
+ * Inputs: member (DEVICE, N uint8 set bitmask, or NULL: one set = whole grid, as
+ * after sl_solve), owner (DEVICE, N uint8: dL/dV(j) goes to set owner[j] only;
+ * NULL: to every set), policy (DEVICE, n_sets*N uint8 controls from the forward
+ * call with want_policy), dLdV (DEVICE, N in p->dtype).
+ * Output: dLdl (DEVICE, N in p->dtype; 0 on target nodes). */
+int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
+               const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,
+               void *ws, size_t ws_bytes, sl_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

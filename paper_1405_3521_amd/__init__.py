@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "DeviceProblem", "RaOpts", "SolveOpts", "lib", "lib_path", "to_device", "solve",
-    "reconstruct", "solve_isa", "isa", "SlError",
+    "reconstruct", "solve_isa", "isa", "adjoint", "SlError", "HJBSolve",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -99,6 +99,12 @@ def lib():
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, P(SlStats), C.c_void_p]
         L.sl_solve_isa.restype = C.c_int
+        L.sl_adjoint_workspace_size.argtypes = [P(SlProblem), C.c_int]
+        L.sl_adjoint_workspace_size.restype = C.c_size_t
+        L.sl_adjoint.argtypes = [P(SlProblem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_double, C.c_long, C.c_void_p, C.c_size_t,
+                                 P(SlStats), C.c_void_p]
+        L.sl_adjoint.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -328,3 +334,44 @@ def isa(p: DeviceProblem, ra: RaOpts, opts: SolveOpts = SolveOpts(), want_sets: 
     st["ms_ra"] = st_ra["ms_total"]
     st["ra_sweeps_max"] = st_ra["sweeps_max"]
     return V, owner, member, label, pol, Vs, st
+
+
+def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float = None,
+            max_iters: int = 100_000, workspace=None):
+    """dL/dl of a loss with gradient dL/dV, the forward's controls frozen.
+
+    ``tol``: stop when the adjoint state changes by at most tol (plus the
+    library's rounding allowance, 16 eps max|lambda|) in one iteration; default 0.
+
+    ``policy``: from the forward call (``solve``: N entries; ``solve_isa``:
+    n_comp*N).  With ``member`` (sets) ``owner`` routes dL/dV to the owning set.
+    Returns (dLdl, stats)."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    n_sets = p.n_comp if member is not None else 1
+    _check_tensor(policy, torch.uint8, n_sets * p.N, "policy")
+    _check_tensor(dLdV, p.dtype, p.N, "dLdV")
+    if member is not None:
+        _check_tensor(member, torch.uint8, p.N, "member")
+        _check_tensor(owner, torch.uint8, p.N, "owner")
+    if tol is None:
+        tol = 0.0
+    ws_bytes = L.sl_adjoint_workspace_size(C.byref(cp), n_sets)
+    if ws_bytes == 0:
+        raise ValueError("invalid problem")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    out = torch.empty(p.N, dtype=p.dtype, device=dev)
+    st = SlStats()
+    rc = L.sl_adjoint(C.byref(cp), _ptr(member), _ptr(owner), _ptr(policy), _ptr(dLdV),
+                      _ptr(out), float(tol), int(max_iters), _ptr(ws), ws.numel(), C.byref(st),
+                      _stream())
+    if rc < 0:
+        raise SlError("sl_adjoint", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    return out, d
+
+
+from .autograd import HJBSolve  # noqa: E402

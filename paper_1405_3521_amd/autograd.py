@@ -1,0 +1,45 @@
+"""torch.autograd wrapper: the SL fixed point V as a differentiable function of
+the running cost l (the argmin controls and the reconstructed sets frozen).
+
+    V = HJBSolve.apply(cost, problem, member, ra, opts, adj_rtol)
+
+Forward: ``solve`` (member None) or ``solve_isa`` on the given sets, with the
+policy exported.  Backward: ``adjoint`` of the policy-frozen scheme with dL/dV
+routed to the owning set; the sets are piecewise constant in l, so they carry no
+gradient.  Autograd then chains through whatever produced ``cost`` (for example
+l = exp(theta)).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+
+class HJBSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cost, problem, member=None, ra=None, opts=None, adj_rtol=1e-7):
+        from . import SolveOpts, solve, solve_isa
+        p = dataclasses.replace(problem, cost=cost.detach().contiguous())
+        o = dataclasses.replace(opts or SolveOpts(), want_policy=True)
+        if member is None:
+            V, pol, st = solve(p, o)
+            owner = None
+        else:
+            V, owner, pol, _, st = solve_isa(p, ra, member, o)
+        ctx.problem = p
+        ctx.member = member
+        ctx.owner = owner
+        ctx.policy = pol
+        ctx.adj_rtol = adj_rtol
+        ctx.stats = st
+        return V
+
+    @staticmethod
+    def backward(ctx, dV):
+        from . import adjoint
+        g = dV.detach().to(ctx.problem.dtype).contiguous()
+        scale = float(g.abs().max())
+        tol = ctx.adj_rtol * scale
+        dLdl, st = adjoint(ctx.problem, ctx.policy, g, ctx.member, ctx.owner, tol=tol)
+        return dLdl, None, None, None, None, None

@@ -206,6 +206,7 @@ struct Exec {
             x.done_sweeps = 0;
             x.pad = 0;
             x.final_res = 0ull;
+            x.scale[0] = x.scale[1] = x.scale[2] = 0ull;
         }
         HIPCHK(hipMemcpyAsync(sds, host_sds.data(), sizeof(SdDesc<T>) * n_sd,
                               hipMemcpyHostToDevice, s));
@@ -726,6 +727,124 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     return status;
 }
 
+// ------------------------------------------------------------------- adjoint
+template <typename T>
+struct AdjPlan {
+    T *lam = nullptr, *acc = nullptr, *ctrl = nullptr;
+    AdjDesc<T> *ads = nullptr;
+    SdState *st = nullptr;
+    ExecCounters *cnt = nullptr;
+    FieldStats *fs = nullptr;
+};
+
+template <typename T>
+void plan_adjoint(const sl_problem *p, int n_sets, Arena &a, AdjPlan<T> &P) {
+    const size_t N = nodes_of(p);
+    P.lam = a.take<T>((size_t)n_sets * N);
+    P.acc = a.take<T>((size_t)n_sets * 2 * N);
+    P.ctrl = a.take<T>((size_t)p->m * p->dim);
+    P.ads = a.take<AdjDesc<T>>(n_sets);
+    P.st = a.take<SdState>(n_sets);
+    P.cnt = a.take<ExecCounters>(1);
+    P.fs = a.take<FieldStats>(1);
+}
+
+template <typename T>
+int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
+                 const uint8_t *policy, const T *dLdV, T *dLdl, double tol, long max_iters,
+                 void *ws, size_t ws_bytes, sl_stats *stats, hipStream_t s) {
+    Timer tm;
+    tm.mark(0, s);
+    const size_t N = nodes_of(p);
+    const int n_sets = member ? p->n_comp : 1;
+    Arena a{(char *)ws, ws_bytes};
+    AdjPlan<T> P;
+    plan_adjoint<T>(p, n_sets, a, P);
+    if (!a.fits()) return SL_ERR_WORKSPACE;
+    FieldStats fs{};
+    int rc = gather_field_stats<T>(p, p->target, (const T *)p->speed, (const T *)p->cost, N,
+                                   p->n_comp, P.fs, &fs, s);
+    if (rc) return rc;
+    if ((rc = check_fields(fs))) return rc;
+    double beta, w, emax;
+    scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
+    std::vector<double> e;
+    control_table(p, p->n, p->h, e, &emax);
+    std::vector<T> et(e.size());
+    for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
+    HIPCHK(hipMemcpyAsync(P.ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(P.lam, 0, sizeof(T) * (size_t)n_sets * N, s));
+    HIPCHK(hipMemsetAsync(P.acc, 0, sizeof(T) * (size_t)n_sets * 2 * N, s));
+    std::vector<AdjDesc<T>> hd(n_sets);
+    for (int i = 0; i < n_sets; ++i) {
+        AdjDesc<T> &d = hd[i];
+        d.lam = P.lam + (size_t)i * N;
+        d.acc[0] = P.acc + (size_t)i * 2 * N;
+        d.acc[1] = d.acc[0] + N;
+        d.g = dLdV;
+        d.owner = member ? owner : nullptr;
+        d.policy = policy + (size_t)i * N;
+        d.speed = (const T *)p->speed;
+        d.target = p->target;
+        d.member = member;
+        d.ctrl = P.ctrl;
+        d.beta = (T)beta;
+        for (int k = 0; k < 3; ++k) d.n[k] = k < p->dim ? p->n[k] : 1;
+        d.m = p->m;
+        d.bit = i;
+        d.set = i;
+    }
+    HIPCHK(hipMemcpyAsync(P.ads, hd.data(), sizeof(AdjDesc<T>) * n_sets, hipMemcpyHostToDevice, s));
+    std::vector<SdState> hs(n_sets);
+    for (auto &x : hs) {
+        x = SdState{};
+        x.conv_at = -1;
+    }
+    HIPCHK(hipMemcpyAsync(P.st, hs.data(), sizeof(SdState) * n_sets, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(P.cnt, 0, sizeof(ExecCounters), s));
+    // rounding-level stop: atomics reorder the sums, so the state settles to
+    // within a few ulps of its largest entry
+    const double scale_rel = 16.0 * (sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    int bps = (int)((N + kThreads - 1) / kThreads);
+    bps = std::max(1, std::min(bps, 2048));
+    int *active = pinned().active;
+    if (!active) return SL_ERR_HIP;
+    tm.mark(1, s);
+    long it = 0;
+    int status = SL_NOT_CONVERGED;
+    const int chunk = 32;
+    while (it < max_iters) {
+        const long todo = std::min<long>(chunk, max_iters - it);
+        for (long i = 0; i < todo; ++i, ++it)
+            HIPCHK(launch_adjoint_iter<T>(p->dim, P.ads, P.st, n_sets, bps, P.cnt, (int)it, tol,
+                                          scale_rel, s));
+        HIPCHK(launch_bookkeep(P.st, n_sets, (int)it, tol, P.cnt, 0, s, scale_rel));
+        HIPCHK(hipMemcpyAsync(active, &P.cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (*active == 0) {
+            status = SL_OK;
+            break;
+        }
+    }
+    HIPCHK(launch_bookkeep(P.st, n_sets, (int)it, tol, P.cnt, 1, s, scale_rel));
+    HIPCHK(launch_adjoint_combine<T>(P.ads, n_sets, p->target, N, (T)w, dLdl, s));
+    tm.mark(2, s);
+    ExecCounters c{};
+    HIPCHK(hipMemcpyAsync(hs.data(), P.st, sizeof(SdState) * n_sets, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&c, P.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    fill_stats(stats, hs, c.nc_updates, it);
+    if (stats) {
+        stats->ms_ra = 0.0;
+        stats->ms_fine = tm.ms(1, 2);
+        stats->ms_total = tm.ms(0, 2);
+        stats->set_fraction_max = 0.0;
+        stats->ms_sweeps = 0.0;
+        stats->sweep_launches = it;
+    }
+    return status;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -821,6 +940,36 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
                                (float *)V_sets, stats, s);
     return isa_impl<double>(p, ra, member, o, ws, ws_bytes, (double *)V, owner, policy,
                             (double *)V_sets, stats, s);
+}
+
+size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets) {
+    if (validate(p) != SL_OK || n_sets < 1 || n_sets > SL_MAX_COMP) return 0;
+    Arena a{nullptr, 0};
+    if (p->dtype == SL_F32) {
+        AdjPlan<float> P;
+        plan_adjoint<float>(p, n_sets, a, P);
+    } else {
+        AdjPlan<double> P;
+        plan_adjoint<double>(p, n_sets, a, P);
+    }
+    return a.off + 256;
+}
+
+int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
+               const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,
+               void *ws, size_t ws_bytes, sl_stats *stats, void *stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
+    if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
+    const int n_sets = member ? p->n_comp : 1;
+    if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == SL_F32)
+        return adjoint_impl<float>(p, member, owner, policy, (const float *)dLdV, (float *)dLdl,
+                                   tol, max_iters, ws, ws_bytes, stats, s);
+    return adjoint_impl<double>(p, member, owner, policy, (const double *)dLdV, (double *)dLdl,
+                                tol, max_iters, ws, ws_bytes, stats, s);
 }
 
 }  // extern "C"

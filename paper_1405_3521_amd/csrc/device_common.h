@@ -1,0 +1,142 @@
+// Device helpers shared by the sweep and adjoint kernels: explicit fused
+// multiply-add (the library is built with -ffp-contract=off), foot splitting,
+// FP64 block max-reduction to a residual slot, and the per-sub-domain
+// convergence bookkeeping run by one work-group per launch.
+#pragma once
+#include "internal.h"
+
+namespace slhjb {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T fma_(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fma_<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fma_<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T min_(T a, T b) { return a < b ? a : b; }
+template <>
+__device__ __forceinline__ float min_<float>(float a, float b) { return __builtin_fminf(a, b); }
+template <>
+__device__ __forceinline__ double min_<double>(double a, double b) { return __builtin_fmin(a, b); }
+
+// Split a foot coordinate into the integer cell index (tile-local, >= 0) and the
+// fractional part.  FP32: local coordinate u > 0, so truncation is the floor and
+// the fractional part is exact.  FP64: global coordinate (may be < 0 near the
+// box), floor and subtraction exactly as the scheme's reference order.
+template <typename T>
+struct Foot;
+template <>
+struct Foot<float> {
+    static __device__ __forceinline__ void split(float u, int origin, int &i, float &t) {
+        (void)origin;
+        i = (int)u;
+        t = __builtin_amdgcn_fractf(u);
+    }
+};
+template <>
+struct Foot<double> {
+    static __device__ __forceinline__ void split(double u, int origin, int &i, double &t) {
+        double f = __builtin_floor(u);
+        t = u - f;
+        i = (int)f - origin;
+    }
+};
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(v, off, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void block_max_to(double v, unsigned long long *dst) {
+    __shared__ double red[kThreads / 64];
+    __syncthreads();                    // a previous call's reader is done with red[]
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int i = 1; i < kThreads / 64; ++i) m = red[i] > m ? red[i] : m;
+        if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__device__ __forceinline__ void block_sum_to(unsigned v, unsigned long long *dst) {
+    __shared__ unsigned red[kThreads / 64];
+    __syncthreads();                    // a previous call's reader is done with red[]
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < kThreads / 64; ++i) s += red[i];
+        if (s) atomicAdd(dst, s);
+    }
+}
+
+// Effective stopping tolerance of a sub-domain: tol plus, for iterations whose
+// state only settles to rounding level (the atomic adjoint), scale_rel times the
+// largest |state| seen in the same sweep.
+__device__ __forceinline__ double eff_tol(const SdState *s, int slot, double tol,
+                                          double scale_rel) {
+    if (scale_rel <= 0.0) return tol;
+    return tol + scale_rel * __longlong_as_double((long long)s->scale[slot]);
+}
+
+// Convergence bookkeeping before sweep `sweep` (one work-group).
+__device__ void bookkeep_block(SdState *st, int n_sd, int sweep, double tol,
+                               ExecCounters *cnt, int final_pass, double scale_rel = 0.0) {
+    __shared__ int active;
+    if (threadIdx.x == 0) active = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_sd; i += blockDim.x) {
+        SdState &s = st[i];
+        if (s.conv_at < 0) {
+            const int prev = (sweep + 2) % 3;
+            const double r = __longlong_as_double((long long)s.res[prev]);
+            if (sweep > 0 && r <= eff_tol(&s, prev, tol, scale_rel)) {
+                s.conv_at = sweep - 1;
+                s.final_buf = sweep & 1;
+                s.done_sweeps = sweep;
+                s.final_res = s.res[prev];
+            } else {
+                if (final_pass) {
+                    s.final_buf = sweep & 1;
+                    s.done_sweeps = sweep;
+                    s.final_res = s.res[prev];
+                }
+                atomicAdd(&active, 1);
+            }
+        }
+        s.res[(sweep + 1) % 3] = 0ull;
+        s.scale[(sweep + 1) % 3] = 0ull;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) cnt->n_active = active;
+}
+
+// Should work items of this sd be skipped at `sweep`?  Reads only data finished
+// before this launch started.
+__device__ __forceinline__ bool sd_skip(const SdState *s, int sweep, double tol,
+                                        double scale_rel = 0.0) {
+    if (s->conv_at >= 0) return true;
+    if (sweep > 0) {
+        const int prev = (sweep + 2) % 3;
+        const double r = __longlong_as_double((long long)s->res[prev]);
+        if (r <= eff_tol(s, prev, tol, scale_rel)) return true;
+    }
+    return false;
+}
+
+}  // namespace
+}  // namespace slhjb

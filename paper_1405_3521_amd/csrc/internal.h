@@ -50,6 +50,7 @@ struct SdState {
     int done_sweeps;            // sweeps applied to this sd
     int pad;
     unsigned long long final_res;  // residual of the last sweep (set by bookkeeping)
+    unsigned long long scale[3];   // max |state| per sweep slot (adjoint: rounding level)
 };
 
 struct WorkItem {
@@ -76,6 +77,25 @@ struct FieldStats {
     int first_node[SL_MAX_COMP];    // lowest node index per component (INT_MAX: none)
 };
 
+// Per-set description of the adjoint iteration (device memory).
+template <typename T>
+struct AdjDesc {
+    T *lam;                     // adjoint state per node
+    T *acc[2];                  // inflow accumulators (ping-pong)
+    const T *g;                 // dL/dV per node
+    const uint8_t *owner;       // set owning each node's value, or nullptr (all)
+    const uint8_t *policy;      // frozen control index per node (>= m: none)
+    const T *speed;             // speed per node or nullptr (= 1)
+    const int8_t *target;       // target ids (>= 0: fixed, no adjoint)
+    const uint8_t *member;      // set bitmask or nullptr
+    const T *ctrl;              // m*dim control displacements
+    T beta;
+    int n[3];
+    int m;
+    int bit;
+    int set;
+};
+
 struct LaunchCfg {
     int dim;
     int dtype;                  // SL_F32 / SL_F64
@@ -92,7 +112,8 @@ hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int 
 // Bookkeeping before sweep `sweep` (marks sds converged, resets slots, counts
 // active sds); `final_pass` also settles final_buf of unconverged sds.
 hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep, double tol,
-                           ExecCounters *cnt, int final_pass, hipStream_t s);
+                           ExecCounters *cnt, int final_pass, hipStream_t s,
+                           double scale_rel = 0.0);
 // Supported tile shapes per (dim) for the autotuner; returns count.
 int sweep_variants(int dim, LaunchCfg *out, int cap);
 
@@ -158,5 +179,14 @@ hipError_t launch_copy_final(const SdDesc<T> *sds_dev, const SdState *st, int i,
 // member popcounts per bit (for set fractions)
 hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long long *counts8,
                                 hipStream_t s);
+
+// ---- launchers (adjoint.hip) ------------------------------------------------
+template <typename T>
+hipError_t launch_adjoint_iter(int dim, const AdjDesc<T> *ads, SdState *st, int n_sets,
+                               int blocks_per_set, ExecCounters *cnt, int iter, double tol,
+                               double scale_rel, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_t *target,
+                                  size_t N, T w, T *dLdl, hipStream_t s);
 
 }  // namespace slhjb

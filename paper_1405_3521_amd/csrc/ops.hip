@@ -5,6 +5,8 @@
 // (HBM/L2 bound); grid-stride loops with 256-thread work-groups.
 #include "internal.h"
 
+#include <climits>
+
 namespace slhjb {
 
 namespace {
@@ -59,6 +61,9 @@ __global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int
                               const int8_t *target, size_t n, int n_comp, FieldStats *fs) {
     double smax = 0.0, cmax = 0.0, dmax = 0.0;
     int bad_s = 0, bad_c = 0, ntar = 0, bad_t = 0;
+    int first[SL_MAX_COMP];
+#pragma unroll
+    for (int c = 0; c < SL_MAX_COMP; ++c) first[c] = INT_MAX;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         if (speed) {
@@ -78,7 +83,13 @@ __global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int
         const int t = target[i];
         if (t >= 0) {
             ++ntar;
-            if (t < n_comp) atomicMin(&fs->first_node[t], (int)i); else ++bad_t;
+            if (t < n_comp) {
+#pragma unroll
+                for (int c = 0; c < SL_MAX_COMP; ++c)
+                    if (c == t && (int)i < first[c]) first[c] = (int)i;
+            } else {
+                ++bad_t;
+            }
         }
     }
 #pragma unroll
@@ -90,6 +101,11 @@ __global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int
         bad_c += __shfl_xor(bad_c, off, 64);
         ntar += __shfl_xor(ntar, off, 64);
         bad_t += __shfl_xor(bad_t, off, 64);
+#pragma unroll
+        for (int c = 0; c < SL_MAX_COMP; ++c) {
+            const int f = __shfl_xor(first[c], off, 64);
+            first[c] = f < first[c] ? f : first[c];
+        }
     }
     if ((threadIdx.x & 63) == 0) {
         if (smax > 0.0) atomicMax(&fs->speed_max, (unsigned long long)__double_as_longlong(smax));
@@ -99,6 +115,8 @@ __global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int
         if (bad_c) atomicAdd(&fs->bad_cost, bad_c);
         if (ntar) atomicAdd(&fs->n_target, ntar);
         if (bad_t) atomicAdd(&fs->bad_target, bad_t);
+        for (int c = 0; c < n_comp; ++c)
+            if (first[c] != INT_MAX) atomicMin(&fs->first_node[c], first[c]);
     }
 }
 

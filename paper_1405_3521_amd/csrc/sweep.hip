@@ -20,126 +20,11 @@
 //     for bit by any IEEE implementation of the same order.
 //   * the per-sd residual max|V_new - V| is reduced in FP64 (wave shuffles, LDS,
 //     one 64-bit atomicMax per work-group on the bit pattern).
-#include "internal.h"
+#include "device_common.h"
 
 namespace slhjb {
 
 namespace {
-
-template <typename T>
-__device__ __forceinline__ T fma_(T a, T b, T c);
-template <>
-__device__ __forceinline__ float fma_<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <>
-__device__ __forceinline__ double fma_<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <typename T>
-__device__ __forceinline__ T min_(T a, T b) { return a < b ? a : b; }
-template <>
-__device__ __forceinline__ float min_<float>(float a, float b) { return __builtin_fminf(a, b); }
-template <>
-__device__ __forceinline__ double min_<double>(double a, double b) { return __builtin_fmin(a, b); }
-
-// Split a foot coordinate into the integer cell index (tile-local, >= 0) and the
-// fractional part.  FP32: local coordinate u > 0, so truncation is the floor and
-// the fractional part is exact.  FP64: global coordinate (may be < 0 near the
-// box), floor and subtraction exactly as the scheme's reference order.
-template <typename T>
-struct Foot;
-template <>
-struct Foot<float> {
-    static __device__ __forceinline__ void split(float u, int origin, int &i, float &t) {
-        (void)origin;
-        i = (int)u;
-        t = __builtin_amdgcn_fractf(u);
-    }
-};
-template <>
-struct Foot<double> {
-    static __device__ __forceinline__ void split(double u, int origin, int &i, double &t) {
-        double f = __builtin_floor(u);
-        t = u - f;
-        i = (int)f - origin;
-    }
-};
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        double o = __shfl_xor(v, off, 64);
-        v = v > o ? v : o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ void block_max_to(double v, unsigned long long *dst) {
-    __shared__ double red[kThreads / 64];
-    v = wave_max(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-#pragma unroll
-        for (int i = 1; i < kThreads / 64; ++i) m = red[i] > m ? red[i] : m;
-        if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
-    }
-}
-
-__device__ __forceinline__ void block_sum_to(unsigned v, unsigned long long *dst) {
-    __shared__ unsigned red[kThreads / 64];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long s = 0;
-        for (int i = 0; i < kThreads / 64; ++i) s += red[i];
-        if (s) atomicAdd(dst, s);
-    }
-}
-
-// Convergence bookkeeping before sweep `sweep` (one work-group).
-__device__ void bookkeep_block(SdState *st, int n_sd, int sweep, double tol,
-                               ExecCounters *cnt, int final_pass) {
-    __shared__ int active;
-    if (threadIdx.x == 0) active = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_sd; i += blockDim.x) {
-        SdState &s = st[i];
-        if (s.conv_at < 0) {
-            const double r = __longlong_as_double((long long)s.res[(sweep + 2) % 3]);
-            if (sweep > 0 && r <= tol) {
-                s.conv_at = sweep - 1;
-                s.final_buf = sweep & 1;
-                s.done_sweeps = sweep;
-                s.final_res = s.res[(sweep + 2) % 3];
-            } else {
-                if (final_pass) {
-                    s.final_buf = sweep & 1;
-                    s.done_sweeps = sweep;
-                    s.final_res = s.res[(sweep + 2) % 3];
-                }
-                atomicAdd(&active, 1);
-            }
-        }
-        s.res[(sweep + 1) % 3] = 0ull;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) cnt->n_active = active;
-}
-
-// Should work items of this sd be skipped at `sweep`?  Reads only data finished
-// before this launch started.
-__device__ __forceinline__ bool sd_skip(const SdState *s, int sweep, double tol) {
-    if (s->conv_at >= 0) return true;
-    if (sweep > 0) {
-        const double r = __longlong_as_double((long long)s->res[(sweep + 2) % 3]);
-        if (r <= tol) return true;
-    }
-    return false;
-}
 
 // ------------------------------------------------------------------ 2D kernel
 template <typename T, int TX, int TY, int H, bool POLICY>
@@ -437,8 +322,8 @@ __global__ void k_flip(SdState *st, int n_sd) {
 }
 
 __global__ void k_bookkeep(SdState *st, int n_sd, int sweep, double tol, ExecCounters *cnt,
-                           int final_pass) {
-    bookkeep_block(st, n_sd, sweep, tol, cnt, final_pass);
+                           int final_pass, double scale_rel) {
+    bookkeep_block(st, n_sd, sweep, tol, cnt, final_pass, scale_rel);
 }
 
 // ------------------------------------------------------------ dispatch tables
@@ -551,9 +436,9 @@ hipError_t launch_flip(SdState *st, int n_sd, hipStream_t s) {
 }
 
 hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep, double tol, ExecCounters *cnt,
-                           int final_pass, hipStream_t s) {
+                           int final_pass, hipStream_t s, double scale_rel) {
     hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(kThreads), 0, s, st, n_sd, sweep, tol, cnt,
-                       final_pass);
+                       final_pass, scale_rel);
     return hipGetLastError();
 }
 

@@ -1,0 +1,124 @@
+"""The C-ABI library without a GPU: it loads, exports every function the header
+declares, and rejects bad arguments on the host before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1405_3521_amd as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slhjb.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_][\w]*\s*\**\s*(sl_\w+)\s*\(", src, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    L = S.lib()
+    names = declared_functions()
+    assert len(names) >= 7
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in slhjb.h but not exported"
+
+
+def test_abi_version_matches_header():
+    m = re.search(r"#define SLHJB_ABI_VERSION (\d+)", open(HEADER).read())
+    assert S.lib().sl_abi_version() == int(m.group(1))
+
+
+def test_status_strings():
+    L = S.lib()
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert L.sl_status_string(code)
+    assert b"unknown" in L.sl_status_string(42)
+
+
+def _problem(**kw):
+    vel = np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0]])
+    p = S.SlProblem()
+    p.dim = 2
+    p.n[0], p.n[1], p.n[2] = 9, 9, 1
+    for d in range(3):
+        p.lo[d], p.hi[d] = -1.0, 1.0
+    p.m = 4
+    p.velocity = vel.ctypes.data_as(C.POINTER(C.c_double))
+    p.target = C.c_void_p(0x1000)          # never dereferenced on the host
+    p.n_comp = 1
+    p.lambda_ = 1.0
+    p.h = 0.25
+    p.v_ghost = 1.0
+    p.disc = 0
+    p.dtype = 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p, vel
+
+
+def test_workspace_query_rejects_invalid_problems():
+    L = S.lib()
+    assert L.sl_solve_workspace_size(None) == 0
+    good, keep = _problem()
+    assert L.sl_solve_workspace_size(C.byref(good)) > 0
+    for bad in (dict(dim=4), dict(m=0), dict(m=300), dict(n_comp=0), dict(n_comp=9),
+                dict(lambda_=0.0), dict(h=-1.0), dict(disc=5), dict(dtype=7),
+                dict(v_ghost=float("nan"))):
+        p, keep = _problem(**bad)
+        assert L.sl_solve_workspace_size(C.byref(p)) == 0, bad
+    p, keep = _problem()
+    p.n[0] = 2
+    assert L.sl_solve_workspace_size(C.byref(p)) == 0
+
+
+def test_solve_argument_errors_before_device_work():
+    L = S.lib()
+    p, keep = _problem()
+    opts = S.SlSolveOpts(0.0, 100, 0, 0, 0)
+    st = S.SlStats()
+    buf = C.create_string_buffer(64)
+    # null problem / options / outputs
+    assert L.sl_solve(None, C.byref(opts), buf, 64, buf, None, C.byref(st), None) == -1
+    assert L.sl_solve(C.byref(p), None, buf, 64, buf, None, C.byref(st), None) == -1
+    assert L.sl_solve(C.byref(p), C.byref(opts), buf, 64, None, None, C.byref(st), None) == -1
+    # unsupported dimension
+    q, keep2 = _problem(dim=1)
+    assert L.sl_solve(C.byref(q), C.byref(opts), buf, 64, buf, None, C.byref(st), None) == -3
+    # bad options
+    bad = S.SlSolveOpts(-1.0, 100, 0, 0, 0)
+    assert L.sl_solve(C.byref(p), C.byref(bad), buf, 64, buf, None, C.byref(st), None) == -1
+    bad = S.SlSolveOpts(0.0, 0, 0, 0, 0)
+    assert L.sl_solve(C.byref(p), C.byref(bad), buf, 64, buf, None, C.byref(st), None) == -1
+    # workspace too small
+    assert L.sl_solve(C.byref(p), C.byref(opts), buf, 64, buf, None, C.byref(st), None) == -5
+
+
+def test_reconstruction_argument_errors():
+    L = S.lib()
+    p, keep = _problem()
+    st = S.SlStats()
+    buf = C.create_string_buffer(64)
+    ra = S.SlRaOpts(3, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)     # 3 does not divide n-1 = 8
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) == 0
+    assert L.sl_reconstruct(C.byref(p), C.byref(ra), buf, 64, buf, buf, None, None,
+                            C.byref(st), None) == -1
+    ra = S.SlRaOpts(2, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
+    assert L.sl_reconstruct(C.byref(p), C.byref(ra), buf, 64, buf, buf, None, None,
+                            C.byref(st), None) == -5
+    ra = S.SlRaOpts(4, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)     # coarse grid of 3 nodes: allowed
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
+    ra = S.SlRaOpts(8, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)     # coarse grid of 2 nodes: too coarse
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) == 0
+
+
+def test_binding_raises_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(S, "_LIB", None)
+    monkeypatch.setattr(S, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        S.lib()

@@ -1,0 +1,157 @@
+"""GPU adjoint and autograd against the FP64 oracle.
+
+The adjoint kernel is fed the oracle's inputs (policy, sets, owner, dL/dV) and
+must reproduce the oracle's dL/dl (FP32: relative l2 <= 1e-4; FP64: <= 1e-12; the
+atomics only change the summation order).  End to end, the autograd gradient of
+sum (V[obs] - V_obs)^2 with respect to theta (l = exp(theta)) is checked against
+central differences of the oracle's FP64 forward solve."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1405_3521_amd as S
+import workloads as W
+from oracle import isa as I
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def pol_u8(pol):
+    return np.where(pol < 0, 255, pol).astype(np.uint8)
+
+
+def gpu_tol(g, dtype):
+    """Atomics change the summation order between iterations, so the adjoint
+    state settles only to within a few ulps; the library's stopping test adds a
+    rounding allowance, so no extra tolerance is needed."""
+    return 0.0
+
+
+def _obs_grad(p, V, Vobs, obs):
+    g = np.zeros(p.N)
+    g[obs] = 2.0 * (V[obs] - Vobs)
+    return g
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
+@pytest.mark.parametrize("n", [65, 129])
+def test_adjoint_kernel_global(n, dtype, tol):
+    p = W.c5_adjoint(n=n, n_obs=min(2000, n * n // 8))
+    say("case: adjoint global", n, dtype)
+    V, pol, _, _ = O.solve(p)
+    Vt, _, _, _ = O.solve(p.with_(cost=np.exp(p.meta["theta_true"])))
+    obs = p.meta["obs"]
+    gV = _obs_grad(p, V, Vt[obs], obs)
+    _, dLdl_o, it_o, _ = O.adjoint(p, pol, gV)
+    dp = S.to_device(p, dtype)
+    g_t = torch.as_tensor(gV, dtype=dtype, device=DEV)
+    pol_t = torch.as_tensor(pol_u8(pol), device=DEV)
+    dLdl, st = S.adjoint(dp, pol_t, g_t, tol=gpu_tol(gV, dtype))
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  rel l2", err, "iters gpu", st["sweeps_max"], "oracle", it_o)
+    assert st["converged"]
+    assert err <= tol
+
+
+def test_adjoint_kernel_isa():
+    """Sets frozen, dL/dV routed to the owner set, per-set adjoints summed."""
+    p = W.c5_adjoint(n=129, n_obs=1500)
+    Vbar, owner, rec, Vs, _ = I.isa(p)
+    _, pols, _ = I.solve_subdomains(p, rec.member, want_policy=True)
+    Vt = I.isa(p.with_(cost=np.exp(p.meta["theta_true"])))[0]
+    obs = p.meta["obs"]
+    gV = _obs_grad(p, Vbar, Vt[obs], obs)
+    dLdl_o, _ = I.adjoint_isa(p, rec.member, pols, owner, gV)
+    dp = S.to_device(p, torch.float32)
+    pol_t = torch.as_tensor(np.concatenate([pol_u8(q) for q in pols]), device=DEV)
+    dLdl, st = S.adjoint(dp, pol_t, torch.as_tensor(gV, dtype=torch.float32, device=DEV),
+                         member=torch.as_tensor(rec.member, device=DEV),
+                         owner=torch.as_tensor(owner, device=DEV),
+                         tol=gpu_tol(gV, torch.float32))
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  isa adjoint rel l2", err)
+    assert err <= 1e-4
+
+
+def test_adjoint_full_size_c5():
+    """Full adjoint configuration (513^2, 2000 observations, 4 targets)."""
+    p = W.c5_adjoint()
+    say("case: adjoint 513 full size")
+    V, pol, _, _ = O.solve(p)
+    Vt, _, _, _ = O.solve(p.with_(cost=np.exp(p.meta["theta_true"])))
+    obs = p.meta["obs"]
+    gV = _obs_grad(p, V, Vt[obs], obs)
+    _, dLdl_o, _, _ = O.adjoint(p, pol, gV)
+    dp = S.to_device(p, torch.float32)
+    dLdl, st = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
+                         torch.as_tensor(gV, dtype=torch.float32, device=DEV),
+                         tol=gpu_tol(gV, torch.float32))
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  rel l2", err, "iters", st["sweeps_max"])
+    assert err <= 1e-4
+
+
+def test_adjoint_nonnegative_for_nonnegative_g():
+    p = W.c5_adjoint(n=65)
+    V, pol, _, _ = O.solve(p)
+    rng = np.random.Generator(np.random.PCG64(9))
+    gV = rng.random(p.N)
+    dp = S.to_device(p, torch.float32)
+    dLdl, _ = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
+                        torch.as_tensor(gV, dtype=torch.float32, device=DEV),
+                        tol=gpu_tol(gV, torch.float32))
+    assert float(dLdl.min()) >= 0.0
+
+
+@pytest.mark.parametrize("mode", ["global", "isa"])
+def test_autograd_gradient_against_fd(mode):
+    """theta -> l = exp(theta) -> V (GPU, FP32) -> loss; theta.grad against central
+    differences of the oracle's FP64 loss (eps = 1e-6 along dense directions)."""
+    p = W.c5_adjoint(n=65, n_obs=300)
+    obs = p.meta["obs"]
+    member = None
+    if mode == "isa":
+        rec = I.reconstruct(p)
+        member = rec.member
+
+    def oracle_V(theta):
+        q = p.with_(cost=np.exp(theta))
+        if member is None:
+            return O.solve(q)[0]
+        Vs, _ = I.solve_subdomains(q, member)
+        return I.assemble(Vs, member, q.v_ghost)[0]
+
+    Vobs = oracle_V(p.meta["theta_true"])[obs]
+
+    def loss_o(theta):
+        return float(np.sum((oracle_V(theta)[obs] - Vobs) ** 2))
+
+    dp = S.to_device(p, torch.float32)
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q)
+    theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device=DEV).requires_grad_(True)
+    mem_t = None if member is None else torch.as_tensor(member, device=DEV)
+    V = S.HJBSolve.apply(torch.exp(theta), dp, mem_t, ra, S.SolveOpts(tol=0.0), 0.0)
+    obs_t = torch.as_tensor(obs, device=DEV)
+    Vobs_t = torch.as_tensor(Vobs, dtype=torch.float32, device=DEV)
+    loss = ((V[obs_t] - Vobs_t) ** 2).sum()
+    loss.backward()
+    grad = theta.grad.detach().cpu().numpy().astype(np.float64)
+    th = p.meta["theta"]
+    rng = np.random.Generator(np.random.PCG64(705))
+    eps = 1e-6
+    for _ in range(4):
+        d = rng.normal(size=p.N)
+        fd = (loss_o(th + eps * d) - loss_o(th - eps * d)) / (2 * eps)
+        an = float(grad @ d)
+        say(f"  {mode}: fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+        assert abs(fd - an) <= 1e-3 * abs(fd)
