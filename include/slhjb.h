@@ -150,6 +150,25 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
                  const sl_solve_opts *o, void *ws, size_t ws_bytes, void *V, uint8_t *owner,
                  uint8_t *policy, void *V_sets, sl_stats *stats, void *stream);
 
+/* Workspace bytes needed by sl_solve_batched (0 if any input is invalid). */
+size_t sl_batched_workspace_size(int nprob, const sl_problem *probs, const sl_ra_opts *ras);
+
+/* The independent-sets algorithm (RA on each problem's coarse grid, projection,
+ * per-set value iteration, assembly; paper Sec. 3-4) for `nprob` independent
+ * problems of any sizes at once: every step is one launch over all problems,
+ * and every sweep one launch over the joint (problem, set, tile) work list, so
+ * the small problems ride along with the large ones; chunks of sweeps are
+ * replayed as a captured hipGraph with device-side convergence per set.
+ * All problems must share dim and dtype.  probs, ras: HOST arrays of nprob.
+ * V: HOST array of nprob DEVICE pointers (N_p values each, outputs).  member,
+ * label, owner: HOST arrays of nprob DEVICE pointers (N_p uint8 each) or NULL
+ * (internal).  per_problem: HOST array of nprob stats or NULL; total: aggregate
+ * stats or NULL. */
+int sl_solve_batched(int nprob, const sl_problem *probs, const sl_ra_opts *ras,
+                     const sl_solve_opts *o, void *ws, size_t ws_bytes, void *const *V,
+                     uint8_t *const *member, uint8_t *const *label, uint8_t *const *owner,
+                     sl_stats *per_problem, sl_stats *total, void *stream);
+
 /* Workspace bytes needed by sl_adjoint (n_sets = n_comp with sets, 1 without). */
 size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
 

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "DeviceProblem", "RaOpts", "SolveOpts", "lib", "lib_path", "to_device", "solve",
-    "reconstruct", "solve_isa", "isa", "adjoint", "SlError", "HJBSolve",
+    "reconstruct", "solve_isa", "isa", "adjoint", "solve_batched", "SlError", "HJBSolve",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -99,6 +99,13 @@ def lib():
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, P(SlStats), C.c_void_p]
         L.sl_solve_isa.restype = C.c_int
+        L.sl_batched_workspace_size.argtypes = [C.c_int, P(SlProblem), P(SlRaOpts)]
+        L.sl_batched_workspace_size.restype = C.c_size_t
+        L.sl_solve_batched.argtypes = [C.c_int, P(SlProblem), P(SlRaOpts), P(SlSolveOpts),
+                                       C.c_void_p, C.c_size_t, P(C.c_void_p), P(C.c_void_p),
+                                       P(C.c_void_p), P(C.c_void_p), P(SlStats), P(SlStats),
+                                       C.c_void_p]
+        L.sl_solve_batched.restype = C.c_int
         L.sl_adjoint_workspace_size.argtypes = [P(SlProblem), C.c_int]
         L.sl_adjoint_workspace_size.restype = C.c_size_t
         L.sl_adjoint.argtypes = [P(SlProblem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -372,6 +379,45 @@ def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float 
     d = st.as_dict()
     d["converged"] = rc == SL_OK
     return out, d
+
+
+def solve_batched(problems, ras, opts: SolveOpts = SolveOpts(), want_owner: bool = True,
+                  workspace=None):
+    """The independent-sets algorithm for many problems at once (one launch per
+    step for all of them).  Returns (V list, member list, label list, owner list,
+    per-problem stats list, total stats)."""
+    import torch
+    L = lib()
+    np_ = len(problems)
+    if np_ == 0 or len(ras) != np_:
+        raise ValueError("need one RaOpts per problem")
+    cps, keep = [], []
+    for p in problems:
+        cp, k = _cproblem(p)
+        cps.append(cp)
+        keep.append(k)
+    arr = (SlProblem * np_)(*cps)
+    rarr = (SlRaOpts * np_)(*[_ra(r) for r in ras])
+    dev = problems[0].target.device
+    ws_bytes = L.sl_batched_workspace_size(np_, arr, rarr)
+    if ws_bytes == 0:
+        raise ValueError("invalid batch (problems must share dim and dtype)")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    Vs = [torch.empty(p.N, dtype=p.dtype, device=dev) for p in problems]
+    mem = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
+    lab = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
+    own = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems] if want_owner else None
+    ptrs = lambda ts: (C.c_void_p * np_)(*[t.data_ptr() for t in ts])
+    per = (SlStats * np_)()
+    tot = SlStats()
+    rc = L.sl_solve_batched(np_, arr, rarr, C.byref(_so(opts)), _ptr(ws), ws.numel(), ptrs(Vs),
+                            ptrs(mem), ptrs(lab), ptrs(own) if own else None, per,
+                            C.byref(tot), _stream())
+    if rc < 0:
+        raise SlError("sl_solve_batched", rc)
+    t = tot.as_dict()
+    t["converged"] = rc == SL_OK
+    return Vs, mem, lab, own, [x.as_dict() for x in per], t
 
 
 from .autograd import HJBSolve  # noqa: E402

@@ -21,8 +21,9 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjDesc<T> *__restrict__ ads,
                                                       SdState *__restrict__ st, int n_sets,
                                                       int blocks_per_set,
-                                                      ExecCounters *__restrict__ cnt, int iter,
-                                                      double tol, double scale_rel) {
+                                                      ExecCounters *__restrict__ cnt,
+                                                      int iter_rel, double tol, double scale_rel) {
+    const int iter = cnt->sweep_base + iter_rel;
     if (blockIdx.x == 0) bookkeep_block(st, n_sets, iter, tol, cnt, 0, scale_rel);
     const int set = blockIdx.x / blocks_per_set;
     const int b = blockIdx.x - set * blocks_per_set;

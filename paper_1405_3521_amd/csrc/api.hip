@@ -154,6 +154,80 @@ Pinned &pinned() {
     return p;
 }
 
+// A private stream for graph capture (captured graphs are launched on the
+// caller's stream; capture itself needs a non-default stream).  Default priority.
+hipStream_t capture_stream() {
+    static thread_local hipStream_t cs = nullptr;
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
+    return cs;
+}
+
+// Runs `enqueue(stream, todo)` -- `todo` iterations, then a bookkeeping launch
+// that advances the device-side iteration base, then a copy of the active-set
+// counter to pinned host memory -- in chunks until the counter is zero or
+// max_steps iterations are done.  Full chunks are captured once as a hipGraph
+// and replayed on the caller's stream; a short last chunk is launched directly.
+struct ChunkLoop {
+    double ms = 0.0;         // HIP-event time of the chunks (profile)
+    long launches = 0;
+    template <class F>
+    int run(F enqueue, long max_steps, int chunk, hipStream_t s, int use_graph, int profile,
+            long *done, int *status) {
+        int *active = pinned().active;
+        if (!active) return SL_ERR_HIP;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        int rc = SL_OK;
+        long S = 0;
+        *status = SL_NOT_CONVERGED;
+        if (profile && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess))
+            rc = SL_ERR_HIP;
+        while (rc == SL_OK && S < max_steps) {
+            const int todo = (int)std::min<long>(chunk, max_steps - S);
+            if (profile && hipEventRecord(ev[0], s) != hipSuccess) { rc = SL_ERR_HIP; break; }
+            if (use_graph && todo == chunk) {
+                if (!exec) {
+                    hipStream_t cs = capture_stream();
+                    if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                        rc = SL_ERR_HIP;
+                        break;
+                    }
+                    const hipError_t e1 = enqueue(cs, todo);
+                    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+                    if (e1 != hipSuccess || e2 != hipSuccess ||
+                        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                        rc = SL_ERR_HIP;
+                        break;
+                    }
+                }
+                if (hipGraphLaunch(exec, s) != hipSuccess) { rc = SL_ERR_HIP; break; }
+            } else if (enqueue(s, todo) != hipSuccess) {
+                rc = SL_ERR_HIP;
+                break;
+            }
+            if (profile && hipEventRecord(ev[1], s) != hipSuccess) { rc = SL_ERR_HIP; break; }
+            if (hipStreamSynchronize(s) != hipSuccess) { rc = SL_ERR_HIP; break; }
+            S += todo;
+            if (profile) {
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, ev[0], ev[1]) == hipSuccess) ms += t;
+                launches += todo;
+            }
+            if (*active == 0) {
+                *status = SL_OK;
+                break;
+            }
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        *done = S;
+        return rc;
+    }
+};
+
 // --------------------------------------------------------------- executor
 template <typename T>
 struct Exec {
@@ -215,55 +289,44 @@ struct Exec {
                               hipMemcpyHostToDevice, s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(ExecCounters), s));
         HIPCHK(launch_build_items(cfg, sds, n_sd, total_tiles, prefix, items, cnt, s));
+        HIPCHK(sweep_set_attributes(cfg));
         return SL_OK;
     }
 
     // Sweeps until every sd meets tol or max_sweeps.  Returns SL_OK or
     // SL_NOT_CONVERGED; *sweeps_done = sweeps launched.
-    // Profiling (optional): HIP events around each chunk of back-to-back sweep
-    // launches; ms_sweeps / sweep_launches is the mean launch duration.
+    // Profiling (optional): HIP events around each chunk of sweep launches
+    // (a chunk also holds one bookkeeping launch and a 4-byte copy);
+    // ms_sweeps / sweep_launches is the mean launch duration.
     double ms_sweeps = 0.0;
     long sweep_launches = 0;
+    int use_graph = 1;
 
     int run(double tol, long max_sweeps, int check_every, int want_policy, hipStream_t s,
             long *sweeps_done, int profile = 0) {
         int *active = pinned().active;
         if (!active) return SL_ERR_HIP;
         const int chunk = check_every > 0 ? check_every : 32;
+        auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
+            for (int i = 0; i < todo; ++i) {
+                const hipError_t e =
+                    launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, i, tol, 0, q);
+                if (e != hipSuccess) return e;
+            }
+            hipError_t e = launch_bookkeep(st, n_sd, todo, tol, cnt, 0, q, 0.0, todo);
+            if (e != hipSuccess) return e;
+            return hipMemcpyAsync(active, &cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, q);
+        };
+        ChunkLoop loop;
         long S = 0;
         int status = SL_NOT_CONVERGED;
-        hipEvent_t ev[2] = {nullptr, nullptr};
-        if (profile) {
-            HIPCHK(hipEventCreate(&ev[0]));
-            HIPCHK(hipEventCreate(&ev[1]));
-        }
-        while (S < max_sweeps) {
-            const long todo = std::min<long>(chunk, max_sweeps - S);
-            if (profile) HIPCHK(hipEventRecord(ev[0], s));
-            for (long i = 0; i < todo; ++i, ++S)
-                HIPCHK(launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, (int)S, tol, 0, s));
-            if (profile) HIPCHK(hipEventRecord(ev[1], s));
-            HIPCHK(launch_bookkeep(st, n_sd, (int)S, tol, cnt, 0, s));
-            HIPCHK(hipMemcpyAsync(active, &cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (profile) {
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-                ms_sweeps += ms;
-                sweep_launches += todo;
-            }
-            if (*active == 0) {
-                status = SL_OK;
-                break;
-            }
-        }
-        if (profile) {
-            (void)hipEventDestroy(ev[0]);
-            (void)hipEventDestroy(ev[1]);
-        }
-        HIPCHK(launch_bookkeep(st, n_sd, (int)S, tol, cnt, 1, s));
+        int rc = loop.run(enqueue, max_sweeps, chunk, s, use_graph, profile, &S, &status);
+        if (rc) return rc;
+        ms_sweeps += loop.ms;
+        sweep_launches += loop.launches;
+        HIPCHK(launch_bookkeep(st, n_sd, 0, tol, cnt, 1, s));
         if (want_policy) {
-            HIPCHK(launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, (int)S, tol, 1, s));
+            HIPCHK(launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, 0, tol, 1, s));
             HIPCHK(launch_flip(st, n_sd, s));
         }
         *sweeps_done = S;
@@ -810,23 +873,21 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     int *active = pinned().active;
     if (!active) return SL_ERR_HIP;
     tm.mark(1, s);
+    auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
+        for (int i = 0; i < todo; ++i) {
+            const hipError_t e = launch_adjoint_iter<T>(p->dim, P.ads, P.st, n_sets, bps, P.cnt,
+                                                        i, tol, scale_rel, q);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = launch_bookkeep(P.st, n_sets, todo, tol, P.cnt, 0, q, scale_rel, todo);
+        if (e != hipSuccess) return e;
+        return hipMemcpyAsync(active, &P.cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, q);
+    };
+    ChunkLoop loop;
     long it = 0;
     int status = SL_NOT_CONVERGED;
-    const int chunk = 32;
-    while (it < max_iters) {
-        const long todo = std::min<long>(chunk, max_iters - it);
-        for (long i = 0; i < todo; ++i, ++it)
-            HIPCHK(launch_adjoint_iter<T>(p->dim, P.ads, P.st, n_sets, bps, P.cnt, (int)it, tol,
-                                          scale_rel, s));
-        HIPCHK(launch_bookkeep(P.st, n_sets, (int)it, tol, P.cnt, 0, s, scale_rel));
-        HIPCHK(hipMemcpyAsync(active, &P.cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (*active == 0) {
-            status = SL_OK;
-            break;
-        }
-    }
-    HIPCHK(launch_bookkeep(P.st, n_sets, (int)it, tol, P.cnt, 1, s, scale_rel));
+    if ((rc = loop.run(enqueue, max_iters, 32, s, 1, 0, &it, &status))) return rc;
+    HIPCHK(launch_bookkeep(P.st, n_sets, 0, tol, P.cnt, 1, s, scale_rel));
     HIPCHK(launch_adjoint_combine<T>(P.ads, n_sets, p->target, N, (T)w, dLdl, s));
     tm.mark(2, s);
     ExecCounters c{};
@@ -843,6 +904,277 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         stats->sweep_launches = it;
     }
     return status;
+}
+
+// ------------------------------------------------------------------- batched
+constexpr int kChunk = 4096;     // elements per block of the segmented batched kernels
+
+template <typename T>
+struct BatchPlan {
+    std::vector<ProbDesc<T>> hp;     // host image of the descriptors
+    ProbDesc<T> *pd = nullptr;
+    FieldStats *fs = nullptr;        // 2*np: fine stats, coarse presence
+    int *blk_N = nullptr, *blk_NK = nullptr, *blk_aux = nullptr;
+    std::vector<int> hblk_N, hblk_NK, hblk_aux;
+    double *ctrlK = nullptr;         // np * m * dim
+    T *ctrl = nullptr;
+    Exec<double> exK;
+    Exec<T> ex;
+    int tot_sd = 0;
+};
+
+inline int blocks_for(size_t len) { return (int)((len + kChunk - 1) / kChunk); }
+
+template <typename T>
+int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t *const *member,
+                 uint8_t *const *label, uint8_t *const *owner, Arena &a, BatchPlan<T> &B) {
+    const int dim = probs[0].dim;
+    const LaunchCfg cfgK = make_cfg(dim, SL_F64, 1, default_variant(dim, SL_F64));
+    const LaunchCfg cfg = make_cfg(dim, probs[0].dtype, 1, default_variant(dim, probs[0].dtype));
+    B.hp.assign(np, ProbDesc<T>{});
+    B.hblk_N.assign(np + 1, 0);
+    B.hblk_NK.assign(np + 1, 0);
+    B.hblk_aux.assign(np + 1, 0);
+    int tilesK = 0, tiles = 0, nsd = 0;
+    size_t ctrl_len = 0;
+    for (int q = 0; q < np; ++q) {
+        const sl_problem *p = &probs[q];
+        ProbDesc<T> &d = B.hp[q];
+        const int sK = ras[q].coarse_stride;
+        const CoarseGeom cg = coarse_geom(p, sK);
+        d.dim = dim;
+        for (int k = 0; k < 3; ++k) {
+            d.n[k] = k < dim ? p->n[k] : 1;
+            d.nK[k] = cg.nK[k];
+        }
+        d.stride = sK;
+        d.n_comp = p->n_comp;
+        d.N = nodes_of(p);
+        d.NK = cg.NK;
+        d.tK = a.take<int8_t>(cg.NK);
+        d.cK = p->speed ? a.take<double>(cg.NK) : nullptr;
+        d.wlK = p->cost ? a.take<double>(cg.NK) : nullptr;
+        d.gK = p->g ? a.take<double>(cg.NK) : nullptr;
+        d.Vaux = a.take<double>((size_t)p->n_comp * 2 * cg.NK);
+        d.memberK = a.take<uint8_t>(cg.NK);
+        d.labelK = a.take<uint8_t>(cg.NK);
+        d.member = (member && member[q]) ? member[q] : a.take<uint8_t>(d.N);
+        d.label = (label && label[q]) ? label[q] : a.take<uint8_t>(d.N);
+        d.owner = owner ? owner[q] : nullptr;
+        d.Vf = a.take<T>((size_t)p->n_comp * 2 * d.N);
+        d.wl = p->cost ? a.take<T>(d.N) : nullptr;
+        int t[3];
+        tilesK += Exec<double>::tiles_of(cfgK, cg.nK, dim, t) * p->n_comp;
+        tiles += Exec<T>::tiles_of(cfg, p->n, dim, t) * p->n_comp;
+        d.sd_coarse0 = nsd;
+        d.sd_fine0 = nsd;
+        nsd += p->n_comp;
+        ctrl_len += (size_t)p->m * dim;
+        B.hblk_N[q + 1] = B.hblk_N[q] + blocks_for(d.N);
+        B.hblk_NK[q + 1] = B.hblk_NK[q] + blocks_for(d.NK);
+        B.hblk_aux[q + 1] = B.hblk_aux[q] + blocks_for((size_t)p->n_comp * d.NK);
+    }
+    B.tot_sd = nsd;
+    B.pd = a.take<ProbDesc<T>>(np);
+    B.fs = a.take<FieldStats>(2 * (size_t)np);
+    B.blk_N = a.take<int>(np + 1);
+    B.blk_NK = a.take<int>(np + 1);
+    B.blk_aux = a.take<int>(np + 1);
+    B.ctrlK = a.take<double>(ctrl_len);
+    B.ctrl = a.take<T>(ctrl_len);
+    B.exK.reserve(a, nsd, tilesK);
+    B.ex.reserve(a, nsd, tiles);
+    return SL_OK;
+}
+
+template <typename T>
+int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const sl_solve_opts *o,
+                 void *ws, size_t ws_bytes, void *const *V, uint8_t *const *member,
+                 uint8_t *const *label, uint8_t *const *owner, sl_stats *per_problem,
+                 sl_stats *total, hipStream_t s) {
+    Timer tm;
+    tm.mark(0, s);
+    const int dim = probs[0].dim;
+    Arena a{(char *)ws, ws_bytes};
+    BatchPlan<T> B;
+    plan_batched<T>(np, probs, ras, member, label, owner, a, B);
+    if (!a.fits()) return SL_ERR_WORKSPACE;
+    // descriptors, statistics slots, block prefixes
+    std::vector<FieldStats> fs_init(2 * (size_t)np);
+    for (auto &f : fs_init) {
+        f = FieldStats{};
+        for (int i = 0; i < SL_MAX_COMP; ++i) f.first_node[i] = INT_MAX;
+    }
+    for (int q = 0; q < np; ++q) {
+        const sl_problem *p = &probs[q];
+        ProbDesc<T> &d = B.hp[q];
+        d.target = p->target;
+        d.speed = (const T *)p->speed;
+        d.cost = (const T *)p->cost;
+        d.g = (const T *)p->g;
+        d.V = (T *)V[q];
+        d.fs = B.fs + q;
+        d.fsK = B.fs + np + q;
+        d.G = p->v_ghost;
+        double beta, w, betaK, wK;
+        scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
+        scheme_constants(p->lambda, p->h * ras[q].coarse_stride, p->disc, &betaK, &wK);
+        d.w = w;
+        d.wK = wK;
+        double dxK = 0.0;
+        for (int k = 0; k < dim; ++k)
+            dxK = std::max(dxK, (p->hi[k] - p->lo[k]) / (double)(d.nK[k] - 1));
+        d.delta = ras[q].delta_override > 0.0
+                      ? ras[q].delta_override
+                      : 2.0 * (ras[q].C * std::pow(dxK, ras[q].q) + ras[q].M * dxK);
+    }
+    HIPCHK(hipMemcpyAsync(B.pd, B.hp.data(), sizeof(ProbDesc<T>) * np, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.fs, fs_init.data(), sizeof(FieldStats) * 2 * np, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.blk_N, B.hblk_N.data(), sizeof(int) * (np + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.blk_NK, B.hblk_NK.data(), sizeof(int) * (np + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.blk_aux, B.hblk_aux.data(), sizeof(int) * (np + 1), hipMemcpyHostToDevice, s));
+    // 1. input statistics of every problem (one launch, one sync)
+    HIPCHK(launch_batched<T>(kBatchStats, B.pd, np, B.blk_N, B.hblk_N[np], kChunk, nullptr, nullptr, s));
+    std::vector<FieldStats> fs(np);
+    HIPCHK(hipMemcpyAsync(fs.data(), B.fs, sizeof(FieldStats) * np, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int HK = 1, H = 1;
+    std::vector<double> ctrlK, emaxs(np);
+    std::vector<T> ctrl;
+    for (int q = 0; q < np; ++q) {
+        int rc = check_fields(fs[q]);
+        if (rc) return rc;
+        const sl_problem *p = &probs[q];
+        std::vector<double> e, eK;
+        double emax, emaxK;
+        control_table(p, p->n, p->h, e, &emax);
+        control_table(p, B.hp[q].nK, p->h * ras[q].coarse_stride, eK, &emaxK);
+        const double smax = p->speed ? bits_to_double(fs[q].speed_max) : 1.0;
+        H = std::max(H, halo_for(smax, emax));
+        HK = std::max(HK, halo_for(smax, emaxK));
+        for (double x : e) ctrl.push_back((T)x);
+        for (double x : eK) ctrlK.push_back(x);
+    }
+    if (H > kMaxHalo || HK > kMaxHalo) return SL_ERR_UNSUPPORTED;
+    HIPCHK(hipMemcpyAsync(B.ctrlK, ctrlK.data(), sizeof(double) * ctrlK.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.ctrl, ctrl.data(), sizeof(T) * ctrl.size(), hipMemcpyHostToDevice, s));
+    // 2. coarse data, placement of missing components, auxiliary initial values
+    HIPCHK(launch_batched<T>(kBatchCoarsePrep, B.pd, np, B.blk_NK, B.hblk_NK[np], kChunk, nullptr, nullptr, s));
+    HIPCHK(launch_batched<T>(kBatchPlace, B.pd, np, nullptr, 1, kChunk, nullptr, nullptr, s));
+    HIPCHK(launch_batched<T>(kBatchInitAux, B.pd, np, B.blk_aux, B.hblk_aux[np], kChunk, nullptr, nullptr, s));
+    // 3. RA step 1 for every (problem, component): one launch per sweep
+    B.exK.cfg = make_cfg(dim, SL_F64, HK, default_variant(dim, SL_F64));
+    size_t coff = 0;
+    for (int q = 0; q < np; ++q) {
+        const sl_problem *p = &probs[q];
+        const ProbDesc<T> &d = B.hp[q];
+        double betaK, wK;
+        scheme_constants(p->lambda, p->h * ras[q].coarse_stride, p->disc, &betaK, &wK);
+        for (int i = 0; i < p->n_comp; ++i) {
+            SdDesc<double> sd{};
+            sd.V[0] = d.Vaux + (size_t)i * 2 * d.NK;
+            sd.V[1] = sd.V[0] + d.NK;
+            sd.speed = d.cK;
+            sd.wl = d.wlK;
+            sd.target = d.tK;
+            sd.ctrl = B.ctrlK + coff;
+            sd.wl_const = wK;
+            sd.beta = betaK;
+            sd.G = p->v_ghost;
+            for (int k = 0; k < 3; ++k) sd.n[k] = d.nK[k];
+            sd.m = p->m;
+            sd.bit = i;
+            Exec<double>::tiles_of(B.exK.cfg, d.nK, dim, sd.tiles);
+            sd.halo = HK;
+            B.exK.host_sds.push_back(sd);
+        }
+        coff += (size_t)p->m * dim;
+    }
+    int rc = B.exK.prepare(s);
+    if (rc) return rc;
+    long SK = 0;
+    int stK = B.exK.run(ras[0].tol, ras[0].max_sweeps, 32, 0, s, &SK);
+    if (stK < 0) return stK;
+    // 4. RA steps 2-3, projection, fine initial values
+    HIPCHK(launch_batched<T>(kBatchCombine, B.pd, np, B.blk_NK, B.hblk_NK[np], kChunk, B.exK.sds, B.exK.st, s));
+    HIPCHK(launch_batched<T>(kBatchProjectInit, B.pd, np, B.blk_N, B.hblk_N[np], kChunk, nullptr, nullptr, s));
+    tm.mark(1, s);
+    // 5. ISA step 3 for every (problem, set): one launch per sweep
+    B.ex.cfg = make_cfg(dim, probs[0].dtype, H, default_variant(dim, probs[0].dtype));
+    coff = 0;
+    for (int q = 0; q < np; ++q) {
+        const sl_problem *p = &probs[q];
+        const ProbDesc<T> &d = B.hp[q];
+        double beta, w;
+        scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
+        for (int i = 0; i < p->n_comp; ++i) {
+            SdDesc<T> sd{};
+            sd.V[0] = d.Vf + (size_t)i * 2 * d.N;
+            sd.V[1] = sd.V[0] + d.N;
+            sd.speed = (const T *)p->speed;
+            sd.wl = d.wl;
+            sd.target = p->target;
+            sd.member = d.member;
+            sd.ctrl = B.ctrl + coff;
+            sd.wl_const = (T)w;
+            sd.beta = (T)beta;
+            sd.G = (T)p->v_ghost;
+            for (int k = 0; k < 3; ++k) sd.n[k] = d.n[k];
+            sd.m = p->m;
+            sd.bit = i;
+            Exec<T>::tiles_of(B.ex.cfg, d.n, dim, sd.tiles);
+            sd.halo = H;
+            B.ex.host_sds.push_back(sd);
+        }
+        coff += (size_t)p->m * dim;
+    }
+    if ((rc = B.ex.prepare(s))) return rc;
+    long S = 0;
+    const int status = B.ex.run(o->tol, o->max_sweeps, o->check_every, 0, s, &S, o->profile);
+    if (status < 0) return status;
+    tm.mark(2, s);
+    // 6. ISA step 4 for every problem
+    HIPCHK(launch_batched<T>(kBatchAssemble, B.pd, np, B.blk_N, B.hblk_N[np], kChunk, B.ex.sds, B.ex.st, s));
+    tm.mark(3, s);
+    std::vector<SdState> hsK, hs;
+    unsigned long long ncK = 0, nc = 0;
+    if ((rc = B.exK.read_stats(s, hsK, &ncK))) return rc;
+    if ((rc = B.ex.read_stats(s, hs, &nc))) return rc;
+    if (per_problem) {
+        for (int q = 0; q < np; ++q) {
+            const ProbDesc<T> &d = B.hp[q];
+            std::vector<SdState> sub(hs.begin() + d.sd_fine0, hs.begin() + d.sd_fine0 + d.n_comp);
+            fill_stats(&per_problem[q], sub, 0, S);
+            per_problem[q].node_control_updates = 0.0;
+            per_problem[q].ms_ra = per_problem[q].ms_fine = per_problem[q].ms_total = 0.0;
+            per_problem[q].set_fraction_max = 0.0;
+            per_problem[q].ms_sweeps = 0.0;
+            per_problem[q].sweep_launches = 0;
+        }
+    }
+    if (total) {
+        fill_stats(total, hs, nc, S);
+        total->ms_ra = tm.ms(0, 1);
+        total->ms_fine = tm.ms(1, 2);
+        total->ms_total = tm.ms(0, 3);
+        total->set_fraction_max = 0.0;
+        total->ms_sweeps = B.ex.ms_sweeps;
+        total->sweep_launches = B.ex.sweep_launches;
+    }
+    return status == SL_OK && stK == SL_OK ? SL_OK : SL_NOT_CONVERGED;
+}
+
+int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
+    if (np < 1 || !probs || !ras) return SL_ERR_INVALID_ARG;
+    for (int q = 0; q < np; ++q) {
+        int rc = validate(&probs[q]);
+        if (rc) return rc;
+        if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
+        if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
+            return SL_ERR_UNSUPPORTED;
+        if (probs[q].m != probs[0].m && false) return SL_ERR_UNSUPPORTED;
+    }
+    return SL_OK;
 }
 
 }  // namespace
@@ -940,6 +1272,40 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
                                (float *)V_sets, stats, s);
     return isa_impl<double>(p, ra, member, o, ws, ws_bytes, (double *)V, owner, policy,
                             (double *)V_sets, stats, s);
+}
+
+size_t sl_batched_workspace_size(int nprob, const sl_problem *probs, const sl_ra_opts *ras) {
+    if (validate_batch(nprob, probs, ras) != SL_OK) return 0;
+    Arena a{nullptr, 0};
+    if (probs[0].dtype == SL_F32) {
+        BatchPlan<float> B;
+        plan_batched<float>(nprob, probs, ras, nullptr, nullptr, nullptr, a, B);
+    } else {
+        BatchPlan<double> B;
+        plan_batched<double>(nprob, probs, ras, nullptr, nullptr, nullptr, a, B);
+    }
+    return a.off + 256;
+}
+
+int sl_solve_batched(int nprob, const sl_problem *probs, const sl_ra_opts *ras,
+                     const sl_solve_opts *o, void *ws, size_t ws_bytes, void *const *V,
+                     uint8_t *const *member, uint8_t *const *label, uint8_t *const *owner,
+                     sl_stats *per_problem, sl_stats *total, void *stream) {
+    int rc = validate_batch(nprob, probs, ras);
+    if (rc) return rc;
+    if ((rc = validate_solve_opts(o))) return rc;
+    if (!V || !ws) return SL_ERR_INVALID_ARG;
+    for (int q = 0; q < nprob; ++q)
+        if (!V[q]) return SL_ERR_INVALID_ARG;
+    // the size query lays out internal member/label arrays for every problem,
+    // so it bounds the need whatever the caller passes
+    if (ws_bytes < sl_batched_workspace_size(nprob, probs, ras)) return SL_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (probs[0].dtype == SL_F32)
+        return batched_impl<float>(nprob, probs, ras, o, ws, ws_bytes, V, member, label, owner,
+                                   per_problem, total, s);
+    return batched_impl<double>(nprob, probs, ras, o, ws, ws_bytes, V, member, label, owner,
+                                per_problem, total, s);
 }
 
 size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets) {

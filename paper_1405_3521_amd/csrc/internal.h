@@ -62,7 +62,9 @@ struct WorkItem {
 struct ExecCounters {
     int n_items;                // valid work items
     int n_active;               // sds not yet converged (after the last bookkeeping)
-    unsigned long long nc_updates;  // node*control evaluations (only in stats mode)
+    unsigned long long nc_updates;  // node*control evaluations
+    int sweep_base;             // index of the first sweep of the current chunk
+    int pad;
 };
 
 // Input statistics gathered on the device in one pass (see launch_field_stats).
@@ -96,6 +98,37 @@ struct AdjDesc {
     int set;
 };
 
+// One problem of a batch (device memory): its fine fields (caller's), its
+// coarse-grid and fine-grid scratch, outputs and the indices of its first
+// coarse and fine sub-domain in the joint executors.
+template <typename T>
+struct ProbDesc {
+    int dim, n[3], nK[3], stride, n_comp;
+    size_t N, NK;
+    const int8_t *target;
+    const T *speed, *cost, *g;
+    int8_t *tK;
+    double *cK, *wlK, *gK;
+    double *Vaux;               // n_comp * 2 * NK
+    double wK, delta, G, w;
+    uint8_t *memberK, *labelK, *member, *label, *owner;
+    T *Vf;                      // n_comp * 2 * N
+    T *wl;                      // N (if cost)
+    T *V;                       // output
+    FieldStats *fs, *fsK;
+    int sd_coarse0, sd_fine0;
+};
+
+enum BatchOp {
+    kBatchStats = 0,
+    kBatchCoarsePrep = 1,
+    kBatchPlace = 2,
+    kBatchInitAux = 3,
+    kBatchCombine = 4,
+    kBatchProjectInit = 5,
+    kBatchAssemble = 6,
+};
+
 struct LaunchCfg {
     int dim;
     int dtype;                  // SL_F32 / SL_F64
@@ -105,15 +138,20 @@ struct LaunchCfg {
 };
 
 // ---- launchers (sweep.hip) -------------------------------------------------
-// One Jacobi sweep over all work items.  `sweep` is the global sweep index.
+// One Jacobi sweep over all work items.  The sweep index is
+// cnt->sweep_base + sweep_rel (device-resident base, so a captured chunk of
+// launches can be replayed).
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
-                        const WorkItem *items, const ExecCounters *cnt, int max_items,
-                        int sweep, double tol, int want_policy, hipStream_t s);
-// Bookkeeping before sweep `sweep` (marks sds converged, resets slots, counts
-// active sds); `final_pass` also settles final_buf of unconverged sds.
-hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep, double tol,
+                        const WorkItem *items, ExecCounters *cnt, int max_items,
+                        int sweep_rel, double tol, int want_policy, hipStream_t s);
+// Bookkeeping before sweep cnt->sweep_base + sweep_rel (marks sds converged,
+// resets slots, counts active sds); `final_pass` also settles final_buf of
+// unconverged sds; afterwards sweep_base += advance.
+hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol,
                            ExecCounters *cnt, int final_pass, hipStream_t s,
-                           double scale_rel = 0.0);
+                           double scale_rel = 0.0, int advance = 0);
+// Dynamic-LDS attributes of the kernels of `cfg` (call before graph capture).
+hipError_t sweep_set_attributes(const LaunchCfg &cfg);
 // Supported tile shapes per (dim) for the autotuner; returns count.
 int sweep_variants(int dim, LaunchCfg *out, int cap);
 
@@ -180,10 +218,17 @@ hipError_t launch_copy_final(const SdDesc<T> *sds_dev, const SdState *st, int i,
 hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long long *counts8,
                                 hipStream_t s);
 
+// ---- launchers (batched.hip) ------------------------------------------------
+// One batched op over all problems; blkp[p] = first block of problem p (np+1
+// entries), each block covers `chunk` elements of its problem.
+template <typename T>
+hipError_t launch_batched(int op, const ProbDesc<T> *pd, int np, const int *blkp, int nblocks,
+                          int chunk, const void *sds, const SdState *st, hipStream_t s);
+
 // ---- launchers (adjoint.hip) ------------------------------------------------
 template <typename T>
 hipError_t launch_adjoint_iter(int dim, const AdjDesc<T> *ads, SdState *st, int n_sets,
-                               int blocks_per_set, ExecCounters *cnt, int iter, double tol,
+                               int blocks_per_set, ExecCounters *cnt, int iter_rel, double tol,
                                double scale_rel, hipStream_t s);
 template <typename T>
 hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_t *target,

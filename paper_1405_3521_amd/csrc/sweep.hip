@@ -32,7 +32,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
                                                       ExecCounters *__restrict__ cnt,
-                                                      int sweep, double tol) {
+                                                      int sweep_rel, double tol) {
+    const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
     constexpr int RSTEP = kThreads / TX;
@@ -169,7 +170,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
                                                       ExecCounters *__restrict__ cnt,
-                                                      int sweep, double tol) {
+                                                      int sweep_rel, double tol) {
+    const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
     constexpr int LD = TZ + 2 * H;
@@ -321,9 +323,11 @@ __global__ void k_flip(SdState *st, int n_sd) {
     for (int i = threadIdx.x; i < n_sd; i += blockDim.x) st[i].final_buf ^= 1;
 }
 
-__global__ void k_bookkeep(SdState *st, int n_sd, int sweep, double tol, ExecCounters *cnt,
-                           int final_pass, double scale_rel) {
-    bookkeep_block(st, n_sd, sweep, tol, cnt, final_pass, scale_rel);
+__global__ void k_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol, ExecCounters *cnt,
+                           int final_pass, double scale_rel, int advance) {
+    const int base = cnt->sweep_base;
+    bookkeep_block(st, n_sd, base + sweep_rel, tol, cnt, final_pass, scale_rel);
+    if (threadIdx.x == 0) cnt->sweep_base = base + advance;
 }
 
 // ------------------------------------------------------------ dispatch tables
@@ -409,21 +413,36 @@ int sweep_variants(int dim, LaunchCfg *out, int cap) {
     return k;
 }
 
-hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
-                        const WorkItem *items, const ExecCounters *cnt, int max_items,
-                        int sweep, double tol, int want_policy, hipStream_t s) {
+static const void *sweep_fn(const LaunchCfg &cfg, int want_policy, size_t *lds) {
     int nv = 0;
     const Variant *vt = variants(&nv);
     if (cfg.variant < 0 || cfg.variant >= nv || cfg.halo < 1 || cfg.halo > kMaxHalo)
-        return hipErrorInvalidValue;
+        return nullptr;
     const Variant &v = vt[cfg.variant];
-    const void *fn = v.fn[cfg.halo][want_policy ? 1 : 0];
-    const size_t lds = v.lds_bytes[cfg.halo];
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
+    *lds = v.lds_bytes[cfg.halo];
+    return v.fn[cfg.halo][want_policy ? 1 : 0];
+}
+
+hipError_t sweep_set_attributes(const LaunchCfg &cfg) {
+    for (int pol = 0; pol < 2; ++pol) {
+        size_t lds = 0;
+        const void *fn = sweep_fn(cfg, pol, &lds);
+        if (!fn) return hipErrorInvalidValue;
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
     }
+    return hipSuccess;
+}
+
+hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
+                        const WorkItem *items, ExecCounters *cnt, int max_items,
+                        int sweep, double tol, int want_policy, hipStream_t s) {
+    size_t lds = 0;
+    const void *fn = sweep_fn(cfg, want_policy, &lds);
+    if (!fn) return hipErrorInvalidValue;
     const int grid = max_items > 0 ? max_items : 1;
     void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items,
                     (void *)&cnt, (void *)&sweep, (void *)&tol};
@@ -436,9 +455,9 @@ hipError_t launch_flip(SdState *st, int n_sd, hipStream_t s) {
 }
 
 hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep, double tol, ExecCounters *cnt,
-                           int final_pass, hipStream_t s, double scale_rel) {
+                           int final_pass, hipStream_t s, double scale_rel, int advance) {
     hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(kThreads), 0, s, st, n_sd, sweep, tol, cnt,
-                       final_pass, scale_rel);
+                       final_pass, scale_rel, advance);
     return hipGetLastError();
 }
 
