@@ -35,6 +35,9 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.3 T lane-ops/s
 #   foot 2 fma, cell index 2, fraction 2, 1-tau 2, Q1 weights 4 mul,
 #   interpolation 1 mul + 3 fma, candidate 1 fma, min 1  -> 18
 OPS_PER_NC_2D = 18
+# 3D: foot 3 fma, index 3, fraction 3, 1-tau 3, weights 4 + 8 mul,
+#     interpolation 1 mul + 7 fma, candidate 1 fma, min 1 -> 34
+OPS_PER_NC_3D = 34
 # Algorithmic HBM bytes per node per sweep (FP32): read V, write V, read c,
 # read the member mask (1 B), read the target id (1 B).
 BYTES_PER_NODE_SWEEP = 4 + 4 + 4 + 1 + 1
@@ -48,7 +51,120 @@ def parse():
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--legs", default="c3,c4,c5",
+                    help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
+                         "c5 (adjoint 513^2); empty for none")
     return ap.parse_args()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def leg_c3(steps: int):
+    """3D anisotropic 257^3, 8 target balls, 128 controls: ISA to sup-res<1e-6."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    p = W.c3_aniso3d()
+    dp = S.to_device(p, torch.float32, "cuda:0")
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q)
+    opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1)
+    S.isa(dp, ra, opts)
+    _sync()
+    t0 = time.perf_counter()
+    sts = [S.isa(dp, ra, opts)[-1] for _ in range(steps)]
+    _sync()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    nc = np.mean([x["node_control_updates"] for x in sts])
+    launches = np.mean([x["sweep_launches"] for x in sts])
+    ms_launch = np.sum([x["ms_sweeps"] for x in sts]) / np.sum([x["sweep_launches"] for x in sts])
+    ach = OPS_PER_NC_3D * nc / launches / (ms_launch / 1e3) / 1e12
+    return {"workload": "aniso3d 257^3, 8 balls r=0.04, 128 Fibonacci controls, SPD M "
+                        "(cond 4), ISA (RA on 65^3) to sup-res<1e-6",
+            "time_to_converge_ms": ms, "node_control_updates_per_s": nc / (ms / 1e3),
+            "sweeps": int(np.mean([x["sweeps_max"] for x in sts])),
+            "ms_reconstruct": float(np.mean([x["ms_ra"] for x in sts])),
+            "set_fraction_max": float(np.mean([x["set_fraction_max"] for x in sts])),
+            "sweep_ms_per_launch": ms_launch, "valu_tops": ach, "valu_frac": ach / PEAK_VALU_TOPS,
+            "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"]}
+
+
+def leg_c4(steps: int):
+    """512 independent 2D problems (sides 16..512): one batched solve vs one
+    solve call per problem."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    probs = W.c4_batch()
+    dps = [S.to_device(p, torch.float32, "cuda:0") for p in probs]
+    ras = [S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q) for p in probs]
+    opts = S.SolveOpts(tol=1e-6, autotune=2)
+    S.solve_batched(dps, ras, opts)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = S.solve_batched(dps, ras, opts)
+    _sync()
+    ms_b = (time.perf_counter() - t0) / steps * 1e3
+    tot = out[-1]
+    t0 = time.perf_counter()
+    single = S.SolveOpts(tol=1e-6)
+    for dp, ra in zip(dps, ras):
+        S.isa(dp, ra, single)
+    _sync()
+    ms_single = (time.perf_counter() - t0) * 1e3
+    return {"workload": "512 problems, sides log-uniform in [16,512], 1-6 disks, 32 controls, "
+                        "ISA each, sup-res<1e-6",
+            "total_nodes": int(sum(p.N for p in probs)),
+            "batched_ms": ms_b, "per_problem_calls_ms": ms_single,
+            "batched_speedup": ms_single / ms_b, "sweeps_max": int(tot["sweeps_max"]),
+            "tile": list(tot["tile"]), "schedule": tot["mode"],
+            "node_control_updates_per_s": tot["node_control_updates"] / (ms_b / 1e3)}
+
+
+def leg_c5(steps: int):
+    """Adjoint 513^2: loss sum (V - V_obs)^2 on 2000 nodes, l = exp(theta); ISA
+    forward with the policy exported, then the adjoint (sets frozen)."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    p = W.c5_adjoint()
+    dp = S.to_device(p, torch.float32, "cuda:0")
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q)
+    member, label, _ = S.reconstruct(dp, ra)
+    th_true = torch.as_tensor(p.meta["theta_true"], dtype=torch.float32, device="cuda:0")
+    fwd_opts = S.SolveOpts(tol=1e-6, autotune=1)
+    V_obs = S.HJBSolve.apply(torch.exp(th_true), dp, member, ra, fwd_opts)
+    obs = torch.as_tensor(p.meta["obs"], device="cuda:0")
+    V_obs = V_obs[obs].detach()
+    theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device="cuda:0")
+
+    def fwd_bwd():
+        th = theta.clone().requires_grad_(True)
+        V = S.HJBSolve.apply(torch.exp(th), dp, member, ra, fwd_opts)
+        loss = ((V[obs] - V_obs) ** 2).sum()
+        _sync()
+        t1 = time.perf_counter()
+        loss.backward()
+        _sync()
+        return time.perf_counter() - t1, th.grad
+
+    fwd_bwd()
+    t0 = time.perf_counter()
+    t_bwd = 0.0
+    for _ in range(steps):
+        tb, g = fwd_bwd()
+        t_bwd += tb
+    _sync()
+    t_all = (time.perf_counter() - t0) / steps
+    t_bwd /= steps
+    return {"workload": "adjoint 513^2, 4 targets, l = exp(theta), theta ~ N(0, 0.1^2), "
+                        "2000 observations, ISA forward (sets frozen), sup-res<1e-6",
+            "forward_ms": (t_all - t_bwd) * 1e3, "adjoint_ms": t_bwd * 1e3,
+            "adjoint_over_forward": t_bwd / (t_all - t_bwd),
+            "grads_per_s": 1.0 / t_all, "adjoint_only_per_s": 1.0 / t_bwd}
 
 
 def cpu_baseline(prob, budget_s: float):
@@ -87,7 +203,9 @@ def main():
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
     ra = S.RaOpts(coarse_stride=prob.coarse_stride, C=prob.ra_C, M=prob.ra_M, q=prob.ra_q)
-    opts = S.SolveOpts(tol=1e-6, profile=True)
+    # the warm-up step runs the autotuner (complete solves as trials); the
+    # timed steps use its cached pick
+    opts = S.SolveOpts(tol=1e-6, profile=True, autotune=2)
 
     def step():
         return S.isa(dp, ra, opts)
@@ -147,13 +265,24 @@ def main():
             "unit": "T VALU lane-ops/s",
             "frac": achieved / PEAK_VALU_TOPS,
             "traffic": None,
-            "kernel": "k_sweep2d<float,64,16,H>",
+            "kernel": f"k_sweep2d<float,{stats[0]['tile'][0]},{stats[0]['tile'][1]},H> "
+                      f"(schedule {stats[0]['mode']})",
             "ms_per_launch": ms_launch,
             "node_controls_per_launch": nc_per_launch,
             "hbm_gbs_algorithmic": hbm_gbs,
             "hbm_frac_algorithmic": hbm_gbs / PEAK_HBM_GBS,
         },
     }
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x]:
+        fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5}[leg]
+        t0 = time.perf_counter()
+        legs[leg] = fn(max(1, min(args.steps, 3)))
+        print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    if legs:
+        res["legs"] = legs
+    if "c5" in legs:
+        res["adjoint_grads_per_s"] = legs["c5"]["grads_per_s"]
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -94,6 +94,11 @@ typedef struct sl_solve_opts {
     int want_policy;          /* write the first minimising control index per node   */
     int check_every;          /* sweeps between host convergence polls (0 = default 32) */
     int profile;              /* 1: time the sweep launches with HIP events (stats.ms_sweeps) */
+    int autotune;             /* 0: default kernel; 1: on the first call with a new shape,
+                                 time the first 96 sweeps of every (tile shape, schedule)
+                                 candidate and cache the fastest; 2: same with complete
+                                 solves as trials; -k: use candidate k-1 (testing aid,
+                                 k <= sl_tune_candidates(dim, dtype))                    */
 } sl_solve_opts;
 
 /* Per-call statistics (HOST struct filled at the end of a call). */
@@ -108,10 +113,16 @@ typedef struct sl_stats {
     double set_fraction_max;  /* max_i |Sigma_i| / N on the fine grid (ISA calls)     */
     double ms_sweeps;         /* profile: HIP-event time spanning the sweep launches  */
     long sweep_launches;      /* profile: number of sweep launches timed              */
+    int variant;              /* sweep kernel variant used (tile shape)               */
+    int mode;                 /* work schedule used: 0 per item, 1 queue, 2 stride    */
+    int tile[3];              /* tile shape used                                      */
 } sl_stats;
 
 const char *sl_status_string(int status);
 int sl_abi_version(void);
+/* Number of sweep-kernel configurations (tile shape x work schedule) the
+ * autotuner chooses from for (dim, dtype); 0 if unsupported. */
+int sl_tune_candidates(int dim, int dtype);
 
 /* Workspace bytes needed by sl_solve for problem `p` (0 if `p` is invalid). */
 size_t sl_solve_workspace_size(const sl_problem *p);

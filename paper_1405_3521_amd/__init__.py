@@ -55,7 +55,7 @@ class SlRaOpts(C.Structure):
 
 class SlSolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_sweeps", C.c_long), ("want_policy", C.c_int),
-                ("check_every", C.c_int), ("profile", C.c_int)]
+                ("check_every", C.c_int), ("profile", C.c_int), ("autotune", C.c_int)]
 
 
 class SlStats(C.Structure):
@@ -63,10 +63,14 @@ class SlStats(C.Structure):
                 ("node_control_updates", C.c_double), ("ms_ra", C.c_double),
                 ("ms_fine", C.c_double), ("ms_total", C.c_double), ("n_subdomains", C.c_int),
                 ("n_unreachable", C.c_int), ("set_fraction_max", C.c_double),
-                ("ms_sweeps", C.c_double), ("sweep_launches", C.c_long)]
+                ("ms_sweeps", C.c_double), ("sweep_launches", C.c_long), ("variant", C.c_int),
+                ("mode", C.c_int), ("tile", C.c_int * 3)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["tile"] = tuple(self.tile)
+        return d
+
 
 
 def lib_path() -> str:
@@ -84,6 +88,8 @@ def lib():
         L.sl_status_string.argtypes = [C.c_int]
         L.sl_status_string.restype = C.c_char_p
         L.sl_abi_version.restype = C.c_int
+        L.sl_tune_candidates.argtypes = [C.c_int, C.c_int]
+        L.sl_tune_candidates.restype = C.c_int
         L.sl_solve_workspace_size.argtypes = [P(SlProblem)]
         L.sl_solve_workspace_size.restype = C.c_size_t
         L.sl_solve.argtypes = [P(SlProblem), P(SlSolveOpts), C.c_void_p, C.c_size_t, C.c_void_p,
@@ -167,6 +173,7 @@ class SolveOpts:
     want_policy: bool = False
     check_every: int = 0
     profile: bool = False
+    autotune: int = 0
 
 
 def to_device(prob, dtype=None, device: str = "cuda:0") -> DeviceProblem:
@@ -242,7 +249,7 @@ def _ra(o: RaOpts) -> SlRaOpts:
 
 def _so(o: SolveOpts) -> SlSolveOpts:
     return SlSolveOpts(o.tol, o.max_sweeps, int(bool(o.want_policy)), o.check_every,
-                       int(bool(o.profile)))
+                       int(bool(o.profile)), int(o.autotune))
 
 
 def _workspace(nbytes: int, device):

@@ -13,7 +13,10 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 using namespace slhjb;
@@ -76,6 +79,7 @@ int validate_solve_opts(const sl_solve_opts *o) {
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return SL_ERR_INVALID_ARG;
     if (o->max_sweeps < 1 || o->max_sweeps > 100000000L) return SL_ERR_INVALID_ARG;
     if (o->check_every < 0) return SL_ERR_INVALID_ARG;
+    if (o->autotune > 2) return SL_ERR_INVALID_ARG;
     return SL_OK;
 }
 
@@ -126,6 +130,8 @@ int halo_for(double speed_max, double emax) {
     return (int)std::floor(D * (1.0 + 1e-6) + 1e-3) + 1;
 }
 
+int max_halo(int dim) { return dim == 2 ? kMaxHalo : kMaxHalo3D; }
+
 int default_variant(int dim, int dtype) {
     if (dim == 2) return dtype == SL_F32 ? 0 : 4;
     return dtype == SL_F32 ? 5 : 8;
@@ -138,6 +144,7 @@ LaunchCfg make_cfg(int dim, int dtype, int halo, int variant) {
     for (int i = 0; i < nv && i < 16; ++i)
         if (all[i].variant == variant) c = all[i];
     c.halo = halo;
+    c.mode = 0;
     return c;
 }
 
@@ -228,6 +235,56 @@ struct ChunkLoop {
     }
 };
 
+// ------------------------------------------------------------------ autotuner
+// Kernel configurations are chosen per problem shape by timing candidates on
+// the caller's problem; the winner is cached for the life of the process.
+struct TuneKey {
+    int dim, dtype, m, halo, nsd, size_class;
+    bool operator<(const TuneKey &o) const {
+        const int a[6] = {dim, dtype, m, halo, nsd, size_class};
+        const int b[6] = {o.dim, o.dtype, o.m, o.halo, o.nsd, o.size_class};
+        return std::lexicographical_compare(a, a + 6, b, b + 6);
+    }
+};
+std::map<TuneKey, std::pair<int, int>> &tune_cache() {
+    static std::map<TuneKey, std::pair<int, int>> c;
+    return c;
+}
+std::mutex &tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo) {
+    LaunchCfg all[16];
+    const int nv = sweep_variants(dim, all, 16);
+    std::vector<LaunchCfg> out;
+    for (int i = 0; i < nv && i < 16; ++i) {
+        if (all[i].dtype != dtype) continue;
+        for (int mode = 0; mode < 3; ++mode) {
+            LaunchCfg c = all[i];
+            c.halo = halo;
+            c.mode = mode;
+            out.push_back(c);
+        }
+    }
+    return out;
+}
+
+// Most tiles any variant of (dim, dtype) needs on a grid of n nodes.
+int max_tiles(int dim, int dtype, const int *n) {
+    LaunchCfg all[16];
+    const int nv = sweep_variants(dim, all, 16);
+    int best = 1;
+    for (int i = 0; i < nv && i < 16; ++i) {
+        if (all[i].dtype != dtype) continue;
+        int tot = 1;
+        for (int d = 0; d < dim; ++d) tot *= (n[d] + all[i].tile[d] - 1) / all[i].tile[d];
+        best = std::max(best, tot);
+    }
+    return best;
+}
+
 // --------------------------------------------------------------- executor
 template <typename T>
 struct Exec {
@@ -237,6 +294,7 @@ struct Exec {
     WorkItem *items = nullptr;      // device
     ExecCounters *cnt = nullptr;    // device
     int *prefix = nullptr;          // device
+    uint8_t *changed = nullptr;     // device, 2 * tiles: per-tile change flags
     int n_sd = 0;
     int total_tiles = 0;
     std::vector<SdDesc<T>> host_sds;
@@ -248,6 +306,7 @@ struct Exec {
         items = a.take<WorkItem>(tiles_total > 0 ? tiles_total : 1);
         cnt = a.take<ExecCounters>(1);
         prefix = a.take<int>(nsd);
+        changed = a.take<uint8_t>(2 * (size_t)(tiles_total > 0 ? tiles_total : 1));
     }
 
     static int tiles_of(const LaunchCfg &cfg, const int *n, int dim, int *t) {
@@ -288,6 +347,7 @@ struct Exec {
         HIPCHK(hipMemcpyAsync(prefix, host_prefix.data(), sizeof(int) * n_sd,
                               hipMemcpyHostToDevice, s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(ExecCounters), s));
+        HIPCHK(hipMemsetAsync(changed, 0, 2 * (size_t)(total_tiles > 0 ? total_tiles : 1), s));
         HIPCHK(launch_build_items(cfg, sds, n_sd, total_tiles, prefix, items, cnt, s));
         HIPCHK(sweep_set_attributes(cfg));
         return SL_OK;
@@ -309,8 +369,8 @@ struct Exec {
         const int chunk = check_every > 0 ? check_every : 32;
         auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
             for (int i = 0; i < todo; ++i) {
-                const hipError_t e =
-                    launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, i, tol, 0, q);
+                const hipError_t e = launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, i,
+                                                  tol, 0, changed, total_tiles, q);
                 if (e != hipSuccess) return e;
             }
             hipError_t e = launch_bookkeep(st, n_sd, todo, tol, cnt, 0, q, 0.0, todo);
@@ -326,11 +386,90 @@ struct Exec {
         sweep_launches += loop.launches;
         HIPCHK(launch_bookkeep(st, n_sd, 0, tol, cnt, 1, s));
         if (want_policy) {
-            HIPCHK(launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, 0, tol, 1, s));
+            HIPCHK(launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, 0, tol, 1, changed,
+                                total_tiles, s));
             HIPCHK(launch_flip(st, n_sd, s));
         }
         *sweeps_done = S;
         return status;
+    }
+
+    void retile() {
+        for (auto &d : host_sds) tiles_of(cfg, d.n, cfg.dim, d.tiles);
+    }
+
+    // Initial values (reinit(stream)), descriptors, work list and the sweeps,
+    // with the kernel configuration taken from the tuner when autotune > 0.
+    template <class Reinit>
+    int solve_tuned(int autotune, Reinit reinit, double tol, long max_sweeps, int check_every,
+                    int want_policy, hipStream_t s, long *sweeps_done, int profile) {
+        if (autotune < 0) {                  // forced candidate (testing)
+            const std::vector<LaunchCfg> cands = tune_candidates(cfg.dim, cfg.dtype, cfg.halo);
+            const int k = -autotune - 1;
+            if (k >= (int)cands.size()) return SL_ERR_INVALID_ARG;
+            cfg = cands[k];
+        }
+        if (autotune > 0) {
+            long nodes = 0;
+            for (const auto &d : host_sds) nodes += (long)d.n[0] * d.n[1] * d.n[2];
+            int sc = 0;
+            while ((1L << sc) < nodes) ++sc;
+            const TuneKey key{cfg.dim, cfg.dtype, host_sds.empty() ? 0 : host_sds[0].m, cfg.halo,
+                              (int)host_sds.size(), sc};
+            bool found = false;
+            std::pair<int, int> pick;
+            {
+                std::lock_guard<std::mutex> lk(tune_mutex());
+                auto it = tune_cache().find(key);
+                if (it != tune_cache().end()) {
+                    found = true;
+                    pick = it->second;
+                }
+            }
+            if (!found) {
+                const std::vector<LaunchCfg> cands = tune_candidates(cfg.dim, cfg.dtype, cfg.halo);
+                hipEvent_t e0, e1;
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                double best = 1e300;
+                pick = {cfg.variant, cfg.mode};
+                const long trial = autotune == 1 ? std::min<long>(96, max_sweeps) : max_sweeps;
+                for (const LaunchCfg &c : cands) {
+                    cfg = c;
+                    retile();
+                    HIPCHK(reinit(s));
+                    int rc = prepare(s);
+                    if (rc) return rc;
+                    HIPCHK(hipEventRecord(e0, s));
+                    long Sx = 0;
+                    rc = run(tol, trial, check_every, 0, s, &Sx, 0);
+                    if (rc < 0) return rc;
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    const double score = autotune == 1 ? ms / std::max<long>(Sx, 1) : ms;
+                    if (score < best) {
+                        best = score;
+                        pick = {c.variant, c.mode};
+                    }
+                }
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                std::lock_guard<std::mutex> lk(tune_mutex());
+                tune_cache()[key] = pick;
+            }
+            const int halo = cfg.halo;
+            cfg = make_cfg(cfg.dim, cfg.dtype, halo, pick.first);
+            cfg.mode = pick.second;
+            ms_sweeps = 0.0;
+            sweep_launches = 0;
+        }
+        retile();
+        HIPCHK(reinit(s));
+        int rc = prepare(s);
+        if (rc) return rc;
+        return run(tol, max_sweeps, check_every, want_policy, s, sweeps_done, profile);
     }
 
     int read_stats(hipStream_t s, std::vector<SdState> &out, unsigned long long *nc) {
@@ -364,6 +503,13 @@ void fill_stats(sl_stats *stats, const std::vector<SdState> &hs, unsigned long l
     stats->node_control_updates = (double)nc;
     stats->n_subdomains = (int)hs.size();
     stats->n_unreachable = 0;
+}
+
+void fill_cfg(sl_stats *stats, const LaunchCfg &c) {
+    if (!stats) return;
+    stats->variant = c.variant;
+    stats->mode = c.mode;
+    for (int d = 0; d < 3; ++d) stats->tile[d] = c.tile[d];
 }
 
 struct Timer {
@@ -419,9 +565,8 @@ template <typename T>
 int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **ctrl,
                 FieldStats **fs, int variant) {
     const size_t N = nodes_of(p);
-    const LaunchCfg cfg = make_cfg(p->dim, p->dtype, 1, variant);
-    int t[3];
-    const int tiles = Exec<T>::tiles_of(cfg, p->n, p->dim, t);
+    (void)variant;
+    const int tiles = max_tiles(p->dim, p->dtype, p->n);
     Vb[0] = a.take<T>(N);
     Vb[1] = a.take<T>(N);
     *wl = p->cost ? a.take<T>(N) : nullptr;
@@ -457,16 +602,21 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     control_table(p, p->n, p->h, e, &emax);
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
     const int H = halo_for(smax, emax);
-    if (H > kMaxHalo) return SL_ERR_UNSUPPORTED;
+    if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     ex.cfg = make_cfg(p->dim, p->dtype, H, variant);
 
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
     if (p->cost) HIPCHK((launch_scale_field<T, T>((const T *)p->cost, wl, N, w, s)));
-    for (int b = 0; b < 2; ++b)
-        HIPCHK(launch_init_values<T>(Vb[b], p->target, (const T *)p->g, (T)p->v_ghost, -1, N, s));
-
+    auto reinit = [&](hipStream_t q) -> hipError_t {
+        for (int b = 0; b < 2; ++b) {
+            const hipError_t e = launch_init_values<T>(Vb[b], p->target, (const T *)p->g,
+                                                       (T)p->v_ghost, -1, N, q);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     SdDesc<T> d{};
     d.V[0] = Vb[0];
     d.V[1] = Vb[1];
@@ -486,12 +636,11 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     Exec<T>::tiles_of(ex.cfg, p->n, p->dim, d.tiles);
     d.halo = H;
     ex.host_sds.push_back(d);
-    if ((rc = ex.prepare(s))) return rc;
     if (o->want_policy && policy) HIPCHK(hipMemsetAsync(policy, 0xFF, N, s));
     tm.mark(1, s);
     long S = 0;
-    const int status = ex.run(o->tol, o->max_sweeps, o->check_every, o->want_policy && policy, s, &S,
-                              o->profile);
+    const int status = ex.solve_tuned(o->autotune, reinit, o->tol, o->max_sweeps, o->check_every,
+                                      o->want_policy && policy, s, &S, o->profile);
     if (status < 0) return status;
     HIPCHK(launch_copy_final<T>(ex.sds, ex.st, 0, V, N, s));
     tm.mark(2, s);
@@ -507,6 +656,7 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
         stats->ms_sweeps = ex.ms_sweeps;
         stats->sweep_launches = ex.sweep_launches;
     }
+    fill_cfg(stats, ex.cfg);
     return status;
 }
 
@@ -571,8 +721,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     P.lbK = a.take<uint8_t>(cg.NK);
     P.fsK = a.take<FieldStats>(1);
     P.exK.reserve(a, nc, tilesK * nc);
-    const LaunchCfg cfg = make_cfg(p->dim, p->dtype, 1, default_variant(p->dim, p->dtype));
-    const int tiles = Exec<T>::tiles_of(cfg, p->n, p->dim, t);
+    const int tiles = max_tiles(p->dim, p->dtype, p->n);
     P.Vf = a.take<T>((size_t)nc * 2 * N);
     P.wl = p->cost ? a.take<T>(N) : nullptr;
     P.ctrl = a.take<T>((size_t)p->m * p->dim);
@@ -640,7 +789,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     HIPCHK(hipMemcpyAsync(P.ctrlK, e.data(), sizeof(double) * e.size(), hipMemcpyHostToDevice, s));
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
     const int HK = halo_for(smax, emaxK);
-    if (HK > kMaxHalo) return SL_ERR_UNSUPPORTED;
+    if (HK > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.exK.cfg = make_cfg(p->dim, SL_F64, HK, default_variant(p->dim, SL_F64));
     for (int i = 0; i < nc; ++i) {
         double *V0 = P.Vaux + (size_t)i * 2 * cg.NK;
@@ -726,17 +875,24 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     control_table(p, p->n, p->h, e, &emax);
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
     const int H = halo_for(smax, emax);
-    if (H > kMaxHalo) return SL_ERR_UNSUPPORTED;
+    if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.ex.cfg = make_cfg(p->dim, p->dtype, H, default_variant(p->dim, p->dtype));
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(P.ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
     if (p->cost) HIPCHK((launch_scale_field<T, T>((const T *)p->cost, P.wl, N, w, s)));
+    auto reinit = [&](hipStream_t q) -> hipError_t {
+        for (int i = 0; i < nc; ++i)
+            for (int b = 0; b < 2; ++b) {
+                const hipError_t e =
+                    launch_init_values<T>(P.Vf + (size_t)i * 2 * N + b * N, p->target,
+                                          (const T *)p->g, (T)p->v_ghost, -1, N, q);
+                if (e != hipSuccess) return e;
+            }
+        return hipSuccess;
+    };
     for (int i = 0; i < nc; ++i) {
         T *V0 = P.Vf + (size_t)i * 2 * N;
-        for (int b = 0; b < 2; ++b)
-            HIPCHK(launch_init_values<T>(V0 + b * N, p->target, (const T *)p->g, (T)p->v_ghost,
-                                         -1, N, s));
         SdDesc<T> d{};
         d.V[0] = V0;
         d.V[1] = V0 + N;
@@ -756,12 +912,12 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
         d.halo = H;
         P.ex.host_sds.push_back(d);
     }
-    if ((rc = P.ex.prepare(s))) return rc;
     if (o->want_policy && policy) HIPCHK(hipMemsetAsync(policy, 0xFF, (size_t)nc * N, s));
     tm.mark(1, s);
     long S = 0;
-    const int status = P.ex.run(o->tol, o->max_sweeps, o->check_every, o->want_policy && policy,
-                                s, &S, o->profile);
+    const int status = P.ex.solve_tuned(o->autotune, reinit, o->tol, o->max_sweeps,
+                                        o->check_every, o->want_policy && policy, s, &S,
+                                        o->profile);
     if (status < 0) return status;
     tm.mark(2, s);
     HIPCHK(launch_assemble<T>(P.ex.sds, P.ex.st, nc, member, N, (T)p->v_ghost, V, owner, s));
@@ -787,6 +943,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
         stats->ms_sweeps = P.ex.ms_sweeps;
         stats->sweep_launches = P.ex.sweep_launches;
     }
+    fill_cfg(stats, P.ex.cfg);
     return status;
 }
 
@@ -930,7 +1087,6 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
                  uint8_t *const *label, uint8_t *const *owner, Arena &a, BatchPlan<T> &B) {
     const int dim = probs[0].dim;
     const LaunchCfg cfgK = make_cfg(dim, SL_F64, 1, default_variant(dim, SL_F64));
-    const LaunchCfg cfg = make_cfg(dim, probs[0].dtype, 1, default_variant(dim, probs[0].dtype));
     B.hp.assign(np, ProbDesc<T>{});
     B.hblk_N.assign(np + 1, 0);
     B.hblk_NK.assign(np + 1, 0);
@@ -965,7 +1121,7 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
         d.wl = p->cost ? a.take<T>(d.N) : nullptr;
         int t[3];
         tilesK += Exec<double>::tiles_of(cfgK, cg.nK, dim, t) * p->n_comp;
-        tiles += Exec<T>::tiles_of(cfg, p->n, dim, t) * p->n_comp;
+        tiles += max_tiles(dim, p->dtype, p->n) * p->n_comp;
         d.sd_coarse0 = nsd;
         d.sd_fine0 = nsd;
         nsd += p->n_comp;
@@ -1055,7 +1211,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         for (double x : e) ctrl.push_back((T)x);
         for (double x : eK) ctrlK.push_back(x);
     }
-    if (H > kMaxHalo || HK > kMaxHalo) return SL_ERR_UNSUPPORTED;
+    if (H > max_halo(dim) || HK > max_halo(dim)) return SL_ERR_UNSUPPORTED;
     HIPCHK(hipMemcpyAsync(B.ctrlK, ctrlK.data(), sizeof(double) * ctrlK.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(B.ctrl, ctrl.data(), sizeof(T) * ctrl.size(), hipMemcpyHostToDevice, s));
     // 2. coarse data, placement of missing components, auxiliary initial values
@@ -1097,7 +1253,10 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     if (stK < 0) return stK;
     // 4. RA steps 2-3, projection, fine initial values
     HIPCHK(launch_batched<T>(kBatchCombine, B.pd, np, B.blk_NK, B.hblk_NK[np], kChunk, B.exK.sds, B.exK.st, s));
-    HIPCHK(launch_batched<T>(kBatchProjectInit, B.pd, np, B.blk_N, B.hblk_N[np], kChunk, nullptr, nullptr, s));
+    auto reinit = [&](hipStream_t q) -> hipError_t {
+        return launch_batched<T>(kBatchProjectInit, B.pd, np, B.blk_N, B.hblk_N[np], kChunk,
+                                 nullptr, nullptr, q);
+    };
     tm.mark(1, s);
     // 5. ISA step 3 for every (problem, set): one launch per sweep
     B.ex.cfg = make_cfg(dim, probs[0].dtype, H, default_variant(dim, probs[0].dtype));
@@ -1128,9 +1287,9 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         }
         coff += (size_t)p->m * dim;
     }
-    if ((rc = B.ex.prepare(s))) return rc;
     long S = 0;
-    const int status = B.ex.run(o->tol, o->max_sweeps, o->check_every, 0, s, &S, o->profile);
+    const int status = B.ex.solve_tuned(o->autotune, reinit, o->tol, o->max_sweeps,
+                                        o->check_every, 0, s, &S, o->profile);
     if (status < 0) return status;
     tm.mark(2, s);
     // 6. ISA step 4 for every problem
@@ -1161,6 +1320,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         total->ms_sweeps = B.ex.ms_sweeps;
         total->sweep_launches = B.ex.sweep_launches;
     }
+    fill_cfg(total, B.ex.cfg);
     return status == SL_OK && stK == SL_OK ? SL_OK : SL_NOT_CONVERGED;
 }
 
@@ -1196,6 +1356,11 @@ const char *sl_status_string(int status) {
 }
 
 int sl_abi_version(void) { return SLHJB_ABI_VERSION; }
+
+int sl_tune_candidates(int dim, int dtype) {
+    if ((dim != 2 && dim != 3) || (dtype != SL_F32 && dtype != SL_F64)) return 0;
+    return (int)tune_candidates(dim, dtype, 1).size();
+}
 
 size_t sl_solve_workspace_size(const sl_problem *p) {
     if (validate(p) != SL_OK) return 0;

@@ -54,19 +54,23 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-__device__ __forceinline__ void block_max_to(double v, unsigned long long *dst) {
+// Block max of v, folded into *dst (FP64 bit pattern, atomicMax); returns the
+// block max on thread 0 (0 elsewhere).
+__device__ __forceinline__ double block_max_to(double v, unsigned long long *dst) {
     __shared__ double red[kThreads / 64];
     __syncthreads();                    // a previous call's reader is done with red[]
     v = wave_max(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
+    double m = 0.0;
     if (threadIdx.x == 0) {
-        double m = red[0];
+        m = red[0];
 #pragma unroll
         for (int i = 1; i < kThreads / 64; ++i) m = red[i] > m ? red[i] : m;
         if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
     }
+    return m;
 }
 
 __device__ __forceinline__ void block_sum_to(unsigned v, unsigned long long *dst) {
@@ -122,7 +126,20 @@ __device__ void bookkeep_block(SdState *st, int n_sd, int sweep, double tol,
         s.scale[(sweep + 1) % 3] = 0ull;
     }
     __syncthreads();
-    if (threadIdx.x == 0) cnt->n_active = active;
+    if (threadIdx.x == 0) {
+        cnt->n_active = active;
+        cnt->queue[(sweep + 1) % 3] = 0;    // work queue of the next sweep
+    }
+}
+
+// Next work item of this sweep for the whole work-group (dynamic queue: one
+// atomic per item, broadcast through LDS).
+__device__ __forceinline__ int next_item(ExecCounters *cnt, int slot) {
+    __shared__ int s_item;
+    __syncthreads();                    // everyone has read the previous s_item
+    if (threadIdx.x == 0) s_item = atomicAdd(&cnt->queue[slot], 1);
+    __syncthreads();
+    return s_item;
 }
 
 // Should work items of this sd be skipped at `sweep`?  Reads only data finished

@@ -19,7 +19,8 @@
 
 namespace slhjb {
 
-constexpr int kMaxHalo = 8;            // largest supported halo (cells)
+constexpr int kMaxHalo = 16;           // largest supported halo (cells), 2D
+constexpr int kMaxHalo3D = 8;          // largest supported halo (cells), 3D
 constexpr int kThreads = 256;          // threads per sweep work-group (4 waves)
 
 // Per-sub-domain description (device memory, read-only during a sweep).
@@ -65,6 +66,8 @@ struct ExecCounters {
     unsigned long long nc_updates;  // node*control evaluations
     int sweep_base;             // index of the first sweep of the current chunk
     int pad;
+    int queue[3];               // per-sweep work-queue heads (slot = sweep % 3)
+    int pad2;
 };
 
 // Input statistics gathered on the device in one pass (see launch_field_stats).
@@ -135,23 +138,29 @@ struct LaunchCfg {
     int tile[3];                // tile shape
     int halo;                   // H
     int variant;                // kernel variant id (autotuner)
+    int grid_cap;               // resident work-groups (persistent grid), 0 = unset
+    int mode;                   // 0: one work-group per item; 1: resident grid + atomic
+                                // work queue; 2: resident grid + static grid stride
 };
 
 // ---- launchers (sweep.hip) -------------------------------------------------
 // One Jacobi sweep over all work items.  The sweep index is
 // cnt->sweep_base + sweep_rel (device-resident base, so a captured chunk of
 // launches can be replayed).
+// `changed`: 2 * flag_stride per-tile change flags (parity of the sweep).
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
                         const WorkItem *items, ExecCounters *cnt, int max_items,
-                        int sweep_rel, double tol, int want_policy, hipStream_t s);
+                        int sweep_rel, double tol, int want_policy, uint8_t *changed,
+                        int flag_stride, hipStream_t s);
 // Bookkeeping before sweep cnt->sweep_base + sweep_rel (marks sds converged,
 // resets slots, counts active sds); `final_pass` also settles final_buf of
 // unconverged sds; afterwards sweep_base += advance.
 hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol,
                            ExecCounters *cnt, int final_pass, hipStream_t s,
                            double scale_rel = 0.0, int advance = 0);
-// Dynamic-LDS attributes of the kernels of `cfg` (call before graph capture).
-hipError_t sweep_set_attributes(const LaunchCfg &cfg);
+// Dynamic-LDS attributes of the kernels of `cfg` (call before graph capture);
+// sets cfg.grid_cap to the number of resident work-groups.
+hipError_t sweep_set_attributes(LaunchCfg &cfg);
 // Supported tile shapes per (dim) for the autotuner; returns count.
 int sweep_variants(int dim, LaunchCfg *out, int cap);
 

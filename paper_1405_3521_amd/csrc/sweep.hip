@@ -22,146 +22,199 @@
 //     one 64-bit atomicMax per work-group on the bit pattern).
 #include "device_common.h"
 
+#include <algorithm>
+
 namespace slhjb {
 
 namespace {
 
+// Active-tile test (exact skipping).  With Jacobi double buffering, if no node
+// of the tiles that a tile's halo reaches changed in sweep s-1, the tile's new
+// values equal its old ones, and the output buffer already holds them (it holds
+// the iterate of sweep s-1, equal to that of sweep s).  `prev` holds the flags
+// written in sweep s-1 (1 = some node of the tile changed).
+template <int RX, int RY, int RZ>
+__device__ __forceinline__ bool neighbourhood_changed(const uint8_t *prev, int off, const int *t,
+                                                      const int *nt) {
+    bool any = false;
+    for (int dz = -RZ; dz <= RZ; ++dz) {
+        const int z = t[2] + dz;
+        if (z < 0 || z >= nt[2]) continue;
+        for (int dy = -RY; dy <= RY; ++dy) {
+            const int y = t[1] + dy;
+            if (y < 0 || y >= nt[1]) continue;
+            for (int dx = -RX; dx <= RX; ++dx) {
+                const int x = t[0] + dx;
+                if (x < 0 || x >= nt[0]) continue;
+                any |= prev[off + (z * nt[1] + y) * nt[0] + x] != 0;
+            }
+        }
+    }
+    return any;
+}
+
 // ------------------------------------------------------------------ 2D kernel
+// Persistent: a resident grid of work-groups takes work items from a per-sweep
+// atomic queue until the list is exhausted.
 template <typename T, int TX, int TY, int H, bool POLICY>
 __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
                                                       ExecCounters *__restrict__ cnt,
-                                                      int sweep_rel, double tol) {
+                                                      int sweep_rel, double tol,
+                                                      uint8_t *__restrict__ changed,
+                                                      int flag_stride, int mode) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
     constexpr int RSTEP = kThreads / TX;
     constexpr int NPT = TY / RSTEP;
+    constexpr int RX = (H + TX - 1) / TX, RY = (H + TY - 1) / TY;
     static_assert(kThreads % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
     __shared__ T lds[LW * LH];
 
     if (!POLICY && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
-    if ((int)blockIdx.x >= cnt->n_items) return;
-    const WorkItem it = items[blockIdx.x];
-    SdState *sst = st + it.sd;
-    if (!POLICY && sd_skip(sst, sweep, tol)) return;
-    const SdDesc<T> &d = sds[it.sd];
-    const int n0 = d.n[0], n1 = d.n[1];
-    const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
-    const int src = POLICY ? sst->final_buf : (sweep & 1);
-    const T *__restrict__ Vin = d.V[src];
-    T *__restrict__ Vout = d.V[src ^ 1];
-    const uint8_t *__restrict__ mem = d.member;
-    const int bit = d.bit;
-    const T G = d.G;
-
-    for (int q = threadIdx.x; q < LW * LH; q += kThreads) {
-        const int ly = q / LW;
-        const int lx = q - ly * LW;
-        const int gx = x0 - H + lx, gy = y0 - H + ly;
-        T v = G;
-        if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1) {
-            const size_t j = (size_t)gy * n0 + gx;
-            if (!mem || ((mem[j] >> bit) & 1)) v = Vin[j];
-        }
-        lds[q] = v;
-    }
-    __syncthreads();
-
+    const int n_items = cnt->n_items;
+    const uint8_t *prev = changed + (size_t)((sweep + 1) & 1) * flag_stride;
+    uint8_t *cur = changed + (size_t)(sweep & 1) * flag_stride;
     const int tx = threadIdx.x % TX;
     const int ty0 = threadIdx.x / TX;
-    const int gx = x0 + tx;
-    T c[NPT], ux0[NPT], uy0[NPT], wl[NPT], best[NPT];
-    int arg[NPT];
-    bool act[NPT];
-    int any = 0;
-#pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        const int ty = ty0 + r * RSTEP;
-        const int gy = y0 + ty;
-        act[r] = false;
-        c[r] = T(0);                        // inactive lanes: foot = own node
-        wl[r] = d.wl_const;
-        if (gx < n0 && gy < n1) {
-            const size_t j = (size_t)gy * n0 + gx;
-            const bool inset = !mem || ((mem[j] >> bit) & 1);
-            act[r] = inset && d.target[j] < 0;
-            if (act[r]) {
-                c[r] = d.speed ? d.speed[j] : T(1);
-                if (d.wl) wl[r] = d.wl[j];
-            }
-        }
-        any |= act[r];
-        if (sizeof(T) == 4) {
-            ux0[r] = (T)(tx + H);
-            uy0[r] = (T)(ty + H);
-        } else {
-            ux0[r] = (T)gx;
-            uy0[r] = (T)gy;
-        }
-        best[r] = (T)INFINITY;
-        arg[r] = 0;
-    }
-    const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
-    const T beta = d.beta;
-    const T *__restrict__ ctrl = d.ctrl;
-    const int m = d.m;
-    if (__any(any)) {
-        for (int k = 0; k < m; ++k) {
-            const T ex = ctrl[2 * k], ey = ctrl[2 * k + 1];
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                T ux, uy;
-                if (sizeof(T) == 4) {
-                    ux = fma_(c[r], ex, ux0[r]);
-                    uy = fma_(c[r], ey, uy0[r]);
-                } else {
-                    ux = ux0[r] + ex * c[r];
-                    uy = uy0[r] + ey * c[r];
-                }
-                int ix, iy;
-                T fx, fy;
-                Foot<T>::split(ux, ox, ix, fx);
-                Foot<T>::split(uy, oy, iy, fy);
-                const int base = iy * LW + ix;
-                const T v00 = lds[base], v10 = lds[base + 1];
-                const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
-                const T ax = T(1) - fx, ay = T(1) - fy;
-                const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
-                T acc = w00 * v00;
-                acc = fma_(w10, v10, acc);
-                acc = fma_(w01, v01, acc);
-                acc = fma_(w11, v11, acc);
-                const T cand = fma_(beta, acc, wl[r]);
-                if (POLICY) {
-                    if (cand < best[r]) {
-                        best[r] = cand;
-                        arg[r] = k;
-                    }
-                } else {
-                    best[r] = min_(best[r], cand);
-                }
-            }
-        }
-    }
-    double rmax = 0.0;
     unsigned nact = 0;
+    const int slot = sweep % 3;
+    // mode 0: one item per work-group, scheduled by the hardware;
+    // mode 1: resident grid taking items from the sweep's atomic queue;
+    // mode 2: resident grid walking the list with a grid stride.
+    for (int item = mode == 1 ? next_item(cnt, slot) : (int)blockIdx.x; item < n_items;
+         item = mode == 1 ? next_item(cnt, slot)
+                          : (mode == 2 ? item + (int)gridDim.x : n_items)) {
+        const WorkItem it = items[item];
+        SdState *sst = st + it.sd;
+        if (!POLICY && sd_skip(sst, sweep, tol)) continue;
+        const SdDesc<T> &d = sds[it.sd];
+        const int tflat = d.tile_offset + it.t[1] * d.tiles[0] + it.t[0];
+        if (!POLICY && sweep > 0 &&
+            !neighbourhood_changed<RX, RY, 0>(prev, d.tile_offset, it.t, d.tiles)) {
+            if (threadIdx.x == 0) cur[tflat] = 0;
+            continue;
+        }
+        const int n0 = d.n[0], n1 = d.n[1];
+        const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
+        const int src = POLICY ? sst->final_buf : (sweep & 1);
+        const T *__restrict__ Vin = d.V[src];
+        T *__restrict__ Vout = d.V[src ^ 1];
+        const uint8_t *__restrict__ mem = d.member;
+        const int bit = d.bit;
+        const T G = d.G;
+
+        __syncthreads();                 // LDS of the previous item is no longer read
+        for (int q = threadIdx.x; q < LW * LH; q += kThreads) {
+            const int ly = q / LW;
+            const int lx = q - ly * LW;
+            const int gx = x0 - H + lx, gy = y0 - H + ly;
+            T v = G;
+            if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1) {
+                const size_t j = (size_t)gy * n0 + gx;
+                if (!mem || ((mem[j] >> bit) & 1)) v = Vin[j];
+            }
+            lds[q] = v;
+        }
+        __syncthreads();
+
+        const int gx = x0 + tx;
+        T c[NPT], ux0[NPT], uy0[NPT], wl[NPT], best[NPT];
+        int arg[NPT];
+        bool act[NPT];
+        int any = 0;
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        if (!act[r]) continue;
-        const int ty = ty0 + r * RSTEP;
-        const size_t j = (size_t)(y0 + ty) * n0 + gx;
-        Vout[j] = best[r];
-        if (POLICY) d.policy[j] = (uint8_t)arg[r];
-        const double dv = __builtin_fabs((double)best[r] - (double)lds[(ty + H) * LW + tx + H]);
-        rmax = dv > rmax ? dv : rmax;
-        ++nact;
+        for (int r = 0; r < NPT; ++r) {
+            const int ty = ty0 + r * RSTEP;
+            const int gy = y0 + ty;
+            act[r] = false;
+            c[r] = T(0);                        // inactive lanes: foot = own node
+            wl[r] = d.wl_const;
+            if (gx < n0 && gy < n1) {
+                const size_t j = (size_t)gy * n0 + gx;
+                const bool inset = !mem || ((mem[j] >> bit) & 1);
+                act[r] = inset && d.target[j] < 0;
+                if (act[r]) {
+                    c[r] = d.speed ? d.speed[j] : T(1);
+                    if (d.wl) wl[r] = d.wl[j];
+                }
+            }
+            any |= act[r];
+            if (sizeof(T) == 4) {
+                ux0[r] = (T)(tx + H);
+                uy0[r] = (T)(ty + H);
+            } else {
+                ux0[r] = (T)gx;
+                uy0[r] = (T)gy;
+            }
+            best[r] = (T)INFINITY;
+            arg[r] = 0;
+        }
+        const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
+        const T beta = d.beta;
+        const T *__restrict__ ctrl = d.ctrl;
+        const int m = d.m;
+        if (__any(any)) {
+            for (int k = 0; k < m; ++k) {
+                const T ex = ctrl[2 * k], ey = ctrl[2 * k + 1];
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) {
+                    T ux, uy;
+                    if (sizeof(T) == 4) {
+                        ux = fma_(c[r], ex, ux0[r]);
+                        uy = fma_(c[r], ey, uy0[r]);
+                    } else {
+                        ux = ux0[r] + ex * c[r];
+                        uy = uy0[r] + ey * c[r];
+                    }
+                    int ix, iy;
+                    T fx, fy;
+                    Foot<T>::split(ux, ox, ix, fx);
+                    Foot<T>::split(uy, oy, iy, fy);
+                    const int base = iy * LW + ix;
+                    const T v00 = lds[base], v10 = lds[base + 1];
+                    const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
+                    const T ax = T(1) - fx, ay = T(1) - fy;
+                    const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
+                    T acc = w00 * v00;
+                    acc = fma_(w10, v10, acc);
+                    acc = fma_(w01, v01, acc);
+                    acc = fma_(w11, v11, acc);
+                    const T cand = fma_(beta, acc, wl[r]);
+                    if (POLICY) {
+                        if (cand < best[r]) {
+                            best[r] = cand;
+                            arg[r] = k;
+                        }
+                    } else {
+                        best[r] = min_(best[r], cand);
+                    }
+                }
+            }
+        }
+        double rmax = 0.0;
+        unsigned na = 0;
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            if (!act[r]) continue;
+            const int ty = ty0 + r * RSTEP;
+            const size_t j = (size_t)(y0 + ty) * n0 + gx;
+            Vout[j] = best[r];
+            if (POLICY) d.policy[j] = (uint8_t)arg[r];
+            const double dv =
+                __builtin_fabs((double)best[r] - (double)lds[(ty + H) * LW + tx + H]);
+            rmax = dv > rmax ? dv : rmax;
+            ++na;
+        }
+        nact += na * (unsigned)m;
+        if (!POLICY) {
+            const double bm = block_max_to(rmax, &sst->res[sweep % 3]);
+            if (threadIdx.x == 0) cur[tflat] = bm > 0.0 ? 1 : 0;
+        }
     }
-    if (!POLICY) {
-        block_max_to(rmax, &sst->res[sweep % 3]);
-        block_sum_to(nact * (unsigned)m, &cnt->nc_updates);
-    }
+    if (!POLICY) block_sum_to(nact, &cnt->nc_updates);
 }
 
 // ------------------------------------------------------------------ 3D kernel
@@ -170,7 +223,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
                                                       ExecCounters *__restrict__ cnt,
-                                                      int sweep_rel, double tol) {
+                                                      int sweep_rel, double tol,
+                                                      uint8_t *__restrict__ changed,
+                                                      int flag_stride, int mode) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
@@ -180,143 +235,164 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
     static_assert(kThreads % TXY == 0 || TXY % kThreads == 0, "tile/thread mismatch");
     constexpr int ZSTEP = kThreads / TXY;              // z planes covered per pass
     constexpr int NPT = TZ / ZSTEP;
+    constexpr int RX = (H + TX - 1) / TX, RY = (H + TY - 1) / TY, RZ = (H + TZ - 1) / TZ;
     static_assert(ZSTEP >= 1 && TZ % ZSTEP == 0, "tile/thread mismatch");
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
 
     if (!POLICY && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
-    if ((int)blockIdx.x >= cnt->n_items) return;
-    const WorkItem it = items[blockIdx.x];
-    SdState *sst = st + it.sd;
-    if (!POLICY && sd_skip(sst, sweep, tol)) return;
-    const SdDesc<T> &d = sds[it.sd];
-    const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
-    const int x0 = it.t[0] * TX, y0 = it.t[1] * TY, z0 = it.t[2] * TZ;
-    const int src = POLICY ? sst->final_buf : (sweep & 1);
-    const T *__restrict__ Vin = d.V[src];
-    T *__restrict__ Vout = d.V[src ^ 1];
-    const uint8_t *__restrict__ mem = d.member;
-    const int bit = d.bit;
-    const T G = d.G;
-
-    for (int q = threadIdx.x; q < PL * LD; q += kThreads) {
-        const int lz = q / PL;
-        const int rem = q - lz * PL;
-        const int ly = rem / LW;
-        const int lx = rem - ly * LW;
-        const int gx = x0 - H + lx, gy = y0 - H + ly, gz = z0 - H + lz;
-        T v = G;
-        if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
-            (unsigned)gz < (unsigned)n2) {
-            const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
-            if (!mem || ((mem[j] >> bit) & 1)) v = Vin[j];
-        }
-        lds[q] = v;
-    }
-    __syncthreads();
-
+    const int n_items = cnt->n_items;
+    const uint8_t *prev = changed + (size_t)((sweep + 1) & 1) * flag_stride;
+    uint8_t *cur = changed + (size_t)(sweep & 1) * flag_stride;
     const int tx = threadIdx.x % TX;
     const int ty = (threadIdx.x / TX) % TY;
     const int tz0 = threadIdx.x / TXY;
-    const int gx = x0 + tx, gy = y0 + ty;
-    T c[NPT], ux0[NPT], uy0[NPT], uz0[NPT], wl[NPT], best[NPT];
-    int arg[NPT];
-    bool act[NPT];
-    int any = 0;
-#pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        const int tz = tz0 + r * ZSTEP;
-        const int gz = z0 + tz;
-        act[r] = false;
-        c[r] = T(0);                        // inactive lanes: foot = own node
-        wl[r] = d.wl_const;
-        if (gx < n0 && gy < n1 && gz < n2) {
-            const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
-            const bool inset = !mem || ((mem[j] >> bit) & 1);
-            act[r] = inset && d.target[j] < 0;
-            if (act[r]) {
-                c[r] = d.speed ? d.speed[j] : T(1);
-                if (d.wl) wl[r] = d.wl[j];
-            }
-        }
-        any |= act[r];
-        if (sizeof(T) == 4) {
-            ux0[r] = (T)(tx + H);
-            uy0[r] = (T)(ty + H);
-            uz0[r] = (T)(tz + H);
-        } else {
-            ux0[r] = (T)gx;
-            uy0[r] = (T)gy;
-            uz0[r] = (T)gz;
-        }
-        best[r] = (T)INFINITY;
-        arg[r] = 0;
-    }
-    const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
-    const T beta = d.beta;
-    const T *__restrict__ ctrl = d.ctrl;
-    const int m = d.m;
-    if (__any(any)) {
-        for (int k = 0; k < m; ++k) {
-            const T ex = ctrl[3 * k], ey = ctrl[3 * k + 1], ez = ctrl[3 * k + 2];
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                T ux, uy, uz;
-                if (sizeof(T) == 4) {
-                    ux = fma_(c[r], ex, ux0[r]);
-                    uy = fma_(c[r], ey, uy0[r]);
-                    uz = fma_(c[r], ez, uz0[r]);
-                } else {
-                    ux = ux0[r] + ex * c[r];
-                    uy = uy0[r] + ey * c[r];
-                    uz = uz0[r] + ez * c[r];
-                }
-                int ix, iy, iz;
-                T fx, fy, fz;
-                Foot<T>::split(ux, ox, ix, fx);
-                Foot<T>::split(uy, oy, iy, fy);
-                Foot<T>::split(uz, oz, iz, fz);
-                const int base = (iz * LH + iy) * LW + ix;
-                const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
-                const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
-                T acc = (w00 * az) * lds[base];
-                acc = fma_(w10 * az, lds[base + 1], acc);
-                acc = fma_(w01 * az, lds[base + LW], acc);
-                acc = fma_(w11 * az, lds[base + LW + 1], acc);
-                acc = fma_(w00 * fz, lds[base + PL], acc);
-                acc = fma_(w10 * fz, lds[base + PL + 1], acc);
-                acc = fma_(w01 * fz, lds[base + PL + LW], acc);
-                acc = fma_(w11 * fz, lds[base + PL + LW + 1], acc);
-                const T cand = fma_(beta, acc, wl[r]);
-                if (POLICY) {
-                    if (cand < best[r]) {
-                        best[r] = cand;
-                        arg[r] = k;
-                    }
-                } else {
-                    best[r] = min_(best[r], cand);
-                }
-            }
-        }
-    }
-    double rmax = 0.0;
     unsigned nact = 0;
+    const int slot = sweep % 3;
+    // mode 0: one item per work-group, scheduled by the hardware;
+    // mode 1: resident grid taking items from the sweep's atomic queue;
+    // mode 2: resident grid walking the list with a grid stride.
+    for (int item = mode == 1 ? next_item(cnt, slot) : (int)blockIdx.x; item < n_items;
+         item = mode == 1 ? next_item(cnt, slot)
+                          : (mode == 2 ? item + (int)gridDim.x : n_items)) {
+        const WorkItem it = items[item];
+        SdState *sst = st + it.sd;
+        if (!POLICY && sd_skip(sst, sweep, tol)) continue;
+        const SdDesc<T> &d = sds[it.sd];
+        const int tflat = d.tile_offset + (it.t[2] * d.tiles[1] + it.t[1]) * d.tiles[0] + it.t[0];
+        if (!POLICY && sweep > 0 &&
+            !neighbourhood_changed<RX, RY, RZ>(prev, d.tile_offset, it.t, d.tiles)) {
+            if (threadIdx.x == 0) cur[tflat] = 0;
+            continue;
+        }
+        const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+        const int x0 = it.t[0] * TX, y0 = it.t[1] * TY, z0 = it.t[2] * TZ;
+        const int src = POLICY ? sst->final_buf : (sweep & 1);
+        const T *__restrict__ Vin = d.V[src];
+        T *__restrict__ Vout = d.V[src ^ 1];
+        const uint8_t *__restrict__ mem = d.member;
+        const int bit = d.bit;
+        const T G = d.G;
+
+        __syncthreads();                 // LDS of the previous item is no longer read
+        for (int q = threadIdx.x; q < PL * LD; q += kThreads) {
+            const int lz = q / PL;
+            const int rem = q - lz * PL;
+            const int ly = rem / LW;
+            const int lx = rem - ly * LW;
+            const int gx = x0 - H + lx, gy = y0 - H + ly, gz = z0 - H + lz;
+            T v = G;
+            if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                (unsigned)gz < (unsigned)n2) {
+                const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+                if (!mem || ((mem[j] >> bit) & 1)) v = Vin[j];
+            }
+            lds[q] = v;
+        }
+        __syncthreads();
+
+        const int gx = x0 + tx, gy = y0 + ty;
+        T c[NPT], ux0[NPT], uy0[NPT], uz0[NPT], wl[NPT], best[NPT];
+        int arg[NPT];
+        bool act[NPT];
+        int any = 0;
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        if (!act[r]) continue;
-        const int tz = tz0 + r * ZSTEP;
-        const size_t j = ((size_t)(z0 + tz) * n1 + gy) * n0 + gx;
-        Vout[j] = best[r];
-        if (POLICY) d.policy[j] = (uint8_t)arg[r];
-        const double dv = __builtin_fabs(
-            (double)best[r] - (double)lds[((tz + H) * LH + ty + H) * LW + tx + H]);
-        rmax = dv > rmax ? dv : rmax;
-        ++nact;
+        for (int r = 0; r < NPT; ++r) {
+            const int tz = tz0 + r * ZSTEP;
+            const int gz = z0 + tz;
+            act[r] = false;
+            c[r] = T(0);                        // inactive lanes: foot = own node
+            wl[r] = d.wl_const;
+            if (gx < n0 && gy < n1 && gz < n2) {
+                const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+                const bool inset = !mem || ((mem[j] >> bit) & 1);
+                act[r] = inset && d.target[j] < 0;
+                if (act[r]) {
+                    c[r] = d.speed ? d.speed[j] : T(1);
+                    if (d.wl) wl[r] = d.wl[j];
+                }
+            }
+            any |= act[r];
+            if (sizeof(T) == 4) {
+                ux0[r] = (T)(tx + H);
+                uy0[r] = (T)(ty + H);
+                uz0[r] = (T)(tz + H);
+            } else {
+                ux0[r] = (T)gx;
+                uy0[r] = (T)gy;
+                uz0[r] = (T)gz;
+            }
+            best[r] = (T)INFINITY;
+            arg[r] = 0;
+        }
+        const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
+        const T beta = d.beta;
+        const T *__restrict__ ctrl = d.ctrl;
+        const int m = d.m;
+        if (__any(any)) {
+            for (int k = 0; k < m; ++k) {
+                const T ex = ctrl[3 * k], ey = ctrl[3 * k + 1], ez = ctrl[3 * k + 2];
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) {
+                    T ux, uy, uz;
+                    if (sizeof(T) == 4) {
+                        ux = fma_(c[r], ex, ux0[r]);
+                        uy = fma_(c[r], ey, uy0[r]);
+                        uz = fma_(c[r], ez, uz0[r]);
+                    } else {
+                        ux = ux0[r] + ex * c[r];
+                        uy = uy0[r] + ey * c[r];
+                        uz = uz0[r] + ez * c[r];
+                    }
+                    int ix, iy, iz;
+                    T fx, fy, fz;
+                    Foot<T>::split(ux, ox, ix, fx);
+                    Foot<T>::split(uy, oy, iy, fy);
+                    Foot<T>::split(uz, oz, iz, fz);
+                    const int base = (iz * LH + iy) * LW + ix;
+                    const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
+                    const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
+                    T acc = (w00 * az) * lds[base];
+                    acc = fma_(w10 * az, lds[base + 1], acc);
+                    acc = fma_(w01 * az, lds[base + LW], acc);
+                    acc = fma_(w11 * az, lds[base + LW + 1], acc);
+                    acc = fma_(w00 * fz, lds[base + PL], acc);
+                    acc = fma_(w10 * fz, lds[base + PL + 1], acc);
+                    acc = fma_(w01 * fz, lds[base + PL + LW], acc);
+                    acc = fma_(w11 * fz, lds[base + PL + LW + 1], acc);
+                    const T cand = fma_(beta, acc, wl[r]);
+                    if (POLICY) {
+                        if (cand < best[r]) {
+                            best[r] = cand;
+                            arg[r] = k;
+                        }
+                    } else {
+                        best[r] = min_(best[r], cand);
+                    }
+                }
+            }
+        }
+        double rmax = 0.0;
+        unsigned na = 0;
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            if (!act[r]) continue;
+            const int tz = tz0 + r * ZSTEP;
+            const size_t j = ((size_t)(z0 + tz) * n1 + gy) * n0 + gx;
+            Vout[j] = best[r];
+            if (POLICY) d.policy[j] = (uint8_t)arg[r];
+            const double dv = __builtin_fabs(
+                (double)best[r] - (double)lds[((tz + H) * LH + ty + H) * LW + tx + H]);
+            rmax = dv > rmax ? dv : rmax;
+            ++na;
+        }
+        nact += na * (unsigned)m;
+        if (!POLICY) {
+            const double bm = block_max_to(rmax, &sst->res[sweep % 3]);
+            if (threadIdx.x == 0) cur[tflat] = bm > 0.0 ? 1 : 0;
+        }
     }
-    if (!POLICY) {
-        block_max_to(rmax, &sst->res[sweep % 3]);
-        block_sum_to(nact * (unsigned)m, &cnt->nc_updates);
-    }
+    if (!POLICY) block_sum_to(nact, &cnt->nc_updates);
 }
 
 __global__ void k_flip(SdState *st, int n_sd) {
@@ -331,8 +407,7 @@ __global__ void k_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol, Exe
 }
 
 // ------------------------------------------------------------ dispatch tables
-using SweepFn = void (*)(const void *, SdState *, int, const WorkItem *, ExecCounters *, int,
-                         double);
+
 
 struct Variant {
     int dim, dtype, tile[3];
@@ -361,7 +436,10 @@ Variant make2d() {
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = 1;
     fill2d<T, TX, TY, 1>(v); fill2d<T, TX, TY, 2>(v); fill2d<T, TX, TY, 3>(v);
     fill2d<T, TX, TY, 4>(v); fill2d<T, TX, TY, 5>(v); fill2d<T, TX, TY, 6>(v);
-    fill2d<T, TX, TY, 7>(v); fill2d<T, TX, TY, 8>(v);
+    fill2d<T, TX, TY, 7>(v); fill2d<T, TX, TY, 8>(v); fill2d<T, TX, TY, 9>(v);
+    fill2d<T, TX, TY, 10>(v); fill2d<T, TX, TY, 11>(v); fill2d<T, TX, TY, 12>(v);
+    fill2d<T, TX, TY, 13>(v); fill2d<T, TX, TY, 14>(v); fill2d<T, TX, TY, 15>(v);
+    fill2d<T, TX, TY, 16>(v);
     return v;
 }
 template <typename T, int TX, int TY, int TZ>
@@ -416,14 +494,22 @@ int sweep_variants(int dim, LaunchCfg *out, int cap) {
 static const void *sweep_fn(const LaunchCfg &cfg, int want_policy, size_t *lds) {
     int nv = 0;
     const Variant *vt = variants(&nv);
-    if (cfg.variant < 0 || cfg.variant >= nv || cfg.halo < 1 || cfg.halo > kMaxHalo)
-        return nullptr;
+    if (cfg.variant < 0 || cfg.variant >= nv || cfg.halo < 1) return nullptr;
     const Variant &v = vt[cfg.variant];
+    if (cfg.halo > (v.dim == 2 ? kMaxHalo : kMaxHalo3D) || !v.fn[cfg.halo][0]) return nullptr;
     *lds = v.lds_bytes[cfg.halo];
     return v.fn[cfg.halo][want_policy ? 1 : 0];
 }
 
-hipError_t sweep_set_attributes(const LaunchCfg &cfg) {
+hipError_t sweep_set_attributes(LaunchCfg &cfg) {
+    static int n_cu = 0;
+    if (!n_cu) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            n_cu = 256;
+    }
+    int cap = 1 << 30;
     for (int pol = 0; pol < 2; ++pol) {
         size_t lds = 0;
         const void *fn = sweep_fn(cfg, pol, &lds);
@@ -433,19 +519,29 @@ hipError_t sweep_set_attributes(const LaunchCfg &cfg) {
                                                (int)lds);
             if (e != hipSuccess) return e;
         }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cap = std::min(cap, per_cu * n_cu);
     }
+    cfg.grid_cap = cap;
     return hipSuccess;
 }
 
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
                         const WorkItem *items, ExecCounters *cnt, int max_items,
-                        int sweep, double tol, int want_policy, hipStream_t s) {
+                        int sweep, double tol, int want_policy, uint8_t *changed,
+                        int flag_stride, hipStream_t s) {
     size_t lds = 0;
     const void *fn = sweep_fn(cfg, want_policy, &lds);
     if (!fn) return hipErrorInvalidValue;
-    const int grid = max_items > 0 ? max_items : 1;
-    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items,
-                    (void *)&cnt, (void *)&sweep, (void *)&tol};
+    int grid = max_items > 0 ? max_items : 1;
+    int persistent = cfg.mode;
+    if (persistent && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
+    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&cnt,
+                    (void *)&sweep, (void *)&tol, (void *)&changed, (void *)&flag_stride,
+                    (void *)&persistent};
     return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s);
 }
 

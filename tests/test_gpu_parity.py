@@ -219,3 +219,37 @@ def test_tiny_grid_and_whole_target():
     q = p.with_(target=np.zeros(p.N, dtype=np.int8))
     V, _, st = S.solve(S.to_device(q, torch.float64))
     assert (host(V) == 0).all()
+
+
+# ------------------------------------------------------ every kernel configuration
+@pytest.mark.parametrize("dim", [2, 3])
+def test_every_tuner_candidate_matches_oracle(dim):
+    """Each (tile shape, work schedule) the autotuner may pick gives the oracle's
+    fixed point (FP32 <= 1e-5; FP64 bit-exact), with tile skipping active."""
+    if dim == 2:
+        p = W.c2_multitarget(n=97, m=32)
+    else:
+        p = W.c3_aniso3d(n=25, m=32, n_balls=3, r=0.15)
+    Vo, _, _, _ = O.solve(p)
+    for dtype in (torch.float32, torch.float64):
+        code = 0 if dtype == torch.float32 else 1
+        ncand = S.lib().sl_tune_candidates(dim, code)
+        assert ncand >= 3
+        dp = S.to_device(p, dtype)
+        for k in range(ncand):
+            V, _, st = S.solve(dp, S.SolveOpts(tol=0.0, autotune=-(k + 1)))
+            Vg = host(V).astype(np.float64)
+            say("  candidate", dim, dtype, k, st["tile"], st["mode"], np.abs(Vg - Vo).max())
+            if dtype == torch.float64:
+                assert np.array_equal(Vg, Vo), (k, st["tile"], st["mode"])
+            else:
+                assert np.abs(Vg - Vo).max() <= 1e-5, (k, st["tile"], st["mode"])
+
+
+def test_autotuned_isa_matches_oracle():
+    p = W.c2_multitarget(n=129, m=64)
+    dp = S.to_device(p, torch.float32)
+    V, owner, member, label, _, _, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, autotune=2))
+    Vbar, _, rec, _, _ = I.isa(p)
+    assert np.abs(host(V).astype(np.float64) - Vbar).max() <= 1e-5
+    say("  tuned:", st["tile"], st["mode"])
