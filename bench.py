@@ -82,7 +82,8 @@ def leg_c3(steps: int):
     import workloads as W
     p = W.c3_aniso3d()
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q)
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
+                  autotune=1)
     opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1)
     S.isa(dp, ra, opts)
     _sync()
@@ -112,7 +113,8 @@ def leg_c4(steps: int):
     import workloads as W
     probs = W.c4_batch()
     dps = [S.to_device(p, torch.float32, "cuda:0") for p in probs]
-    ras = [S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q) for p in probs]
+    ras = [S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
+                  autotune=1) for p in probs]
     opts = S.SolveOpts(tol=1e-6, autotune=2)
     S.solve_batched(dps, ras, opts)
     _sync()
@@ -123,9 +125,11 @@ def leg_c4(steps: int):
     ms_b = (time.perf_counter() - t0) / steps * 1e3
     tot = out[-1]
     t0 = time.perf_counter()
+    # one call per problem, default kernels (no per-size tuning inside the timing)
     single = S.SolveOpts(tol=1e-6)
-    for dp, ra in zip(dps, ras):
-        S.isa(dp, ra, single)
+    for dp, p in zip(dps, probs):
+        S.isa(dp, S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q,
+                           tol=p.ra_tol), single)
     _sync()
     ms_single = (time.perf_counter() - t0) * 1e3
     return {"workload": "512 problems, sides log-uniform in [16,512], 1-6 disks, 32 controls, "
@@ -145,7 +149,8 @@ def leg_c5(steps: int):
     import workloads as W
     p = W.c5_adjoint()
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q)
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
+                  autotune=1)
     member, label, _ = S.reconstruct(dp, ra)
     th_true = torch.as_tensor(p.meta["theta_true"], dtype=torch.float32, device="cuda:0")
     fwd_opts = S.SolveOpts(tol=1e-6, autotune=1)
@@ -244,7 +249,8 @@ def main():
 
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=prob.coarse_stride, C=prob.ra_C, M=prob.ra_M, q=prob.ra_q)
+    ra = S.RaOpts(coarse_stride=prob.coarse_stride, C=prob.ra_C, M=prob.ra_M, q=prob.ra_q,
+                  tol=prob.ra_tol, autotune=1)
     # --sweep-config k forces candidate k-1; 0 lets the warm-up step run the
     # autotuner (complete solves as trials) and the timed steps use its pick
     opts = S.SolveOpts(tol=1e-6, profile=True,

@@ -85,6 +85,8 @@ typedef struct sl_ra_opts {
     double delta_override;    /* > 0: use this delta instead                          */
     double tol;               /* coarse stopping tolerance on max|V_new - V| (0 = until nothing changes) */
     long max_sweeps;          /* coarse sweep cap                                     */
+    int autotune;             /* as sl_solve_opts.autotune, for the coarse sweeps (the FP64
+                                 results do not depend on the kernel configuration)   */
 } sl_ra_opts;
 
 /* Value-iteration options. */

@@ -104,12 +104,15 @@ def ra_delta(probK) -> float:
     return 2.0 * (probK.ra_C * math.pow(dx, probK.ra_q) + probK.ra_M * dx)
 
 
-def reconstruct_on(probK, delta: Optional[float] = None, tol: float = 0.0,
+def reconstruct_on(probK, delta: Optional[float] = None, tol: Optional[float] = None,
                    max_sweeps: int = 10**7):
-    """RA steps 1-3 on the grid of ``probK``: auxiliary solves, min, threshold.
+    """RA steps 1-3 on the grid of ``probK``: auxiliary solves (to ``tol``, default
+    the problem's ``ra_tol``), min, threshold.
     Returns (member bitmask, label, V_aux list, V, delta, sweeps)."""
     if delta is None:
         delta = ra_delta(probK)
+    if tol is None:
+        tol = probK.ra_tol
     fixed = fixed_mask(probK)
     V_aux, sweeps = [], []
     for i in range(probK.n_comp):                          # step 1

@@ -50,7 +50,7 @@ class SlProblem(C.Structure):
 class SlRaOpts(C.Structure):
     _fields_ = [("coarse_stride", C.c_int), ("C", C.c_double), ("M", C.c_double),
                 ("q", C.c_double), ("delta_override", C.c_double), ("tol", C.c_double),
-                ("max_sweeps", C.c_long)]
+                ("max_sweeps", C.c_long), ("autotune", C.c_int)]
 
 
 class SlSolveOpts(C.Structure):
@@ -164,6 +164,7 @@ class RaOpts:
     delta_override: float = 0.0
     tol: float = 0.0
     max_sweeps: int = 10_000_000
+    autotune: int = 0
 
 
 @dataclass
@@ -244,7 +245,8 @@ def _stream():
 
 
 def _ra(o: RaOpts) -> SlRaOpts:
-    return SlRaOpts(o.coarse_stride, o.C, o.M, o.q, o.delta_override, o.tol, o.max_sweeps)
+    return SlRaOpts(o.coarse_stride, o.C, o.M, o.q, o.delta_override, o.tol, o.max_sweeps,
+                    int(o.autotune))
 
 
 def _so(o: SolveOpts) -> SlSolveOpts:

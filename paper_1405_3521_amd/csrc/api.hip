@@ -94,6 +94,7 @@ int validate_ra(const sl_problem *p, const sl_ra_opts *ra) {
         return SL_ERR_INVALID_ARG;
     if (!(ra->delta_override >= 0.0) && !(ra->delta_override < 0.0)) return SL_ERR_INVALID_ARG;
     if (!(ra->tol >= 0.0) || ra->max_sweeps < 1) return SL_ERR_INVALID_ARG;
+    if (ra->autotune > 2) return SL_ERR_INVALID_ARG;
     return SL_OK;
 }
 
@@ -704,9 +705,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     const size_t N = nodes_of(p);
     const CoarseGeom cg = coarse_geom(p, ra->coarse_stride);
     const int nc = p->n_comp;
-    const LaunchCfg cfgK = make_cfg(p->dim, SL_F64, 1, default_variant(p->dim, SL_F64));
-    int t[3];
-    const int tilesK = Exec<double>::tiles_of(cfgK, cg.nK, p->dim, t);
+    const int tilesK = max_tiles(p->dim, SL_F64, cg.nK);
     P.cK_t = a.take<T>(cg.NK);
     P.lK_t = a.take<T>(cg.NK);
     P.gK_t = a.take<T>(cg.NK);
@@ -791,11 +790,18 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     const int HK = halo_for(smax, emaxK);
     if (HK > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.exK.cfg = make_cfg(p->dim, SL_F64, HK, default_variant(p->dim, SL_F64));
+    auto reinit = [&](hipStream_t q) -> hipError_t {
+        for (int i = 0; i < nc; ++i)
+            for (int b = 0; b < 2; ++b) {
+                const hipError_t e = launch_init_values<double>(
+                    P.Vaux + (size_t)i * 2 * cg.NK + b * cg.NK, P.tK, p->g ? P.gK : nullptr,
+                    p->v_ghost, i, cg.NK, q);
+                if (e != hipSuccess) return e;
+            }
+        return hipSuccess;
+    };
     for (int i = 0; i < nc; ++i) {
         double *V0 = P.Vaux + (size_t)i * 2 * cg.NK;
-        for (int b = 0; b < 2; ++b)
-            HIPCHK(launch_init_values<double>(V0 + b * cg.NK, P.tK, p->g ? P.gK : nullptr,
-                                              p->v_ghost, i, cg.NK, s));
         SdDesc<double> d{};
         d.V[0] = V0;
         d.V[1] = V0 + cg.NK;
@@ -815,9 +821,9 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
         d.halo = HK;
         P.exK.host_sds.push_back(d);
     }
-    if ((rc = P.exK.prepare(s))) return rc;
     long S = 0;
-    const int status = P.exK.run(ra->tol, ra->max_sweeps, 32, 0, s, &S);
+    const int status =
+        P.exK.solve_tuned(ra->autotune, reinit, ra->tol, ra->max_sweeps, 32, 0, s, &S, 0);
     if (status < 0) return status;
 
     // RA steps 2-3: min, threshold, label on the final auxiliary iterates.
@@ -1086,7 +1092,6 @@ template <typename T>
 int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t *const *member,
                  uint8_t *const *label, uint8_t *const *owner, Arena &a, BatchPlan<T> &B) {
     const int dim = probs[0].dim;
-    const LaunchCfg cfgK = make_cfg(dim, SL_F64, 1, default_variant(dim, SL_F64));
     B.hp.assign(np, ProbDesc<T>{});
     B.hblk_N.assign(np + 1, 0);
     B.hblk_NK.assign(np + 1, 0);
@@ -1120,7 +1125,7 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
         d.Vf = a.take<T>((size_t)p->n_comp * 2 * d.N);
         d.wl = p->cost ? a.take<T>(d.N) : nullptr;
         int t[3];
-        tilesK += Exec<double>::tiles_of(cfgK, cg.nK, dim, t) * p->n_comp;
+        tilesK += max_tiles(dim, SL_F64, cg.nK) * p->n_comp;
         tiles += max_tiles(dim, p->dtype, p->n) * p->n_comp;
         d.sd_coarse0 = nsd;
         d.sd_fine0 = nsd;
@@ -1217,7 +1222,10 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     // 2. coarse data, placement of missing components, auxiliary initial values
     HIPCHK(launch_batched<T>(kBatchCoarsePrep, B.pd, np, B.blk_NK, B.hblk_NK[np], kChunk, nullptr, nullptr, s));
     HIPCHK(launch_batched<T>(kBatchPlace, B.pd, np, nullptr, 1, kChunk, nullptr, nullptr, s));
-    HIPCHK(launch_batched<T>(kBatchInitAux, B.pd, np, B.blk_aux, B.hblk_aux[np], kChunk, nullptr, nullptr, s));
+    auto reinitK = [&](hipStream_t q) -> hipError_t {
+        return launch_batched<T>(kBatchInitAux, B.pd, np, B.blk_aux, B.hblk_aux[np], kChunk,
+                                 nullptr, nullptr, q);
+    };
     // 3. RA step 1 for every (problem, component): one launch per sweep
     B.exK.cfg = make_cfg(dim, SL_F64, HK, default_variant(dim, SL_F64));
     size_t coff = 0;
@@ -1246,10 +1254,10 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         }
         coff += (size_t)p->m * dim;
     }
-    int rc = B.exK.prepare(s);
-    if (rc) return rc;
+    int rc = SL_OK;
     long SK = 0;
-    int stK = B.exK.run(ras[0].tol, ras[0].max_sweeps, 32, 0, s, &SK);
+    int stK = B.exK.solve_tuned(ras[0].autotune, reinitK, ras[0].tol, ras[0].max_sweeps, 32, 0,
+                                s, &SK, 0);
     if (stK < 0) return stK;
     // 4. RA steps 2-3, projection, fine initial values
     HIPCHK(launch_batched<T>(kBatchCombine, B.pd, np, B.blk_NK, B.hblk_NK[np], kChunk, B.exK.sds, B.exK.st, s));

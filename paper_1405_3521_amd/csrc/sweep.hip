@@ -465,6 +465,10 @@ const Variant *variants(int *count) {
         make3d<float, 32, 8, 4>(), // 6
         make3d<float, 16, 16, 4>(),// 7
         make3d<double, 16, 8, 8>(),// 8: FP64 3D
+        make2d<double, 32, 8>(),   // 9: FP64 2D, small tiles (coarse grids)
+        make2d<double, 16, 16>(),  // 10
+        make3d<double, 8, 8, 8>(), // 11: FP64 3D, small tiles
+        make3d<double, 16, 8, 4>(),// 12
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;

@@ -19,7 +19,7 @@ DEV = "cuda:0"
 
 
 def ra_of(p):
-    return S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q)
+    return S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
 
 
 def host(t):
@@ -253,3 +253,16 @@ def test_autotuned_isa_matches_oracle():
     Vbar, _, rec, _, _ = I.isa(p)
     assert np.abs(host(V).astype(np.float64) - Vbar).max() <= 1e-5
     say("  tuned:", st["tile"], st["mode"])
+
+
+def test_reconstruction_with_tuned_coarse_kernels():
+    """The coarse FP64 pass gives the oracle's sets whatever kernel the tuner picks."""
+    p = W.c2_multitarget(n=257, m=64)
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    ra.autotune = 2
+    member, label, st, mK, lK = S.reconstruct(dp, ra, want_coarse=True)
+    rec = I.reconstruct(p)
+    assert np.array_equal(host(mK), rec.member_K)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)

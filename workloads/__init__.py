@@ -56,6 +56,7 @@ class Problem:
     ra_C: float = 0.5                    # RA threshold 2 (C dx^q + M dx); these
     ra_M: float = 0.5                    # defaults give delta = 2 dx of the coarse grid
     ra_q: float = 1.0
+    ra_tol: float = 1e-10                # coarse stopping tolerance (same on every side)
     meta: dict = field(default_factory=dict)
 
     @property
