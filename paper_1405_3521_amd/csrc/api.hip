@@ -296,10 +296,15 @@ struct Exec {
     ExecCounters *cnt = nullptr;    // device
     int *prefix = nullptr;          // device
     uint8_t *changed = nullptr;     // device, 2 * tiles: per-tile change flags
+    int *class_off_dev = nullptr;   // device, kMaxClasses: item segment of each halo class
     int n_sd = 0;
     int total_tiles = 0;
     std::vector<SdDesc<T>> host_sds;
     std::vector<int> host_prefix;
+    // halo classes: sub-domains grouped by the halo they need; one launch per
+    // class and sweep, each with the kernel instantiated for that halo
+    std::vector<LaunchCfg> ccfg;
+    std::vector<int> class_off, class_cap;
 
     void reserve(Arena &a, int nsd, int tiles_total) {
         sds = a.take<SdDesc<T>>(nsd);
@@ -308,6 +313,7 @@ struct Exec {
         cnt = a.take<ExecCounters>(1);
         prefix = a.take<int>(nsd);
         changed = a.take<uint8_t>(2 * (size_t)(tiles_total > 0 ? tiles_total : 1));
+        class_off_dev = a.take<int>(kMaxClasses);
     }
 
     static int tiles_of(const LaunchCfg &cfg, const int *n, int dim, int *t) {
@@ -332,6 +338,28 @@ struct Exec {
             acc += host_sds[i].tiles[0] * host_sds[i].tiles[1] * host_sds[i].tiles[2];
         }
         total_tiles = acc;
+        // halo classes (ascending halo)
+        std::vector<int> halos;
+        for (const auto &d : host_sds) halos.push_back(d.halo > 0 ? d.halo : cfg.halo);
+        std::vector<int> uniq = halos;
+        std::sort(uniq.begin(), uniq.end());
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        if ((int)uniq.size() > kMaxClasses) return SL_ERR_UNSUPPORTED;
+        ccfg.assign(uniq.size(), cfg);
+        class_cap.assign(uniq.size(), 0);
+        class_off.assign(kMaxClasses, 0);
+        for (int i = 0; i < n_sd; ++i) {
+            const int c = (int)(std::lower_bound(uniq.begin(), uniq.end(), halos[i]) - uniq.begin());
+            host_sds[i].cls = c;
+            class_cap[c] += host_sds[i].tiles[0] * host_sds[i].tiles[1] * host_sds[i].tiles[2];
+        }
+        for (size_t c = 0; c < uniq.size(); ++c) {
+            ccfg[c].halo = uniq[c];
+            if (c > 0) class_off[c] = class_off[c - 1] + class_cap[c - 1];
+            HIPCHK(sweep_set_attributes(ccfg[c]));
+        }
+        HIPCHK(hipMemcpyAsync(class_off_dev, class_off.data(), sizeof(int) * kMaxClasses,
+                              hipMemcpyHostToDevice, s));
         std::vector<SdState> hs(n_sd);
         for (auto &x : hs) {
             x.res[0] = x.res[1] = x.res[2] = 0ull;
@@ -349,9 +377,23 @@ struct Exec {
                               hipMemcpyHostToDevice, s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(ExecCounters), s));
         HIPCHK(hipMemsetAsync(changed, 0, 2 * (size_t)(total_tiles > 0 ? total_tiles : 1), s));
-        HIPCHK(launch_build_items(cfg, sds, n_sd, total_tiles, prefix, items, cnt, s));
-        HIPCHK(sweep_set_attributes(cfg));
+        HIPCHK(launch_build_items(cfg, sds, n_sd, total_tiles, prefix, items, cnt, class_off_dev, s));
         return SL_OK;
+    }
+
+    // One sweep (or the policy pass): one launch per non-empty halo class.
+    hipError_t launch_classes(int sweep_rel, double tol, int want_policy, hipStream_t q) {
+        bool first = true;
+        for (size_t c = 0; c < ccfg.size(); ++c) {
+            if (class_cap[c] == 0) continue;
+            const hipError_t e =
+                launch_sweep(ccfg[c], sds, st, n_sd, items + class_off[c], cnt, class_cap[c],
+                             sweep_rel, tol, want_policy, changed, total_tiles, (int)c,
+                             first ? 1 : 0, q);
+            if (e != hipSuccess) return e;
+            first = false;
+        }
+        return hipSuccess;
     }
 
     // Sweeps until every sd meets tol or max_sweeps.  Returns SL_OK or
@@ -370,8 +412,7 @@ struct Exec {
         const int chunk = check_every > 0 ? check_every : 32;
         auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
             for (int i = 0; i < todo; ++i) {
-                const hipError_t e = launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, i,
-                                                  tol, 0, changed, total_tiles, q);
+                const hipError_t e = launch_classes(i, tol, 0, q);
                 if (e != hipSuccess) return e;
             }
             hipError_t e = launch_bookkeep(st, n_sd, todo, tol, cnt, 0, q, 0.0, todo);
@@ -387,8 +428,7 @@ struct Exec {
         sweep_launches += loop.launches;
         HIPCHK(launch_bookkeep(st, n_sd, 0, tol, cnt, 1, s));
         if (want_policy) {
-            HIPCHK(launch_sweep(cfg, sds, st, n_sd, items, cnt, total_tiles, 0, tol, 1, changed,
-                                total_tiles, s));
+            HIPCHK(launch_classes(0, tol, 1, s));
             HIPCHK(launch_flip(st, n_sd, s));
         }
         *sweeps_done = S;
@@ -1200,6 +1240,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     HIPCHK(hipMemcpyAsync(fs.data(), B.fs, sizeof(FieldStats) * np, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     int HK = 1, H = 1;
+    std::vector<int> Hq(np, 1), HKq(np, 1);      // per-problem halos (halo classes)
     std::vector<double> ctrlK, emaxs(np);
     std::vector<T> ctrl;
     for (int q = 0; q < np; ++q) {
@@ -1211,8 +1252,10 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         control_table(p, p->n, p->h, e, &emax);
         control_table(p, B.hp[q].nK, p->h * ras[q].coarse_stride, eK, &emaxK);
         const double smax = p->speed ? bits_to_double(fs[q].speed_max) : 1.0;
-        H = std::max(H, halo_for(smax, emax));
-        HK = std::max(HK, halo_for(smax, emaxK));
+        Hq[q] = halo_for(smax, emax);
+        HKq[q] = halo_for(smax, emaxK);
+        H = std::max(H, Hq[q]);
+        HK = std::max(HK, HKq[q]);
         for (double x : e) ctrl.push_back((T)x);
         for (double x : eK) ctrlK.push_back(x);
     }
@@ -1249,7 +1292,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.m = p->m;
             sd.bit = i;
             Exec<double>::tiles_of(B.exK.cfg, d.nK, dim, sd.tiles);
-            sd.halo = HK;
+            sd.halo = HKq[q];
             B.exK.host_sds.push_back(sd);
         }
         coff += (size_t)p->m * dim;
@@ -1290,7 +1333,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.m = p->m;
             sd.bit = i;
             Exec<T>::tiles_of(B.ex.cfg, d.n, dim, sd.tiles);
-            sd.halo = H;
+            sd.halo = Hq[q];
             B.ex.host_sds.push_back(sd);
         }
         coff += (size_t)p->m * dim;

@@ -126,18 +126,16 @@ __device__ void bookkeep_block(SdState *st, int n_sd, int sweep, double tol,
         s.scale[(sweep + 1) % 3] = 0ull;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        cnt->n_active = active;
-        cnt->queue[(sweep + 1) % 3] = 0;    // work queue of the next sweep
-    }
+    if (threadIdx.x < kMaxClasses) cnt->class_queue[threadIdx.x][(sweep + 1) % 3] = 0;
+    if (threadIdx.x == 0) cnt->n_active = active;   // queues of the next sweep reset above
 }
 
 // Next work item of this sweep for the whole work-group (dynamic queue: one
 // atomic per item, broadcast through LDS).
-__device__ __forceinline__ int next_item(ExecCounters *cnt, int slot) {
+__device__ __forceinline__ int next_item(int *queue) {
     __shared__ int s_item;
     __syncthreads();                    // everyone has read the previous s_item
-    if (threadIdx.x == 0) s_item = atomicAdd(&cnt->queue[slot], 1);
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
     __syncthreads();
     return s_item;
 }

@@ -21,6 +21,7 @@ namespace slhjb {
 
 constexpr int kMaxHalo = 16;           // largest supported halo (cells), 2D
 constexpr int kMaxHalo3D = 8;          // largest supported halo (cells), 3D
+constexpr int kMaxClasses = 16;        // halo classes per executor (one launch each per sweep)
 constexpr int kThreads = 256;          // threads per sweep work-group (4 waves)
 
 // Per-sub-domain description (device memory, read-only during a sweep).
@@ -40,7 +41,8 @@ struct SdDesc {
     int bit;                    // member bit of this sd
     int tiles[3];               // tiles per axis
     int tile_offset;            // first global tile id of this sd
-    int halo;                   // halo this sd needs (<= launch halo)
+    int halo;                   // halo this sd needs
+    int cls;                    // halo class (its work items live in that class's segment)
 };
 
 // Per-sub-domain convergence state (device memory).
@@ -66,8 +68,10 @@ struct ExecCounters {
     unsigned long long nc_updates;  // node*control evaluations
     int sweep_base;             // index of the first sweep of the current chunk
     int pad;
-    int queue[3];               // per-sweep work-queue heads (slot = sweep % 3)
+    int queue[3];               // unused (kept for layout)
     int pad2;
+    int class_items[kMaxClasses];      // work items per halo class
+    int class_queue[kMaxClasses][3];   // per-class, per-sweep work-queue heads
 };
 
 // Input statistics gathered on the device in one pass (see launch_field_stats).
@@ -148,10 +152,12 @@ struct LaunchCfg {
 // cnt->sweep_base + sweep_rel (device-resident base, so a captured chunk of
 // launches can be replayed).
 // `changed`: 2 * flag_stride per-tile change flags (parity of the sweep).
+// `items` is the segment of halo class `cls` (capacity max_items); only the
+// launch with do_bookkeep runs the convergence bookkeeping of the sweep.
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
                         const WorkItem *items, ExecCounters *cnt, int max_items,
                         int sweep_rel, double tol, int want_policy, uint8_t *changed,
-                        int flag_stride, hipStream_t s);
+                        int flag_stride, int cls, int do_bookkeep, hipStream_t s);
 // Bookkeeping before sweep cnt->sweep_base + sweep_rel (marks sds converged,
 // resets slots, counts active sds); `final_pass` also settles final_buf of
 // unconverged sds; afterwards sweep_base += advance.
@@ -185,10 +191,11 @@ hipError_t launch_init_values(T *V, const int8_t *target, const T *g, T G, int c
                               size_t n, hipStream_t s);
 // Build work items for sds whose grids are tiled with cfg.tile; sds with member
 // masks only get tiles that contain a member node.
+// Items of an sd go to the segment of its halo class (class_off[cls] onward).
 template <typename T>
 hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, int n_sd,
                               int total_tiles, const int *tile_prefix_dev, WorkItem *items,
-                              ExecCounters *cnt, hipStream_t s);
+                              ExecCounters *cnt, const int *class_off, hipStream_t s);
 // Coarse grid gather: dst[k] = src[k*s per axis]
 template <typename T>
 hipError_t launch_gather_coarse(const T *src, T *dst, const int *n, const int *nK, int dim,

@@ -150,7 +150,7 @@ __global__ void k_init_values(T *V, const int8_t *target, const T *g, T G, int c
 template <typename T>
 __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
                               const int *tile_prefix, int tx, int ty, int tz,
-                              WorkItem *items, ExecCounters *cnt) {
+                              WorkItem *items, ExecCounters *cnt, const int *class_off) {
     __shared__ int hit;
     const int g = blockIdx.x;
     if (g >= total_tiles) return;
@@ -183,13 +183,13 @@ __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
     }
     __syncthreads();
     if (threadIdx.x == 0 && hit) {
-        const int slot = atomicAdd(&cnt->n_items, 1);
+        const int slot = atomicAdd(&cnt->class_items[d.cls], 1);
         WorkItem w;
         w.sd = sd;
         w.t[0] = t0;
         w.t[1] = t1;
         w.t[2] = t2;
-        items[slot] = w;
+        items[class_off[d.cls] + slot] = w;
     }
 }
 
@@ -404,15 +404,15 @@ template hipError_t launch_init_values<double>(double *, const int8_t *, const d
 template <typename T>
 hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, int n_sd,
                               int total_tiles, const int *tile_prefix_dev, WorkItem *items,
-                              ExecCounters *cnt, hipStream_t s) {
+                              ExecCounters *cnt, const int *class_off, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_build_items<T>, dim3(total_tiles), dim3(kOpThreads), 0, s, sds_dev,
                        n_sd, total_tiles, tile_prefix_dev, cfg.tile[0], cfg.tile[1],
-                       cfg.tile[2], items, cnt);
+                       cfg.tile[2], items, cnt, class_off);
     return hipGetLastError();
 }
-template hipError_t launch_build_items<float>(const LaunchCfg &, const SdDesc<float> *, int, int, const int *, WorkItem *, ExecCounters *, hipStream_t);
-template hipError_t launch_build_items<double>(const LaunchCfg &, const SdDesc<double> *, int, int, const int *, WorkItem *, ExecCounters *, hipStream_t);
+template hipError_t launch_build_items<float>(const LaunchCfg &, const SdDesc<float> *, int, int, const int *, WorkItem *, ExecCounters *, const int *, hipStream_t);
+template hipError_t launch_build_items<double>(const LaunchCfg &, const SdDesc<double> *, int, int, const int *, WorkItem *, ExecCounters *, const int *, hipStream_t);
 
 template <typename T>
 hipError_t launch_gather_coarse(const T *src, T *dst, const int *n, const int *nK, int dim,

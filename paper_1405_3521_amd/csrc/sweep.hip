@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
                                                       ExecCounters *__restrict__ cnt,
                                                       int sweep_rel, double tol,
                                                       uint8_t *__restrict__ changed,
-                                                      int flag_stride, int mode) {
+                                                      int flag_stride, int mode, int cls,
+                                                      int do_bookkeep) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
@@ -73,8 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
     static_assert(kThreads % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
     __shared__ T lds[LW * LH];
 
-    if (!POLICY && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
-    const int n_items = cnt->n_items;
+    if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
+    const int n_items = cnt->class_items[cls];
     const uint8_t *prev = changed + (size_t)((sweep + 1) & 1) * flag_stride;
     uint8_t *cur = changed + (size_t)(sweep & 1) * flag_stride;
     const int tx = threadIdx.x % TX;
@@ -84,8 +85,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
     // mode 0: one item per work-group, scheduled by the hardware;
     // mode 1: resident grid taking items from the sweep's atomic queue;
     // mode 2: resident grid walking the list with a grid stride.
-    for (int item = mode == 1 ? next_item(cnt, slot) : (int)blockIdx.x; item < n_items;
-         item = mode == 1 ? next_item(cnt, slot)
+    int *queue = &cnt->class_queue[cls][slot];
+    for (int item = mode == 1 ? next_item(queue) : (int)blockIdx.x; item < n_items;
+         item = mode == 1 ? next_item(queue)
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
         const WorkItem it = items[item];
         SdState *sst = st + it.sd;
@@ -225,7 +227,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                                                       ExecCounters *__restrict__ cnt,
                                                       int sweep_rel, double tol,
                                                       uint8_t *__restrict__ changed,
-                                                      int flag_stride, int mode) {
+                                                      int flag_stride, int mode, int cls,
+                                                      int do_bookkeep) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
@@ -240,8 +243,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
 
-    if (!POLICY && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
-    const int n_items = cnt->n_items;
+    if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
+    const int n_items = cnt->class_items[cls];
     const uint8_t *prev = changed + (size_t)((sweep + 1) & 1) * flag_stride;
     uint8_t *cur = changed + (size_t)(sweep & 1) * flag_stride;
     const int tx = threadIdx.x % TX;
@@ -252,8 +255,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
     // mode 0: one item per work-group, scheduled by the hardware;
     // mode 1: resident grid taking items from the sweep's atomic queue;
     // mode 2: resident grid walking the list with a grid stride.
-    for (int item = mode == 1 ? next_item(cnt, slot) : (int)blockIdx.x; item < n_items;
-         item = mode == 1 ? next_item(cnt, slot)
+    int *queue = &cnt->class_queue[cls][slot];
+    for (int item = mode == 1 ? next_item(queue) : (int)blockIdx.x; item < n_items;
+         item = mode == 1 ? next_item(queue)
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
         const WorkItem it = items[item];
         SdState *sst = st + it.sd;
@@ -536,7 +540,7 @@ hipError_t sweep_set_attributes(LaunchCfg &cfg) {
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
                         const WorkItem *items, ExecCounters *cnt, int max_items,
                         int sweep, double tol, int want_policy, uint8_t *changed,
-                        int flag_stride, hipStream_t s) {
+                        int flag_stride, int cls, int do_bookkeep, hipStream_t s) {
     size_t lds = 0;
     const void *fn = sweep_fn(cfg, want_policy, &lds);
     if (!fn) return hipErrorInvalidValue;
@@ -545,7 +549,7 @@ hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int 
     if (persistent && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
     void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&cnt,
                     (void *)&sweep, (void *)&tol, (void *)&changed, (void *)&flag_stride,
-                    (void *)&persistent};
+                    (void *)&persistent, (void *)&cls, (void *)&do_bookkeep};
     return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s);
 }
 
