@@ -4,10 +4,16 @@ paper Sec. 4), step by step as the paper lists them, on top of the FP64 SL solve
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 Readings of the paper used here:
-  * the coarse grid K is "partially superimposed" on the fine grid G: every s-th
-    fine node (stride ``prob.coarse_stride``); K inherits speed, cost, drift and
-    targets at the coincident nodes; a component with no coincident node gets the
-    coarse node nearest its lowest-index fine node; the SL step on K is h*s;
+  * the coarse grid K is a second uniform grid on the same box (Sec. 4 lets the
+    two triangulations differ; only both must cover the domain): nK_d nodes per
+    axis (``prob.coarse_n``, or every s-th fine node for a stride s dividing
+    n_d - 1).  Coarse node k of an axis lies at fine coordinate
+    k (n_d - 1)/(nK_d - 1).  K takes speed, cost and drift by the scheme's own
+    Q1 interpolation of the fine fields there (exact copies at coincident nodes),
+    target id and exit cost g from the nearest fine node (ties rounded up); a
+    component with no coarse node gets the coarse node nearest its lowest-index
+    fine node; the SL step on K is h times the largest ratio
+    (n_d - 1)/(nK_d - 1);
   * the auxiliary problem i (RA step 1, "T_i with boundary X_i") keeps component i
     at g and holds every other component's target nodes at the ghost value, a
     boundary datum larger than g ((gcond));
@@ -49,23 +55,89 @@ class Reconstruction:
     sweeps: List[int]
 
 
-def coarse_problem(prob):
-    """The superimposed coarse grid K (every s-th node) and its problem data."""
+def coarse_nodes(prob) -> tuple:
+    """Nodes per axis of the coarse grid K: ``prob.coarse_n`` when given, else every
+    s-th fine node (s = ``prob.coarse_stride`` must divide n_d - 1)."""
+    if getattr(prob, "coarse_n", None):
+        nK = tuple(int(k) for k in prob.coarse_n[:prob.dim])
+        for d in range(prob.dim):
+            if not 3 <= nK[d] <= prob.n[d]:
+                raise ValueError("coarse node counts must lie in [3, n_d]")
+        return nK
     s = int(prob.coarse_stride)
-    shp = prob.shape()
-    nK = tuple((prob.n[d] - 1) // s + 1 for d in range(prob.dim))
     for d in range(prob.dim):
         if (prob.n[d] - 1) % s:
             raise ValueError("coarse stride must divide n-1 on every axis")
-    sl = tuple(slice(None, None, s) for _ in range(prob.dim))
+    return tuple((prob.n[d] - 1) // s + 1 for d in range(prob.dim))
 
-    def sub(a):
+
+def fine_coordinate_of_coarse(n: int, nK: int):
+    """Coarse node k of an axis sits at fine coordinate k (n-1)/(nK-1) = i0 + t with
+    integer i0 and t = r/(nK-1) in [0, 1).  Returns (i0, i1 = min(i0+1, n-1), t, the
+    nearest fine index with ties rounded up), all by integer arithmetic but t."""
+    k = np.arange(nK, dtype=np.int64)
+    P = k * (n - 1)
+    i0 = P // (nK - 1)
+    r = P % (nK - 1)
+    t = r.astype(np.float64) / float(nK - 1)
+    i1 = np.minimum(i0 + 1, n - 1)
+    near = i0 + (2 * r >= nK - 1)
+    return i0, i1, t, near
+
+
+def coarse_coordinate_of_fine(n: int, nK: int):
+    """Fine node j of an axis sits at coarse coordinate j (nK-1)/(n-1) = c + r/(n-1).
+    Returns (c, r) as integers."""
+    j = np.arange(n, dtype=np.int64)
+    P = j * (nK - 1)
+    return P // (n - 1), P % (n - 1)
+
+
+def sample_q1(field: np.ndarray, n: tuple, nK: tuple) -> np.ndarray:
+    """Q1 (multilinear) interpolation of a fine node field at the coarse nodes, in
+    FP64: corner weights are products over the axes in axis order, and the corner
+    terms are summed in corner order starting from 0 (corner bit d = upper node on
+    axis d).  A coarse node that coincides with a fine node gets its value exactly."""
+    dim = len(n)
+    F = np.asarray(field, dtype=np.float64).reshape(tuple(reversed(n)))
+    maps = [fine_coordinate_of_coarse(n[d], nK[d]) for d in range(dim)]
+    acc = np.zeros(tuple(reversed(nK)))
+    for corner in range(1 << dim):
+        w = None
+        idx = []
+        for d in range(dim):
+            i0, i1, t, _ = maps[d]
+            up = (corner >> d) & 1
+            wd = t if up else (1.0 - t)
+            shape = [1] * dim
+            shape[dim - 1 - d] = nK[d]            # numpy axis of grid axis d
+            wd = wd.reshape(shape)
+            w = wd if w is None else w * wd
+            idx.append(i1 if up else i0)
+        acc = acc + w * F[np.ix_(*reversed(idx))]
+    return acc.reshape(-1)
+
+
+def coarse_problem(prob):
+    """The coarse grid K and its problem data (see the module notes)."""
+    dim = prob.dim
+    nK = coarse_nodes(prob)
+    n = tuple(prob.n[:dim])
+    shp = prob.shape()
+    near = [fine_coordinate_of_coarse(n[d], nK[d])[3] for d in range(dim)]
+    nearest_ix = np.ix_(*reversed(near))
+
+    def nearest(a):
         return None if a is None else np.ascontiguousarray(
-            np.asarray(a).reshape(shp)[sl]).reshape(-1)
+            np.asarray(a).reshape(shp)[nearest_ix]).reshape(-1)
 
-    tid = sub(prob.target).copy()
-    g = sub(prob.g)
+    def q1(a):
+        return None if a is None else sample_q1(a, n, nK)
+
+    tid = nearest(prob.target).copy()
+    g = nearest(prob.g)
     ftid = np.asarray(prob.target)
+    cmap = [coarse_coordinate_of_fine(n[d], nK[d]) for d in range(dim)]
     for i in range(prob.n_comp):
         if (tid == i).any():
             continue
@@ -73,16 +145,13 @@ def coarse_problem(prob):
         if nodes.size == 0:
             continue
         j = int(nodes[0])
-        ij = []
-        rem = j
-        for d in range(prob.dim):
-            ij.append(rem % prob.n[d])
-            rem //= prob.n[d]
-        kk = [min((ij[d] + s // 2) // s, nK[d] - 1) for d in range(prob.dim)]
-        jk = 0
-        stride = 1
-        for d in range(prob.dim):
-            jk += kk[d] * stride
+        jk, stride, rem = 0, 1, j
+        for d in range(dim):
+            jd = rem % n[d]
+            rem //= n[d]
+            c, r = int(cmap[d][0][jd]), int(cmap[d][1][jd])
+            kd = min(c + (1 if 2 * r >= n[d] - 1 else 0), nK[d] - 1)
+            jk += kd * stride
             stride *= nK[d]
         if tid[jk] < 0:
             tid[jk] = i
@@ -91,11 +160,12 @@ def coarse_problem(prob):
                 g[jk] = np.asarray(prob.g)[j]
     drift = None
     if prob.drift is not None:
-        dr = np.asarray(prob.drift).reshape(shp + (prob.dim,))
-        drift = np.ascontiguousarray(dr[sl]).reshape(-1, prob.dim)
-    return prob.with_(name=prob.name + "_K", n=nK, target=tid, speed=sub(prob.speed),
-                      cost=sub(prob.cost), g=g, drift=drift, h=prob.step * s,
-                      coarse_stride=1)
+        dr = np.asarray(prob.drift).reshape(-1, dim)
+        drift = np.stack([sample_q1(dr[:, d], n, nK) for d in range(dim)], axis=1)
+    ratio = max((n[d] - 1) / (nK[d] - 1) for d in range(dim))
+    return prob.with_(name=prob.name + "_K", n=nK, target=tid, speed=q1(prob.speed),
+                      cost=q1(prob.cost), g=g, drift=drift, h=prob.step * ratio,
+                      coarse_stride=1, coarse_n=None)
 
 
 def ra_delta(probK) -> float:
@@ -134,7 +204,7 @@ def reconstruct_on(probK, delta: Optional[float] = None, tol: Optional[float] = 
     return member, label, V_aux, V, delta, sweeps
 
 
-def project(member_K: np.ndarray, label_K: np.ndarray, nK: tuple, n: tuple, s: int):
+def project(member_K: np.ndarray, label_K: np.ndarray, nK: tuple, n: tuple):
     """ISA step 2: Con(.) projection of the coarse sets to the fine grid (integer
     only), orphan repair, and the nearest-coarse-node label."""
     dim = len(n)
@@ -152,12 +222,13 @@ def project(member_K: np.ndarray, label_K: np.ndarray, nK: tuple, n: tuple, s: i
         cells_and = v.copy() if cells_and is None else (cells_and & v)
         cells_or = v.copy() if cells_or is None else (cells_or | v)
     # per fine index and axis: the (up to two) coarse cells whose closure holds it
-    cand = []
+    cand, near = [], []
     for d in range(dim):
-        j = np.arange(n[d])
-        hi_c = np.minimum(j // s, nK[d] - 2)
-        lo_c = np.where(j % s == 0, np.maximum(j // s - 1, 0), hi_c)
+        c, r = coarse_coordinate_of_fine(n[d], nK[d])
+        hi_c = np.minimum(c, nK[d] - 2)
+        lo_c = np.where(r == 0, np.maximum(c - 1, 0), hi_c)
         cand.append((lo_c, hi_c))
+        near.append(np.minimum(c + (2 * r >= n[d] - 1), nK[d] - 1))
     mem = np.zeros(tuple(reversed(n)), dtype=np.uint8)
     orf = np.zeros_like(mem)
     for choice in range(1 << dim):
@@ -166,7 +237,6 @@ def project(member_K: np.ndarray, label_K: np.ndarray, nK: tuple, n: tuple, s: i
         mem |= cells_and[ix]
         orf |= cells_or[ix]
     mem = np.where(mem == 0, orf, mem).astype(np.uint8)
-    near = [np.minimum((np.arange(n[d]) + s // 2) // s, nK[d] - 1) for d in range(dim)]
     lab = lK[np.ix_(*reversed(near))]
     return mem.reshape(-1), np.ascontiguousarray(lab).reshape(-1)
 
@@ -175,7 +245,7 @@ def reconstruct(prob, delta: Optional[float] = None, max_sweeps: int = 10**7) ->
     """ISA steps 1-2: RA on the coarse grid K, projection to the fine grid."""
     probK = coarse_problem(prob)
     mK, lK, V_aux, VK, delta, sweeps = reconstruct_on(probK, delta, max_sweeps=max_sweeps)
-    mem, lab = project(mK, lK, probK.n, prob.n, prob.coarse_stride)
+    mem, lab = project(mK, lK, probK.n, prob.n)
     return Reconstruction(mK, lK, V_aux, VK, delta, probK.n, mem, lab, sweeps)
 
 

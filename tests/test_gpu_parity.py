@@ -125,7 +125,7 @@ def test_reconstruction_full_size_c2_labels():
     mKo, lKo, _, _, _, _ = I.reconstruct_on(probK)
     assert np.array_equal(host(mK), mKo)
     assert np.array_equal(host(lK), lKo)
-    mem, lab = I.project(mKo, lKo, probK.n, p.n, p.coarse_stride)
+    mem, lab = I.project(mKo, lKo, probK.n, p.n)
     assert np.array_equal(host(member), mem)
     assert np.array_equal(host(label), lab)
 

@@ -45,10 +45,12 @@ def test_jacobi_matches_exact_policy_iteration(name, mk):
     assert (pol[clear] == pol_x[clear]).all()
 
 
-def _con_bruteforce(member_K, nK, n, s):
-    """Con(.) by geometry: fine node x (in coarse units x/s) is in set i iff a closed
-    coarse cell containing x has all corners in set i; orphans take every set at
-    the corners of the cells containing them."""
+def _con_bruteforce(member_K, nK, n):
+    """Con(.) by geometry: fine node j of an axis lies at coarse coordinate
+    j (nK-1)/(n-1) (both grids span the same box); it is in set i iff a closed
+    coarse cell containing it has all corners in set i; orphans take every set at
+    the corners of the cells containing them.  Containment is tested exactly in
+    integers: base (n-1) <= j (nK-1) <= (base+1) (n-1)."""
     dim = len(n)
     mK = member_K.reshape(tuple(reversed(nK)))
 
@@ -59,7 +61,8 @@ def _con_bruteforce(member_K, nK, n, s):
     for fine in itertools.product(*[range(n[d]) for d in range(dim)]):
         cells = []
         for base in itertools.product(*[range(nK[d] - 1) for d in range(dim)]):
-            if all(base[d] * s <= fine[d] <= (base[d] + 1) * s for d in range(dim)):
+            if all(base[d] * (n[d] - 1) <= fine[d] * (nK[d] - 1) <= (base[d] + 1) * (n[d] - 1)
+                   for d in range(dim)):
                 cells.append(base)
         full = 0
         anyb = 0
@@ -75,26 +78,31 @@ def _con_bruteforce(member_K, nK, n, s):
     return out.reshape(-1)
 
 
-@pytest.mark.parametrize("dim,nK,s,seed", [(2, (5, 4), 3, 1), (2, (6, 6), 2, 2),
-                                           (3, (3, 4, 3), 2, 3), (2, (4, 4), 1, 4)])
-def test_projection_matches_geometric_bruteforce(dim, nK, s, seed):
+@pytest.mark.parametrize("dim,nK,n,seed", [
+    (2, (5, 4), (13, 10), 1), (2, (6, 6), (11, 11), 2), (3, (3, 4, 3), (5, 7, 5), 3),
+    (2, (4, 4), (4, 4), 4),
+    # coarse grids not nested in the fine grid
+    (2, (5, 4), (12, 11), 5), (2, (7, 3), (10, 8), 6), (3, (3, 4, 4), (7, 6, 9), 7),
+    (2, (15, 15), (41, 41), 8)])
+def test_projection_matches_geometric_bruteforce(dim, nK, n, seed):
     """ISA step 2 (Sec. 4, Con(.) = union of the cells with all vertices in the set)
     against a geometric brute force on random coarse bitmasks."""
+    from fractions import Fraction
     rng = np.random.Generator(np.random.PCG64(seed))
     NK = int(np.prod(nK))
     # random sets with some structure: a few bits set with high probability
     member_K = (rng.random((NK, 3)) < np.array([0.7, 0.5, 0.3])).astype(np.uint8)
     member_K = (member_K[:, 0] | (member_K[:, 1] << 1) | (member_K[:, 2] << 2)).astype(np.uint8)
     label_K = rng.integers(0, 3, NK).astype(np.uint8)
-    n = tuple((nK[d] - 1) * s + 1 for d in range(dim))
-    mem, lab = I.project(member_K, label_K, nK, n, s)
-    assert (mem == _con_bruteforce(member_K, nK, n, s)).all()
-    # nearest coarse node label (ties rounded up)
+    mem, lab = I.project(member_K, label_K, nK, n)
+    assert (mem == _con_bruteforce(member_K, nK, n)).all()
+    # nearest coarse node label (ties rounded up), by exact rational rounding
     lk = label_K.reshape(tuple(reversed(nK)))
     for j in range(int(np.prod(n))):
         idx, r = [], j
         for d in range(dim):
             idx.append(r % n[d])
             r //= n[d]
-        near = [min(int(np.floor(idx[d] / s + 0.5)), nK[d] - 1) for d in range(dim)]
+        near = [min(int(Fraction(idx[d] * (nK[d] - 1), n[d] - 1) + Fraction(1, 2)), nK[d] - 1)
+                for d in range(dim)]
         assert lab[j] == lk[tuple(reversed(near))]

@@ -28,6 +28,7 @@ import numpy as np
 __all__ = [
     "Problem", "grid_axes", "node_coords", "controls_2d", "controls_3d_fibonacci",
     "spd_matrix", "gaussian_field", "separated_centres", "ball_targets", "coarse_stride",
+    "coarse_nodes_for",
     "c1_eikonal", "c2_multitarget", "c3_aniso3d", "c4_batch", "c5_adjoint",
     "strip_problem", "box_distance_problem", "vdp_problem", "obs_nodes",
 ]
@@ -53,6 +54,7 @@ class Problem:
     v_ghost: float = 1.0
     disc: str = "exp"                    # "exp": beta=e^{-lam h}; "paper": beta=1/(1+lam h)
     coarse_stride: int = 1
+    coarse_n: Optional[tuple] = None     # coarse nodes per axis; None -> every coarse_stride-th node
     ra_C: float = 0.5                    # RA threshold 2 (C dx^q + M dx); these
     ra_M: float = 0.5                    # defaults give delta = 2 dx of the coarse grid
     ra_q: float = 1.0
@@ -213,6 +215,15 @@ def coarse_stride(n: int, dx: float, r_min: float) -> int:
     return 1
 
 
+def coarse_nodes_for(n: int, width: float, r_min: float, max_ratio: int = 8,
+                     min_nodes: int = 17) -> int:
+    """Coarse nodes on an axis of n fine nodes (any count, not nested in general):
+    the fewest with a coarse step <= r_min (so every target ball of radius r_min
+    holds coarse nodes) and <= max_ratio fine steps, at least min_nodes, at most n."""
+    k = max(min_nodes - 1, math.ceil((n - 1) / max_ratio), math.ceil(width / r_min - 1e-9))
+    return min(n, k + 1)
+
+
 # -------------------------------------------------------------------------- problems
 def c1_eikonal(n: int = 101, m: int = 32) -> Problem:
     """2D eikonal min-time on [-1,1]^2, f = a (|a| = 1), l = 1, point target at the
@@ -261,7 +272,9 @@ def c3_aniso3d(n: int = 257, m: int = 128, n_balls: int = 8, r: float = 0.04,
 def c4_batch(count: int = 512, seed: int = 404, n_min: int = 16, n_max: int = 512,
              m: int = 32, r: float = 0.05) -> List[Problem]:
     """Independent 2D problems with side lengths log-uniform in [n_min, n_max],
-    1-6 target disks each and a smooth seeded speed field (sigma = 0.1 physical)."""
+    1-6 target disks each and a smooth seeded speed field (sigma = 0.1 physical).
+    The sides are arbitrary, so each coarse grid is chosen by node count
+    (``coarse_nodes_for``) rather than by a stride dividing n - 1."""
     out = []
     for p in range(count):
         rng = np.random.Generator(np.random.PCG64(seed + p))
@@ -272,9 +285,10 @@ def c4_batch(count: int = 512, seed: int = 404, n_min: int = 16, n_max: int = 51
         c = f32(np.exp(0.5 * g)).reshape(-1)
         cen = separated_centres(k, 2, 0.3, seed + p + 200000)
         tid = ball_targets((n, n), (-1.0, -1.0), (1.0, 1.0), cen, r)
+        nK = coarse_nodes_for(n, 2.0, r)
         out.append(Problem(name=f"batch{p}_{n}", dim=2, n=(n, n), lo=(-1.0, -1.0),
                            hi=(1.0, 1.0), velocity=controls_2d(m), target=tid, n_comp=k,
-                           speed=c, v_ghost=1.0, coarse_stride=coarse_stride(n, dx, r),
+                           speed=c, v_ghost=1.0, coarse_n=(nK, nK),
                            meta={"centres": cen, "r": r}))
     return out
 
