@@ -82,7 +82,7 @@ def leg_c3(steps: int):
     import workloads as W
     p = W.c3_aniso3d()
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
                   autotune=1)
     opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1)
     S.isa(dp, ra, opts)
@@ -113,7 +113,7 @@ def leg_c4(steps: int):
     import workloads as W
     probs = W.c4_batch()
     dps = [S.to_device(p, torch.float32, "cuda:0") for p in probs]
-    ras = [S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
+    ras = [S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
                   autotune=1) for p in probs]
     opts = S.SolveOpts(tol=1e-6, autotune=2)
     S.solve_batched(dps, ras, opts)
@@ -128,7 +128,7 @@ def leg_c4(steps: int):
     # one call per problem, default kernels (no per-size tuning inside the timing)
     single = S.SolveOpts(tol=1e-6)
     for dp, p in zip(dps, probs):
-        S.isa(dp, S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q,
+        S.isa(dp, S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q,
                            tol=p.ra_tol), single)
     _sync()
     ms_single = (time.perf_counter() - t0) * 1e3
@@ -149,7 +149,7 @@ def leg_c5(steps: int):
     import workloads as W
     p = W.c5_adjoint()
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
                   autotune=1)
     member, label, _ = S.reconstruct(dp, ra)
     th_true = torch.as_tensor(p.meta["theta_true"], dtype=torch.float32, device="cuda:0")
@@ -249,7 +249,7 @@ def main():
 
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=prob.coarse_stride, C=prob.ra_C, M=prob.ra_M, q=prob.ra_q,
+    ra = S.RaOpts(coarse_stride=prob.coarse_stride, coarse_n=prob.coarse_n, C=prob.ra_C, M=prob.ra_M, q=prob.ra_q,
                   tol=prob.ra_tol, autotune=1)
     # --sweep-config k forces candidate k-1; 0 lets the warm-up step run the
     # autotuner (complete solves as trials) and the timed steps use its pick

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SLHJB_ABI_VERSION 1
+#define SLHJB_ABI_VERSION 2
 #define SL_MAX_COMP 8
 #define SL_MAX_CONTROLS 256
 
@@ -80,7 +80,17 @@ typedef struct sl_problem {
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */
 typedef struct sl_ra_opts {
-    int coarse_stride;        /* s >= 1 dividing n_d - 1: coarse grid K = every s-th node */
+    int coarse_stride;        /* s >= 1 dividing n_d - 1: coarse grid K = every s-th node
+                                 (used when coarse_n[0] == 0)                           */
+    int coarse_n[3];          /* > 0: K has coarse_n[d] nodes per used axis, 3 <= coarse_n[d]
+                                 <= n[d], on the same box; it need not be nested in the fine
+                                 grid (Sec. 4 asks only that both grids cover the domain).
+                                 Coarse node k of an axis sits at fine coordinate
+                                 k (n_d - 1)/(coarse_n[d] - 1); K takes speed and cost by Q1
+                                 interpolation of the fine fields (FP64, corner weights as
+                                 products in axis order, corners summed in order from 0),
+                                 target ids and g from the nearest fine node (ties up); the
+                                 coarse step is h * max_d (n_d - 1)/(coarse_n[d] - 1).   */
     double C, M, q;           /* threshold delta = 2 (C dx_K^q + M dx_K) (Prop. 3.1)  */
     double delta_override;    /* > 0: use this delta instead                          */
     double tol;               /* coarse stopping tolerance on max|V_new - V| (0 = until nothing changes) */
@@ -118,6 +128,8 @@ typedef struct sl_stats {
     int variant;              /* sweep kernel variant used (tile shape)               */
     int mode;                 /* work schedule used: 0 per item, 1 queue, 2 stride    */
     int tile[3];              /* tile shape used                                      */
+    long ra_sweeps_max;       /* RA: most coarse sweeps of one auxiliary problem
+                                 (sl_reconstruct, sl_solve_batched; else 0)           */
 } sl_stats;
 
 const char *sl_status_string(int status);
@@ -146,7 +158,10 @@ size_t sl_isa_workspace_size(const sl_problem *p, const sl_ra_opts *ra);
  * fused multiply-add accumulation in corner order, candidate fma(beta, I, w l)),
  * so the labels are reproducible bit for bit.
  * Outputs (DEVICE, N uint8 each): member = bitmask of the sets containing each
- * fine node; label = coarse argmin component at the nearest coarse node.
+ * fine node (Con(.): the union of the closed coarse cells with every corner in the
+ * set; a fine node in no such cell takes every set present at the corners of the
+ * cells holding it); label = coarse argmin component at the nearest coarse node
+ * (ties rounded up).  Cells and nearest nodes are located in exact integers.
  * member_K, label_K (DEVICE, N_K uint8 each) may be NULL. */
 int sl_reconstruct(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t ws_bytes,
                    uint8_t *member, uint8_t *label, uint8_t *member_K, uint8_t *label_K,

@@ -48,7 +48,8 @@ class SlProblem(C.Structure):
 
 
 class SlRaOpts(C.Structure):
-    _fields_ = [("coarse_stride", C.c_int), ("C", C.c_double), ("M", C.c_double),
+    _fields_ = [("coarse_stride", C.c_int), ("coarse_n", C.c_int * 3), ("C", C.c_double),
+                ("M", C.c_double),
                 ("q", C.c_double), ("delta_override", C.c_double), ("tol", C.c_double),
                 ("max_sweeps", C.c_long), ("autotune", C.c_int)]
 
@@ -64,7 +65,7 @@ class SlStats(C.Structure):
                 ("ms_fine", C.c_double), ("ms_total", C.c_double), ("n_subdomains", C.c_int),
                 ("n_unreachable", C.c_int), ("set_fraction_max", C.c_double),
                 ("ms_sweeps", C.c_double), ("sweep_launches", C.c_long), ("variant", C.c_int),
-                ("mode", C.c_int), ("tile", C.c_int * 3)]
+                ("mode", C.c_int), ("tile", C.c_int * 3), ("ra_sweeps_max", C.c_long)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -158,6 +159,7 @@ class DeviceProblem:
 @dataclass
 class RaOpts:
     coarse_stride: int = 1
+    coarse_n: Optional[tuple] = None      # coarse nodes per axis (any counts); None -> stride
     C: float = 0.5
     M: float = 0.5
     q: float = 1.0
@@ -245,8 +247,16 @@ def _stream():
 
 
 def _ra(o: RaOpts) -> SlRaOpts:
-    return SlRaOpts(o.coarse_stride, o.C, o.M, o.q, o.delta_override, o.tol, o.max_sweeps,
-                    int(o.autotune))
+    cn = tuple(o.coarse_n or ()) + (0, 0, 0)
+    return SlRaOpts(o.coarse_stride, (C.c_int * 3)(*[int(x) for x in cn[:3]]), o.C, o.M, o.q,
+                    o.delta_override, o.tol, o.max_sweeps, int(o.autotune))
+
+
+def coarse_nodes(p, ra: RaOpts) -> tuple:
+    """Nodes per axis of the coarse grid that ``ra`` describes for problem ``p``."""
+    if ra.coarse_n:
+        return tuple(int(ra.coarse_n[d]) for d in range(p.dim))
+    return tuple((p.n[d] - 1) // ra.coarse_stride + 1 for d in range(p.dim))
 
 
 def _so(o: SolveOpts) -> SlSolveOpts:
@@ -297,9 +307,7 @@ def reconstruct(p: DeviceProblem, ra: RaOpts, want_coarse: bool = False, workspa
     ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
     member = torch.empty(p.N, dtype=torch.uint8, device=dev)
     label = torch.empty(p.N, dtype=torch.uint8, device=dev)
-    NK = 1
-    for d in range(p.dim):
-        NK *= (p.n[d] - 1) // ra.coarse_stride + 1
+    NK = int(np.prod(coarse_nodes(p, ra)))
     mK = torch.empty(NK, dtype=torch.uint8, device=dev) if want_coarse else None
     lK = torch.empty(NK, dtype=torch.uint8, device=dev) if want_coarse else None
     st = SlStats()

@@ -85,10 +85,15 @@ int validate_solve_opts(const sl_solve_opts *o) {
 
 int validate_ra(const sl_problem *p, const sl_ra_opts *ra) {
     if (!ra) return SL_ERR_INVALID_ARG;
-    if (ra->coarse_stride < 1) return SL_ERR_INVALID_ARG;
-    for (int d = 0; d < p->dim; ++d) {
-        if ((p->n[d] - 1) % ra->coarse_stride) return SL_ERR_INVALID_ARG;
-        if ((p->n[d] - 1) / ra->coarse_stride + 1 < 3) return SL_ERR_INVALID_ARG;
+    if (ra->coarse_n[0] > 0) {
+        for (int d = 0; d < p->dim; ++d)
+            if (ra->coarse_n[d] < 3 || ra->coarse_n[d] > p->n[d]) return SL_ERR_INVALID_ARG;
+    } else {
+        if (ra->coarse_stride < 1) return SL_ERR_INVALID_ARG;
+        for (int d = 0; d < p->dim; ++d) {
+            if ((p->n[d] - 1) % ra->coarse_stride) return SL_ERR_INVALID_ARG;
+            if ((p->n[d] - 1) / ra->coarse_stride + 1 < 3) return SL_ERR_INVALID_ARG;
+        }
     }
     if (!std::isfinite(ra->C) || !std::isfinite(ra->M) || !std::isfinite(ra->q))
         return SL_ERR_INVALID_ARG;
@@ -544,6 +549,15 @@ void fill_stats(sl_stats *stats, const std::vector<SdState> &hs, unsigned long l
     stats->node_control_updates = (double)nc;
     stats->n_subdomains = (int)hs.size();
     stats->n_unreachable = 0;
+    stats->ra_sweeps_max = 0;
+}
+
+// Most sweeps over sub-domains [b, e) of a state vector (S for unconverged ones).
+long sweeps_of(const std::vector<SdState> &hs, size_t b, size_t e, long S) {
+    long smax = 0;
+    for (size_t i = b; i < e && i < hs.size(); ++i)
+        smax = std::max(smax, hs[i].conv_at >= 0 ? (long)hs[i].conv_at + 1 : S);
+    return smax;
 }
 
 void fill_cfg(sl_stats *stats, const LaunchCfg &c) {
@@ -708,22 +722,28 @@ struct CoarseGeom {
     double hK;
 };
 
-CoarseGeom coarse_geom(const sl_problem *p, int s) {
+// The coarse grid K: coarse_n nodes per axis, else every s-th fine node; the SL
+// step on K is h times the largest spacing ratio (n_d - 1)/(nK_d - 1).
+CoarseGeom coarse_geom(const sl_problem *p, const sl_ra_opts *ra) {
     CoarseGeom g{};
     g.NK = 1;
+    double ratio = 0.0;
     for (int d = 0; d < 3; ++d) {
-        g.nK[d] = d < p->dim ? (p->n[d] - 1) / s + 1 : 1;
+        if (d >= p->dim) {
+            g.nK[d] = 1;
+            continue;
+        }
+        g.nK[d] = ra->coarse_n[0] > 0 ? ra->coarse_n[d] : (p->n[d] - 1) / ra->coarse_stride + 1;
         g.NK *= (size_t)g.nK[d];
+        ratio = std::max(ratio, (double)(p->n[d] - 1) / (double)(g.nK[d] - 1));
     }
-    g.hK = p->h * s;
+    g.hK = p->h * ratio;
     return g;
 }
 
 template <typename T>
 struct IsaPlan {
     // coarse
-    T *cK_t = nullptr;             // gathered speed (dtype)
-    T *lK_t = nullptr;             // gathered cost (dtype)
     double *cK = nullptr, *wlK = nullptr, *gK = nullptr, *ctrlK = nullptr, *gK_src = nullptr;
     T *gK_t = nullptr;
     int8_t *tK = nullptr;
@@ -743,11 +763,9 @@ struct IsaPlan {
 template <typename T>
 void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P) {
     const size_t N = nodes_of(p);
-    const CoarseGeom cg = coarse_geom(p, ra->coarse_stride);
+    const CoarseGeom cg = coarse_geom(p, ra);
     const int nc = p->n_comp;
     const int tilesK = max_tiles(p->dim, SL_F64, cg.nK);
-    P.cK_t = a.take<T>(cg.NK);
-    P.lK_t = a.take<T>(cg.NK);
     P.gK_t = a.take<T>(cg.NK);
     P.cK = a.take<double>(cg.NK);
     P.wlK = a.take<double>(cg.NK);
@@ -780,8 +798,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     IsaPlan<T> P;
     plan_isa<T>(p, ra, a, P);
     if (!a.fits()) return SL_ERR_WORKSPACE;
-    const int sK = ra->coarse_stride;
-    const CoarseGeom cg = coarse_geom(p, sK);
+    const CoarseGeom cg = coarse_geom(p, ra);
     const int nc = p->n_comp;
 
     // fine-grid statistics: validation and lowest node per component
@@ -791,20 +808,16 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     if (rc) return rc;
     if ((rc = check_fields(fs))) return rc;
 
-    // coarse problem data: every s-th node, widened to FP64
-    if (p->speed) {
-        HIPCHK(launch_gather_coarse<T>((const T *)p->speed, P.cK_t, p->n, cg.nK, p->dim, sK, 1, s));
-        HIPCHK((launch_scale_field<T, double>(P.cK_t, P.cK, cg.NK, 1.0, s)));
-    }
+    // coarse problem data: speed and cost by Q1 interpolation in FP64 (exact copies
+    // at coincident nodes), target ids and g from the nearest fine node
     double betaK, wK, emaxK;
     scheme_constants(p->lambda, cg.hK, p->disc, &betaK, &wK);
-    if (p->cost) {
-        HIPCHK(launch_gather_coarse<T>((const T *)p->cost, P.lK_t, p->n, cg.nK, p->dim, sK, 1, s));
-        HIPCHK((launch_scale_field<T, double>(P.lK_t, P.wlK, cg.NK, wK, s)));
-    }
-    if (p->g)
-        HIPCHK(launch_gather_coarse<T>((const T *)p->g, P.gK_t, p->n, cg.nK, p->dim, sK, 1, s));
-    HIPCHK(launch_gather_coarse_i8(p->target, P.tK, p->n, cg.nK, p->dim, sK, s));
+    if (p->speed)
+        HIPCHK(launch_sample_coarse<T>((const T *)p->speed, P.cK, p->n, cg.nK, p->dim, 1, 1.0, s));
+    if (p->cost)
+        HIPCHK(launch_sample_coarse<T>((const T *)p->cost, P.wlK, p->n, cg.nK, p->dim, 1, wK, s));
+    if (p->g) HIPCHK(launch_gather_nearest<T>((const T *)p->g, P.gK_t, p->n, cg.nK, p->dim, s));
+    HIPCHK(launch_gather_nearest<int8_t>(p->target, P.tK, p->n, cg.nK, p->dim, s));
     // components without a coincident coarse node: place them (in the field's own
     // dtype), then widen g to FP64
     {
@@ -818,7 +831,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
         const int *firstK = reinterpret_cast<const int *>(
             reinterpret_cast<const char *>(P.fsK) + offsetof(FieldStats, first_node));
         HIPCHK(launch_place_missing<T>(P.tK, p->g ? P.gK_t : nullptr, (const T *)p->g,
-                                       first_fine, firstK, p->n, cg.nK, p->dim, sK, nc, s));
+                                       first_fine, firstK, p->n, cg.nK, p->dim, nc, s));
         if (p->g) HIPCHK((launch_scale_field<T, double>(P.gK_t, P.gK, cg.NK, 1.0, s)));
     }
 
@@ -880,13 +893,14 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     uint8_t *lbK = label_K ? label_K : P.lbK;
     HIPCHK(launch_ra_combine(P.Vpack, nc, cg.NK, P.tK, delta, mK, lbK, s));
     // ISA step 2: projection to the fine grid
-    HIPCHK(launch_project(mK, lbK, cg.nK, p->n, p->dim, sK, member, label, s));
+    HIPCHK(launch_project(mK, lbK, cg.nK, p->n, p->dim, member, label, s));
     tm.mark(1, s);
     std::vector<SdState> hs;
     unsigned long long ncu = 0;
     if ((rc = P.exK.read_stats(s, hs, &ncu))) return rc;
     fill_stats(stats, hs, ncu, S);
     if (stats) {
+        stats->ra_sweeps_max = sweeps_of(hs, 0, hs.size(), S);
         stats->ms_ra = tm.ms(0, 1);
         stats->ms_fine = 0.0;
         stats->ms_total = tm.ms(0, 1);
@@ -1141,14 +1155,12 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
     for (int q = 0; q < np; ++q) {
         const sl_problem *p = &probs[q];
         ProbDesc<T> &d = B.hp[q];
-        const int sK = ras[q].coarse_stride;
-        const CoarseGeom cg = coarse_geom(p, sK);
+        const CoarseGeom cg = coarse_geom(p, &ras[q]);
         d.dim = dim;
         for (int k = 0; k < 3; ++k) {
             d.n[k] = k < dim ? p->n[k] : 1;
             d.nK[k] = cg.nK[k];
         }
-        d.stride = sK;
         d.n_comp = p->n_comp;
         d.N = nodes_of(p);
         d.NK = cg.NK;
@@ -1219,7 +1231,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         d.G = p->v_ghost;
         double beta, w, betaK, wK;
         scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
-        scheme_constants(p->lambda, p->h * ras[q].coarse_stride, p->disc, &betaK, &wK);
+        scheme_constants(p->lambda, coarse_geom(p, &ras[q]).hK, p->disc, &betaK, &wK);
         d.w = w;
         d.wK = wK;
         double dxK = 0.0;
@@ -1250,7 +1262,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         std::vector<double> e, eK;
         double emax, emaxK;
         control_table(p, p->n, p->h, e, &emax);
-        control_table(p, B.hp[q].nK, p->h * ras[q].coarse_stride, eK, &emaxK);
+        control_table(p, B.hp[q].nK, coarse_geom(p, &ras[q]).hK, eK, &emaxK);
         const double smax = p->speed ? bits_to_double(fs[q].speed_max) : 1.0;
         Hq[q] = halo_for(smax, emax);
         HKq[q] = halo_for(smax, emaxK);
@@ -1276,7 +1288,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         const sl_problem *p = &probs[q];
         const ProbDesc<T> &d = B.hp[q];
         double betaK, wK;
-        scheme_constants(p->lambda, p->h * ras[q].coarse_stride, p->disc, &betaK, &wK);
+        scheme_constants(p->lambda, coarse_geom(p, &ras[q]).hK, p->disc, &betaK, &wK);
         for (int i = 0; i < p->n_comp; ++i) {
             SdDesc<double> sd{};
             sd.V[0] = d.Vaux + (size_t)i * 2 * d.NK;
@@ -1355,6 +1367,8 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             const ProbDesc<T> &d = B.hp[q];
             std::vector<SdState> sub(hs.begin() + d.sd_fine0, hs.begin() + d.sd_fine0 + d.n_comp);
             fill_stats(&per_problem[q], sub, 0, S);
+            per_problem[q].ra_sweeps_max =
+                sweeps_of(hsK, d.sd_coarse0, d.sd_coarse0 + d.n_comp, SK);
             per_problem[q].node_control_updates = 0.0;
             per_problem[q].ms_ra = per_problem[q].ms_fine = per_problem[q].ms_total = 0.0;
             per_problem[q].set_fraction_max = 0.0;
@@ -1364,6 +1378,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     }
     if (total) {
         fill_stats(total, hs, nc, S);
+        total->ra_sweeps_max = sweeps_of(hsK, 0, hsK.size(), SK);
         total->ms_ra = tm.ms(0, 1);
         total->ms_fine = tm.ms(1, 2);
         total->ms_total = tm.ms(0, 3);

@@ -96,24 +96,26 @@ __global__ __launch_bounds__(kB) void k_b_stats(const ProbDesc<T> *pd, const int
     }
 }
 
-// Coarse data of every problem: every s-th fine node, widened to FP64, cost
-// weighted by the coarse step's w; coarse target presence per component.
+// Coarse data of every problem: Q1 interpolation (FP64) of speed and cost at the
+// coarse nodes, the cost weighted by the coarse step's w; target id and g from the
+// nearest fine node; coarse target presence per component.
 template <typename T>
 __global__ __launch_bounds__(kB) void k_b_coarse_prep(const ProbDesc<T> *pd, const int *blkp,
                                                       int np, int chunk) {
     const Seg sg = segment(blkp, np, chunk, 0);
     const ProbDesc<T> &d = pd[sg.p];
     const size_t end = sg.end < d.NK ? sg.end : d.NK;
-    const int s = d.stride;
     for (size_t k = sg.begin + threadIdx.x; k < end; k += kB) {
-        const int a = (int)(k % d.nK[0]);
-        const int b = (int)((k / d.nK[0]) % d.nK[1]);
-        const int c = (int)(k / ((size_t)d.nK[0] * d.nK[1]));
-        const size_t j = ((size_t)c * s * d.n[1] + (size_t)b * s) * d.n[0] + (size_t)a * s;
+        AxisPos ax[3];
+        ax[0] = fine_pos_of_coarse((int)(k % d.nK[0]), d.n[0], d.nK[0]);
+        ax[1] = fine_pos_of_coarse((int)((k / d.nK[0]) % d.nK[1]), d.n[1], d.nK[1]);
+        ax[2] = d.dim == 3 ? fine_pos_of_coarse((int)(k / ((size_t)d.nK[0] * d.nK[1])), d.n[2], d.nK[2])
+                           : AxisPos{0, 0, 0, 0.0};
+        const size_t j = ((size_t)ax[2].near * d.n[1] + ax[1].near) * d.n[0] + ax[0].near;
         const int t = d.target[j];
         d.tK[k] = (int8_t)t;
-        if (d.speed) d.cK[k] = (double)d.speed[j];
-        if (d.cost) d.wlK[k] = d.wK * (double)d.cost[j];
+        if (d.speed) d.cK[k] = 1.0 * sample_q1(d.speed, 1, 0, d.n[0], d.n[1], d.dim, ax);
+        if (d.cost) d.wlK[k] = d.wK * sample_q1(d.cost, 1, 0, d.n[0], d.n[1], d.dim, ax);
         if (d.g) d.gK[k] = (double)d.g[j];
         if (t >= 0 && t < d.n_comp) atomicMin(&d.fsK->first_node[t], (int)k);
     }
@@ -124,16 +126,15 @@ __global__ void k_b_place_missing(const ProbDesc<T> *pd, int np) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const ProbDesc<T> &d = pd[p];
-    const int s = d.stride;
     for (int i = 0; i < d.n_comp; ++i) {
         if (d.fsK->first_node[i] != INT_MAX) continue;
         const int j = d.fs->first_node[i];
         if (j == INT_MAX) continue;
         const int a = j % d.n[0], b = (j / d.n[0]) % d.n[1], c = j / (d.n[0] * d.n[1]);
-        int ka = (a + s / 2) / s, kb = (b + s / 2) / s, kc = (c + s / 2) / s;
-        ka = ka < d.nK[0] - 1 ? ka : d.nK[0] - 1;
-        kb = kb < d.nK[1] - 1 ? kb : d.nK[1] - 1;
-        kc = kc < d.nK[2] - 1 ? kc : d.nK[2] - 1;
+        int lo, hi, ka, kb, kc = 0;
+        coarse_cells_of_fine(a, d.n[0], d.nK[0], lo, hi, ka);
+        coarse_cells_of_fine(b, d.n[1], d.nK[1], lo, hi, kb);
+        if (d.dim == 3) coarse_cells_of_fine(c, d.n[2], d.nK[2], lo, hi, kc);
         const size_t jk = ((size_t)kc * d.nK[1] + kb) * d.nK[0] + ka;
         if (d.tK[jk] < 0) {
             d.tK[jk] = (int8_t)i;
@@ -191,17 +192,6 @@ __global__ __launch_bounds__(kB) void k_b_combine(const ProbDesc<T> *pd, const S
     }
 }
 
-__device__ __forceinline__ void b_cells_of(int j, int s, int nK, int &lo, int &hi) {
-    hi = j / s;
-    hi = hi < nK - 2 ? hi : nK - 2;
-    if (j % s == 0) {
-        lo = j / s - 1;
-        lo = lo > 0 ? lo : 0;
-    } else {
-        lo = hi;
-    }
-}
-
 // ISA step 2 of every problem (Con(.) projection, orphan repair, label) and the
 // fine initial values / cost weights.
 template <typename T>
@@ -210,17 +200,17 @@ __global__ __launch_bounds__(kB) void k_b_project_init(const ProbDesc<T> *pd, co
     const Seg sg = segment(blkp, np, chunk, 0);
     const ProbDesc<T> &d = pd[sg.p];
     const size_t end = sg.end < d.N ? sg.end : d.N;
-    const int s = d.stride, dim = d.dim;
-    const int k0 = d.nK[0], k1 = d.nK[1], k2 = d.nK[2];
+    const int dim = d.dim;
+    const int k0 = d.nK[0], k1 = d.nK[1];
     for (size_t j = sg.begin + threadIdx.x; j < end; j += kB) {
         const int a = (int)(j % d.n[0]);
         const int b = (int)((j / d.n[0]) % d.n[1]);
         const int c = (int)(j / ((size_t)d.n[0] * d.n[1]));
-        int lo[3], hi[3];
-        b_cells_of(a, s, k0, lo[0], hi[0]);
-        b_cells_of(b, s, k1, lo[1], hi[1]);
-        if (dim == 3) b_cells_of(c, s, k2, lo[2], hi[2]);
-        else lo[2] = hi[2] = 0;
+        int lo[3], hi[3], nr[3];
+        coarse_cells_of_fine(a, d.n[0], k0, lo[0], hi[0], nr[0]);
+        coarse_cells_of_fine(b, d.n[1], k1, lo[1], hi[1], nr[1]);
+        if (dim == 3) coarse_cells_of_fine(c, d.n[2], d.nK[2], lo[2], hi[2], nr[2]);
+        else lo[2] = hi[2] = nr[2] = 0;
         unsigned full = 0, anyb = 0;
         for (int ch = 0; ch < (1 << dim); ++ch) {
             const int ca = (ch & 1) ? hi[0] : lo[0];
@@ -237,12 +227,7 @@ __global__ __launch_bounds__(kB) void k_b_project_init(const ProbDesc<T> *pd, co
         }
         const unsigned bits = full ? full : anyb;
         d.member[j] = (uint8_t)bits;
-        int na = (a + s / 2) / s, nb = (b + s / 2) / s, nc = (c + s / 2) / s;
-        na = na < k0 - 1 ? na : k0 - 1;
-        nb = nb < k1 - 1 ? nb : k1 - 1;
-        nc = nc < k2 - 1 ? nc : k2 - 1;
-        if (dim < 3) nc = 0;
-        d.label[j] = d.labelK[((size_t)nc * k1 + nb) * k0 + na];
+        d.label[j] = d.labelK[((size_t)nr[2] * k1 + nr[1]) * k0 + nr[0]];
         // fine initial values (targets at g, others at the ghost value) in every
         // set's two buffers, and the per-node cost weight
         const T v = d.target[j] >= 0 ? (d.g ? d.g[j] : T(0)) : (T)d.G;

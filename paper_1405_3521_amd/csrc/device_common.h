@@ -45,6 +45,63 @@ struct Foot<double> {
     }
 };
 
+// ---- coarse grid K and fine grid G on the same box (any node counts)
+// Coarse node k of an axis (n fine, nK coarse nodes) lies at fine coordinate
+// k (n-1)/(nK-1) = i0 + r/(nK-1): the two fine nodes around it, the fraction, and
+// the nearest fine node (ties rounded up).  Integer arithmetic except t.
+struct AxisPos {
+    int i0, i1, near;
+    double t;
+};
+
+__device__ __forceinline__ AxisPos fine_pos_of_coarse(int k, int n, int nK) {
+    const long long P = (long long)k * (n - 1);
+    const int q = nK - 1;
+    AxisPos a;
+    a.i0 = (int)(P / q);
+    const int r = (int)(P - (long long)a.i0 * q);
+    a.t = (double)r / (double)q;
+    a.i1 = a.i0 + 1 < n ? a.i0 + 1 : n - 1;
+    a.near = a.i0 + (2 * r >= q ? 1 : 0);
+    return a;
+}
+
+// Fine node j of an axis lies at coarse coordinate j (nK-1)/(n-1) = c + r/(n-1):
+// the coarse cells [lo, hi] whose closure holds it and its nearest coarse node.
+__device__ __forceinline__ void coarse_cells_of_fine(int j, int n, int nK, int &lo, int &hi,
+                                                     int &near) {
+    const long long P = (long long)j * (nK - 1);
+    const int q = n - 1;
+    const int c = (int)(P / q);
+    const int r = (int)(P - (long long)c * q);
+    hi = c < nK - 2 ? c : nK - 2;
+    lo = r == 0 ? (c - 1 > 0 ? c - 1 : 0) : hi;
+    near = c + (2 * r >= q ? 1 : 0);
+    near = near < nK - 1 ? near : nK - 1;
+}
+
+// Q1 value of a fine node field (comps values per node, component q) at coarse
+// node (ax[0], ax[1], ax[2]), in FP64: corner weights are products over the axes
+// in axis order, corner terms summed in corner order from 0 (corner bit d = upper
+// node on axis d).  Compiled without contraction, so the value is reproducible.
+template <typename T>
+__device__ __forceinline__ double sample_q1(const T *f, int comps, int q, int n0, int n1,
+                                            int dim, const AxisPos *ax) {
+    double acc = 0.0;
+    for (int corner = 0; corner < (1 << dim); ++corner) {
+        double w = 1.0;
+        int id[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+            const bool up = (corner >> d) & 1;
+            w = w * (up ? ax[d].t : 1.0 - ax[d].t);
+            id[d] = up ? ax[d].i1 : ax[d].i0;
+        }
+        const size_t j = ((size_t)id[2] * n1 + id[1]) * n0 + id[0];
+        acc = acc + w * (double)f[j * comps + q];
+    }
+    return acc;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

@@ -110,7 +110,7 @@ struct AdjDesc {
 // coarse and fine sub-domain in the joint executors.
 template <typename T>
 struct ProbDesc {
-    int dim, n[3], nK[3], stride, n_comp;
+    int dim, n[3], nK[3], n_comp;
     size_t N, NK;
     const int8_t *target;
     const T *speed, *cost, *g;
@@ -196,17 +196,19 @@ template <typename T>
 hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, int n_sd,
                               int total_tiles, const int *tile_prefix_dev, WorkItem *items,
                               ExecCounters *cnt, const int *class_off, hipStream_t s);
-// Coarse grid gather: dst[k] = src[k*s per axis]
+// Coarse data: Q1 interpolation (FP64) of a fine field at the coarse nodes, times
+// scale; discrete data from the nearest fine node.
 template <typename T>
-hipError_t launch_gather_coarse(const T *src, T *dst, const int *n, const int *nK, int dim,
-                                int stride, int comps, hipStream_t s);
-hipError_t launch_gather_coarse_i8(const int8_t *src, int8_t *dst, const int *n,
-                                   const int *nK, int dim, int stride, hipStream_t s);
-// Place components without a coincident coarse node (single thread, in order).
+hipError_t launch_sample_coarse(const T *src, double *dst, const int *n, const int *nK, int dim,
+                                int comps, double scale, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_nearest(const T *src, T *dst, const int *n, const int *nK, int dim,
+                                 hipStream_t s);
+// Place components without a coarse node (single thread, in order).
 template <typename T>
 hipError_t launch_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,
                                 const int *firstK, const int *n, const int *nK, int dim,
-                                int stride, int n_comp, hipStream_t s);
+                                int n_comp, hipStream_t s);
 // One-pass input statistics (fs must be pre-initialised: zeros, first_node = INT_MAX).
 template <typename T>
 hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
@@ -219,7 +221,7 @@ hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const in
                              double delta, uint8_t *memberK, uint8_t *labelK, hipStream_t s);
 // ISA step 2: Con(.) projection + orphan repair + nearest-node label.
 hipError_t launch_project(const uint8_t *memberK, const uint8_t *labelK, const int *nK,
-                          const int *n, int dim, int stride, uint8_t *member, uint8_t *label,
+                          const int *n, int dim, uint8_t *member, uint8_t *label,
                           hipStream_t s);
 // ISA step 4: V = min over member sets (final buffers from SdState), owner.
 template <typename T>

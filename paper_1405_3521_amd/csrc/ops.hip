@@ -3,7 +3,7 @@
 // projection to the fine grid, the min-assembly of the sub-domain values and the
 // construction of the (sub-domain, tile) work list.  All are streaming kernels
 // (HBM/L2 bound); grid-stride loops with 256-thread work-groups.
-#include "internal.h"
+#include "device_common.h"
 
 #include <climits>
 
@@ -193,39 +193,54 @@ __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
     }
 }
 
+// Coarse data of the RA: Q1 interpolation (FP64) of a fine field at every coarse
+// node, times `scale` (1 for speed, the coarse step's w for the cost).
 template <typename T>
-__global__ void k_gather_coarse(const T *src, T *dst, int n0, int n1, int k0, int k1, int k2,
-                                int stride, int comps) {
+__global__ void k_sample_coarse(const T *src, double *dst, int n0, int n1, int n2, int k0,
+                                int k1, int k2, int dim, int comps, double scale) {
     const size_t NK = (size_t)k0 * k1 * k2;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < NK;
          i += (size_t)gridDim.x * blockDim.x) {
-        const int a = (int)(i % k0);
-        const int b = (int)((i / k0) % k1);
-        const int c = (int)(i / ((size_t)k0 * k1));
-        const size_t j = ((size_t)c * stride * n1 + (size_t)b * stride) * n0 + (size_t)a * stride;
-        for (int q = 0; q < comps; ++q) dst[i * comps + q] = src[j * comps + q];
+        AxisPos ax[3];
+        ax[0] = fine_pos_of_coarse((int)(i % k0), n0, k0);
+        ax[1] = fine_pos_of_coarse((int)((i / k0) % k1), n1, k1);
+        ax[2] = dim == 3 ? fine_pos_of_coarse((int)(i / ((size_t)k0 * k1)), n2, k2) : AxisPos{0, 0, 0, 0.0};
+        for (int q = 0; q < comps; ++q)
+            dst[i * comps + q] = scale * sample_q1(src, comps, q, n0, n1, dim, ax);
     }
 }
 
-// Components with no coincident coarse node get the coarse node nearest to
-// their lowest-index fine node (components in index order; an occupied coarse
-// node is not taken over).  firstK: lowest coarse node per component (or INT_MAX).
+// Discrete coarse data (target ids, exit costs): the value at the nearest fine node.
+template <typename T>
+__global__ void k_gather_nearest(const T *src, T *dst, int n0, int n1, int n2, int k0, int k1,
+                                 int k2, int dim) {
+    const size_t NK = (size_t)k0 * k1 * k2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < NK;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int a = fine_pos_of_coarse((int)(i % k0), n0, k0).near;
+        const int b = fine_pos_of_coarse((int)((i / k0) % k1), n1, k1).near;
+        const int c = dim == 3 ? fine_pos_of_coarse((int)(i / ((size_t)k0 * k1)), n2, k2).near : 0;
+        dst[i] = src[((size_t)c * n1 + b) * n0 + a];
+    }
+}
+
+// Components with no coarse node get the coarse node nearest to their
+// lowest-index fine node (components in index order; an occupied coarse node is
+// not taken over).  firstK: lowest coarse node per component (or INT_MAX).
 template <typename T>
 __global__ void k_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,
-                                const int *firstK, int n0, int n1, int k0, int k1, int k2,
-                                int dim, int stride, int n_comp) {
+                                const int *firstK, int n0, int n1, int n2, int k0, int k1,
+                                int k2, int dim, int n_comp) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     for (int i = 0; i < n_comp; ++i) {
         if (firstK[i] != 0x7fffffff) continue;
         const int j = first_fine[i];
         if (j == 0x7fffffff) continue;
         const int a = j % n0, b = (j / n0) % n1, c = j / (n0 * n1);
-        int ka = (a + stride / 2) / stride, kb = (b + stride / 2) / stride,
-            kc = (c + stride / 2) / stride;
-        ka = ka < k0 - 1 ? ka : k0 - 1;
-        kb = kb < k1 - 1 ? kb : k1 - 1;
-        kc = kc < k2 - 1 ? kc : k2 - 1;
-        if (dim < 3) kc = 0;
+        int lo, hi, ka, kb, kc = 0;
+        coarse_cells_of_fine(a, n0, k0, lo, hi, ka);
+        coarse_cells_of_fine(b, n1, k1, lo, hi, kb);
+        if (dim == 3) coarse_cells_of_fine(c, n2, k2, lo, hi, kc);
         const size_t jk = ((size_t)kc * k1 + kb) * k0 + ka;
         if (tK[jk] < 0) {
             tK[jk] = (int8_t)i;
@@ -256,32 +271,19 @@ __global__ void k_ra_combine(const double *Vaux, int n_comp, size_t NK, const in
     }
 }
 
-// Per fine index along one axis: the coarse cells whose closure holds it.
-__device__ __forceinline__ void cells_of(int j, int s, int nK, int &lo, int &hi) {
-    hi = j / s;
-    hi = hi < nK - 2 ? hi : nK - 2;
-    if (j % s == 0) {
-        lo = j / s - 1;
-        lo = lo > 0 ? lo : 0;
-    } else {
-        lo = hi;
-    }
-}
-
 __global__ void k_project(const uint8_t *mK, const uint8_t *lK, int k0, int k1, int k2,
-                          int n0, int n1, int n2, int dim, int s, uint8_t *member,
-                          uint8_t *label) {
+                          int n0, int n1, int n2, int dim, uint8_t *member, uint8_t *label) {
     const size_t N = (size_t)n0 * n1 * n2;
     for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
          j += (size_t)gridDim.x * blockDim.x) {
         const int a = (int)(j % n0);
         const int b = (int)((j / n0) % n1);
         const int c = (int)(j / ((size_t)n0 * n1));
-        int lo[3], hi[3];
-        cells_of(a, s, k0, lo[0], hi[0]);
-        cells_of(b, s, k1, lo[1], hi[1]);
-        if (dim == 3) cells_of(c, s, k2, lo[2], hi[2]);
-        else { lo[2] = hi[2] = 0; }
+        int lo[3], hi[3], nr[3];
+        coarse_cells_of_fine(a, n0, k0, lo[0], hi[0], nr[0]);
+        coarse_cells_of_fine(b, n1, k1, lo[1], hi[1], nr[1]);
+        if (dim == 3) coarse_cells_of_fine(c, n2, k2, lo[2], hi[2], nr[2]);
+        else { lo[2] = hi[2] = nr[2] = 0; }
         unsigned full = 0, anyb = 0;
         const int ncell = 1 << dim;
         for (int ch = 0; ch < ncell; ++ch) {
@@ -298,12 +300,7 @@ __global__ void k_project(const uint8_t *mK, const uint8_t *lK, int k0, int k1, 
             full |= andb;
         }
         member[j] = (uint8_t)(full ? full : anyb);
-        int na = (a + s / 2) / s, nb = (b + s / 2) / s, nc = (c + s / 2) / s;
-        na = na < k0 - 1 ? na : k0 - 1;
-        nb = nb < k1 - 1 ? nb : k1 - 1;
-        nc = nc < k2 - 1 ? nc : k2 - 1;
-        if (dim < 3) nc = 0;
-        label[j] = lK[((size_t)nc * k1 + nb) * k0 + na];
+        label[j] = lK[((size_t)nr[2] * k1 + nr[1]) * k0 + nr[0]];
     }
 }
 
@@ -415,34 +412,40 @@ template hipError_t launch_build_items<float>(const LaunchCfg &, const SdDesc<fl
 template hipError_t launch_build_items<double>(const LaunchCfg &, const SdDesc<double> *, int, int, const int *, WorkItem *, ExecCounters *, const int *, hipStream_t);
 
 template <typename T>
-hipError_t launch_gather_coarse(const T *src, T *dst, const int *n, const int *nK, int dim,
-                                int stride, int comps, hipStream_t s) {
+hipError_t launch_sample_coarse(const T *src, double *dst, const int *n, const int *nK, int dim,
+                                int comps, double scale, hipStream_t s) {
     const size_t NK = (size_t)nK[0] * nK[1] * (dim == 3 ? nK[2] : 1);
-    hipLaunchKernelGGL(k_gather_coarse<T>, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, src, dst,
-                       n[0], n[1], nK[0], nK[1], dim == 3 ? nK[2] : 1, stride, comps);
+    hipLaunchKernelGGL(k_sample_coarse<T>, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, src, dst,
+                       n[0], n[1], dim == 3 ? n[2] : 1, nK[0], nK[1], dim == 3 ? nK[2] : 1, dim,
+                       comps, scale);
     return hipGetLastError();
 }
-template hipError_t launch_gather_coarse<float>(const float *, float *, const int *, const int *, int, int, int, hipStream_t);
-template hipError_t launch_gather_coarse<double>(const double *, double *, const int *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_sample_coarse<float>(const float *, double *, const int *, const int *, int, int, double, hipStream_t);
+template hipError_t launch_sample_coarse<double>(const double *, double *, const int *, const int *, int, int, double, hipStream_t);
 
-hipError_t launch_gather_coarse_i8(const int8_t *src, int8_t *dst, const int *n, const int *nK,
-                                   int dim, int stride, hipStream_t s) {
+template <typename T>
+hipError_t launch_gather_nearest(const T *src, T *dst, const int *n, const int *nK, int dim,
+                                 hipStream_t s) {
     const size_t NK = (size_t)nK[0] * nK[1] * (dim == 3 ? nK[2] : 1);
-    hipLaunchKernelGGL(k_gather_coarse<int8_t>, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, src,
-                       dst, n[0], n[1], nK[0], nK[1], dim == 3 ? nK[2] : 1, stride, 1);
+    hipLaunchKernelGGL(k_gather_nearest<T>, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, src, dst,
+                       n[0], n[1], dim == 3 ? n[2] : 1, nK[0], nK[1], dim == 3 ? nK[2] : 1, dim);
     return hipGetLastError();
 }
+template hipError_t launch_gather_nearest<float>(const float *, float *, const int *, const int *, int, hipStream_t);
+template hipError_t launch_gather_nearest<double>(const double *, double *, const int *, const int *, int, hipStream_t);
+template hipError_t launch_gather_nearest<int8_t>(const int8_t *, int8_t *, const int *, const int *, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,
                                 const int *firstK, const int *n, const int *nK, int dim,
-                                int stride, int n_comp, hipStream_t s) {
+                                int n_comp, hipStream_t s) {
     hipLaunchKernelGGL(k_place_missing<T>, dim3(1), dim3(64), 0, s, tK, gK, g, first_fine, firstK,
-                       n[0], n[1], nK[0], nK[1], dim == 3 ? nK[2] : 1, dim, stride, n_comp);
+                       n[0], n[1], dim == 3 ? n[2] : 1, nK[0], nK[1], dim == 3 ? nK[2] : 1, dim,
+                       n_comp);
     return hipGetLastError();
 }
-template hipError_t launch_place_missing<float>(int8_t *, float *, const float *, const int *, const int *, const int *, const int *, int, int, int, hipStream_t);
-template hipError_t launch_place_missing<double>(int8_t *, double *, const double *, const int *, const int *, const int *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_place_missing<float>(int8_t *, float *, const float *, const int *, const int *, const int *, const int *, int, int, hipStream_t);
+template hipError_t launch_place_missing<double>(int8_t *, double *, const double *, const int *, const int *, const int *, const int *, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
@@ -463,12 +466,12 @@ hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const in
 }
 
 hipError_t launch_project(const uint8_t *memberK, const uint8_t *labelK, const int *nK,
-                          const int *n, int dim, int stride, uint8_t *member, uint8_t *label,
+                          const int *n, int dim, uint8_t *member, uint8_t *label,
                           hipStream_t s) {
     const size_t N = (size_t)n[0] * n[1] * (dim == 3 ? n[2] : 1);
     hipLaunchKernelGGL(k_project, dim3(grid_for(N)), dim3(kOpThreads), 0, s, memberK, labelK,
                        nK[0], nK[1], dim == 3 ? nK[2] : 1, n[0], n[1], dim == 3 ? n[2] : 1, dim,
-                       stride, member, label);
+                       member, label);
     return hipGetLastError();
 }
 

@@ -103,18 +103,27 @@ def test_reconstruction_argument_errors():
     p, keep = _problem()
     st = S.SlStats()
     buf = C.create_string_buffer(64)
-    ra = S.SlRaOpts(3, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)     # 3 does not divide n-1 = 8
+    nested = lambda s: S.SlRaOpts(s, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    counts = lambda a, b: S.SlRaOpts(1, (C.c_int * 3)(a, b, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    ra = nested(3)                                         # 3 does not divide n-1 = 8
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) == 0
     assert L.sl_reconstruct(C.byref(p), C.byref(ra), buf, 64, buf, buf, None, None,
                             C.byref(st), None) == -1
-    ra = S.SlRaOpts(2, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    ra = nested(2)
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
     assert L.sl_reconstruct(C.byref(p), C.byref(ra), buf, 64, buf, buf, None, None,
                             C.byref(st), None) == -5
-    ra = S.SlRaOpts(4, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)     # coarse grid of 3 nodes: allowed
+    ra = nested(4)                                         # coarse grid of 3 nodes: allowed
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
-    ra = S.SlRaOpts(8, 0.5, 0.5, 1.0, 0.0, 0.0, 1000)     # coarse grid of 2 nodes: too coarse
+    ra = nested(8)                                         # coarse grid of 2 nodes: too coarse
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) == 0
+    # node counts: any 3 <= nK_d <= n_d (here n = 9), nested or not
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(counts(4, 6))) > 0
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(counts(9, 3))) > 0
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(counts(2, 5))) == 0
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(counts(5, 10))) == 0
+    assert L.sl_reconstruct(C.byref(p), C.byref(counts(5, 0)), buf, 64, buf, buf, None, None,
+                            C.byref(st), None) == -1
 
 
 def test_binding_raises_without_library(monkeypatch, tmp_path):

@@ -137,7 +137,7 @@ def test_autograd_gradient_against_fd(mode):
         return float(np.sum((oracle_V(theta)[obs] - Vobs) ** 2))
 
     dp = S.to_device(p, torch.float32)
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
     theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device=DEV).requires_grad_(True)
     mem_t = None if member is None else torch.as_tensor(member, device=DEV)
     V = S.HJBSolve.apply(torch.exp(theta), dp, mem_t, ra, S.SolveOpts(tol=0.0), 0.0)

@@ -16,7 +16,7 @@ def say(*a):
 
 
 def ra_of(p):
-    return S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
+    return S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])

@@ -19,7 +19,7 @@ DEV = "cuda:0"
 
 
 def ra_of(p):
-    return S.RaOpts(coarse_stride=p.coarse_stride, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
+    return S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
 
 
 def host(t):
@@ -130,6 +130,38 @@ def test_reconstruction_full_size_c2_labels():
     assert np.array_equal(host(label), lab)
 
 
+@pytest.mark.parametrize("n,nK", [(129, (47, 53)), (257, (61, 61)), (100, (41, 41))])
+def test_reconstruction_bit_exact_non_nested_coarse_grid(n, nK):
+    """A coarse grid of any node counts (not nested in the fine grid): Q1 coarse
+    data, nearest-node targets, Con(.) located in integers; sets and labels equal
+    the oracle's bit for bit, on K and on the fine grid."""
+    p = W.c2_multitarget(n=n, m=64).with_(coarse_n=nK)
+    say("case: reconstruct non-nested", n, nK)
+    dp = S.to_device(p, torch.float32)
+    member, label, st, mK, lK = S.reconstruct(dp, ra_of(p), want_coarse=True)
+    rec = I.reconstruct(p)
+    assert np.array_equal(host(mK), rec.member_K)
+    assert np.array_equal(host(lK), rec.label_K)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
+
+
+def test_isa_fp64_bit_exact_non_nested_with_cost():
+    """FP64 ISA with a running cost, exit costs g and a 35^2 coarse grid under a
+    97^2 fine grid: every value and owner bit-exact."""
+    p = W.c2_multitarget(n=97, m=32)
+    rng = np.random.Generator(np.random.PCG64(31))
+    p = p.with_(cost=W.f32(np.exp(rng.normal(0, 0.3, p.N))), v_ghost=4.0,
+                g=W.f32(rng.uniform(0, 0.2, p.N)), coarse_n=(35, 35))
+    say("case: isa fp64 non-nested cost")
+    dp = S.to_device(p, torch.float64)
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0))
+    Vbar, own_o, rec, Vs_o, _ = I.isa(p)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(V), Vbar)
+    assert np.array_equal(host(owner), own_o)
+
+
 # ------------------------------------------------------------------------- ISA
 @pytest.mark.parametrize("n", [129, 257])
 def test_isa_fp32_parity(n):
@@ -178,10 +210,12 @@ def test_global_3d_fp64_bit_exact():
     assert np.array_equal(host(V), Vo)
 
 
-@pytest.mark.parametrize("n", [33, 41])
-def test_isa_3d_fp32_parity(n):
+@pytest.mark.parametrize("n,nK", [(33, None), (41, None), (30, (11, 13, 9))])
+def test_isa_3d_fp32_parity(n, nK):
     p = W.c3_aniso3d(n=n, m=64, n_balls=4, r=0.12)
-    say("case: 3d fp32 isa", n, "stride", p.coarse_stride)
+    if nK is not None:
+        p = p.with_(coarse_n=nK)
+    say("case: 3d fp32 isa", n, "stride", p.coarse_stride, "coarse nodes", nK)
     dp = S.to_device(p, torch.float32)
     V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0))
     Vbar, own_o, rec, Vs_o, _ = I.isa(p)
