@@ -10,6 +10,10 @@ from oracle import isa as I
 
 pytestmark = pytest.mark.gpu
 
+# sweep cap of the fixed-point solves: a solve that has not converged by then
+# returns (and fails its checks) instead of running on
+CAP = 50_000
+
 
 def say(*a):
     print(*a, flush=True)
@@ -27,7 +31,7 @@ def test_batched_matches_oracle(dtype):
     say("case: batched", dtype, [p.n[0] for p in probs])
     dps = [S.to_device(p, dtype) for p in probs]
     Vs, mem, lab, own, per, tot = S.solve_batched(dps, [ra_of(p) for p in probs],
-                                                  S.SolveOpts(tol=0.0))
+                                                  S.SolveOpts(tol=0.0, max_sweeps=CAP))
     assert tot["converged"]
     for p, V, m, l, o in zip(probs, Vs, mem, lab, own):
         Vbar, owner, rec, _, _ = I.isa(p)
@@ -49,8 +53,8 @@ def test_batched_equals_single_problem_calls():
     probs = W.c4_batch(count=6, seed=900, n_min=20, n_max=70)
     dps = [S.to_device(p, torch.float32) for p in probs]
     ras = [ra_of(p) for p in probs]
-    Vs, mem, lab, own, per, tot = S.solve_batched(dps, ras, S.SolveOpts(tol=0.0))
+    Vs, mem, lab, own, per, tot = S.solve_batched(dps, ras, S.SolveOpts(tol=0.0, max_sweeps=CAP))
     for dp, ra, V, m in zip(dps, ras, Vs, mem):
-        V1, o1, m1, l1, _, _, st = S.isa(dp, ra, S.SolveOpts(tol=0.0))
+        V1, o1, m1, l1, _, _, st = S.isa(dp, ra, S.SolveOpts(tol=0.0, max_sweeps=CAP))
         assert torch.equal(m1, m)
         assert float((V1 - V).abs().max()) <= 1e-6

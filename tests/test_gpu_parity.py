@@ -15,6 +15,10 @@ from oracle import isa as I
 
 pytestmark = pytest.mark.gpu
 
+# sweep cap of the fixed-point solves: a solve that has not converged by then
+# returns (and fails its checks) instead of running on
+CAP = 50_000
+
 DEV = "cuda:0"
 
 
@@ -36,7 +40,7 @@ def test_global_fp64_bit_exact(n):
     """FP64 global solve: same operation order as the oracle -> identical bits."""
     p = W.c1_eikonal(n)
     say("case: global fp64 eikonal", n)
-    V, _, st = S.solve(S.to_device(p, torch.float64), S.SolveOpts(tol=0.0))
+    V, _, st = S.solve(S.to_device(p, torch.float64), S.SolveOpts(tol=0.0, max_sweeps=CAP))
     Vo, _, so, _ = O.solve(p)
     Vg = host(V)
     assert np.array_equal(Vg, Vo), np.abs(Vg - Vo).max()
@@ -62,7 +66,7 @@ def test_global_fp32_parity(n, m):
     else:
         p = W.c2_multitarget(n=n, m=m)
     say("case: global fp32 multitarget", n, m)
-    V, pol, st = S.solve(S.to_device(p, torch.float32), S.SolveOpts(tol=0.0, want_policy=True))
+    V, pol, st = S.solve(S.to_device(p, torch.float32), S.SolveOpts(tol=0.0, max_sweeps=CAP, want_policy=True))
     Vo, polo, _, _ = O.solve(p)
     err = np.abs(host(V).astype(np.float64) - Vo).max()
     say("  sup err", err, "sweeps", st["sweeps_max"])
@@ -155,7 +159,7 @@ def test_isa_fp64_bit_exact_non_nested_with_cost():
                 g=W.f32(rng.uniform(0, 0.2, p.N)), coarse_n=(35, 35))
     say("case: isa fp64 non-nested cost")
     dp = S.to_device(p, torch.float64)
-    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0))
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP))
     Vbar, own_o, rec, Vs_o, _ = I.isa(p)
     assert np.array_equal(host(member), rec.member)
     assert np.array_equal(host(V), Vbar)
@@ -171,9 +175,10 @@ def test_isa_fp32_parity(n):
     p = W.c2_multitarget(n=n, m=64)
     say("case: isa fp32", n)
     dp = S.to_device(p, torch.float32)
-    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0),
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP),
                                                want_sets=True)
     Vbar, own_o, rec, Vs_o, _ = I.isa(p)
+    assert st["converged"]
     assert np.array_equal(host(member), rec.member)
     err = np.abs(host(V).astype(np.float64) - Vbar).max()
     say("  sup err", err, "sweeps", st["sweeps_max"])
@@ -194,7 +199,7 @@ def test_isa_fp64_bit_exact():
     """FP64 ISA: every set's solve and the assembly are bit-exact."""
     p = W.c2_multitarget(n=97, m=32)
     dp = S.to_device(p, torch.float64)
-    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0),
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP),
                                                want_sets=True)
     Vbar, own_o, rec, Vs_o, _ = I.isa(p)
     assert np.array_equal(host(V), Vbar)
@@ -205,7 +210,7 @@ def test_isa_fp64_bit_exact():
 def test_global_3d_fp64_bit_exact():
     p = W.c3_aniso3d(n=21, m=32, n_balls=3, r=0.15)
     say("case: 3d fp64 global")
-    V, _, st = S.solve(S.to_device(p, torch.float64), S.SolveOpts(tol=0.0))
+    V, _, st = S.solve(S.to_device(p, torch.float64), S.SolveOpts(tol=0.0, max_sweeps=CAP))
     Vo, _, so, _ = O.solve(p)
     assert np.array_equal(host(V), Vo)
 
@@ -217,12 +222,13 @@ def test_isa_3d_fp32_parity(n, nK):
         p = p.with_(coarse_n=nK)
     say("case: 3d fp32 isa", n, "stride", p.coarse_stride, "coarse nodes", nK)
     dp = S.to_device(p, torch.float32)
-    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0))
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP))
     Vbar, own_o, rec, Vs_o, _ = I.isa(p)
+    assert st["converged"]
     assert np.array_equal(host(member), rec.member)
     assert np.array_equal(host(label), rec.label)
     err = np.abs(host(V).astype(np.float64) - Vbar).max()
-    say("  sup err", err)
+    say("  sup err", err, "sweeps", st["sweeps_max"])
     assert err <= 1e-5
 
 
@@ -271,7 +277,7 @@ def test_every_tuner_candidate_matches_oracle(dim):
         assert ncand >= 3
         dp = S.to_device(p, dtype)
         for k in range(ncand):
-            V, _, st = S.solve(dp, S.SolveOpts(tol=0.0, autotune=-(k + 1)))
+            V, _, st = S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=-(k + 1)))
             Vg = host(V).astype(np.float64)
             say("  candidate", dim, dtype, k, st["tile"], st["mode"], np.abs(Vg - Vo).max())
             if dtype == torch.float64:
@@ -283,7 +289,7 @@ def test_every_tuner_candidate_matches_oracle(dim):
 def test_autotuned_isa_matches_oracle():
     p = W.c2_multitarget(n=129, m=64)
     dp = S.to_device(p, torch.float32)
-    V, owner, member, label, _, _, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, autotune=2))
+    V, owner, member, label, _, _, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=2))
     Vbar, _, rec, _, _ = I.isa(p)
     assert np.abs(host(V).astype(np.float64) - Vbar).max() <= 1e-5
     say("  tuned:", st["tile"], st["mode"])
