@@ -300,10 +300,11 @@ struct Exec {
     WorkItem *items = nullptr;      // device
     ExecCounters *cnt = nullptr;    // device
     int *prefix = nullptr;          // device
-    uint8_t *changed = nullptr;     // device, 2 * tiles: per-tile change flags
+    int *stamp = nullptr;           // device, 2 x tiles: sweep each tile must be computed in
     int *class_off_dev = nullptr;   // device, kMaxClasses: item segment of each halo class
     int n_sd = 0;
     int total_tiles = 0;
+    int stamp_stride = 1;           // tiles reserved (stride of the two stamp arrays)
     std::vector<SdDesc<T>> host_sds;
     std::vector<int> host_prefix;
     // halo classes: sub-domains grouped by the halo they need; one launch per
@@ -317,7 +318,8 @@ struct Exec {
         items = a.take<WorkItem>(tiles_total > 0 ? tiles_total : 1);
         cnt = a.take<ExecCounters>(1);
         prefix = a.take<int>(nsd);
-        changed = a.take<uint8_t>(2 * (size_t)(tiles_total > 0 ? tiles_total : 1));
+        stamp_stride = tiles_total > 0 ? tiles_total : 1;
+        stamp = a.take<int>(2 * (size_t)stamp_stride);
         class_off_dev = a.take<int>(kMaxClasses);
     }
 
@@ -381,7 +383,7 @@ struct Exec {
         HIPCHK(hipMemcpyAsync(prefix, host_prefix.data(), sizeof(int) * n_sd,
                               hipMemcpyHostToDevice, s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(ExecCounters), s));
-        HIPCHK(hipMemsetAsync(changed, 0, 2 * (size_t)(total_tiles > 0 ? total_tiles : 1), s));
+        HIPCHK(hipMemsetAsync(stamp, 0xFF, sizeof(int) * 2 * (size_t)stamp_stride, s));
         HIPCHK(launch_build_items(cfg, sds, n_sd, total_tiles, prefix, items, cnt, class_off_dev, s));
         return SL_OK;
     }
@@ -393,7 +395,7 @@ struct Exec {
             if (class_cap[c] == 0) continue;
             const hipError_t e =
                 launch_sweep(ccfg[c], sds, st, n_sd, items + class_off[c], cnt, class_cap[c],
-                             sweep_rel, tol, want_policy, changed, total_tiles, (int)c,
+                             sweep_rel, tol, want_policy, stamp, stamp_stride, (int)c,
                              first ? 1 : 0, q);
             if (e != hipSuccess) return e;
             first = false;

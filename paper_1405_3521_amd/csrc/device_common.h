@@ -113,8 +113,9 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Block max of v, folded into *dst (FP64 bit pattern, atomicMax); returns the
 // block max on thread 0 (0 elsewhere).
+template <int NT = kThreads>
 __device__ __forceinline__ double block_max_to(double v, unsigned long long *dst) {
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[NT / 64];
     __syncthreads();                    // a previous call's reader is done with red[]
     v = wave_max(v);
     const int w = threadIdx.x >> 6;
@@ -124,14 +125,15 @@ __device__ __forceinline__ double block_max_to(double v, unsigned long long *dst
     if (threadIdx.x == 0) {
         m = red[0];
 #pragma unroll
-        for (int i = 1; i < kThreads / 64; ++i) m = red[i] > m ? red[i] : m;
+        for (int i = 1; i < NT / 64; ++i) m = red[i] > m ? red[i] : m;
         if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
     }
     return m;
 }
 
+template <int NT = kThreads>
 __device__ __forceinline__ void block_sum_to(unsigned v, unsigned long long *dst) {
-    __shared__ unsigned red[kThreads / 64];
+    __shared__ unsigned red[NT / 64];
     __syncthreads();                    // a previous call's reader is done with red[]
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -140,7 +142,7 @@ __device__ __forceinline__ void block_sum_to(unsigned v, unsigned long long *dst
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
-        for (int i = 0; i < kThreads / 64; ++i) s += red[i];
+        for (int i = 0; i < NT / 64; ++i) s += red[i];
         if (s) atomicAdd(dst, s);
     }
 }

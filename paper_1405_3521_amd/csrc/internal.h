@@ -59,6 +59,8 @@ struct SdState {
 struct WorkItem {
     int sd;
     int t[3];                   // tile coordinates
+    int tflat;                  // global tile index (sd's tile_offset + local index)
+    int pad[3];
 };
 
 // Counters shared by a launch sequence (device memory).
@@ -145,19 +147,22 @@ struct LaunchCfg {
     int grid_cap;               // resident work-groups (persistent grid), 0 = unset
     int mode;                   // 0: one work-group per item; 1: resident grid + atomic
                                 // work queue; 2: resident grid + static grid stride
+    int threads;                // work-group size of the variant
 };
 
 // ---- launchers (sweep.hip) -------------------------------------------------
 // One Jacobi sweep over all work items.  The sweep index is
 // cnt->sweep_base + sweep_rel (device-resident base, so a captured chunk of
 // launches can be replayed).
-// `changed`: 2 * flag_stride per-tile change flags (parity of the sweep).
+// `stamp`: 2 * stamp_stride ints, per sweep parity and tile: the sweep in which
+// the tile must be computed (a tile that changes in sweep s stamps its
+// neighbourhood with s + 1 in the other parity's array).
 // `items` is the segment of halo class `cls` (capacity max_items); only the
 // launch with do_bookkeep runs the convergence bookkeeping of the sweep.
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
                         const WorkItem *items, ExecCounters *cnt, int max_items,
-                        int sweep_rel, double tol, int want_policy, uint8_t *changed,
-                        int flag_stride, int cls, int do_bookkeep, hipStream_t s);
+                        int sweep_rel, double tol, int want_policy, int *stamp,
+                        int stamp_stride, int cls, int do_bookkeep, hipStream_t s);
 // Bookkeeping before sweep cnt->sweep_base + sweep_rel (marks sds converged,
 // resets slots, counts active sds); `final_pass` also settles final_buf of
 // unconverged sds; afterwards sweep_base += advance.

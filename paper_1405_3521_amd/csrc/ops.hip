@@ -189,6 +189,8 @@ __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
         w.t[0] = t0;
         w.t[1] = t1;
         w.t[2] = t2;
+        w.tflat = g;
+        w.pad[0] = w.pad[1] = w.pad[2] = 0;
         items[class_off[d.cls] + slot] = w;
     }
 }

@@ -28,15 +28,18 @@ namespace slhjb {
 
 namespace {
 
-// Active-tile test (exact skipping).  With Jacobi double buffering, if no node
-// of the tiles that a tile's halo reaches changed in sweep s-1, the tile's new
-// values equal its old ones, and the output buffer already holds them (it holds
-// the iterate of sweep s-1, equal to that of sweep s).  `prev` holds the flags
-// written in sweep s-1 (1 = some node of the tile changed).
+// Exact active-tile skipping.  With Jacobi double buffering, if no node of the
+// tiles that a tile's halo reaches changed in sweep s-1, the tile's new values
+// equal its old ones, and the output buffer already holds them (it holds the
+// iterate of sweep s-1, equal to that of sweep s).  A tile that changes in sweep
+// s therefore stamps every tile of its neighbourhood (itself included) with s+1,
+// and sweep s computes a tile iff its stamp is s.  The stamps are double buffered
+// by sweep parity: sweep s reads stamp[s & 1], written only in sweep s-1, and
+// writes stamp[(s+1) & 1], so every wave of a work-group reads the same value and
+// takes the same decision.  Concurrent writers store the same value.
 template <int RX, int RY, int RZ>
-__device__ __forceinline__ bool neighbourhood_changed(const uint8_t *prev, int off, const int *t,
-                                                      const int *nt) {
-    bool any = false;
+__device__ __forceinline__ void stamp_neighbourhood(int *next, int off, const int *t,
+                                                    const int *nt, int s) {
     for (int dz = -RZ; dz <= RZ; ++dz) {
         const int z = t[2] + dz;
         if (z < 0 || z >= nt[2]) continue;
@@ -46,24 +49,23 @@ __device__ __forceinline__ bool neighbourhood_changed(const uint8_t *prev, int o
             for (int dx = -RX; dx <= RX; ++dx) {
                 const int x = t[0] + dx;
                 if (x < 0 || x >= nt[0]) continue;
-                any |= prev[off + (z * nt[1] + y) * nt[0] + x] != 0;
+                next[off + (z * nt[1] + y) * nt[0] + x] = s;
             }
         }
     }
-    return any;
 }
 
 // ------------------------------------------------------------------ 2D kernel
 // Persistent: a resident grid of work-groups takes work items from a per-sweep
 // atomic queue until the list is exhausted.
-template <typename T, int TX, int TY, int H, bool POLICY>
-__global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
+template <typename T, int TX, int TY, int H, bool POLICY, int S>
+__global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
                                                       ExecCounters *__restrict__ cnt,
                                                       int sweep_rel, double tol,
-                                                      uint8_t *__restrict__ changed,
-                                                      int flag_stride, int mode, int cls,
+                                                      int *__restrict__ stamp,
+                                                      int stamp_stride, int mode, int cls,
                                                       int do_bookkeep) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
@@ -72,14 +74,21 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
     constexpr int NPT = TY / RSTEP;
     constexpr int RX = (H + TX - 1) / TX, RY = (H + TY - 1) / TY;
     static_assert(kThreads % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
+    // S groups of kThreads threads share a tile: the same nodes, every S-th control
+    // each (k = g, g + S, ...); group 0 takes the minimum over the groups' partial
+    // results (exact, so the values do not depend on S; on ties the lowest control
+    // index wins, as in one pass).
+    constexpr int NT = kThreads * S;
     __shared__ T lds[LW * LH];
+    __shared__ T part[S > 1 ? (S - 1) * TX * TY : 1];
+    __shared__ int parg[(S > 1 && POLICY) ? (S - 1) * TX * TY : 1];
 
     if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
     const int n_items = cnt->class_items[cls];
-    const uint8_t *prev = changed + (size_t)((sweep + 1) & 1) * flag_stride;
-    uint8_t *cur = changed + (size_t)(sweep & 1) * flag_stride;
-    const int tx = threadIdx.x % TX;
-    const int ty0 = threadIdx.x / TX;
+    const int grp = S > 1 ? (int)threadIdx.x / kThreads : 0;
+    const int lt = S > 1 ? (int)threadIdx.x % kThreads : (int)threadIdx.x;
+    const int tx = lt % TX;
+    const int ty0 = lt / TX;
     unsigned nact = 0;
     const int slot = sweep % 3;
     // mode 0: one item per work-group, scheduled by the hardware;
@@ -91,14 +100,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
         const WorkItem it = items[item];
         SdState *sst = st + it.sd;
-        if (!POLICY && sd_skip(sst, sweep, tol)) continue;
-        const SdDesc<T> &d = sds[it.sd];
-        const int tflat = d.tile_offset + it.t[1] * d.tiles[0] + it.t[0];
-        if (!POLICY && sweep > 0 &&
-            !neighbourhood_changed<RX, RY, 0>(prev, d.tile_offset, it.t, d.tiles)) {
-            if (threadIdx.x == 0) cur[tflat] = 0;
-            continue;
+        if (!POLICY) {
+            const int stp = stamp[(size_t)(sweep & 1) * stamp_stride + it.tflat];
+            if (sd_skip(sst, sweep, tol) || (sweep > 0 && stp != sweep)) continue;
         }
+        const SdDesc<T> &d = sds[it.sd];
         const int n0 = d.n[0], n1 = d.n[1];
         const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
         const int src = POLICY ? sst->final_buf : (sweep & 1);
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
         const T G = d.G;
 
         __syncthreads();                 // LDS of the previous item is no longer read
-        for (int q = threadIdx.x; q < LW * LH; q += kThreads) {
+        for (int q = threadIdx.x; q < LW * LH; q += NT) {
             const int ly = q / LW;
             const int lx = q - ly * LW;
             const int gx = x0 - H + lx, gy = y0 - H + ly;
@@ -159,7 +165,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
         const T *__restrict__ ctrl = d.ctrl;
         const int m = d.m;
         if (__any(any)) {
-            for (int k = 0; k < m; ++k) {
+#pragma unroll 2
+            for (int k = grp; k < m; k += S) {
                 const T ex = ctrl[2 * k], ey = ctrl[2 * k + 1];
 #pragma unroll
                 for (int r = 0; r < NPT; ++r) {
@@ -211,11 +218,40 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
                 }
             }
         }
+        if (S > 1) {
+            if (grp > 0) {
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) {
+                    const int node = (ty0 + r * RSTEP) * TX + tx;
+                    part[(grp - 1) * TX * TY + node] = best[r];
+                    if (POLICY) parg[(grp - 1) * TX * TY + node] = arg[r];
+                }
+            }
+            __syncthreads();
+            if (grp == 0) {
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) {
+                    const int node = (ty0 + r * RSTEP) * TX + tx;
+                    for (int g = 1; g < S; ++g) {
+                        const T v = part[(g - 1) * TX * TY + node];
+                        if (POLICY) {
+                            const int a = parg[(g - 1) * TX * TY + node];
+                            if (v < best[r] || (v == best[r] && a < arg[r])) {
+                                best[r] = v;
+                                arg[r] = a;
+                            }
+                        } else {
+                            best[r] = min_(best[r], v);
+                        }
+                    }
+                }
+            }
+        }
         double rmax = 0.0;
         unsigned na = 0;
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            if (!act[r]) continue;
+            if (!act[r] || grp > 0) continue;
             const int ty = ty0 + r * RSTEP;
             const size_t j = (size_t)(y0 + ty) * n0 + gx;
             Vout[j] = best[r];
@@ -227,11 +263,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep2d(const SdDesc<T> *__restric
         }
         nact += na * (unsigned)m;
         if (!POLICY) {
-            const double bm = block_max_to(rmax, &sst->res[sweep % 3]);
-            if (threadIdx.x == 0) cur[tflat] = bm > 0.0 ? 1 : 0;
+            const double bm = block_max_to<NT>(rmax, &sst->res[sweep % 3]);
+            if (threadIdx.x == 0 && bm > 0.0)
+                stamp_neighbourhood<RX, RY, 0>(stamp + (size_t)((sweep + 1) & 1) * stamp_stride,
+                                             d.tile_offset, it.t, d.tiles, sweep + 1);
         }
     }
-    if (!POLICY) block_sum_to(nact, &cnt->nc_updates);
+    if (!POLICY) block_sum_to<NT>(nact, &cnt->nc_updates);
 }
 
 // ------------------------------------------------------------------ 3D kernel
@@ -241,8 +279,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                                                       const WorkItem *__restrict__ items,
                                                       ExecCounters *__restrict__ cnt,
                                                       int sweep_rel, double tol,
-                                                      uint8_t *__restrict__ changed,
-                                                      int flag_stride, int mode, int cls,
+                                                      int *__restrict__ stamp,
+                                                      int stamp_stride, int mode, int cls,
                                                       int do_bookkeep) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
@@ -260,8 +298,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
 
     if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
     const int n_items = cnt->class_items[cls];
-    const uint8_t *prev = changed + (size_t)((sweep + 1) & 1) * flag_stride;
-    uint8_t *cur = changed + (size_t)(sweep & 1) * flag_stride;
     const int tx = threadIdx.x % TX;
     const int ty = (threadIdx.x / TX) % TY;
     const int tz0 = threadIdx.x / TXY;
@@ -276,14 +312,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
         const WorkItem it = items[item];
         SdState *sst = st + it.sd;
-        if (!POLICY && sd_skip(sst, sweep, tol)) continue;
-        const SdDesc<T> &d = sds[it.sd];
-        const int tflat = d.tile_offset + (it.t[2] * d.tiles[1] + it.t[1]) * d.tiles[0] + it.t[0];
-        if (!POLICY && sweep > 0 &&
-            !neighbourhood_changed<RX, RY, RZ>(prev, d.tile_offset, it.t, d.tiles)) {
-            if (threadIdx.x == 0) cur[tflat] = 0;
-            continue;
+        if (!POLICY) {
+            const int stp = stamp[(size_t)(sweep & 1) * stamp_stride + it.tflat];
+            if (sd_skip(sst, sweep, tol) || (sweep > 0 && stp != sweep)) continue;
         }
+        const SdDesc<T> &d = sds[it.sd];
         const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
         const int x0 = it.t[0] * TX, y0 = it.t[1] * TY, z0 = it.t[2] * TZ;
         const int src = POLICY ? sst->final_buf : (sweep & 1);
@@ -426,7 +459,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         nact += na * (unsigned)m;
         if (!POLICY) {
             const double bm = block_max_to(rmax, &sst->res[sweep % 3]);
-            if (threadIdx.x == 0) cur[tflat] = bm > 0.0 ? 1 : 0;
+            if (threadIdx.x == 0 && bm > 0.0)
+                stamp_neighbourhood<RX, RY, RZ>(stamp + (size_t)((sweep + 1) & 1) * stamp_stride,
+                                             d.tile_offset, it.t, d.tiles, sweep + 1);
         }
     }
     if (!POLICY) block_sum_to(nact, &cnt->nc_updates);
@@ -447,15 +482,15 @@ __global__ void k_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol, Exe
 
 
 struct Variant {
-    int dim, dtype, tile[3];
+    int dim, dtype, tile[3], threads;
     const void *fn[kMaxHalo + 1][2];    // [H][policy]
     size_t lds_bytes[kMaxHalo + 1];     // dynamic LDS (3D only)
 };
 
-template <typename T, int TX, int TY, int H>
+template <typename T, int TX, int TY, int H, int S>
 void fill2d(Variant &v) {
-    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false>;
-    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true>;
+    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S>;
+    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S>;
     v.lds_bytes[H] = 0;
 }
 template <typename T, int TX, int TY, int TZ, int H>
@@ -465,18 +500,19 @@ void fill3d(Variant &v) {
     v.lds_bytes[H] = sizeof(T) * (size_t)(TX + 2 * H) * (TY + 2 * H) * (TZ + 2 * H);
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, int S = 1>
 Variant make2d() {
     Variant v{};
     v.dim = 2;
     v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = 1;
-    fill2d<T, TX, TY, 1>(v); fill2d<T, TX, TY, 2>(v); fill2d<T, TX, TY, 3>(v);
-    fill2d<T, TX, TY, 4>(v); fill2d<T, TX, TY, 5>(v); fill2d<T, TX, TY, 6>(v);
-    fill2d<T, TX, TY, 7>(v); fill2d<T, TX, TY, 8>(v); fill2d<T, TX, TY, 9>(v);
-    fill2d<T, TX, TY, 10>(v); fill2d<T, TX, TY, 11>(v); fill2d<T, TX, TY, 12>(v);
-    fill2d<T, TX, TY, 13>(v); fill2d<T, TX, TY, 14>(v); fill2d<T, TX, TY, 15>(v);
-    fill2d<T, TX, TY, 16>(v);
+    v.threads = kThreads * S;
+    fill2d<T, TX, TY, 1, S>(v); fill2d<T, TX, TY, 2, S>(v); fill2d<T, TX, TY, 3, S>(v);
+    fill2d<T, TX, TY, 4, S>(v); fill2d<T, TX, TY, 5, S>(v); fill2d<T, TX, TY, 6, S>(v);
+    fill2d<T, TX, TY, 7, S>(v); fill2d<T, TX, TY, 8, S>(v); fill2d<T, TX, TY, 9, S>(v);
+    fill2d<T, TX, TY, 10, S>(v); fill2d<T, TX, TY, 11, S>(v); fill2d<T, TX, TY, 12, S>(v);
+    fill2d<T, TX, TY, 13, S>(v); fill2d<T, TX, TY, 14, S>(v); fill2d<T, TX, TY, 15, S>(v);
+    fill2d<T, TX, TY, 16, S>(v);
     return v;
 }
 template <typename T, int TX, int TY, int TZ>
@@ -485,6 +521,7 @@ Variant make3d() {
     v.dim = 3;
     v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = TZ;
+    v.threads = kThreads;
     fill3d<T, TX, TY, TZ, 1>(v); fill3d<T, TX, TY, TZ, 2>(v); fill3d<T, TX, TY, TZ, 3>(v);
     fill3d<T, TX, TY, TZ, 4>(v); fill3d<T, TX, TY, TZ, 5>(v); fill3d<T, TX, TY, TZ, 6>(v);
     fill3d<T, TX, TY, TZ, 7>(v); fill3d<T, TX, TY, TZ, 8>(v);
@@ -506,6 +543,9 @@ const Variant *variants(int *count) {
         make2d<double, 16, 16>(),  // 10
         make3d<double, 8, 8, 8>(), // 11: FP64 3D, small tiles
         make3d<double, 16, 8, 4>(),// 12
+        make2d<float, 32, 16, 2>(), // 13: FP32 2D, controls split over 2 groups
+        make2d<float, 32, 16, 4>(), // 14: ... over 4 groups
+        make2d<float, 64, 8, 4>(),  // 15
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;
@@ -526,6 +566,7 @@ int sweep_variants(int dim, LaunchCfg *out, int cap) {
             out[k].tile[2] = v[i].tile[2];
             out[k].halo = 0;
             out[k].variant = i;
+            out[k].threads = v[i].threads;
         }
         ++k;
     }
@@ -561,7 +602,7 @@ hipError_t sweep_set_attributes(LaunchCfg &cfg) {
             if (e != hipSuccess) return e;
         }
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cfg.threads, lds) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         cap = std::min(cap, per_cu * n_cu);
@@ -572,8 +613,8 @@ hipError_t sweep_set_attributes(LaunchCfg &cfg) {
 
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
                         const WorkItem *items, ExecCounters *cnt, int max_items,
-                        int sweep, double tol, int want_policy, uint8_t *changed,
-                        int flag_stride, int cls, int do_bookkeep, hipStream_t s) {
+                        int sweep, double tol, int want_policy, int *stamp,
+                        int stamp_stride, int cls, int do_bookkeep, hipStream_t s) {
     size_t lds = 0;
     const void *fn = sweep_fn(cfg, want_policy, &lds);
     if (!fn) return hipErrorInvalidValue;
@@ -581,9 +622,10 @@ hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int 
     int persistent = cfg.mode;
     if (persistent && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
     void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&cnt,
-                    (void *)&sweep, (void *)&tol, (void *)&changed, (void *)&flag_stride,
+                    (void *)&sweep, (void *)&tol, (void *)&stamp, (void *)&stamp_stride,
                     (void *)&persistent, (void *)&cls, (void *)&do_bookkeep};
-    return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(cfg.threads > 0 ? cfg.threads : kThreads), args,
+                           lds, s);
 }
 
 hipError_t launch_flip(SdState *st, int n_sd, hipStream_t s) {

@@ -166,6 +166,48 @@ def test_isa_fp64_bit_exact_non_nested_with_cost():
     assert np.array_equal(host(owner), own_o)
 
 
+def test_full_size_c2_every_configuration():
+    """The benchmark's problem (1025^2, 64 controls, 4 disks), every sweep
+    configuration of the autotuner: candidates of one tile shape give the same
+    FP32 values bit for bit (neither the schedule nor the split of the controls
+    over thread groups changes the arithmetic), all agree within 1e-5, and the
+    result is a fixed point of the oracle's FP64 operator on every set up to FP32
+    rounding (a check that needs one oracle sweep, not a whole solve)."""
+    p = W.c2_multitarget()
+    say("case: full-size c2, every configuration")
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    member, label, _ = S.reconstruct(dp, ra)
+    nc = S.lib().sl_tune_candidates(2, 0)
+    by_tile, ref = {}, None
+    for k in range(1, nc + 1):
+        V, own, pol, Vs, st = S.solve_isa(dp, ra, member,
+                                          S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=-k),
+                                          want_sets=True)
+        assert st["converged"], k
+        Vh = host(Vs).reshape(p.n_comp, p.N)
+        say("  candidate", k, "tile", st["tile"], "mode", st["mode"], "sweeps", st["sweeps_max"])
+        key = tuple(st["tile"])
+        if key in by_tile:
+            assert np.array_equal(Vh, by_tile[key]), k
+        else:
+            by_tile[key] = Vh
+        if ref is None:
+            ref = Vh
+        else:
+            assert np.abs(Vh.astype(np.float64) - ref).max() <= 1e-5, k
+    mem = host(member)
+    fixed = O.fixed_mask(p)
+    for i in range(p.n_comp):
+        dom = ((mem >> i) & 1).astype(np.uint8)
+        Vi = ref[i].astype(np.float64)
+        TV, _ = O.apply_T(p, Vi, fixed=fixed, dom=dom)
+        on = dom.astype(bool) & (np.asarray(p.target) < 0)
+        r = np.abs(TV[on] - Vi[on]).max()
+        say("  set", i, "fixed-point residual", r)
+        assert r <= 2e-6
+
+
 # ------------------------------------------------------------------------- ISA
 @pytest.mark.parametrize("n", [129, 257])
 def test_isa_fp32_parity(n):
