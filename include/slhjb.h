@@ -111,6 +111,20 @@ typedef struct sl_solve_opts {
                                  candidate and cache the fastest; 2: same with complete
                                  solves as trials; -k: use candidate k-1 (testing aid,
                                  k <= sl_tune_candidates(dim, dtype))                    */
+    int local_iters;          /* 0: Jacobi sweeps (each reads the previous iterate).
+                                 k > 0 (0 <= k <= 1024): block-asynchronous sweeps: every
+                                 active tile iterates up to k times on its own values in
+                                 on-chip memory, its halo as read at the start of the
+                                 launch, while anything in it changes, and writes back in
+                                 place.  The scheme's evaluation is monotone in the node
+                                 values in both precisions, so from the initial values
+                                 (a supersolution when v_ghost >= max l / lambda) the
+                                 iterates decrease to the same floating-point fixed point
+                                 as Jacobi: with tol = 0 the values match Jacobi's bit for
+                                 bit whenever T(V0) <= V0 holds exactly in floating point
+                                 (e.g. FP32 with v_ghost a power of two).  A "sweep" in the
+                                 statistics is then one launch; tol bounds the largest
+                                 change of one local iteration.                        */
 } sl_solve_opts;
 
 /* Per-call statistics (HOST struct filled at the end of a call). */

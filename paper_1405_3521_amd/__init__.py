@@ -56,7 +56,8 @@ class SlRaOpts(C.Structure):
 
 class SlSolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_sweeps", C.c_long), ("want_policy", C.c_int),
-                ("check_every", C.c_int), ("profile", C.c_int), ("autotune", C.c_int)]
+                ("check_every", C.c_int), ("profile", C.c_int), ("autotune", C.c_int),
+                ("local_iters", C.c_int)]
 
 
 class SlStats(C.Structure):
@@ -177,6 +178,7 @@ class SolveOpts:
     check_every: int = 0
     profile: bool = False
     autotune: int = 0
+    local_iters: int = 0      # 0: Jacobi sweeps; k > 0: block-asynchronous (see sl_solve_opts)
 
 
 def to_device(prob, dtype=None, device: str = "cuda:0") -> DeviceProblem:
@@ -261,7 +263,7 @@ def coarse_nodes(p, ra: RaOpts) -> tuple:
 
 def _so(o: SolveOpts) -> SlSolveOpts:
     return SlSolveOpts(o.tol, o.max_sweeps, int(bool(o.want_policy)), o.check_every,
-                       int(bool(o.profile)), int(o.autotune))
+                       int(bool(o.profile)), int(o.autotune), int(o.local_iters))
 
 
 def _workspace(nbytes: int, device):

@@ -80,6 +80,7 @@ int validate_solve_opts(const sl_solve_opts *o) {
     if (o->max_sweeps < 1 || o->max_sweeps > 100000000L) return SL_ERR_INVALID_ARG;
     if (o->check_every < 0) return SL_ERR_INVALID_ARG;
     if (o->autotune > 2) return SL_ERR_INVALID_ARG;
+    if (o->local_iters < 0 || o->local_iters > 1024) return SL_ERR_INVALID_ARG;
     return SL_OK;
 }
 
@@ -245,11 +246,11 @@ struct ChunkLoop {
 // Kernel configurations are chosen per problem shape by timing candidates on
 // the caller's problem; the winner is cached for the life of the process.
 struct TuneKey {
-    int dim, dtype, m, halo, nsd, size_class;
+    int dim, dtype, m, halo, nsd, size_class, local_iters;
     bool operator<(const TuneKey &o) const {
-        const int a[6] = {dim, dtype, m, halo, nsd, size_class};
-        const int b[6] = {o.dim, o.dtype, o.m, o.halo, o.nsd, o.size_class};
-        return std::lexicographical_compare(a, a + 6, b, b + 6);
+        const int a[7] = {dim, dtype, m, halo, nsd, size_class, local_iters};
+        const int b[7] = {o.dim, o.dtype, o.m, o.halo, o.nsd, o.size_class, o.local_iters};
+        return std::lexicographical_compare(a, a + 7, b, b + 7);
     }
 };
 std::map<TuneKey, std::pair<int, int>> &tune_cache() {
@@ -337,6 +338,9 @@ struct Exec {
     // Upload descriptors and states, build the work list.
     int prepare(hipStream_t s) {
         n_sd = (int)host_sds.size();
+        // block-asynchronous sweeps update in place: both Jacobi buffers are one array
+        if (cfg.local_iters > 0)
+            for (auto &d : host_sds) d.V[1] = d.V[0];
         host_prefix.resize(n_sd);
         int acc = 0;
         for (int i = 0; i < n_sd; ++i) {
@@ -451,19 +455,21 @@ struct Exec {
     template <class Reinit>
     int solve_tuned(int autotune, Reinit reinit, double tol, long max_sweeps, int check_every,
                     int want_policy, hipStream_t s, long *sweeps_done, int profile) {
+        const int local_iters = cfg.local_iters;   // not a tuned parameter
         if (autotune < 0) {                  // forced candidate (testing)
             const std::vector<LaunchCfg> cands = tune_candidates(cfg.dim, cfg.dtype, cfg.halo);
             const int k = -autotune - 1;
             if (k >= (int)cands.size()) return SL_ERR_INVALID_ARG;
             cfg = cands[k];
+            cfg.local_iters = local_iters;
         }
         if (autotune > 0) {
             long nodes = 0;
             for (const auto &d : host_sds) nodes += (long)d.n[0] * d.n[1] * d.n[2];
             int sc = 0;
             while ((1L << sc) < nodes) ++sc;
-            const TuneKey key{cfg.dim, cfg.dtype, host_sds.empty() ? 0 : host_sds[0].m, cfg.halo,
-                              (int)host_sds.size(), sc};
+            const TuneKey key{cfg.dim,   cfg.dtype, host_sds.empty() ? 0 : host_sds[0].m,
+                              cfg.halo,  (int)host_sds.size(), sc, local_iters};
             bool found = false;
             std::pair<int, int> pick;
             {
@@ -484,6 +490,7 @@ struct Exec {
                 const long trial = autotune == 1 ? std::min<long>(96, max_sweeps) : max_sweeps;
                 for (const LaunchCfg &c : cands) {
                     cfg = c;
+                    cfg.local_iters = local_iters;
                     retile();
                     HIPCHK(reinit(s));
                     int rc = prepare(s);
@@ -510,6 +517,7 @@ struct Exec {
             const int halo = cfg.halo;
             cfg = make_cfg(cfg.dim, cfg.dtype, halo, pick.first);
             cfg.mode = pick.second;
+            cfg.local_iters = local_iters;
             ms_sweeps = 0.0;
             sweep_launches = 0;
         }
@@ -661,6 +669,7 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     const int H = halo_for(smax, emax);
     if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     ex.cfg = make_cfg(p->dim, p->dtype, H, variant);
+    ex.cfg.local_iters = o->local_iters;
 
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
@@ -939,6 +948,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     const int H = halo_for(smax, emax);
     if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.ex.cfg = make_cfg(p->dim, p->dtype, H, default_variant(p->dim, p->dtype));
+    P.ex.cfg.local_iters = o->local_iters;
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(P.ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
@@ -1325,6 +1335,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     tm.mark(1, s);
     // 5. ISA step 3 for every (problem, set): one launch per sweep
     B.ex.cfg = make_cfg(dim, probs[0].dtype, H, default_variant(dim, probs[0].dtype));
+    B.ex.cfg.local_iters = o->local_iters;
     coff = 0;
     for (int q = 0; q < np; ++q) {
         const sl_problem *p = &probs[q];

@@ -148,6 +148,8 @@ struct LaunchCfg {
     int mode;                   // 0: one work-group per item; 1: resident grid + atomic
                                 // work queue; 2: resident grid + static grid stride
     int threads;                // work-group size of the variant
+    int local_iters;            // 0: Jacobi sweeps; k > 0: block-asynchronous, up to k
+                                // local iterations per tile and launch (in place)
 };
 
 // ---- launchers (sweep.hip) -------------------------------------------------

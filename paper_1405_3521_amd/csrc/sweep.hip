@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                                                       int sweep_rel, double tol,
                                                       int *__restrict__ stamp,
                                                       int stamp_stride, int mode, int cls,
-                                                      int do_bookkeep) {
+                                                      int do_bookkeep, int local_iters) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
@@ -157,13 +157,26 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                 ux0[r] = (T)gx;
                 uy0[r] = (T)gy;
             }
-            best[r] = (T)INFINITY;
-            arg[r] = 0;
         }
         const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
         const T beta = d.beta;
         const T *__restrict__ ctrl = d.ctrl;
         const int m = d.m;
+        // Jacobi (local_iters == 0): one evaluation per node, written to the other
+        // buffer.  Block-asynchronous (local_iters = k > 0): the tile iterates up to
+        // k times on its own values in LDS, the halo as staged, while anything in it
+        // changes; the values go back in place (both buffers are the same array).
+        const bool async = !POLICY && local_iters > 0;
+        const int iters = async ? local_iters : 1;
+        double rmax = 0.0;
+        unsigned na = 0;
+        bool tile_changed = false;
+        for (int li = 0; li < iters; ++li) {
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            best[r] = (T)INFINITY;
+            arg[r] = 0;
+        }
         if (__any(any)) {
 #pragma unroll 2
             for (int k = grp; k < m; k += S) {
@@ -247,19 +260,50 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                 }
             }
         }
-        double rmax = 0.0;
-        unsigned na = 0;
+        if (async) {
+            int chg = 0;
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) {
-            if (!act[r] || grp > 0) continue;
-            const int ty = ty0 + r * RSTEP;
-            const size_t j = (size_t)(y0 + ty) * n0 + gx;
-            Vout[j] = best[r];
-            if (POLICY) d.policy[j] = (uint8_t)arg[r];
-            const double dv =
-                __builtin_fabs((double)best[r] - (double)lds[(ty + H) * LW + tx + H]);
-            rmax = dv > rmax ? dv : rmax;
-            ++na;
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r] || grp > 0) continue;
+                const int ty = ty0 + r * RSTEP;
+                const T old = lds[(ty + H) * LW + tx + H];
+                const double dv = __builtin_fabs((double)best[r] - (double)old);
+                rmax = dv > rmax ? dv : rmax;
+                chg |= best[r] != old;
+                ++na;
+            }
+            __syncthreads();                 // every read of this iteration is done
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r] || grp > 0) continue;
+                lds[(ty0 + r * RSTEP + H) * LW + tx + H] = best[r];
+            }
+            if (!__syncthreads_or(chg)) break;
+            tile_changed = true;
+        } else {
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r] || grp > 0) continue;
+                const int ty = ty0 + r * RSTEP;
+                const size_t j = (size_t)(y0 + ty) * n0 + gx;
+                // a policy pass over in-place (block-asynchronous) values only
+                // records the argmin, so that it belongs to the returned values
+                if (!POLICY || Vout != Vin) Vout[j] = best[r];
+                if (POLICY) d.policy[j] = (uint8_t)arg[r];
+                const double dv =
+                    __builtin_fabs((double)best[r] - (double)lds[(ty + H) * LW + tx + H]);
+                rmax = dv > rmax ? dv : rmax;
+                ++na;
+            }
+        }
+        }                                    // local iterations
+        if (tile_changed) {
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r] || grp > 0) continue;
+                const int ty = ty0 + r * RSTEP;
+                Vout[(size_t)(y0 + ty) * n0 + gx] = lds[(ty + H) * LW + tx + H];
+            }
         }
         nact += na * (unsigned)m;
         if (!POLICY) {
@@ -281,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                                                       int sweep_rel, double tol,
                                                       int *__restrict__ stamp,
                                                       int stamp_stride, int mode, int cls,
-                                                      int do_bookkeep) {
+                                                      int do_bookkeep, int local_iters) {
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
@@ -374,13 +418,23 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                 uy0[r] = (T)gy;
                 uz0[r] = (T)gz;
             }
-            best[r] = (T)INFINITY;
-            arg[r] = 0;
         }
         const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
         const T beta = d.beta;
         const T *__restrict__ ctrl = d.ctrl;
         const int m = d.m;
+        // Jacobi or block-asynchronous local iterations, as in the 2D kernel
+        const bool async = !POLICY && local_iters > 0;
+        const int iters = async ? local_iters : 1;
+        double rmax = 0.0;
+        unsigned na = 0;
+        bool tile_changed = false;
+        for (int li = 0; li < iters; ++li) {
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            best[r] = (T)INFINITY;
+            arg[r] = 0;
+        }
         if (__any(any)) {
             for (int k = 0; k < m; ++k) {
                 const T ex = ctrl[3 * k], ey = ctrl[3 * k + 1], ez = ctrl[3 * k + 2];
@@ -442,19 +496,49 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                 }
             }
         }
-        double rmax = 0.0;
-        unsigned na = 0;
+        if (async) {
+            int chg = 0;
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) {
-            if (!act[r]) continue;
-            const int tz = tz0 + r * ZSTEP;
-            const size_t j = ((size_t)(z0 + tz) * n1 + gy) * n0 + gx;
-            Vout[j] = best[r];
-            if (POLICY) d.policy[j] = (uint8_t)arg[r];
-            const double dv = __builtin_fabs(
-                (double)best[r] - (double)lds[((tz + H) * LH + ty + H) * LW + tx + H]);
-            rmax = dv > rmax ? dv : rmax;
-            ++na;
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r]) continue;
+                const int tz = tz0 + r * ZSTEP;
+                const T old = lds[((tz + H) * LH + ty + H) * LW + tx + H];
+                const double dv = __builtin_fabs((double)best[r] - (double)old);
+                rmax = dv > rmax ? dv : rmax;
+                chg |= best[r] != old;
+                ++na;
+            }
+            __syncthreads();                 // every read of this iteration is done
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r]) continue;
+                lds[((tz0 + r * ZSTEP + H) * LH + ty + H) * LW + tx + H] = best[r];
+            }
+            if (!__syncthreads_or(chg)) break;
+            tile_changed = true;
+        } else {
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r]) continue;
+                const int tz = tz0 + r * ZSTEP;
+                const size_t j = ((size_t)(z0 + tz) * n1 + gy) * n0 + gx;
+                if (!POLICY || Vout != Vin) Vout[j] = best[r];
+                if (POLICY) d.policy[j] = (uint8_t)arg[r];
+                const double dv = __builtin_fabs(
+                    (double)best[r] - (double)lds[((tz + H) * LH + ty + H) * LW + tx + H]);
+                rmax = dv > rmax ? dv : rmax;
+                ++na;
+            }
+        }
+        }                                    // local iterations
+        if (tile_changed) {
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                if (!act[r]) continue;
+                const int tz = tz0 + r * ZSTEP;
+                Vout[((size_t)(z0 + tz) * n1 + gy) * n0 + gx] =
+                    lds[((tz + H) * LH + ty + H) * LW + tx + H];
+            }
         }
         nact += na * (unsigned)m;
         if (!POLICY) {
@@ -621,9 +705,11 @@ hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int 
     int grid = max_items > 0 ? max_items : 1;
     int persistent = cfg.mode;
     if (persistent && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
+    int local_iters = want_policy ? 0 : cfg.local_iters;
     void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&cnt,
                     (void *)&sweep, (void *)&tol, (void *)&stamp, (void *)&stamp_stride,
-                    (void *)&persistent, (void *)&cls, (void *)&do_bookkeep};
+                    (void *)&persistent, (void *)&cls, (void *)&do_bookkeep,
+                    (void *)&local_iters};
     return hipLaunchKernel(fn, dim3(grid), dim3(cfg.threads > 0 ? cfg.threads : kThreads), args,
                            lds, s);
 }

@@ -94,6 +94,11 @@ def test_solve_argument_errors_before_device_work():
     assert L.sl_solve(C.byref(p), C.byref(bad), buf, 64, buf, None, C.byref(st), None) == -1
     bad = S.SlSolveOpts(0.0, 0, 0, 0, 0)
     assert L.sl_solve(C.byref(p), C.byref(bad), buf, 64, buf, None, C.byref(st), None) == -1
+    for li in (-1, 1025):          # local iterations out of [0, 1024]
+        bad = S.SlSolveOpts(0.0, 100, 0, 0, 0, 0, li)
+        assert L.sl_solve(C.byref(p), C.byref(bad), buf, 64, buf, None, C.byref(st), None) == -1
+    ok = S.SlSolveOpts(0.0, 100, 0, 0, 0, 0, 1024)
+    assert L.sl_solve(C.byref(p), C.byref(ok), buf, 64, buf, None, C.byref(st), None) == -5
     # workspace too small
     assert L.sl_solve(C.byref(p), C.byref(opts), buf, 64, buf, None, C.byref(st), None) == -5
 
