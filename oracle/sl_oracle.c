@@ -22,9 +22,12 @@
  *               "paper" beta = 1/(1 + lam h), w = h               ((Tdef) as printed);
  *   - dynamics f(x, a_k) = c(x) b_k (+ drift(x)), evaluated in grid-index units:
  *       disp_d = (h/dx_d * b_kd) * c_j  (+ h/dx_d * drift_jd),   u_d = i_d + disp_d;
- *   - interpolation in a fixed operation order (weights are products of 1-tau / tau
- *     in axis order; accumulation by fused multiply-add in corner order), so an
- *     implementation that follows the same order gets bit-identical FP64 results.
+ *   - interpolation in a fixed operation order: Q1 as the tensor product of
+ *     one-axis linear interpolations, along x, then y, then z, each evaluated as
+ *     fma(tau, v1, (1 - tau) * v0); an implementation that follows the same order
+ *     gets bit-identical FP64 results.  Every rounding step is monotone in the node
+ *     values, and a constant field equal to a power of two (the ghost value) is
+ *     reproduced exactly.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
  */
@@ -122,6 +125,18 @@ static inline void node_index(const orc_prob *P, long j, long *ij)
     ij[2] = j / (P->n[0] * P->n[1]);
 }
 
+/* Fractional parts tau_d of the foot of control k from node j (index units). */
+static void foot_fractions(const orc_prob *P, long j, const long *ij, int k, double *tau)
+{
+    const double cj = P->c ? P->c[j] : 1.0;
+    for (int d = 0; d < P->dim; ++d) {
+        double disp = P->e[k * P->dim + d] * cj;
+        if (P->q) disp = disp + P->q[j * P->dim + d];
+        double u = (double)ij[d] + disp;
+        tau[d] = u - floor(u);
+    }
+}
+
 /* Q1 stencil at the foot of control k from node j: corner node indices (-1 = ghost:
  * outside the box or outside the domain) and weights.  Returns the corner count. */
 static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx, double *wt)
@@ -159,21 +174,33 @@ static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx,
     return K;
 }
 
+/* Q1 value at the foot from the corner values val[0..2^dim) (bit d of the corner
+ * index = upper node on axis d): linear interpolation along axis 0 between corner
+ * pairs (2s, 2s+1), then along axis 1 between the results, and so on. */
+static double interp_q1(int dim, const double *tau, double *val)
+{
+    int cnt = 1 << dim;
+    for (int d = 0; d < dim; ++d) {
+        const double t = tau[d], a = 1.0 - t;
+        for (int s = 0; s < cnt / 2; ++s) val[s] = fma(t, val[2 * s + 1], a * val[2 * s]);
+        cnt /= 2;
+    }
+    return val[0];
+}
+
 /* One application of T at node j; returns the minimum, *arg = first minimising k. */
 static double apply_node(const orc_prob *P, long j, const double *V, int *arg)
 {
     long ij[3], cidx[ORC_MAX_CORNERS];
-    double wt[ORC_MAX_CORNERS];
+    double wt[ORC_MAX_CORNERS], tau[3], val[ORC_MAX_CORNERS];
     node_index(P, j, ij);
     double best = 0.0;
     int bk = -1;
     for (int k = 0; k < P->m; ++k) {
         int K = stencil(P, j, ij, k, cidx, wt);
-        double r = 0.0;
-        for (int s = 0; s < K; ++s) {
-            double v = cidx[s] >= 0 ? V[cidx[s]] : P->G;
-            r = (s == 0) ? wt[0] * v : fma(wt[s], v, r);
-        }
+        foot_fractions(P, j, ij, k, tau);
+        for (int s = 0; s < K; ++s) val[s] = cidx[s] >= 0 ? V[cidx[s]] : P->G;
+        double r = interp_q1(P->dim, tau, val);
         double cand = fma(P->beta, r, P->wl[j]);
         if (bk < 0 || cand < best) {
             best = cand;

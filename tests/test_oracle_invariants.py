@@ -206,3 +206,33 @@ def test_inclusion_across_nested_coarse_grids(c2_small):
         c = ((coarse >> i) & 1).astype(bool)
         f = ((fine >> i) & 1).astype(bool)
         assert (c | ~f).mean() >= 0.99
+
+
+@pytest.mark.parametrize("which", ["c2_gs", "c3_gs"])
+def test_any_update_order_reaches_the_jacobi_fixed_point(which):
+    """The FP64 evaluation of T is monotone in every node value and maps the
+    initial values (ghost value 1, a power of two) to values no larger, exactly.
+    From that supersolution every order of updates decreases to the greatest
+    floating-point fixed point below it: a block Gauss-Seidel order (three
+    interleaved families of 8^d blocks, updated in turn with the others held)
+    ends on Jacobi's fixed point bit for bit."""
+    p = (W.c2_multitarget(n=65, m=16) if which == "c2_gs"
+         else W.c3_aniso3d(n=13, m=16, n_balls=2, r=0.2))
+    Vj, _, _, _ = O.solve(p)
+    V = O.initial_values(p)
+    TV0, _ = O.apply_T(p, V)
+    assert (TV0 <= V).all()
+    fx = O.fixed_mask(p).astype(bool)
+    X = np.stack(np.unravel_index(np.arange(p.N), tuple(reversed(p.n))), axis=1)
+    family = (X // 8).sum(axis=1) % 3
+    for _ in range(100000):
+        changed = False
+        for b in range(3):
+            hold = (fx | (family != b)).astype(np.uint8)
+            Vn, _ = O.apply_T(p, V, fixed=hold)
+            changed |= not np.array_equal(Vn, V)
+            assert (Vn <= V).all()
+            V = Vn
+        if not changed:
+            break
+    assert np.array_equal(V, Vj)
