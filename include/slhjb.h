@@ -97,6 +97,12 @@ typedef struct sl_ra_opts {
     long max_sweeps;          /* coarse sweep cap                                     */
     int autotune;             /* as sl_solve_opts.autotune, for the coarse sweeps (the FP64
                                  results do not depend on the kernel configuration)   */
+    int local_iters;          /* as sl_solve_opts.local_iters, for the coarse sweeps: 0
+                                 Jacobi; k > 0 block-asynchronous.  With tol = 0 both
+                                 reach the same FP64 fixed point bit for bit (so the sets
+                                 and labels do not depend on it); with tol > 0 the two
+                                 stop on different iterates.  sl_solve_batched takes it
+                                 (like tol and autotune) from the first problem's options. */
 } sl_ra_opts;
 
 /* Value-iteration options. */
@@ -168,8 +174,8 @@ size_t sl_isa_workspace_size(const sl_problem *p, const sl_ra_opts *ra);
 /* Reconstruction of the independent sub-domains (paper Sec. 3, RA steps 1-3, on
  * the coarse grid K of ISA step 1; Sec. 4, ISA step 2 projection to the fine
  * grid).  The coarse auxiliary solves run in FP64 whatever p->dtype is, with the
- * operation order of the scheme fixed (products of 1-tau / tau in axis order,
- * fused multiply-add accumulation in corner order, candidate fma(beta, I, w l)),
+ * operation order of the scheme fixed (Q1 as nested one-axis interpolations
+ * fma(tau, v1, (1 - tau) v0) along x, then y, then z; candidate fma(beta, I, w l)),
  * so the labels are reproducible bit for bit.
  * Outputs (DEVICE, N uint8 each): member = bitmask of the sets containing each
  * fine node (Con(.): the union of the closed coarse cells with every corner in the

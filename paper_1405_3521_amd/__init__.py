@@ -51,7 +51,7 @@ class SlRaOpts(C.Structure):
     _fields_ = [("coarse_stride", C.c_int), ("coarse_n", C.c_int * 3), ("C", C.c_double),
                 ("M", C.c_double),
                 ("q", C.c_double), ("delta_override", C.c_double), ("tol", C.c_double),
-                ("max_sweeps", C.c_long), ("autotune", C.c_int)]
+                ("max_sweeps", C.c_long), ("autotune", C.c_int), ("local_iters", C.c_int)]
 
 
 class SlSolveOpts(C.Structure):
@@ -168,6 +168,7 @@ class RaOpts:
     tol: float = 0.0
     max_sweeps: int = 10_000_000
     autotune: int = 0
+    local_iters: int = 0      # coarse sweeps: 0 Jacobi; k > 0 block-asynchronous
 
 
 @dataclass
@@ -251,7 +252,7 @@ def _stream():
 def _ra(o: RaOpts) -> SlRaOpts:
     cn = tuple(o.coarse_n or ()) + (0, 0, 0)
     return SlRaOpts(o.coarse_stride, (C.c_int * 3)(*[int(x) for x in cn[:3]]), o.C, o.M, o.q,
-                    o.delta_override, o.tol, o.max_sweeps, int(o.autotune))
+                    o.delta_override, o.tol, o.max_sweeps, int(o.autotune), int(o.local_iters))
 
 
 def coarse_nodes(p, ra: RaOpts) -> tuple:

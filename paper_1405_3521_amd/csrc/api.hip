@@ -101,6 +101,7 @@ int validate_ra(const sl_problem *p, const sl_ra_opts *ra) {
     if (!(ra->delta_override >= 0.0) && !(ra->delta_override < 0.0)) return SL_ERR_INVALID_ARG;
     if (!(ra->tol >= 0.0) || ra->max_sweeps < 1) return SL_ERR_INVALID_ARG;
     if (ra->autotune > 2) return SL_ERR_INVALID_ARG;
+    if (ra->local_iters < 0 || ra->local_iters > 1024) return SL_ERR_INVALID_ARG;
     return SL_OK;
 }
 
@@ -854,6 +855,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     const int HK = halo_for(smax, emaxK);
     if (HK > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.exK.cfg = make_cfg(p->dim, SL_F64, HK, default_variant(p->dim, SL_F64));
+    P.exK.cfg.local_iters = ra->local_iters;
     auto reinit = [&](hipStream_t q) -> hipError_t {
         for (int i = 0; i < nc; ++i)
             for (int b = 0; b < 2; ++b) {
@@ -1295,6 +1297,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     };
     // 3. RA step 1 for every (problem, component): one launch per sweep
     B.exK.cfg = make_cfg(dim, SL_F64, HK, default_variant(dim, SL_F64));
+    B.exK.cfg.local_iters = ras[0].local_iters;
     size_t coff = 0;
     for (int q = 0; q < np; ++q) {
         const sl_problem *p = &probs[q];

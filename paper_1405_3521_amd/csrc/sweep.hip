@@ -198,27 +198,18 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                     const int base = iy * LW + ix;
                     const T v00 = lds[base], v10 = lds[base + 1];
                     const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
-                    T acc;
-                    if (sizeof(T) == 4) {
-                        // FP32: Q1 as nested one-axis interpolations fma(f, v1, (1-f) v0).
-                        // Every rounding step is monotone in the node values (so the
-                        // Jacobi iterates from the ghost value decrease to a bitwise
-                        // fixed point), and a field equal to 1.0 or any power of two is
-                        // reproduced exactly: the unreached region keeps its ghost value
-                        // bit for bit, so its tiles are skipped instead of drifting.
-                        const T ax = T(1) - fx, ay = T(1) - fy;
-                        const T a = fma_(fx, v10, ax * v00);
-                        const T b = fma_(fx, v11, ax * v01);
-                        acc = fma_(fy, b, ay * a);
-                    } else {
-                        // FP64: corner weights, the fixed order the labels rely on
-                        const T ax = T(1) - fx, ay = T(1) - fy;
-                        const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
-                        acc = w00 * v00;
-                        acc = fma_(w10, v10, acc);
-                        acc = fma_(w01, v01, acc);
-                        acc = fma_(w11, v11, acc);
-                    }
+                    // Q1 as nested one-axis interpolations fma(f, v1, (1-f) v0), x then
+                    // y.  Every rounding step is monotone in the node values (so the
+                    // iterates from the ghost value decrease to a bitwise fixed point,
+                    // in any update order), and a field equal to a power of two (the
+                    // ghost value) is reproduced exactly: the unreached region keeps
+                    // its value bit for bit, so its tiles are skipped instead of
+                    // drifting.  In FP64 (global index coordinates) this is also the
+                    // fixed operation order the reproducible labels rely on.
+                    const T ax = T(1) - fx, ay = T(1) - fy;
+                    const T a = fma_(fx, v10, ax * v00);
+                    const T b = fma_(fx, v11, ax * v01);
+                    const T acc = fma_(fy, b, ay * a);
                     const T cand = fma_(beta, acc, wl[r]);
                     if (POLICY) {
                         if (cand < best[r]) {
@@ -456,34 +447,19 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     Foot<T>::split(uy, oy, iy, fy);
                     Foot<T>::split(uz, oz, iz, fz);
                     const int base = (iz * LH + iy) * LW + ix;
-                    T acc;
-                    if (sizeof(T) == 4) {
-                        // FP32: nested one-axis interpolations fma(f, v1, (1-f) v0):
-                        // monotone rounding, powers of two reproduced exactly
-                        const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
-                        const T v000 = lds[base], v100 = lds[base + 1];
-                        const T v010 = lds[base + LW], v110 = lds[base + LW + 1];
-                        const T v001 = lds[base + PL], v101 = lds[base + PL + 1];
-                        const T v011 = lds[base + PL + LW], v111 = lds[base + PL + LW + 1];
-                        const T a0 = fma_(fx, v100, ax * v000);
-                        const T b0 = fma_(fx, v110, ax * v010);
-                        const T a1 = fma_(fx, v101, ax * v001);
-                        const T b1 = fma_(fx, v111, ax * v011);
-                        const T c0 = fma_(fy, b0, ay * a0);
-                        const T c1 = fma_(fy, b1, ay * a1);
-                        acc = fma_(fz, c1, az * c0);
-                    } else {
-                        const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
-                        const T w00 = ax * ay, w10 = fx * ay, w01 = ax * fy, w11 = fx * fy;
-                        acc = (w00 * az) * lds[base];
-                        acc = fma_(w10 * az, lds[base + 1], acc);
-                        acc = fma_(w01 * az, lds[base + LW], acc);
-                        acc = fma_(w11 * az, lds[base + LW + 1], acc);
-                        acc = fma_(w00 * fz, lds[base + PL], acc);
-                        acc = fma_(w10 * fz, lds[base + PL + 1], acc);
-                        acc = fma_(w01 * fz, lds[base + PL + LW], acc);
-                        acc = fma_(w11 * fz, lds[base + PL + LW + 1], acc);
-                    }
+                    // nested one-axis interpolations, x, then y, then z (as in 2D)
+                    const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
+                    const T v000 = lds[base], v100 = lds[base + 1];
+                    const T v010 = lds[base + LW], v110 = lds[base + LW + 1];
+                    const T v001 = lds[base + PL], v101 = lds[base + PL + 1];
+                    const T v011 = lds[base + PL + LW], v111 = lds[base + PL + LW + 1];
+                    const T a0 = fma_(fx, v100, ax * v000);
+                    const T b0 = fma_(fx, v110, ax * v010);
+                    const T a1 = fma_(fx, v101, ax * v001);
+                    const T b1 = fma_(fx, v111, ax * v011);
+                    const T c0 = fma_(fy, b0, ay * a0);
+                    const T c1 = fma_(fy, b1, ay * a1);
+                    const T acc = fma_(fz, c1, az * c0);
                     const T cand = fma_(beta, acc, wl[r]);
                     if (POLICY) {
                         if (cand < best[r]) {

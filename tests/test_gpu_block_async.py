@@ -104,3 +104,61 @@ def test_block_async_tolerance_stop_vs_oracle():
         err = np.abs(host(V).astype(np.float64) - Vbar).max()
         say("tol 1e-6, local iterations", k, "sup err", err)
         assert st["converged"] and err <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["2d_nested", "2d_non_nested", "3d"])
+def test_block_async_reconstruction_bit_exact(case):
+    """Block-asynchronous coarse sweeps run to tol = 0 reach the oracle's FP64 Jacobi
+    fixed point bit for bit, so the sets and labels equal the oracle's."""
+    if case == "2d_nested":
+        p = W.c2_multitarget(n=257, m=64)
+    elif case == "2d_non_nested":
+        p = W.c2_multitarget(n=129, m=64).with_(coarse_n=(47, 53))
+    else:
+        p = W.c3_aniso3d(n=33, m=64, n_balls=4, r=0.12)
+    p = p.with_(ra_tol=0.0)
+    dp = S.to_device(p, torch.float32)
+    rec = I.reconstruct(p)
+    for k in (2, 8):
+        ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
+                      q=p.ra_q, tol=0.0, local_iters=k)
+        member, label, st, mK, lK = S.reconstruct(dp, ra, want_coarse=True)
+        say("case", case, "coarse local iterations", k, "launches", st["ra_sweeps_max"],
+            "oracle sweeps", max(rec.sweeps))
+        assert np.array_equal(host(mK), rec.member_K)
+        assert np.array_equal(host(lK), rec.label_K)
+        assert np.array_equal(host(member), rec.member)
+        assert np.array_equal(host(label), rec.label)
+
+
+def test_block_async_fp64_isa_bit_exact():
+    """FP64 sets solved with block-asynchronous sweeps equal the oracle's Jacobi
+    fixed point bit for bit (same operation order, monotone, exact on the ghost)."""
+    p = W.c2_multitarget(n=97, m=32)
+    dp = S.to_device(p, torch.float64)
+    Vbar, own_o, rec, Vs_o, _ = I.isa(p)
+    member = torch.as_tensor(rec.member, device="cuda:0")
+    for k in (1, 4, 16):
+        V, own, pol, Vs, st = S.solve_isa(dp, ra_of(p), member,
+                                          S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=k),
+                                          want_sets=True)
+        assert st["converged"]
+        assert np.array_equal(host(V), Vbar), k
+        assert np.array_equal(host(own), own_o), k
+
+
+def test_block_async_batched_coarse_and_fine():
+    """The batch with block-asynchronous coarse and fine sweeps (tol = 0): sets and
+    labels equal the oracle's per problem; FP32 values equal the Jacobi batch."""
+    probs = [p.with_(ra_tol=0.0) for p in W.c4_batch(count=10, seed=505, n_min=20, n_max=90)]
+    dps = [S.to_device(p, torch.float32) for p in probs]
+    ras = [S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
+                    q=p.ra_q, tol=0.0, local_iters=4) for p in probs]
+    out = S.solve_batched(dps, ras, S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=4))
+    assert out[-1]["converged"]
+    ref = S.solve_batched(dps, [ra_of(p) for p in probs], S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    for p, V, m, l, Vr in zip(probs, out[0], out[1], out[2], ref[0]):
+        rec = I.reconstruct(p)
+        assert np.array_equal(host(m), rec.member), p.name
+        assert np.array_equal(host(l), rec.label), p.name
+        assert torch.equal(V, Vr), p.name
