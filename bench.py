@@ -156,14 +156,14 @@ def leg_c5(steps: int, li: int):
     member, label, _ = S.reconstruct(dp, ra)
     th_true = torch.as_tensor(p.meta["theta_true"], dtype=torch.float32, device="cuda:0")
     fwd_opts = S.SolveOpts(tol=1e-6, autotune=1, local_iters=li)
-    V_obs = S.HJBSolve.apply(torch.exp(th_true), dp, member, ra, fwd_opts)
+    V_obs = S.HJBSolve.apply(torch.exp(th_true), dp, member, ra, fwd_opts, 1e-7, li)
     obs = torch.as_tensor(p.meta["obs"], device="cuda:0")
     V_obs = V_obs[obs].detach()
     theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device="cuda:0")
 
     def fwd_bwd():
         th = theta.clone().requires_grad_(True)
-        V = S.HJBSolve.apply(torch.exp(th), dp, member, ra, fwd_opts)
+        V = S.HJBSolve.apply(torch.exp(th), dp, member, ra, fwd_opts, 1e-7, li)
         loss = ((V[obs] - V_obs) ** 2).sum()
         _sync()
         t1 = time.perf_counter()

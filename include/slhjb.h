@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SLHJB_ABI_VERSION 2
+#define SLHJB_ABI_VERSION 3
 #define SL_MAX_COMP 8
 #define SL_MAX_CONTROLS 256
 
@@ -234,10 +234,18 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
  * after sl_solve), owner (DEVICE, N uint8: dL/dV(j) goes to set owner[j] only;
  * NULL: to every set), policy (DEVICE, n_sets*N uint8 controls from the forward
  * call with want_policy), dLdV (DEVICE, N in p->dtype).
+ * local_iters (0..1024): 0 = the Jacobi iteration above.  k > 0 in 2D, when the
+ * foot reaches at most 8 cells: block-asynchronous tiles.  Every active 32x16 tile
+ * stages lambda, the frozen feet and the inflow from its halo in on-chip memory,
+ * then repeats "lambda = g + inflow" up to k times while a node changes by more
+ * than tol + 16 eps |lambda|, and writes back in place.  Tiles are revisited when
+ * a neighbour changed.  The iteration has nonnegative coefficients and spectral
+ * radius <= beta < 1, so any update order converges to the same lambda (up to
+ * rounding).  Otherwise the Jacobi iteration runs; max_iters counts launches.
  * Output: dLdl (DEVICE, N in p->dtype; 0 on target nodes). */
 int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
                const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,
-               void *ws, size_t ws_bytes, sl_stats *stats, void *stream);
+               int local_iters, void *ws, size_t ws_bytes, sl_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

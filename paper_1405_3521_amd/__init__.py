@@ -117,7 +117,7 @@ def lib():
         L.sl_adjoint_workspace_size.argtypes = [P(SlProblem), C.c_int]
         L.sl_adjoint_workspace_size.restype = C.c_size_t
         L.sl_adjoint.argtypes = [P(SlProblem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                 C.c_void_p, C.c_double, C.c_long, C.c_void_p, C.c_size_t,
+                                 C.c_void_p, C.c_double, C.c_long, C.c_int, C.c_void_p, C.c_size_t,
                                  P(SlStats), C.c_void_p]
         L.sl_adjoint.restype = C.c_int
         _LIB = L
@@ -364,11 +364,12 @@ def isa(p: DeviceProblem, ra: RaOpts, opts: SolveOpts = SolveOpts(), want_sets: 
 
 
 def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float = None,
-            max_iters: int = 100_000, workspace=None):
+            max_iters: int = 100_000, local_iters: int = 0, workspace=None):
     """dL/dl of a loss with gradient dL/dV, the forward's controls frozen.
 
     ``tol``: stop when the adjoint state changes by at most tol (plus the
     library's rounding allowance, 16 eps max|lambda|) in one iteration; default 0.
+    ``local_iters``: 0 Jacobi iteration; k > 0 block-asynchronous tiles (2D).
 
     ``policy``: from the forward call (``solve``: N entries; ``solve_isa``:
     n_comp*N).  With ``member`` (sets) ``owner`` routes dL/dV to the owning set.
@@ -392,7 +393,8 @@ def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float 
     out = torch.empty(p.N, dtype=p.dtype, device=dev)
     st = SlStats()
     rc = L.sl_adjoint(C.byref(cp), _ptr(member), _ptr(owner), _ptr(policy), _ptr(dLdV),
-                      _ptr(out), float(tol), int(max_iters), _ptr(ws), ws.numel(), C.byref(st),
+                      _ptr(out), float(tol), int(max_iters), int(local_iters), _ptr(ws),
+                      ws.numel(), C.byref(st),
                       _stream())
     if rc < 0:
         raise SlError("sl_adjoint", rc)

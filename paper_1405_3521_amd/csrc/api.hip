@@ -313,6 +313,8 @@ struct Exec {
     // class and sweep, each with the kernel instantiated for that halo
     std::vector<LaunchCfg> ccfg;
     std::vector<int> class_off, class_cap;
+    int kind = 0;                   // 0: forward sweeps; 1: adjoint tiles (2D)
+    double scale_rel = 0.0;         // rounding-aware stopping term (adjoint)
 
     void reserve(Arena &a, int nsd, int tiles_total) {
         sds = a.take<SdDesc<T>>(nsd);
@@ -368,7 +370,7 @@ struct Exec {
         for (size_t c = 0; c < uniq.size(); ++c) {
             ccfg[c].halo = uniq[c];
             if (c > 0) class_off[c] = class_off[c - 1] + class_cap[c - 1];
-            HIPCHK(sweep_set_attributes(ccfg[c]));
+            HIPCHK(kind == 1 ? adjoint_tiles_set_attributes(ccfg[c]) : sweep_set_attributes(ccfg[c]));
         }
         HIPCHK(hipMemcpyAsync(class_off_dev, class_off.data(), sizeof(int) * kMaxClasses,
                               hipMemcpyHostToDevice, s));
@@ -399,9 +401,13 @@ struct Exec {
         for (size_t c = 0; c < ccfg.size(); ++c) {
             if (class_cap[c] == 0) continue;
             const hipError_t e =
-                launch_sweep(ccfg[c], sds, st, n_sd, items + class_off[c], cnt, class_cap[c],
-                             sweep_rel, tol, want_policy, stamp, stamp_stride, (int)c,
-                             first ? 1 : 0, q);
+                kind == 1
+                    ? launch_adjoint_tiles<T>(ccfg[c], sds, st, n_sd, items + class_off[c], cnt,
+                                              class_cap[c], sweep_rel, tol, scale_rel, stamp,
+                                              stamp_stride, (int)c, first ? 1 : 0, q)
+                    : launch_sweep(ccfg[c], sds, st, n_sd, items + class_off[c], cnt,
+                                   class_cap[c], sweep_rel, tol, want_policy, stamp,
+                                   stamp_stride, (int)c, first ? 1 : 0, q);
             if (e != hipSuccess) return e;
             first = false;
         }
@@ -427,7 +433,7 @@ struct Exec {
                 const hipError_t e = launch_classes(i, tol, 0, q);
                 if (e != hipSuccess) return e;
             }
-            hipError_t e = launch_bookkeep(st, n_sd, todo, tol, cnt, 0, q, 0.0, todo);
+            hipError_t e = launch_bookkeep(st, n_sd, todo, tol, cnt, 0, q, scale_rel, todo);
             if (e != hipSuccess) return e;
             return hipMemcpyAsync(active, &cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, q);
         };
@@ -438,7 +444,7 @@ struct Exec {
         if (rc) return rc;
         ms_sweeps += loop.ms;
         sweep_launches += loop.launches;
-        HIPCHK(launch_bookkeep(st, n_sd, 0, tol, cnt, 1, s));
+        HIPCHK(launch_bookkeep(st, n_sd, 0, tol, cnt, 1, s, scale_rel));
         if (want_policy) {
             HIPCHK(launch_classes(0, tol, 1, s));
             HIPCHK(launch_flip(st, n_sd, s));
@@ -1029,6 +1035,7 @@ struct AdjPlan {
     SdState *st = nullptr;
     ExecCounters *cnt = nullptr;
     FieldStats *fs = nullptr;
+    Exec<T> ex;                      // block-asynchronous tile path (2D)
 };
 
 template <typename T>
@@ -1041,12 +1048,16 @@ void plan_adjoint(const sl_problem *p, int n_sets, Arena &a, AdjPlan<T> &P) {
     P.st = a.take<SdState>(n_sets);
     P.cnt = a.take<ExecCounters>(1);
     P.fs = a.take<FieldStats>(1);
+    if (p->dim == 2) {
+        const int tiles = ((p->n[0] + kAdjTX - 1) / kAdjTX) * ((p->n[1] + kAdjTY - 1) / kAdjTY);
+        P.ex.reserve(a, n_sets, tiles * n_sets);
+    }
 }
 
 template <typename T>
 int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
                  const uint8_t *policy, const T *dLdV, T *dLdl, double tol, long max_iters,
-                 void *ws, size_t ws_bytes, sl_stats *stats, hipStream_t s) {
+                 int local_iters, void *ws, size_t ws_bytes, sl_stats *stats, hipStream_t s) {
     Timer tm;
     tm.mark(0, s);
     const size_t N = nodes_of(p);
@@ -1103,6 +1114,64 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     bps = std::max(1, std::min(bps, 2048));
     int *active = pinned().active;
     if (!active) return SL_ERR_HIP;
+    const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
+    const int H = halo_for(smax, emax);
+    if (p->dim == 2 && local_iters > 0 && H <= adjoint_tiles_max_halo()) {
+        // block-asynchronous tiles on the sweep executor
+        LaunchCfg cfg{};
+        cfg.dim = 2;
+        cfg.dtype = p->dtype;
+        cfg.tile[0] = kAdjTX;
+        cfg.tile[1] = kAdjTY;
+        cfg.tile[2] = 1;
+        cfg.halo = H;
+        cfg.variant = -1;
+        cfg.threads = kThreads;
+        cfg.local_iters = local_iters;
+        P.ex.cfg = cfg;
+        P.ex.kind = 1;
+        P.ex.scale_rel = scale_rel;
+        P.ex.host_sds.clear();
+        for (int i = 0; i < n_sets; ++i) {
+            SdDesc<T> sd{};
+            sd.V[0] = sd.V[1] = hd[i].lam;
+            sd.speed = (const T *)p->speed;
+            sd.target = p->target;
+            sd.member = member;
+            sd.policy = const_cast<uint8_t *>(policy + (size_t)i * N);
+            sd.ctrl = P.ctrl;
+            sd.beta = (T)beta;
+            for (int k = 0; k < 3; ++k) sd.n[k] = hd[i].n[k];
+            sd.m = p->m;
+            sd.bit = i;
+            Exec<T>::tiles_of(cfg, sd.n, 2, sd.tiles);
+            sd.halo = H;
+            sd.g = dLdV;
+            sd.owner = member ? owner : nullptr;
+            sd.set = i;
+            P.ex.host_sds.push_back(sd);
+        }
+        tm.mark(1, s);
+        if ((rc = P.ex.prepare(s))) return rc;
+        long it = 0;
+        const int status = P.ex.run(tol, max_iters, 32, 0, s, &it, 0);
+        if (status < 0) return status;
+        HIPCHK(launch_adjoint_combine<T>(P.ads, n_sets, p->target, N, (T)w, dLdl, s));
+        tm.mark(2, s);
+        std::vector<SdState> hs2;
+        unsigned long long nc = 0;
+        if ((rc = P.ex.read_stats(s, hs2, &nc))) return rc;
+        fill_stats(stats, hs2, nc, it);
+        if (stats) {
+            stats->ms_ra = 0.0;
+            stats->ms_fine = tm.ms(1, 2);
+            stats->ms_total = tm.ms(0, 2);
+            stats->set_fraction_max = 0.0;
+            stats->ms_sweeps = 0.0;
+            stats->sweep_launches = it;
+        }
+        return status;
+    }
     tm.mark(1, s);
     auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
         for (int i = 0; i < todo; ++i) {
@@ -1570,19 +1639,20 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets) {
 
 int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
                const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,
-               void *ws, size_t ws_bytes, sl_stats *stats, void *stream) {
+               int local_iters, void *ws, size_t ws_bytes, sl_stats *stats, void *stream) {
     int rc = validate(p);
     if (rc) return rc;
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
+    if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == SL_F32)
         return adjoint_impl<float>(p, member, owner, policy, (const float *)dLdV, (float *)dLdl,
-                                   tol, max_iters, ws, ws_bytes, stats, s);
+                                   tol, max_iters, local_iters, ws, ws_bytes, stats, s);
     return adjoint_impl<double>(p, member, owner, policy, (const double *)dLdV, (double *)dLdl,
-                                tol, max_iters, ws, ws_bytes, stats, s);
+                                tol, max_iters, local_iters, ws, ws_bytes, stats, s);
 }
 
 }  // extern "C"

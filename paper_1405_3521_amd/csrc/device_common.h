@@ -102,6 +102,33 @@ __device__ __forceinline__ double sample_q1(const T *f, int comps, int q, int n0
     return acc;
 }
 
+// Exact active-tile skipping.  With Jacobi double buffering, if no node of the
+// tiles that a tile's halo reaches changed in sweep s-1, the tile's new values
+// equal its old ones, and the output buffer already holds them (it holds the
+// iterate of sweep s-1, equal to that of sweep s).  A tile that changes in sweep
+// s therefore stamps every tile of its neighbourhood (itself included) with s+1,
+// and sweep s computes a tile iff its stamp is s.  The stamps are double buffered
+// by sweep parity: sweep s reads stamp[s & 1], written only in sweep s-1, and
+// writes stamp[(s+1) & 1], so every wave of a work-group reads the same value and
+// takes the same decision.  Concurrent writers store the same value.
+template <int RX, int RY, int RZ>
+__device__ __forceinline__ void stamp_neighbourhood(int *next, int off, const int *t,
+                                                    const int *nt, int s) {
+    for (int dz = -RZ; dz <= RZ; ++dz) {
+        const int z = t[2] + dz;
+        if (z < 0 || z >= nt[2]) continue;
+        for (int dy = -RY; dy <= RY; ++dy) {
+            const int y = t[1] + dy;
+            if (y < 0 || y >= nt[1]) continue;
+            for (int dx = -RX; dx <= RX; ++dx) {
+                const int x = t[0] + dx;
+                if (x < 0 || x >= nt[0]) continue;
+                next[off + (z * nt[1] + y) * nt[0] + x] = s;
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

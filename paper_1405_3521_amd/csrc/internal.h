@@ -43,6 +43,10 @@ struct SdDesc {
     int tile_offset;            // first global tile id of this sd
     int halo;                   // halo this sd needs
     int cls;                    // halo class (its work items live in that class's segment)
+    // adjoint solves only (V[0] holds lambda; policy is the frozen forward policy)
+    const T *g;                 // dL/dV per node
+    const uint8_t *owner;       // set owning each node's value, or nullptr (all sets)
+    int set;                    // this sd's set index (compared with owner)
 };
 
 // Per-sub-domain convergence state (device memory).
@@ -255,6 +259,19 @@ template <typename T>
 hipError_t launch_adjoint_iter(int dim, const AdjDesc<T> *ads, SdState *st, int n_sets,
                                int blocks_per_set, ExecCounters *cnt, int iter_rel, double tol,
                                double scale_rel, hipStream_t s);
+// Block-asynchronous adjoint over the tile work items of an executor (2D): every
+// active tile iterates lambda = g + beta P^T lambda up to local_iters times in
+// LDS, the halo's inflow as staged, and writes back in place.
+template <typename T>
+hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdState *st,
+                                int n_sd, const WorkItem *items, ExecCounters *cnt,
+                                int max_items, int iter_rel, double tol, double scale_rel,
+                                int *stamp, int stamp_stride, int cls, int do_bookkeep,
+                                hipStream_t s);
+hipError_t adjoint_tiles_set_attributes(LaunchCfg &cfg);
+int adjoint_tiles_max_halo();
+// Tile shape of the adjoint tile kernel.
+constexpr int kAdjTX = 32, kAdjTY = 16;
 template <typename T>
 hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_t *target,
                                   size_t N, T w, T *dLdl, hipStream_t s);

@@ -47,9 +47,13 @@ def _obs_grad(p, V, Vobs, obs):
     return g
 
 
+LOCAL = [0, 4]        # Jacobi iteration, block-asynchronous tiles
+
+
+@pytest.mark.parametrize("li", LOCAL)
 @pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
 @pytest.mark.parametrize("n", [65, 129])
-def test_adjoint_kernel_global(n, dtype, tol):
+def test_adjoint_kernel_global(n, dtype, tol, li):
     p = W.c5_adjoint(n=n, n_obs=min(2000, n * n // 8))
     say("case: adjoint global", n, dtype)
     V, pol, _, _ = O.solve(p)
@@ -60,14 +64,15 @@ def test_adjoint_kernel_global(n, dtype, tol):
     dp = S.to_device(p, dtype)
     g_t = torch.as_tensor(gV, dtype=dtype, device=DEV)
     pol_t = torch.as_tensor(pol_u8(pol), device=DEV)
-    dLdl, st = S.adjoint(dp, pol_t, g_t, tol=gpu_tol(gV, dtype))
+    dLdl, st = S.adjoint(dp, pol_t, g_t, tol=gpu_tol(gV, dtype), local_iters=li)
     err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
-    say("  rel l2", err, "iters gpu", st["sweeps_max"], "oracle", it_o)
+    say("  local", li, "rel l2", err, "launches gpu", st["sweeps_max"], "oracle iters", it_o)
     assert st["converged"]
     assert err <= tol
 
 
-def test_adjoint_kernel_isa():
+@pytest.mark.parametrize("li", LOCAL)
+def test_adjoint_kernel_isa(li):
     """Sets frozen, dL/dV routed to the owner set, per-set adjoints summed."""
     p = W.c5_adjoint(n=129, n_obs=1500)
     Vbar, owner, rec, Vs, _ = I.isa(p)
@@ -81,13 +86,14 @@ def test_adjoint_kernel_isa():
     dLdl, st = S.adjoint(dp, pol_t, torch.as_tensor(gV, dtype=torch.float32, device=DEV),
                          member=torch.as_tensor(rec.member, device=DEV),
                          owner=torch.as_tensor(owner, device=DEV),
-                         tol=gpu_tol(gV, torch.float32))
+                         tol=gpu_tol(gV, torch.float32), local_iters=li)
     err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
-    say("  isa adjoint rel l2", err)
+    say("  isa adjoint, local", li, "rel l2", err, "launches", st["sweeps_max"])
     assert err <= 1e-4
 
 
-def test_adjoint_full_size_c5():
+@pytest.mark.parametrize("li", LOCAL)
+def test_adjoint_full_size_c5(li):
     """Full adjoint configuration (513^2, 2000 observations, 4 targets)."""
     p = W.c5_adjoint()
     say("case: adjoint 513 full size")
@@ -99,13 +105,14 @@ def test_adjoint_full_size_c5():
     dp = S.to_device(p, torch.float32)
     dLdl, st = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
                          torch.as_tensor(gV, dtype=torch.float32, device=DEV),
-                         tol=gpu_tol(gV, torch.float32))
+                         tol=gpu_tol(gV, torch.float32), local_iters=li)
     err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
-    say("  rel l2", err, "iters", st["sweeps_max"])
+    say("  local", li, "rel l2", err, "launches", st["sweeps_max"])
     assert err <= 1e-4
 
 
-def test_adjoint_nonnegative_for_nonnegative_g():
+@pytest.mark.parametrize("li", LOCAL)
+def test_adjoint_nonnegative_for_nonnegative_g(li):
     p = W.c5_adjoint(n=65)
     V, pol, _, _ = O.solve(p)
     rng = np.random.Generator(np.random.PCG64(9))
@@ -113,12 +120,13 @@ def test_adjoint_nonnegative_for_nonnegative_g():
     dp = S.to_device(p, torch.float32)
     dLdl, _ = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
                         torch.as_tensor(gV, dtype=torch.float32, device=DEV),
-                        tol=gpu_tol(gV, torch.float32))
+                        tol=gpu_tol(gV, torch.float32), local_iters=li)
     assert float(dLdl.min()) >= 0.0
 
 
+@pytest.mark.parametrize("li", LOCAL)
 @pytest.mark.parametrize("mode", ["global", "isa"])
-def test_autograd_gradient_against_fd(mode):
+def test_autograd_gradient_against_fd(mode, li):
     """theta -> l = exp(theta) -> V (GPU, FP32) -> loss; theta.grad against central
     differences of the oracle's FP64 loss (eps = 1e-6 along dense directions)."""
     p = W.c5_adjoint(n=65, n_obs=300)
@@ -144,7 +152,8 @@ def test_autograd_gradient_against_fd(mode):
     ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
     theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device=DEV).requires_grad_(True)
     mem_t = None if member is None else torch.as_tensor(member, device=DEV)
-    V = S.HJBSolve.apply(torch.exp(theta), dp, mem_t, ra, S.SolveOpts(tol=0.0, max_sweeps=CAP), 0.0)
+    opts = S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=li)
+    V = S.HJBSolve.apply(torch.exp(theta), dp, mem_t, ra, opts, 0.0, li)
     obs_t = torch.as_tensor(obs, device=DEV)
     Vobs_t = torch.as_tensor(Vobs, dtype=torch.float32, device=DEV)
     loss = ((V[obs_t] - Vobs_t) ** 2).sum()
@@ -157,5 +166,5 @@ def test_autograd_gradient_against_fd(mode):
         d = rng.normal(size=p.N)
         fd = (loss_o(th + eps * d) - loss_o(th - eps * d)) / (2 * eps)
         an = float(grad @ d)
-        say(f"  {mode}: fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+        say(f"  {mode} local {li}: fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
         assert abs(fd - an) <= 1e-3 * abs(fd)
