@@ -109,7 +109,7 @@ def leg_c3(steps: int, li: int):
 
 def leg_c4(steps: int, li: int):
     """512 independent 2D problems (sides 16..512): one batched solve vs one
-    solve call per problem."""
+    solve call per problem, and vs one solve call per sub-domain."""
     import torch
     import paper_1405_3521_amd as S
     import workloads as W
@@ -134,11 +134,28 @@ def leg_c4(steps: int, li: int):
                            tol=p.ra_tol), single)
     _sync()
     ms_single = (time.perf_counter() - t0) * 1e3
+    # one solve call per sub-domain (the batch's sets, each solved on its own with
+    # its own launches), after each problem's reconstruction
+    members = out[1]
+    ras0 = [S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
+                     q=p.ra_q, tol=p.ra_tol) for p in probs]
+    n_sd = 0
+    _sync()
+    t0 = time.perf_counter()
+    for dp, p, ra, mem in zip(dps, probs, ras0, members):
+        S.reconstruct(dp, ra)
+        for i in range(p.n_comp):
+            S.solve_isa(dp, ra, mem & (1 << i), single, want_owner=False)
+            n_sd += 1
+    _sync()
+    ms_sd = (time.perf_counter() - t0) * 1e3
     return {"workload": "512 problems, sides log-uniform in [16,512], 1-6 disks, 32 controls, "
                         "ISA each, sup-res<1e-6",
             "total_nodes": int(sum(p.N for p in probs)),
             "batched_ms": ms_b, "per_problem_calls_ms": ms_single,
-            "batched_speedup": ms_single / ms_b, "sweeps_max": int(tot["sweeps_max"]),
+            "batched_speedup": ms_single / ms_b,
+            "per_subdomain_calls_ms": ms_sd, "subdomains": n_sd,
+            "batched_vs_per_subdomain": ms_sd / ms_b, "sweeps_max": int(tot["sweeps_max"]),
             "tile": list(tot["tile"]), "schedule": tot["mode"],
             "node_control_updates_per_s": tot["node_control_updates"] / (ms_b / 1e3)}
 
@@ -209,23 +226,32 @@ def stored_traffic(st, nc_per_launch):
 def cpu_baseline(prob, budget_s: float):
     """The FP64 oracle on a bounded sample of the same workload: plain Jacobi
     sweeps of the global 1025^2 problem from the ghost value, as many as fit in
-    about ``budget_s`` seconds.  Reports node*control updates per second."""
+    about ``budget_s`` seconds on all host threads, then a shorter sample on one
+    thread.  Reports node*control updates per second."""
     import oracle as O
-    V = O.initial_values(prob)
     free = int((np.asarray(prob.target) < 0).sum())
     nc_per_sweep = free * prob.m
-    t0 = time.perf_counter()
-    sweeps = 0
-    while True:
-        V, _, _, _ = O.solve(prob, V0=V, max_sweeps=1)
-        sweeps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+
+    def sample(seconds, nthreads):
+        V = O.initial_values(prob)
+        t0 = time.perf_counter()
+        sweeps = 0
+        while True:
+            V, _, _, _ = O.solve(prob, V0=V, max_sweeps=1, nthreads=nthreads)
+            sweeps += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        return sweeps, time.perf_counter() - t0
+
+    cores = O.max_threads()
+    sweeps, dt = sample(budget_s, 0)
+    s1, dt1 = sample(max(2.0, budget_s / 3), 1)
     return {"value": nc_per_sweep * sweeps / dt, "unit": "node*control updates/s",
-            "cores": O.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
+            "value_1_thread": nc_per_sweep * s1 / dt1,
             "sample": f"{sweeps} Jacobi sweeps of the global {prob.n[0]}^2 problem "
-                      f"({nc_per_sweep:.3g} node*control each), FP64, OpenMP over nodes"}
+                      f"({nc_per_sweep:.3g} node*control each), FP64, OpenMP over nodes on all "
+                      f"host threads; {s1} sweeps on one thread for value_1_thread"}
 
 
 def main():

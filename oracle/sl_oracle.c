@@ -246,7 +246,11 @@ static double sweep(const orc_prob *P, const double *V, double *Vn, int32_t *pol
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    /* 0 = every host thread (the count OpenMP starts with), whatever an earlier
+     * call with an explicit count set */
+    static int all_threads = 0;
+    if (!all_threads) all_threads = omp_get_max_threads();
+    omp_set_num_threads(nthreads > 0 ? nthreads : all_threads);
 #else
     (void)nthreads;
 #endif

@@ -107,7 +107,34 @@ __global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int
             first[c] = f < first[c] ? f : first[c];
         }
     }
+    // combine the work-group's waves in LDS, then one thread per work-group
+    // publishes (few same-address atomics)
+    constexpr int NW = kOpThreads / 64;
+    __shared__ double r_s[NW], r_c[NW], r_d[NW];
+    __shared__ int r_bs[NW], r_bc[NW], r_nt[NW], r_bt[NW], r_f[NW][SL_MAX_COMP];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        r_s[w] = smax;
+        r_c[w] = cmax;
+        r_d[w] = dmax;
+        r_bs[w] = bad_s;
+        r_bc[w] = bad_c;
+        r_nt[w] = ntar;
+        r_bt[w] = bad_t;
+        for (int c = 0; c < SL_MAX_COMP; ++c) r_f[w][c] = first[c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < NW; ++k) {
+            smax = r_s[k] > smax ? r_s[k] : smax;
+            cmax = r_c[k] > cmax ? r_c[k] : cmax;
+            dmax = r_d[k] > dmax ? r_d[k] : dmax;
+            bad_s += r_bs[k];
+            bad_c += r_bc[k];
+            ntar += r_nt[k];
+            bad_t += r_bt[k];
+            for (int c = 0; c < SL_MAX_COMP; ++c) first[c] = r_f[k][c] < first[c] ? r_f[k][c] : first[c];
+        }
         if (smax > 0.0) atomicMax(&fs->speed_max, (unsigned long long)__double_as_longlong(smax));
         if (cmax > 0.0) atomicMax(&fs->cost_max, (unsigned long long)__double_as_longlong(cmax));
         if (dmax > 0.0) atomicMax(&fs->drift_max, (unsigned long long)__double_as_longlong(dmax));
@@ -346,9 +373,15 @@ __global__ void k_member_counts(const uint8_t *member, size_t N, unsigned long l
 #pragma unroll
         for (int i = 0; i < 8; ++i) loc[i] += (b >> i) & 1;
     }
+    // wave sums by shuffles, then one LDS atomic per wave and bit
 #pragma unroll
     for (int i = 0; i < 8; ++i)
-        if (loc[i]) atomicAdd(&c[i], loc[i]);
+        for (int off = 32; off >= 1; off >>= 1) loc[i] += __shfl_xor(loc[i], off, 64);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (loc[i]) atomicAdd(&c[i], loc[i]);
+    }
     __syncthreads();
     if (threadIdx.x < 8 && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)c[threadIdx.x]);
 }
@@ -453,7 +486,7 @@ template <typename T>
 hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
                               const int8_t *target, size_t n, int n_comp, FieldStats *fs,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_field_stats<T>, dim3(grid_for(n) < 2048 ? grid_for(n) : 2048),
+    hipLaunchKernelGGL(k_field_stats<T>, dim3(grid_for(n) < 512 ? grid_for(n) : 512),
                        dim3(kOpThreads), 0, s, speed, cost, drift, dim, target, n, n_comp, fs);
     return hipGetLastError();
 }
