@@ -48,9 +48,12 @@ def exact_stencils(prob):
             ij.append(r % n[d])
             r //= n[d]
         c = Fr(1) if prob.speed is None else Fr(float(prob.speed[j]))
+        q = [Fr(0)] * dim if prob.drift is None else \
+            [t[d] * Fr(float(np.asarray(prob.drift).reshape(-1, dim)[j, d])) for d in range(dim)]
         per_k = []
         for k in range(prob.m):
-            u = [ij[d] + t[d] * Fr(float(prob.velocity[k, d])) * c for d in range(dim)]
+            # foot x + h (b(x) + c(x) a_k), in index units
+            u = [ij[d] + t[d] * Fr(float(prob.velocity[k, d])) * c + q[d] for d in range(dim)]
             p = [_floor(x) for x in u]
             tau = [u[d] - p[d] for d in range(dim)]
             st = []

@@ -26,6 +26,9 @@ CASES = [
     ("2d_paper_disc", lambda: _tiny_2d(9, 8, 51, disc="paper")),
     ("2d_m7_odd", lambda: _tiny_2d(9, 7, 61)),
     ("3d_n4_m10", lambda: W.c3_aniso3d(n=4, m=10, n_balls=1, r=0.5)),
+    # control-affine dynamics with a drift (Van der Pol, Sec. 4.1): f = b(x) + (0, a)
+    ("2d_vdp_drift_n9", lambda: W.vdp_problem(9, split=1, n_a=5)),
+    ("2d_vdp_drift_n11_split2", lambda: W.vdp_problem(11, split=2, n_a=7, rho=0.25)),
 ]
 
 

@@ -144,3 +144,25 @@ def test_box_distance_ra_matches_table1():
         ours.append(fr)
     assert all(a >= b for a, b in zip(ours, ours[1:]))
     assert ours[-1] > T["exact_max_set_fraction"]
+
+
+@pytest.mark.parametrize("n", [41, 81])
+def test_constant_drift_exact(n):
+    """Control-affine dynamics f = b + a with a constant drift b = (1, 0) and unit
+    controls, target on the right edge only, h = dx/2: the best control a = e1
+    moves exactly one cell per step (drift and control each half a cell), every
+    other control progresses less towards the target, so the scheme is exact at
+    the nodes: V = 1 - exp(-(1 - x1)/2) (travel time (1 - x1)/2 at speed 2).
+    A dropped or mis-signed drift term changes the travel time."""
+    p = W.strip_problem(n, 1.0)
+    tid = np.full(p.N, -1, dtype=np.int8)
+    tid.reshape(n, n)[:, -1] = 0
+    dx = 2.0 / (n - 1)
+    drift = np.zeros((p.N, 2))
+    drift[:, 0] = 1.0
+    q = p.with_(target=tid, n_comp=1, drift=drift, h=dx / 2, v_ghost=1.0)
+    V, _, _, res = O.solve(q)
+    assert res == 0.0
+    X = W.node_coords(q.n, q.lo, q.hi)
+    ex = 1.0 - np.exp(-(1.0 - X[:, 0]) / 2.0)
+    assert np.abs(V - ex).max() <= 1e-13
