@@ -64,10 +64,16 @@ typedef struct sl_problem {
     int n[3];                 /* nodes per axis (>= 3 on used axes)                  */
     double lo[3], hi[3];      /* box corners; dx_d = (hi_d - lo_d)/(n_d - 1)         */
     int m;                    /* number of discrete controls, 1..SL_MAX_CONTROLS     */
-    const double *velocity;   /* HOST, m*dim: b_k with f(x, a_k) = c(x) b_k           */
+    const double *velocity;   /* HOST, m*dim: b_k with f(x, a_k) = drift(x) + c(x) b_k */
     const void *speed;        /* DEVICE, N values of c(x) >= 0 in `dtype`; NULL = 1   */
     const void *cost;         /* DEVICE, N values of l(x) > 0 in `dtype`; NULL = 1    */
-    const void *drift;        /* DEVICE, N*dim drift b(x) in `dtype` (node-major); NULL = 0 */
+    const void *drift;        /* DEVICE, N*dim drift(x) in `dtype` (node-major); NULL = 0.
+                                 Control-affine dynamics (the Van der Pol example, Sec.
+                                 4.1).  The foot is u_d = i_d + (e_kd c_j + q_jd) in index
+                                 units, q_jd = (h/dx_d) drift_jd in FP64.  The halo covers
+                                 c|e| + |q|.  sl_solve, sl_reconstruct and sl_solve_isa take
+                                 it; sl_solve_batched and sl_adjoint return
+                                 SL_ERR_UNSUPPORTED.                                   */
     const int8_t *target;     /* DEVICE, N: -1 free node, i in [0, n_comp) target of component i */
     const void *g;            /* DEVICE, N exit costs (read on target nodes) in `dtype`; NULL = 0 */
     int n_comp;               /* number of target components, 1..SL_MAX_COMP          */

@@ -138,6 +138,7 @@ class DeviceProblem:
     speed: Optional[object] = None  # torch tensor (N,) of `dtype` or None
     cost: Optional[object] = None
     g: Optional[object] = None
+    drift: Optional[object] = None  # torch tensor (N*dim,) of `dtype`, node-major, or None
     lam: float = 1.0
     h: float = 0.0
     v_ghost: float = 1.0
@@ -196,7 +197,10 @@ def to_device(prob, dtype=None, device: str = "cuda:0") -> DeviceProblem:
         velocity=np.ascontiguousarray(prob.velocity, dtype=np.float64),
         target=dev(prob.target, torch.int8), n_comp=int(prob.n_comp),
         speed=dev(getattr(prob, "speed", None), dtype), cost=dev(getattr(prob, "cost", None), dtype),
-        g=dev(getattr(prob, "g", None), dtype), lam=float(prob.lam),
+        g=dev(getattr(prob, "g", None), dtype),
+        drift=None if getattr(prob, "drift", None) is None
+        else dev(np.asarray(prob.drift).reshape(-1), dtype),
+        lam=float(prob.lam),
         h=float(getattr(prob, "step", 0.0) or prob.h), v_ghost=float(prob.v_ghost),
         disc=prob.disc, dtype=dtype)
 
@@ -219,6 +223,7 @@ def _cproblem(p: DeviceProblem):
     _check_tensor(p.target, torch.int8, N, "target")
     for name in ("speed", "cost", "g"):
         _check_tensor(getattr(p, name), p.dtype, N, name)
+    _check_tensor(p.drift, p.dtype, N * p.dim, "drift")
     vel = np.ascontiguousarray(p.velocity, dtype=np.float64)
     if vel.ndim != 2 or vel.shape[1] != p.dim:
         raise ValueError("velocity must have shape (m, dim)")
@@ -232,7 +237,7 @@ def _cproblem(p: DeviceProblem):
     cp.velocity = vel.ctypes.data_as(C.POINTER(C.c_double))
     cp.speed = _ptr(p.speed)
     cp.cost = _ptr(p.cost)
-    cp.drift = None
+    cp.drift = _ptr(p.drift)
     cp.target = _ptr(p.target)
     cp.g = _ptr(p.g)
     cp.n_comp = p.n_comp

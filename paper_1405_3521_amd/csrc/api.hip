@@ -70,7 +70,6 @@ int validate(const sl_problem *p) {
     if (!std::isfinite(p->v_ghost)) return SL_ERR_INVALID_ARG;
     if (p->disc != SL_DISC_EXP && p->disc != SL_DISC_PAPER) return SL_ERR_INVALID_ARG;
     if (p->dtype != SL_F32 && p->dtype != SL_F64) return SL_ERR_INVALID_ARG;
-    if (p->drift) return SL_ERR_UNSUPPORTED;
     return SL_OK;
 }
 
@@ -130,8 +129,9 @@ void control_table(const sl_problem *p, const int *n, double h, std::vector<doub
         }
 }
 
-int halo_for(double speed_max, double emax) {
-    const double D = speed_max * emax;
+// Cells a foot can reach: c * |e| over the controls plus the drift's |q| (index units).
+int halo_for(double speed_max, double emax, double drift_reach = 0.0) {
+    const double D = speed_max * emax + drift_reach;
     if (!std::isfinite(D)) return INT_MAX;
     // floor(D) + 1 covers both corners of every foot; the margin absorbs the
     // rounding of c*e and of the foot coordinate.
@@ -613,7 +613,7 @@ int gather_field_stats(const sl_problem *p, const int8_t *target, const T *speed
     FieldStats init{};
     for (int i = 0; i < SL_MAX_COMP; ++i) init.first_node[i] = INT_MAX;
     HIPCHK(hipMemcpyAsync(fs_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_field_stats<T>(speed, cost, (const T *)nullptr, p->dim, target, N, n_comp,
+    HIPCHK(launch_field_stats<T>(speed, cost, (const T *)p->drift, p->dim, target, N, n_comp,
                                  fs_dev, s));
     HIPCHK(hipMemcpyAsync(host, fs_dev, sizeof(FieldStats), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -626,6 +626,23 @@ double bits_to_double(unsigned long long b) {
     return d;
 }
 
+// Index-unit factors t_d = h / dx_d of a grid with n nodes per axis (the same
+// expression as the control table's).
+void index_units(const sl_problem *p, const int *n, double h, double *t) {
+    for (int d = 0; d < 3; ++d)
+        t[d] = d < p->dim ? h / ((p->hi[d] - p->lo[d]) / (double)(n[d] - 1)) : 0.0;
+}
+
+// Largest drift displacement per step in cells, max_d t_d * max|b|.
+double drift_reach(const sl_problem *p, const int *n, double h, const FieldStats &fs) {
+    if (!p->drift) return 0.0;
+    double t[3];
+    index_units(p, n, h, t);
+    double tm = 0.0;
+    for (int d = 0; d < p->dim; ++d) tm = std::max(tm, t[d]);
+    return tm * bits_to_double(fs.drift_max);
+}
+
 int check_fields(const FieldStats &fs) {
     if (fs.bad_speed || fs.bad_cost || fs.bad_target) return SL_ERR_INVALID_ARG;
     if (fs.n_target == 0) return SL_ERR_NO_TARGET;
@@ -635,13 +652,15 @@ int check_fields(const FieldStats &fs) {
 // ------------------------------------------------------------ global solve
 template <typename T>
 int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **ctrl,
-                FieldStats **fs, int variant) {
+                FieldStats **fs, int variant, T **q = nullptr) {
     const size_t N = nodes_of(p);
     (void)variant;
     const int tiles = max_tiles(p->dim, p->dtype, p->n);
     Vb[0] = a.take<T>(N);
     Vb[1] = a.take<T>(N);
     *wl = p->cost ? a.take<T>(N) : nullptr;
+    T *qq = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
+    if (q) *q = qq;
     *ctrl = a.take<T>((size_t)p->m * p->dim);
     *fs = a.take<FieldStats>(1);
     ex.reserve(a, 1, tiles);
@@ -657,9 +676,9 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     const int variant = default_variant(p->dim, p->dtype);
     Arena a{(char *)ws, ws_bytes};
     Exec<T> ex;
-    T *Vb[2], *wl, *ctrl;
+    T *Vb[2], *wl, *ctrl, *q = nullptr;
     FieldStats *fs_dev;
-    plan_global<T>(p, a, ex, Vb, &wl, &ctrl, &fs_dev, variant);
+    plan_global<T>(p, a, ex, Vb, &wl, &ctrl, &fs_dev, variant, &q);
     if (!a.fits()) return SL_ERR_WORKSPACE;
 
     FieldStats fs{};
@@ -673,10 +692,15 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     std::vector<double> e;
     control_table(p, p->n, p->h, e, &emax);
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
-    const int H = halo_for(smax, emax);
+    const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
     if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     ex.cfg = make_cfg(p->dim, p->dtype, H, variant);
     ex.cfg.local_iters = o->local_iters;
+    if (p->drift) {
+        double t[3];
+        index_units(p, p->n, p->h, t);
+        HIPCHK(launch_scale_drift<T>((const T *)p->drift, q, N, p->dim, t, s));
+    }
 
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
@@ -695,7 +719,7 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     d.V[1] = Vb[1];
     d.speed = (const T *)p->speed;
     d.wl = wl;
-    d.drift = nullptr;
+    d.drift = q;
     d.target = p->target;
     d.member = nullptr;
     d.policy = policy;
@@ -763,6 +787,7 @@ template <typename T>
 struct IsaPlan {
     // coarse
     double *cK = nullptr, *wlK = nullptr, *gK = nullptr, *ctrlK = nullptr, *gK_src = nullptr;
+    double *qK = nullptr;          // coarse drift in index units (NK * dim)
     T *gK_t = nullptr;
     int8_t *tK = nullptr;
     double *Vaux = nullptr;        // n_comp * 2 * NK
@@ -773,6 +798,7 @@ struct IsaPlan {
     // fine
     T *Vf = nullptr;               // n_comp * 2 * N
     T *wl = nullptr, *ctrl = nullptr;
+    T *q = nullptr;                // fine drift in index units (N * dim)
     FieldStats *fs = nullptr;
     unsigned long long *counts = nullptr;
     Exec<T> ex;
@@ -787,6 +813,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     P.gK_t = a.take<T>(cg.NK);
     P.cK = a.take<double>(cg.NK);
     P.wlK = a.take<double>(cg.NK);
+    P.qK = p->drift ? a.take<double>(cg.NK * (size_t)p->dim) : nullptr;
     P.gK = a.take<double>(cg.NK);
     P.ctrlK = a.take<double>((size_t)p->m * p->dim);
     P.tK = a.take<int8_t>(cg.NK);
@@ -799,6 +826,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     const int tiles = max_tiles(p->dim, p->dtype, p->n);
     P.Vf = a.take<T>((size_t)nc * 2 * N);
     P.wl = p->cost ? a.take<T>(N) : nullptr;
+    P.q = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
     P.ctrl = a.take<T>((size_t)p->m * p->dim);
     P.fs = a.take<FieldStats>(1);
     P.counts = a.take<unsigned long long>(8);
@@ -835,6 +863,14 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     if (p->cost)
         HIPCHK(launch_sample_coarse<T>((const T *)p->cost, P.wlK, p->n, cg.nK, p->dim, 1, wK, s));
     if (p->g) HIPCHK(launch_gather_nearest<T>((const T *)p->g, P.gK_t, p->n, cg.nK, p->dim, s));
+    if (p->drift) {
+        // Q1 samples of the drift, then index units of the coarse step
+        double tK[3];
+        index_units(p, cg.nK, cg.hK, tK);
+        HIPCHK(launch_sample_coarse<T>((const T *)p->drift, P.qK, p->n, cg.nK, p->dim, p->dim,
+                                       1.0, s));
+        HIPCHK(launch_scale_drift<double>(P.qK, P.qK, cg.NK, p->dim, tK, s));
+    }
     HIPCHK(launch_gather_nearest<int8_t>(p->target, P.tK, p->n, cg.nK, p->dim, s));
     // components without a coincident coarse node: place them (in the field's own
     // dtype), then widen g to FP64
@@ -858,7 +894,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     control_table(p, cg.nK, cg.hK, e, &emaxK);
     HIPCHK(hipMemcpyAsync(P.ctrlK, e.data(), sizeof(double) * e.size(), hipMemcpyHostToDevice, s));
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
-    const int HK = halo_for(smax, emaxK);
+    const int HK = halo_for(smax, emaxK, drift_reach(p, cg.nK, cg.hK, fs));
     if (HK > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.exK.cfg = make_cfg(p->dim, SL_F64, HK, default_variant(p->dim, SL_F64));
     P.exK.cfg.local_iters = ra->local_iters;
@@ -879,6 +915,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
         d.V[1] = V0 + cg.NK;
         d.speed = p->speed ? P.cK : nullptr;
         d.wl = p->cost ? P.wlK : nullptr;
+        d.drift = P.qK;
         d.target = P.tK;
         d.member = nullptr;
         d.policy = nullptr;
@@ -953,10 +990,15 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     std::vector<double> e;
     control_table(p, p->n, p->h, e, &emax);
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
-    const int H = halo_for(smax, emax);
+    const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
     if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.ex.cfg = make_cfg(p->dim, p->dtype, H, default_variant(p->dim, p->dtype));
     P.ex.cfg.local_iters = o->local_iters;
+    if (p->drift) {
+        double t[3];
+        index_units(p, p->n, p->h, t);
+        HIPCHK(launch_scale_drift<T>((const T *)p->drift, P.q, N, p->dim, t, s));
+    }
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(P.ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
@@ -978,6 +1020,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
         d.V[1] = V0 + N;
         d.speed = (const T *)p->speed;
         d.wl = P.wl;
+        d.drift = P.q;
         d.target = p->target;
         d.member = member;
         d.policy = policy ? policy + (size_t)i * N : nullptr;
@@ -1483,6 +1526,7 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
+        if (probs[q].drift) return SL_ERR_UNSUPPORTED;
         if (probs[q].m != probs[0].m && false) return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
@@ -1645,6 +1689,7 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
+    if (p->drift) return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

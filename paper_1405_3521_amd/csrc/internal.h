@@ -215,6 +215,10 @@ hipError_t launch_sample_coarse(const T *src, double *dst, const int *n, const i
 template <typename T>
 hipError_t launch_gather_nearest(const T *src, T *dst, const int *n, const int *nK, int dim,
                                  hipStream_t s);
+// Drift in index units, dst = t_d * src per component (t: 3 factors).
+template <typename T>
+hipError_t launch_scale_drift(const T *src, T *dst, size_t N, int dim, const double *t,
+                              hipStream_t s);
 // Place components without a coarse node (single thread, in order).
 template <typename T>
 hipError_t launch_place_missing(int8_t *tK, T *gK, const T *g, const int *first_fine,

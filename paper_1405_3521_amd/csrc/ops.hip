@@ -239,6 +239,20 @@ __global__ void k_sample_coarse(const T *src, double *dst, int n0, int n1, int n
     }
 }
 
+// Drift in index units: dst[j*dim + d] = t_d * src[j*dim + d] (FP64 product; src
+// and dst may be the same array).
+template <typename T>
+__global__ void k_scale_drift(const T *src, T *dst, size_t N, int dim, double t0, double t1,
+                              double t2) {
+    const size_t n = N * (size_t)dim;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int d = (int)(i % (size_t)dim);
+        const double t = d == 0 ? t0 : (d == 1 ? t1 : t2);
+        dst[i] = (T)(t * (double)src[i]);
+    }
+}
+
 // Discrete coarse data (target ids, exit costs): the value at the nearest fine node.
 template <typename T>
 __global__ void k_gather_nearest(const T *src, T *dst, int n0, int n1, int n2, int k0, int k1,
@@ -457,6 +471,17 @@ hipError_t launch_sample_coarse(const T *src, double *dst, const int *n, const i
 }
 template hipError_t launch_sample_coarse<float>(const float *, double *, const int *, const int *, int, int, double, hipStream_t);
 template hipError_t launch_sample_coarse<double>(const double *, double *, const int *, const int *, int, int, double, hipStream_t);
+
+template <typename T>
+hipError_t launch_scale_drift(const T *src, T *dst, size_t N, int dim, const double *t,
+                              hipStream_t s) {
+    const size_t n = N * (size_t)dim;
+    hipLaunchKernelGGL(k_scale_drift<T>, dim3(grid_for(n)), dim3(kOpThreads), 0, s, src, dst, N,
+                       dim, t[0], t[1], t[2]);
+    return hipGetLastError();
+}
+template hipError_t launch_scale_drift<float>(const float *, float *, size_t, int, const double *, hipStream_t);
+template hipError_t launch_scale_drift<double>(const double *, double *, size_t, int, const double *, hipStream_t);
 
 template <typename T>
 hipError_t launch_gather_nearest(const T *src, T *dst, const int *n, const int *nK, int dim,

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         __syncthreads();
 
         const int gx = x0 + tx;
-        T c[NPT], ux0[NPT], uy0[NPT], wl[NPT], best[NPT];
+        T c[NPT], ux0[NPT], uy0[NPT], qx[NPT], qy[NPT], wl[NPT], best[NPT];
         int arg[NPT];
         bool act[NPT];
         int any = 0;
@@ -113,6 +113,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
             act[r] = false;
             c[r] = T(0);                        // inactive lanes: foot = own node
             wl[r] = d.wl_const;
+            T qxv = T(0), qyv = T(0);           // drift in index units
             if (gx < n0 && gy < n1) {
                 const size_t j = (size_t)gy * n0 + gx;
                 const bool inset = !mem || ((mem[j] >> bit) & 1);
@@ -120,16 +121,24 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                 if (act[r]) {
                     c[r] = d.speed ? d.speed[j] : T(1);
                     if (d.wl) wl[r] = d.wl[j];
+                    if (d.drift) {
+                        qxv = d.drift[2 * j];
+                        qyv = d.drift[2 * j + 1];
+                    }
                 }
             }
             any |= act[r];
             if (sizeof(T) == 4) {
-                ux0[r] = (T)(tx + H);
-                uy0[r] = (T)(ty + H);
+                // FP32: the drift folds into the node's tile-local origin
+                ux0[r] = (T)(tx + H) + qxv;
+                uy0[r] = (T)(ty + H) + qyv;
             } else {
+                // FP64: u = i + (e c + q), the reproducible operation order
                 ux0[r] = (T)gx;
                 uy0[r] = (T)gy;
             }
+            qx[r] = sizeof(T) == 4 ? T(0) : qxv;
+            qy[r] = sizeof(T) == 4 ? T(0) : qyv;
         }
         const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
         const T beta = d.beta;
@@ -161,8 +170,8 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                         ux = fma_(c[r], ex, ux0[r]);
                         uy = fma_(c[r], ey, uy0[r]);
                     } else {
-                        ux = ux0[r] + ex * c[r];
-                        uy = uy0[r] + ey * c[r];
+                        ux = ux0[r] + (ex * c[r] + qx[r]);
+                        uy = uy0[r] + (ey * c[r] + qy[r]);
                     }
                     int ix, iy;
                     T fx, fy;
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         __syncthreads();
 
         const int gx = x0 + tx, gy = y0 + ty;
-        T c[NPT], ux0[NPT], uy0[NPT], uz0[NPT], wl[NPT], best[NPT];
+        T c[NPT], ux0[NPT], uy0[NPT], uz0[NPT], qx[NPT], qy[NPT], qz[NPT], wl[NPT], best[NPT];
         int arg[NPT];
         bool act[NPT];
         int any = 0;
@@ -363,6 +372,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
             act[r] = false;
             c[r] = T(0);                        // inactive lanes: foot = own node
             wl[r] = d.wl_const;
+            T qxv = T(0), qyv = T(0), qzv = T(0);
             if (gx < n0 && gy < n1 && gz < n2) {
                 const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
                 const bool inset = !mem || ((mem[j] >> bit) & 1);
@@ -370,18 +380,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                 if (act[r]) {
                     c[r] = d.speed ? d.speed[j] : T(1);
                     if (d.wl) wl[r] = d.wl[j];
+                    if (d.drift) {
+                        qxv = d.drift[3 * j];
+                        qyv = d.drift[3 * j + 1];
+                        qzv = d.drift[3 * j + 2];
+                    }
                 }
             }
             any |= act[r];
             if (sizeof(T) == 4) {
-                ux0[r] = (T)(tx + H);
-                uy0[r] = (T)(ty + H);
-                uz0[r] = (T)(tz + H);
+                ux0[r] = (T)(tx + H) + qxv;
+                uy0[r] = (T)(ty + H) + qyv;
+                uz0[r] = (T)(tz + H) + qzv;
             } else {
                 ux0[r] = (T)gx;
                 uy0[r] = (T)gy;
                 uz0[r] = (T)gz;
             }
+            qx[r] = sizeof(T) == 4 ? T(0) : qxv;
+            qy[r] = sizeof(T) == 4 ? T(0) : qyv;
+            qz[r] = sizeof(T) == 4 ? T(0) : qzv;
         }
         const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
         const T beta = d.beta;
@@ -410,9 +428,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                         uy = fma_(c[r], ey, uy0[r]);
                         uz = fma_(c[r], ez, uz0[r]);
                     } else {
-                        ux = ux0[r] + ex * c[r];
-                        uy = uy0[r] + ey * c[r];
-                        uz = uz0[r] + ez * c[r];
+                        ux = ux0[r] + (ex * c[r] + qx[r]);
+                        uy = uy0[r] + (ey * c[r] + qy[r]);
+                        uz = uz0[r] + (ez * c[r] + qz[r]);
                     }
                     int ix, iy, iz;
                     T fx, fy, fz;

@@ -136,3 +136,20 @@ def test_binding_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         S.lib()
+
+
+def test_drift_accepted_by_solves_and_rejected_by_batch_and_adjoint():
+    """Control-affine dynamics with a drift: sl_solve / sl_reconstruct / sl_solve_isa
+    size a workspace for it; the batch and the adjoint report SL_ERR_UNSUPPORTED
+    before any device work."""
+    L = S.lib()
+    p, keep = _problem(drift=C.c_void_p(0x2000))
+    q, keep2 = _problem()
+    assert L.sl_solve_workspace_size(C.byref(p)) > L.sl_solve_workspace_size(C.byref(q))
+    ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
+    assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) == 0
+    buf = C.create_string_buffer(64)
+    st = S.SlStats()
+    assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
+                        C.byref(st), None) == -3
