@@ -49,7 +49,7 @@ def lib():
         L.orc_scheme_constants.argtypes = [C.c_double, C.c_double, C.c_int, _DP, _DP]
         L.orc_scheme_constants.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
-        common = [C.c_int, _IP, _DP, _DP, C.c_double, C.c_int, _DP, _DP]
+        common = [C.c_int, _IP, _DP, _DP, C.c_double, C.c_int, _DP, _DP, C.c_int, _DP, C.c_int]
         L.orc_apply.argtypes = common + [_DP, _DP, C.c_double, C.c_int, C.c_double, _U8P, _U8P,
                                          _DP, _DP, _I32P, C.c_int]
         L.orc_apply.restype = C.c_int
@@ -91,12 +91,23 @@ def _geom(prob):
 
 
 def _common(prob):
+    """Geometry, the pursuer's table, the speed (per node, or per node and axis) and
+    the evader's table (none for a control problem)."""
     n, lo, hi = _geom(prob)
     b = np.ascontiguousarray(prob.velocity, dtype=np.float64)
     c = _f64(prob.speed)
-    keep = (n, lo, hi, b, c)
+    c_axes = 0
+    if c is not None and c.ndim == 2:
+        if c.shape != (prob.N, prob.dim):
+            raise ValueError("per-axis speed must have shape (N, dim)")
+        c_axes = 1
+        c = np.ascontiguousarray(c.reshape(-1))
+    vb = getattr(prob, "velocity_b", None)
+    bb = None if vb is None else np.ascontiguousarray(vb, dtype=np.float64)
+    mb = 0 if bb is None else int(bb.shape[0])
+    keep = (n, lo, hi, b, c, bb)
     return keep, [prob.dim, _p(n, _IP), _p(lo, _DP), _p(hi, _DP), float(prob.step), prob.m,
-                  _p(b, _DP), _p(c, _DP)]
+                  _p(b, _DP), _p(c, _DP), mb, _p(bb, _DP), c_axes]
 
 
 def max_threads() -> int:
@@ -133,7 +144,8 @@ def initial_values(prob, comp: Optional[int] = None) -> np.ndarray:
 
 
 def apply_T(prob, V, fixed=None, dom=None, nthreads: int = 0):
-    """One application of T: returns (T(V), policy)."""
+    """One application of T: returns (T(V), policy).  For a game the policy of a
+    node is l m + k (evader choice l, pursuer control k)."""
     L = lib()
     keep, com = _common(prob)
     V = _f64(V)

@@ -17,8 +17,10 @@ Readings of the paper used here:
   * the auxiliary problem i (RA step 1, "T_i with boundary X_i") keeps component i
     at g and holds every other component's target nodes at the ghost value, a
     boundary datum larger than g ((gcond));
-  * RA step 2: the (H2) check is skipped (every problem here is a control
-    problem, whose Hamiltonian is convex, Remark 2.1), then V = min_i V_i;
+  * RA step 2: the (H2) check is skipped (a control problem's Hamiltonian is
+    convex, Remark 2.1; for a game the caller vouches for the decomposability
+    condition (C), as the paper shows for its pursuit-evasion example), then
+    V = min_i V_i;
   * RA step 3 threshold delta = 2 (C dx^q + M dx) (Proposition 3.1), dx the coarse
     grid spacing (largest over axes);
   * ISA step 2, Con(.): a fine node belongs to the projected set iff some closed
@@ -158,12 +160,17 @@ def coarse_problem(prob):
             if g is not None:
                 g = g.copy()
                 g[jk] = np.asarray(prob.g)[j]
-    drift = None
-    if prob.drift is not None:
-        dr = np.asarray(prob.drift).reshape(-1, dim)
-        drift = np.stack([sample_q1(dr[:, d], n, nK) for d in range(dim)], axis=1)
+    def q1_axes(a):
+        """A field with one value per node and axis, sampled axis by axis."""
+        a = np.asarray(a).reshape(-1, dim)
+        return np.stack([sample_q1(a[:, d], n, nK) for d in range(dim)], axis=1)
+
+    drift = None if prob.drift is None else q1_axes(prob.drift)
+    speed = prob.speed
+    if speed is not None:
+        speed = q1_axes(speed) if np.asarray(speed).ndim == 2 else q1(speed)
     ratio = max((n[d] - 1) / (nK[d] - 1) for d in range(dim))
-    return prob.with_(name=prob.name + "_K", n=nK, target=tid, speed=q1(prob.speed),
+    return prob.with_(name=prob.name + "_K", n=nK, target=tid, speed=speed,
                       cost=q1(prob.cost), g=g, drift=drift, h=prob.step * ratio,
                       coarse_stride=1, coarse_n=None)
 

@@ -8,7 +8,9 @@
  *
  * What it computes (paper, Section 3, scheme (SL) and operator (Tdef)):
  *   for a free node x_j of the solve domain
- *     [T(V)]_j = min_k { beta * I[V](x_j + h f(x_j, a_k)) + w * l(x_j) }
+ *     [T(V)]_j = max_l min_k { beta * I[V](x_j + h f(x_j, a_k, b_l)) + w * l(x_j) }
+ *   (a differential game, Sec. 2; with one evader choice b_0 = 0 it is the
+ *   control problem's min_k)
  *   fixed (target) nodes keep their value, nodes outside the box or outside the
  *   solve domain read the ghost value G (the paper's ghost nodes, finite here).
  *   I is tensor-product linear (Q1) interpolation on the Cartesian grid.
@@ -20,8 +22,15 @@
  *     (the printed signs of (Tdef) are inconsistent with the Hamiltonian (HJ));
  *   - discount: "exp"   beta = exp(-lam h),  w = (1 - beta)/lam   (default),
  *               "paper" beta = 1/(1 + lam h), w = h               ((Tdef) as printed);
- *   - dynamics f(x, a_k) = c(x) b_k (+ drift(x)), evaluated in grid-index units:
- *       disp_d = (h/dx_d * b_kd) * c_j  (+ h/dx_d * drift_jd),   u_d = i_d + disp_d;
+ *   - dynamics f(x, a_k, b_l) = drift(x) + S(x) (a_k - b_l), S(x) = c(x) times the
+ *     identity, or diag(c_1(x), .., c_d(x)) when per-axis speed factors are given,
+ *     evaluated in grid-index units:
+ *       disp_d = (h/dx_d * (a_kd - b_ld)) * c_jd  (+ h/dx_d * drift_jd),
+ *       u_d = i_d + disp_d
+ *     (for a control problem, without evader choices, the difference is a_kd);
+ *   - game order: the evader (maximising b) chooses first, the pursuer (minimising
+ *     a) answers, as the max-min of (Tdef) is printed; the policy index of a node is
+ *     l m + k for the first maximising l and, within it, the first minimising k;
  *   - interpolation in a fixed operation order: Q1 as the tensor product of
  *     one-axis linear interpolations, along x, then y, then z, each evaluated as
  *     fma(tau, v1, (1 - tau) * v0); an implementation that follows the same order
@@ -45,10 +54,12 @@ typedef struct {
     int dim;
     long n[3];
     long N;
-    int m;
-    double *e;            /* m*dim: (h/dx_d) * b_kd                  */
+    int m;                /* pursuer controls a_k (inner minimum)    */
+    int mb;               /* evader choices b_l (outer maximum), >= 1 */
+    double *e;            /* (mb*m)*dim, row l*m + k: (h/dx_d) * (a_kd - b_ld) */
     double *q;            /* N*dim: (h/dx_d) * drift_jd, or NULL     */
-    const double *c;      /* speed per node, or NULL (= 1)           */
+    const double *c;      /* speed per node (or per node and axis), or NULL (= 1) */
+    int c_axes;           /* 1: c holds dim factors per node          */
     double *wl;           /* w * l_j per node                        */
     double beta;
     double G;
@@ -73,13 +84,15 @@ int orc_scheme_constants(double lam, double h, int disc, double *beta, double *w
 }
 
 static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const double *hi,
-                     double h, int m, const double *b, const double *c, const double *l,
-                     const double *drift, double lam, int disc, double G,
-                     const uint8_t *fixed, const uint8_t *dom)
+                     double h, int m, const double *b, const double *c, int mb,
+                     const double *bb, int c_axes, const double *l, const double *drift,
+                     double lam, int disc, double G, const uint8_t *fixed, const uint8_t *dom)
 {
     double beta, w, t[3];
     memset(P, 0, sizeof(*P));
     if (dim < 1 || dim > 3 || m < 1) return -1;
+    if (bb ? mb < 1 : mb > 1) return -1;
+    if (mb < 1) mb = 1;
     P->dim = dim;
     P->N = 1;
     for (int d = 0; d < 3; ++d) P->n[d] = 1;
@@ -91,11 +104,16 @@ static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const
     }
     if (orc_scheme_constants(lam, h, disc, &beta, &w)) return -1;
     P->m = m;
-    P->e = (double *)malloc(sizeof(double) * (size_t)m * dim);
+    P->mb = mb;
+    P->e = (double *)malloc(sizeof(double) * (size_t)mb * m * dim);
     P->wl = (double *)malloc(sizeof(double) * (size_t)P->N);
     if (!P->e || !P->wl) return -2;
-    for (int k = 0; k < m; ++k)
-        for (int d = 0; d < dim; ++d) P->e[k * dim + d] = t[d] * b[k * dim + d];
+    for (int lb = 0; lb < mb; ++lb)
+        for (int k = 0; k < m; ++k)
+            for (int d = 0; d < dim; ++d) {
+                const double rel = bb ? b[k * dim + d] - bb[lb * dim + d] : b[k * dim + d];
+                P->e[((size_t)lb * m + k) * dim + d] = t[d] * rel;
+            }
     if (drift) {
         P->q = (double *)malloc(sizeof(double) * (size_t)P->N * dim);
         if (!P->q) return -2;
@@ -104,6 +122,7 @@ static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const
     }
     for (long j = 0; j < P->N; ++j) P->wl[j] = w * (l ? l[j] : 1.0);
     P->c = c;
+    P->c_axes = c_axes ? 1 : 0;
     P->beta = beta;
     P->G = G;
     P->fixed = fixed;
@@ -125,12 +144,19 @@ static inline void node_index(const orc_prob *P, long j, long *ij)
     ij[2] = j / (P->n[0] * P->n[1]);
 }
 
-/* Fractional parts tau_d of the foot of control k from node j (index units). */
+/* Speed factor of node j on axis d. */
+static inline double speed_at(const orc_prob *P, long j, int d)
+{
+    if (!P->c) return 1.0;
+    return P->c_axes ? P->c[j * P->dim + d] : P->c[j];
+}
+
+/* Fractional parts tau_d of the foot of table row k (= l m + k_a) from node j
+ * (index units). */
 static void foot_fractions(const orc_prob *P, long j, const long *ij, int k, double *tau)
 {
-    const double cj = P->c ? P->c[j] : 1.0;
     for (int d = 0; d < P->dim; ++d) {
-        double disp = P->e[k * P->dim + d] * cj;
+        double disp = P->e[k * P->dim + d] * speed_at(P, j, d);
         if (P->q) disp = disp + P->q[j * P->dim + d];
         double u = (double)ij[d] + disp;
         tau[d] = u - floor(u);
@@ -144,9 +170,8 @@ static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx,
     const int dim = P->dim;
     double tau[3];
     long p[3];
-    const double cj = P->c ? P->c[j] : 1.0;
     for (int d = 0; d < dim; ++d) {
-        double disp = P->e[k * dim + d] * cj;
+        double disp = P->e[k * dim + d] * speed_at(P, j, d);
         if (P->q) disp = disp + P->q[j * dim + d];
         double u = (double)ij[d] + disp;
         double fl = floor(u);
@@ -188,7 +213,9 @@ static double interp_q1(int dim, const double *tau, double *val)
     return val[0];
 }
 
-/* One application of T at node j; returns the minimum, *arg = first minimising k. */
+/* One application of T at node j: the maximum over the evader's choices l of the
+ * minimum over the pursuer's controls k.  *arg = l m + k of the first maximising l
+ * and, within it, the first minimising k. */
 static double apply_node(const orc_prob *P, long j, const double *V, int *arg)
 {
     long ij[3], cidx[ORC_MAX_CORNERS];
@@ -196,15 +223,24 @@ static double apply_node(const orc_prob *P, long j, const double *V, int *arg)
     node_index(P, j, ij);
     double best = 0.0;
     int bk = -1;
-    for (int k = 0; k < P->m; ++k) {
-        int K = stencil(P, j, ij, k, cidx, wt);
-        foot_fractions(P, j, ij, k, tau);
-        for (int s = 0; s < K; ++s) val[s] = cidx[s] >= 0 ? V[cidx[s]] : P->G;
-        double r = interp_q1(P->dim, tau, val);
-        double cand = fma(P->beta, r, P->wl[j]);
-        if (bk < 0 || cand < best) {
-            best = cand;
-            bk = k;
+    for (int lb = 0; lb < P->mb; ++lb) {
+        double inner = 0.0;
+        int ik = -1;
+        for (int ka = 0; ka < P->m; ++ka) {
+            const int k = lb * P->m + ka;
+            int K = stencil(P, j, ij, k, cidx, wt);
+            foot_fractions(P, j, ij, k, tau);
+            for (int s = 0; s < K; ++s) val[s] = cidx[s] >= 0 ? V[cidx[s]] : P->G;
+            double r = interp_q1(P->dim, tau, val);
+            double cand = fma(P->beta, r, P->wl[j]);
+            if (ik < 0 || cand < inner) {
+                inner = cand;
+                ik = k;
+            }
+        }
+        if (bk < 0 || inner > best) {
+            best = inner;
+            bk = ik;
         }
     }
     *arg = bk;
@@ -268,12 +304,14 @@ int orc_max_threads(void)
 /* Apply T once: TV = T(V), policy (first minimising control, -1 on fixed or
  * non-domain nodes) optional.  Returns 0 or a negative error. */
 int orc_apply(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-              const double *b, const double *c, const double *l, const double *drift, double lam,
-              int disc, double G, const uint8_t *fixed, const uint8_t *dom, const double *V,
-              double *TV, int32_t *policy, int nthreads)
+              const double *b, const double *c, int mb, const double *bb, int c_axes,
+              const double *l, const double *drift, double lam, int disc, double G,
+              const uint8_t *fixed, const uint8_t *dom, const double *V, double *TV,
+              int32_t *policy, int nthreads)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, l, drift, lam, disc, G, fixed, dom);
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, l, drift, lam, disc, G,
+                       fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     set_threads(nthreads);
     (void)sweep(&P, V, TV, policy);
@@ -287,13 +325,14 @@ int orc_apply(int dim, const int *n, const double *lo, const double *hi, double 
  * negative error.  On return V holds the last iterate, policy (optional) the
  * first minimising control of the last sweep. */
 long orc_solve(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-               const double *b, const double *c, const double *l, const double *drift,
-               double lam, int disc, double G, const uint8_t *fixed, const uint8_t *dom,
-               double *V, int32_t *policy, double tol, long max_sweeps, double *residual,
-               int nthreads)
+               const double *b, const double *c, int mb, const double *bb, int c_axes,
+               const double *l, const double *drift, double lam, int disc, double G,
+               const uint8_t *fixed, const uint8_t *dom, double *V, int32_t *policy,
+               double tol, long max_sweeps, double *residual, int nthreads)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, l, drift, lam, disc, G, fixed, dom);
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, l, drift, lam, disc, G,
+                       fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     set_threads(nthreads);
     double *W = (double *)malloc(sizeof(double) * (size_t)P.N);
@@ -317,11 +356,13 @@ long orc_solve(int dim, const int *n, const double *lo, const double *hi, double
 /* Interpolation stencil of the frozen policy: for every node j with policy[j] >= 0,
  * corner indices (-1 = ghost) and weights of I at its foot, 2^dim per node. */
 int orc_policy_stencil(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-                       const double *b, const double *c, const double *drift, const uint8_t *dom,
-                       const int32_t *policy, int64_t *cidx, double *wts)
+                       const double *b, const double *c, int mb, const double *bb, int c_axes,
+                       const double *drift, const uint8_t *dom, const int32_t *policy,
+                       int64_t *cidx, double *wts)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, NULL, drift, 1.0, 0, 0.0, NULL, dom);
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, NULL, drift, 1.0, 0, 0.0,
+                       NULL, dom);
     if (rc) { prob_free(&P); return rc; }
     const int K = 1 << dim;
     for (long j = 0; j < P.N; ++j) {
@@ -348,13 +389,14 @@ int orc_policy_stencil(int dim, const int *n, const double *lo, const double *hi
  * max|lambda_new - lambda| <= tol.  Output: lam_out (N, zero off free nodes) and,
  * if dLdl != NULL, w * lambda.  Returns iterations or a negative error. */
 long orc_adjoint(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-                 const double *b, const double *c, const double *drift, double lam, int disc,
-                 const uint8_t *fixed, const uint8_t *dom, const int32_t *policy,
-                 const double *gV, double *lam_out, double *dLdl, double tol, long max_iters,
-                 double *residual)
+                 const double *b, const double *c, int mb, const double *bb, int c_axes,
+                 const double *drift, double lam, int disc, const uint8_t *fixed,
+                 const uint8_t *dom, const int32_t *policy, const double *gV, double *lam_out,
+                 double *dLdl, double tol, long max_iters, double *residual)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, NULL, drift, lam, disc, 0.0, fixed, dom);
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, NULL, drift, lam, disc, 0.0,
+                       fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     double beta = P.beta, w;
     orc_scheme_constants(lam, h, disc, &beta, &w);
@@ -399,12 +441,14 @@ long orc_adjoint(int dim, const int *n, const double *lo, const double *hi, doub
  * nodes (zero elsewhere), plain Jacobi from zero.  Used for the dot-product test
  * <lambda, w dl> = <gV, Vdot>.  Returns iterations or a negative error. */
 long orc_tangent(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-                 const double *b, const double *c, const double *drift, double lam, int disc,
-                 const uint8_t *fixed, const uint8_t *dom, const int32_t *policy,
-                 const double *dl, double *Vdot, double tol, long max_iters, double *residual)
+                 const double *b, const double *c, int mb, const double *bb, int c_axes,
+                 const double *drift, double lam, int disc, const uint8_t *fixed,
+                 const uint8_t *dom, const int32_t *policy, const double *dl, double *Vdot,
+                 double tol, long max_iters, double *residual)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, dl, drift, lam, disc, 0.0, fixed, dom);
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, dl, drift, lam, disc, 0.0,
+                       fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     const long N = P.N;
     const int K = 1 << dim;

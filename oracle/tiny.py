@@ -9,6 +9,15 @@ until the policy is stable.  The foot positions and Q1 weights are evaluated
 exactly from the (binary64) problem data, so the only inexact inputs are the
 binary64 values of beta and w.  Only practical for grids of a few dozen free
 nodes.
+
+For a differential game (paper Sec. 2; the evader's choice b_l is maximised,
+the pursuer's control a_k minimised) the fixed point is the pointwise maximum over
+the evader's stationary strategies sigma (a choice l per node) of the value of the
+control problem that sigma leaves to the pursuer: for every sigma the game value
+is a supersolution of that problem (T_sigma V <= T V = V, so its value is below),
+and the maximising choices at the game value give a sigma whose value it is.
+``game_value`` enumerates every sigma on a tiny grid and solves each control
+problem by the exact policy iteration above.
 """
 from __future__ import annotations
 
@@ -31,13 +40,26 @@ def _floor(x: Fr) -> int:
     return x.numerator // x.denominator
 
 
+def _table(prob):
+    """Rows of the control table: the pursuer's controls a_k, or for a game the
+    differences a_k - b_l in the order l m + k (exact rationals)."""
+    A = [[Fr(float(x)) for x in row] for row in np.asarray(prob.velocity)]
+    vb = getattr(prob, "velocity_b", None)
+    if vb is None:
+        return A
+    return [[a[d] - Fr(float(b[d])) for d in range(prob.dim)]
+            for b in np.asarray(vb) for a in A]
+
+
 def exact_stencils(prob):
-    """For every free node and control: list of (corner index or -1, weight)."""
+    """For every free node and table row: list of (corner index or -1, weight)."""
     dim, n = prob.dim, prob.n
     N = prob.N
     h = Fr(prob.step)
     t = [h / ((Fr(prob.hi[d]) - Fr(prob.lo[d])) / (n[d] - 1)) for d in range(dim)]
     tgt = np.asarray(prob.target)
+    rows = _table(prob)
+    sp = None if prob.speed is None else np.asarray(prob.speed)
     out = {}
     for j in range(N):
         if tgt[j] >= 0:
@@ -47,13 +69,18 @@ def exact_stencils(prob):
         for d in range(dim):
             ij.append(r % n[d])
             r //= n[d]
-        c = Fr(1) if prob.speed is None else Fr(float(prob.speed[j]))
+        if sp is None:
+            c = [Fr(1)] * dim
+        elif sp.ndim == 2:
+            c = [Fr(float(sp[j, d])) for d in range(dim)]
+        else:
+            c = [Fr(float(sp[j]))] * dim
         q = [Fr(0)] * dim if prob.drift is None else \
             [t[d] * Fr(float(np.asarray(prob.drift).reshape(-1, dim)[j, d])) for d in range(dim)]
         per_k = []
-        for k in range(prob.m):
-            # foot x + h (b(x) + c(x) a_k), in index units
-            u = [ij[d] + t[d] * Fr(float(prob.velocity[k, d])) * c + q[d] for d in range(dim)]
+        for row in rows:
+            # foot x + h (b(x) + S(x) e) with e = a_k (or a_k - b_l), in index units
+            u = [ij[d] + t[d] * row[d] * c[d] + q[d] for d in range(dim)]
             p = [_floor(x) for x in u]
             tau = [u[d] - p[d] for d in range(dim)]
             st = []
@@ -93,8 +120,10 @@ def _solve_exact(A: List[List[Fr]], b: List[Fr]) -> List[Fr]:
     return [M[i][n] for i in range(n)]
 
 
-def policy_iteration(prob, max_iter: int = 100):
-    """Exact fixed point of the scheme by Howard's algorithm.
+def policy_iteration(prob, max_iter: int = 100, st=None, rows=None):
+    """Exact fixed point of the scheme by Howard's algorithm (a control problem:
+    the minimum over the table rows ``rows[j]`` a node may use, all rows when
+    ``rows`` is None).
 
     Returns (V as a list of Fractions over all nodes, policy array, iterations)."""
     beta, w = _consts(prob.lam, prob.step, prob.disc)
@@ -102,11 +131,16 @@ def policy_iteration(prob, max_iter: int = 100):
     tgt = np.asarray(prob.target)
     gv = [Fr(0)] * prob.N if prob.g is None else [Fr(float(x)) for x in prob.g]
     lv = [Fr(1)] * prob.N if prob.cost is None else [Fr(float(x)) for x in prob.cost]
-    st = exact_stencils(prob)
+    if st is None:
+        st = exact_stencils(prob)
     free = sorted(st)
+    if rows is None:
+        if getattr(prob, "velocity_b", None) is not None:
+            raise ValueError("a game needs game_value (or explicit rows)")
+        rows = {j: range(prob.m) for j in free}
     pos = {j: i for i, j in enumerate(free)}
     fixedval = {j: gv[j] for j in range(prob.N) if tgt[j] >= 0}
-    pol = {j: 0 for j in free}
+    pol = {j: rows[j][0] for j in free}
     V = None
     for it in range(1, max_iter + 1):
         nf = len(free)
@@ -140,7 +174,7 @@ def policy_iteration(prob, max_iter: int = 100):
         for j in free:
             cur = val(j, pol[j])
             best, bk = cur, pol[j]
-            for k in range(prob.m):
+            for k in rows[j]:
                 v = val(j, k)
                 if v < best:
                     best, bk = v, k
@@ -173,3 +207,27 @@ def candidate_gaps(prob, V) -> np.ndarray:
         vals.sort()
         gaps[j] = float(vals[1] - vals[0]) if len(vals) > 1 else np.inf
     return gaps
+
+
+def game_value(prob, max_iter: int = 100):
+    """Exact fixed point of the game scheme max_l min_k on a tiny grid: the
+    pointwise maximum, over every stationary evader strategy sigma, of the exact
+    value of the control problem sigma leaves to the pursuer (rows sigma(j) m + k).
+
+    Returns (V as a list of Fractions, the number of strategies, and whether one
+    strategy attains the maximum at every node)."""
+    import itertools
+    mb = np.asarray(prob.velocity_b).shape[0]
+    m = prob.m
+    st = exact_stencils(prob)
+    free = sorted(st)
+    best = None
+    values = []
+    for sigma in itertools.product(range(mb), repeat=len(free)):
+        rows = {j: range(s * m, s * m + m) for j, s in zip(free, sigma)}
+        V, _, _ = policy_iteration(prob, max_iter, st=st, rows=rows)
+        best = V if best is None else [max(a, b) for a, b in zip(best, V)]
+        values.append(V)
+    attained = any(all(v == b for v, b in zip(V, best)) for V in values)
+    return best, mb ** len(free), attained
+

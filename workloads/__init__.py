@@ -12,7 +12,11 @@ Conventions
   ``dx = (hi - lo)/(n - 1)``.  Flat arrays are row-major with x fastest:
   ``j = i0 + n0*(i1 + n1*i2)``.
 * Dynamics are ``f(x, a_k) = c(x) * b_k``: a positive speed field ``c`` times a
-  tabulated velocity ``b_k`` per discrete control (``velocity``, shape ``(m, d)``).
+  tabulated velocity ``b_k`` per discrete control (``velocity``, shape ``(m, d)``),
+  plus an optional drift.  A differential game adds the evader's table
+  (``velocity_b``, shape ``(mb, d)``): ``f(x, a_k, b_l) = drift(x) + S(x)(a_k - b_l)``
+  with ``S`` the speed times the identity, or ``diag(speed[j, :])`` when the speed
+  has one factor per axis (shape ``(N, d)``).
 * ``target[j] = -1`` marks a free node, ``k >= 0`` a node of target component ``k``.
 * Every floating field is rounded to float32 and then stored as float64, so the
   FP32 GPU path and the FP64 oracle see bit-identical inputs.
@@ -31,6 +35,7 @@ __all__ = [
     "coarse_nodes_for",
     "c1_eikonal", "c2_multitarget", "c3_aniso3d", "c4_batch", "c5_adjoint",
     "strip_problem", "box_distance_problem", "vdp_problem", "obs_nodes",
+    "circle_controls", "pursuit_evasion_problem", "strip_game_problem",
 ]
 
 
@@ -45,7 +50,7 @@ class Problem:
     velocity: np.ndarray                 # (m, dim) float64, f(x,a_k) = c(x) * velocity[k]
     target: np.ndarray                   # (N,) int8, -1 free, k >= 0 component k
     n_comp: int
-    speed: Optional[np.ndarray] = None   # (N,) float64 (float32-representable); None -> 1
+    speed: Optional[np.ndarray] = None   # (N,) or per axis (N, dim), float32-representable; None -> 1
     cost: Optional[np.ndarray] = None    # (N,) running cost l(x) > 0; None -> 1
     g: Optional[np.ndarray] = None       # (N,) exit cost on target nodes; None -> 0
     drift: Optional[np.ndarray] = None   # (N, dim) drift b(x), f = b(x) + c(x)*velocity; None -> 0
@@ -59,6 +64,7 @@ class Problem:
     ra_M: float = 0.5                    # defaults give delta = 2 dx of the coarse grid
     ra_q: float = 1.0
     ra_tol: float = 1e-10                # coarse stopping tolerance (same on every side)
+    velocity_b: Optional[np.ndarray] = None  # (mb, dim) evader's table (games); None -> control problem
     meta: dict = field(default_factory=dict)
 
     @property
@@ -385,3 +391,59 @@ def vdp_problem(n: int, split: int = 4, n_a: int = 21, rho: float = 0.2) -> Prob
                    velocity=vel, target=tid, n_comp=split, speed=None,
                    cost=f32(np.sqrt(x1 * x1 + x2 * x2)).clip(min=1e-3),
                    drift=f32(drift), v_ghost=2.0, coarse_stride=1)
+
+
+def circle_controls(m: int, radius: float = 1.0, centre: bool = False) -> np.ndarray:
+    """``m`` equally spaced directions of the given length (angle 2 pi k/m, k from
+    0), and the zero control appended when ``centre``: a discrete ball for a player
+    whose dynamics are linear in its control."""
+    th = 2.0 * math.pi * np.arange(m) / m
+    v = radius * np.stack([np.cos(th), np.sin(th)], axis=1)
+    if centre:
+        v = np.vstack([v, np.zeros((1, 2))])
+    return v
+
+
+def pursuit_evasion_problem(n: int, split: int = 4, m_a: int = 32, m_b: int = 8,
+                            rho: float = 0.2) -> Problem:
+    """Pursuit-evasion game of the paper's Sec. 4.1 on [-1,1]^2: f(x, a, b) =
+    (f1(x)(a1 - b1), f2(x)(a2 - b2)) with f1 = x2 + 1, f2 = 1 (per-axis speed
+    factors), pursuer a in the unit ball (``m_a`` directions on its circle), evader
+    b in the ball of radius 1/2 (``m_b`` directions on its circle and the centre),
+    running cost l = x1^2 + 0.1, capture on the ball |x| <= rho split in ``split``
+    quadrant-shaped slices."""
+    X = node_coords((n, n), (-1.0, -1.0), (1.0, 1.0))
+    x1, x2 = X[:, 0], X[:, 1]
+    speed = np.stack([x2 + 1.0, np.ones_like(x2)], axis=1)
+    inside = x1 * x1 + x2 * x2 <= rho * rho
+    tid = np.full(X.shape[0], -1, dtype=np.int8)
+    if split == 1:
+        comp = np.zeros(X.shape[0], dtype=np.int8)
+    elif split == 4:
+        comp = np.select([(x1 >= 0) & (x2 >= 0), (x1 >= 0) & (x2 < 0), (x1 < 0) & (x2 < 0)],
+                         [0, 1, 2], 3).astype(np.int8)
+    else:
+        raise ValueError("split must be 1 or 4")
+    tid[inside] = comp[inside]
+    return Problem(name=f"pe_{n}_{split}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
+                   velocity=circle_controls(m_a, 1.0),
+                   velocity_b=circle_controls(m_b, 0.5, centre=True),
+                   target=tid, n_comp=split, speed=f32(speed), cost=f32(x1 * x1 + 0.1),
+                   v_ghost=2.0, coarse_stride=1, ra_C=1.0, ra_M=3.0, ra_q=0.5)
+
+
+def strip_game_problem(n: int, evader=(-0.5, 0.5), thick: int = 4, n_y: int = 5) -> Problem:
+    """A game that moves along x1 only: pursuer a in {-1, +1} e1, evader b in
+    ``evader`` (multiples of e1), h = 2 dx, target = the ``thick`` leftmost node
+    columns (g = 0).  Feet land on nodes, so the discrete value has a closed form."""
+    lo, hi = (-1.0, -1.0), (1.0, 1.0)
+    nn = (n, n_y)
+    X = node_coords(nn, lo, hi)
+    i0 = np.arange(X.shape[0]) % n
+    tid = np.where(i0 < thick, 0, -1).astype(np.int8)
+    dx = (hi[0] - lo[0]) / (n - 1)
+    vel = np.array([[-1.0, 0.0], [1.0, 0.0]])
+    vb = np.array([[float(b), 0.0] for b in evader])
+    return Problem(name=f"strip_game_{n}", dim=2, n=nn, lo=lo, hi=hi, velocity=vel,
+                   velocity_b=vb, target=tid, n_comp=1, h=2.0 * dx, v_ghost=4.0)
+
