@@ -3,13 +3,16 @@
  * sub-domains (Festa, "Reconstruction of independent sub-domains for a class of
  * Hamilton-Jacobi equations and its application to parallel computing").
  *
- * Problem (paper Sec. 2, exit-time problem (P1) and equation (HJ), control case):
- *   dynamics   f(x, a_k) = c(x) * b_k   (+ drift(x))   on a discrete control set
+ * Problem (paper Sec. 2, exit-time problem (P1) and equation (HJ)):
+ *   dynamics   f(x, a_k) = c(x) * b_k   (+ drift(x))   on a discrete control set,
+ *   or for a differential game f(x, a_k, b_l) = drift(x) + S(x)(a_k - b_l) with the
+ *   evader's discrete choices b_l (sl_problem.m_b, velocity_b);
  *   running cost l(x) > 0, discount lambda > 0, target set Gamma = union of
  *   components Gamma_i (nodes with target id i), exit cost g on Gamma.
  * Scheme (Sec. 3, (SL) and (Tdef), read as: foot x + h f, cost added, min over
- * controls):  for a free node x_j
- *   V(j) = min_k { beta * I[V](x_j + h f(x_j, a_k)) + w * l(x_j) }
+ * the pursuer's controls, max over the evader's choices):  for a free node x_j
+ *   V(j) = max_l min_k { beta * I[V](x_j + h f(x_j, a_k, b_l)) + w * l(x_j) }
+ *   (a control problem has no evader: V(j) = min_k {...})
  *   I = Q1 (bi/trilinear) interpolation on the Cartesian grid; corners outside
  *   the box or outside the current sub-domain read the ghost value v_ghost;
  *   target nodes keep g.  Discount: SL_DISC_EXP beta = exp(-lambda h),
@@ -41,9 +44,10 @@
 extern "C" {
 #endif
 
-#define SLHJB_ABI_VERSION 3
+#define SLHJB_ABI_VERSION 4
 #define SL_MAX_COMP 8
 #define SL_MAX_CONTROLS 256
+#define SL_MAX_TABLE 4096     /* m * max(m_b, 1): displacement rows of a game       */
 
 typedef enum {
     SL_OK = 0,
@@ -64,8 +68,10 @@ typedef struct sl_problem {
     int n[3];                 /* nodes per axis (>= 3 on used axes)                  */
     double lo[3], hi[3];      /* box corners; dx_d = (hi_d - lo_d)/(n_d - 1)         */
     int m;                    /* number of discrete controls, 1..SL_MAX_CONTROLS     */
-    const double *velocity;   /* HOST, m*dim: b_k with f(x, a_k) = drift(x) + c(x) b_k */
-    const void *speed;        /* DEVICE, N values of c(x) >= 0 in `dtype`; NULL = 1   */
+    const double *velocity;   /* HOST, m*dim: b_k with f(x, a_k) = drift(x) + c(x) b_k
+                                 (for a game: the pursuer's a_k)                       */
+    const void *speed;        /* DEVICE, N values of c(x) >= 0 in `dtype` (N*dim with
+                                 speed_axes); NULL = 1                                 */
     const void *cost;         /* DEVICE, N values of l(x) > 0 in `dtype`; NULL = 1    */
     const void *drift;        /* DEVICE, N*dim drift(x) in `dtype` (node-major); NULL = 0.
                                  Control-affine dynamics (the Van der Pol example, Sec.
@@ -82,6 +88,26 @@ typedef struct sl_problem {
     double v_ghost;           /* value read outside the box / sub-domain; should be >= max(l)/lambda */
     int disc;                 /* sl_disc                                              */
     int dtype;                /* sl_dtype of fields and values                        */
+    int m_b;                  /* differential game (Sec. 2, (Tdef) with max over B): the
+                                 number of evader choices b_l, 1..SL_MAX_CONTROLS with
+                                 m * m_b <= SL_MAX_TABLE; 0 = control problem.  The
+                                 evader chooses first (outer maximum), the pursuer answers
+                                 (inner minimum over the m controls); the displacement of
+                                 the pair is (h/dx_d)(a_kd - b_ld), the difference taken
+                                 first, in FP64.  sl_solve, sl_reconstruct and sl_solve_isa
+                                 take games (without a policy: want_policy with a policy
+                                 buffer returns SL_ERR_UNSUPPORTED); sl_solve_batched and
+                                 sl_adjoint return SL_ERR_UNSUPPORTED.  The sub-domain
+                                 method needs the decomposability condition of Sec. 2
+                                 (the paper shows it for its pursuit-evasion example); the
+                                 library does not check it.                             */
+    const double *velocity_b; /* HOST, m_b*dim: the evader's b_l (NULL iff m_b == 0)   */
+    int speed_axes;           /* 0: speed holds one c(x) per node, S(x) = c(x) I;
+                                 1: speed holds dim factors per node (node-major, N*dim,
+                                 each >= 0), S(x) = diag(c_1(x), .., c_d(x)); the coarse
+                                 grid samples each factor by Q1.  Needs speed != NULL;
+                                 sl_solve_batched and sl_adjoint return
+                                 SL_ERR_UNSUPPORTED.                                   */
 } sl_problem;
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */
@@ -161,7 +187,8 @@ typedef struct sl_stats {
 const char *sl_status_string(int status);
 int sl_abi_version(void);
 /* Number of sweep-kernel configurations (tile shape x work schedule) the
- * autotuner chooses from for (dim, dtype); 0 if unsupported. */
+ * autotuner chooses from for (dim, dtype) in a control problem; 0 if unsupported.
+ * A game chooses from the subset whose kernels give each tile one thread group. */
 int sl_tune_candidates(int dim, int dtype);
 
 /* Workspace bytes needed by sl_solve for problem `p` (0 if `p` is invalid). */

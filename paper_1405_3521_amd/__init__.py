@@ -44,6 +44,7 @@ class SlProblem(C.Structure):
         ("cost", C.c_void_p), ("drift", C.c_void_p), ("target", C.c_void_p), ("g", C.c_void_p),
         ("n_comp", C.c_int), ("lambda_", C.c_double), ("h", C.c_double),
         ("v_ghost", C.c_double), ("disc", C.c_int), ("dtype", C.c_int),
+        ("m_b", C.c_int), ("velocity_b", C.POINTER(C.c_double)), ("speed_axes", C.c_int),
     ]
 
 
@@ -132,10 +133,10 @@ class DeviceProblem:
     n: tuple
     lo: tuple
     hi: tuple
-    velocity: np.ndarray            # host (m, dim) float64
+    velocity: np.ndarray            # host (m, dim) float64 (a game: the pursuer's a_k)
     target: "object"                # torch.int8 device tensor (N,)
     n_comp: int
-    speed: Optional[object] = None  # torch tensor (N,) of `dtype` or None
+    speed: Optional[object] = None  # torch tensor (N,) or, per axis, (N*dim,) of `dtype`, or None
     cost: Optional[object] = None
     g: Optional[object] = None
     drift: Optional[object] = None  # torch tensor (N*dim,) of `dtype`, node-major, or None
@@ -144,6 +145,8 @@ class DeviceProblem:
     v_ghost: float = 1.0
     disc: str = "exp"
     dtype: "object" = None          # torch.float32 / torch.float64
+    velocity_b: Optional[np.ndarray] = None  # host (m_b, dim) float64: the evader's b_l (games)
+    speed_axes: bool = False        # speed holds dim factors per node (node-major)
 
     @property
     def N(self) -> int:
@@ -192,11 +195,16 @@ def to_device(prob, dtype=None, device: str = "cuda:0") -> DeviceProblem:
     def dev(a, dt):
         return None if a is None else torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
 
+    sp = getattr(prob, "speed", None)
+    axes = sp is not None and np.asarray(sp).ndim == 2
+    vb = getattr(prob, "velocity_b", None)
     return DeviceProblem(
         dim=prob.dim, n=tuple(prob.n), lo=tuple(prob.lo), hi=tuple(prob.hi),
         velocity=np.ascontiguousarray(prob.velocity, dtype=np.float64),
         target=dev(prob.target, torch.int8), n_comp=int(prob.n_comp),
-        speed=dev(getattr(prob, "speed", None), dtype), cost=dev(getattr(prob, "cost", None), dtype),
+        speed=None if sp is None else dev(np.asarray(sp).reshape(-1), dtype),
+        speed_axes=axes, cost=dev(getattr(prob, "cost", None), dtype),
+        velocity_b=None if vb is None else np.ascontiguousarray(vb, dtype=np.float64),
         g=dev(getattr(prob, "g", None), dtype),
         drift=None if getattr(prob, "drift", None) is None
         else dev(np.asarray(prob.drift).reshape(-1), dtype),
@@ -221,12 +229,16 @@ def _cproblem(p: DeviceProblem):
     import torch
     N = p.N
     _check_tensor(p.target, torch.int8, N, "target")
-    for name in ("speed", "cost", "g"):
+    for name in ("cost", "g"):
         _check_tensor(getattr(p, name), p.dtype, N, name)
+    _check_tensor(p.speed, p.dtype, N * (p.dim if p.speed_axes else 1), "speed")
     _check_tensor(p.drift, p.dtype, N * p.dim, "drift")
     vel = np.ascontiguousarray(p.velocity, dtype=np.float64)
     if vel.ndim != 2 or vel.shape[1] != p.dim:
         raise ValueError("velocity must have shape (m, dim)")
+    vb = None if p.velocity_b is None else np.ascontiguousarray(p.velocity_b, dtype=np.float64)
+    if vb is not None and (vb.ndim != 2 or vb.shape[1] != p.dim):
+        raise ValueError("velocity_b must have shape (m_b, dim)")
     cp = SlProblem()
     cp.dim = p.dim
     for d in range(3):
@@ -246,7 +258,10 @@ def _cproblem(p: DeviceProblem):
     cp.v_ghost = p.v_ghost
     cp.disc = DISC[p.disc]
     cp.dtype = 0 if p.dtype == torch.float32 else 1
-    return cp, vel           # keep vel alive
+    cp.m_b = 0 if vb is None else vb.shape[0]
+    cp.velocity_b = None if vb is None else vb.ctypes.data_as(C.POINTER(C.c_double))
+    cp.speed_axes = 1 if p.speed_axes else 0
+    return cp, (vel, vb)     # keep the host tables alive
 
 
 def _stream():

@@ -50,10 +50,21 @@ size_t nodes_of(const sl_problem *p) {
     return N;
 }
 
+// Rows of the displacement table: the pursuer's controls for every evader choice.
+int table_rows(const sl_problem *p) { return p->m * (p->m_b > 0 ? p->m_b : 1); }
+bool is_game(const sl_problem *p) { return p->m_b > 0; }
+// Values per node of the speed field.
+int speed_comps(const sl_problem *p) { return p->speed && p->speed_axes ? p->dim : 1; }
+
 int validate(const sl_problem *p) {
     if (!p) return SL_ERR_INVALID_ARG;
     if (p->dim != 2 && p->dim != 3) return SL_ERR_UNSUPPORTED;
     if (p->m < 1 || p->m > SL_MAX_CONTROLS) return SL_ERR_UNSUPPORTED;
+    if (p->m_b < 0 || p->m_b > SL_MAX_CONTROLS) return SL_ERR_UNSUPPORTED;
+    if ((p->m_b > 0) != (p->velocity_b != nullptr)) return SL_ERR_INVALID_ARG;
+    if (table_rows(p) > SL_MAX_TABLE) return SL_ERR_UNSUPPORTED;
+    if (p->speed_axes != 0 && p->speed_axes != 1) return SL_ERR_INVALID_ARG;
+    if (p->speed_axes && !p->speed) return SL_ERR_INVALID_ARG;
     if (p->n_comp < 1 || p->n_comp > SL_MAX_COMP) return SL_ERR_UNSUPPORTED;
     if (!p->velocity || !p->target) return SL_ERR_INVALID_ARG;
     double N = 1;
@@ -65,6 +76,8 @@ int validate(const sl_problem *p) {
     if (N > 2147483647.0) return SL_ERR_UNSUPPORTED;
     for (int i = 0; i < p->m * p->dim; ++i)
         if (!std::isfinite(p->velocity[i])) return SL_ERR_INVALID_ARG;
+    for (int i = 0; i < p->m_b * p->dim; ++i)
+        if (!std::isfinite(p->velocity_b[i])) return SL_ERR_INVALID_ARG;
     if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return SL_ERR_INVALID_ARG;
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return SL_ERR_INVALID_ARG;
     if (!std::isfinite(p->v_ghost)) return SL_ERR_INVALID_ARG;
@@ -115,18 +128,24 @@ void scheme_constants(double lam, double h, int disc, double *beta, double *w) {
     }
 }
 
-// Control displacements in cells per unit speed: e_kd = (h/dx_d) * b_kd.
+// Displacements in cells per unit speed, row l*m + k: e_d = (h/dx_d) * (a_kd - b_ld)
+// (the difference first, in FP64), or (h/dx_d) * a_kd for a control problem.
 void control_table(const sl_problem *p, const int *n, double h, std::vector<double> &e,
                    double *emax) {
     double t[3];
     for (int d = 0; d < p->dim; ++d) t[d] = h / ((p->hi[d] - p->lo[d]) / (double)(n[d] - 1));
-    e.resize((size_t)p->m * p->dim);
+    const int mb = p->m_b > 0 ? p->m_b : 1;
+    e.resize((size_t)table_rows(p) * p->dim);
     *emax = 0.0;
-    for (int k = 0; k < p->m; ++k)
-        for (int d = 0; d < p->dim; ++d) {
-            e[(size_t)k * p->dim + d] = t[d] * p->velocity[(size_t)k * p->dim + d];
-            *emax = std::max(*emax, std::fabs(e[(size_t)k * p->dim + d]));
-        }
+    for (int l = 0; l < mb; ++l)
+        for (int k = 0; k < p->m; ++k)
+            for (int d = 0; d < p->dim; ++d) {
+                const double a = p->velocity[(size_t)k * p->dim + d];
+                const double rel = p->m_b > 0 ? a - p->velocity_b[(size_t)l * p->dim + d] : a;
+                const size_t i = ((size_t)l * p->m + k) * p->dim + d;
+                e[i] = t[d] * rel;
+                *emax = std::max(*emax, std::fabs(e[i]));
+            }
 }
 
 // Cells a foot can reach: c * |e| over the controls plus the drift's |q| (index units).
@@ -247,11 +266,12 @@ struct ChunkLoop {
 // Kernel configurations are chosen per problem shape by timing candidates on
 // the caller's problem; the winner is cached for the life of the process.
 struct TuneKey {
-    int dim, dtype, m, halo, nsd, size_class, local_iters;
+    int dim, dtype, m, m_inner, halo, nsd, size_class, local_iters;
     bool operator<(const TuneKey &o) const {
-        const int a[7] = {dim, dtype, m, halo, nsd, size_class, local_iters};
-        const int b[7] = {o.dim, o.dtype, o.m, o.halo, o.nsd, o.size_class, o.local_iters};
-        return std::lexicographical_compare(a, a + 7, b, b + 7);
+        const int a[8] = {dim, dtype, m, m_inner, halo, nsd, size_class, local_iters};
+        const int b[8] = {o.dim,  o.dtype, o.m,          o.m_inner,
+                          o.halo, o.nsd,   o.size_class, o.local_iters};
+        return std::lexicographical_compare(a, a + 8, b, b + 8);
     }
 };
 std::map<TuneKey, std::pair<int, int>> &tune_cache() {
@@ -263,12 +283,15 @@ std::mutex &tune_mutex() {
     return m;
 }
 
-std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo) {
+// Candidates for (dim, dtype); a game leaves out the variants that split the
+// controls over several thread groups.
+std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo, bool game = false) {
     LaunchCfg all[16];
     const int nv = sweep_variants(dim, all, 16);
     std::vector<LaunchCfg> out;
     for (int i = 0; i < nv && i < 16; ++i) {
         if (all[i].dtype != dtype) continue;
+        if (game && all[i].threads > kThreads) continue;
         for (int mode = 0; mode < 3; ++mode) {
             LaunchCfg c = all[i];
             c.halo = halo;
@@ -463,8 +486,11 @@ struct Exec {
     int solve_tuned(int autotune, Reinit reinit, double tol, long max_sweeps, int check_every,
                     int want_policy, hipStream_t s, long *sweeps_done, int profile) {
         const int local_iters = cfg.local_iters;   // not a tuned parameter
+        bool game = false;
+        for (const auto &d : host_sds) game = game || (d.m_inner > 0 && d.m_inner < d.m);
         if (autotune < 0) {                  // forced candidate (testing)
-            const std::vector<LaunchCfg> cands = tune_candidates(cfg.dim, cfg.dtype, cfg.halo);
+            const std::vector<LaunchCfg> cands =
+                tune_candidates(cfg.dim, cfg.dtype, cfg.halo, game);
             const int k = -autotune - 1;
             if (k >= (int)cands.size()) return SL_ERR_INVALID_ARG;
             cfg = cands[k];
@@ -475,8 +501,14 @@ struct Exec {
             for (const auto &d : host_sds) nodes += (long)d.n[0] * d.n[1] * d.n[2];
             int sc = 0;
             while ((1L << sc) < nodes) ++sc;
-            const TuneKey key{cfg.dim,   cfg.dtype, host_sds.empty() ? 0 : host_sds[0].m,
-                              cfg.halo,  (int)host_sds.size(), sc, local_iters};
+            const TuneKey key{cfg.dim,
+                              cfg.dtype,
+                              host_sds.empty() ? 0 : host_sds[0].m,
+                              host_sds.empty() ? 0 : host_sds[0].m_inner,
+                              cfg.halo,
+                              (int)host_sds.size(),
+                              sc,
+                              local_iters};
             bool found = false;
             std::pair<int, int> pick;
             {
@@ -488,7 +520,8 @@ struct Exec {
                 }
             }
             if (!found) {
-                const std::vector<LaunchCfg> cands = tune_candidates(cfg.dim, cfg.dtype, cfg.halo);
+                const std::vector<LaunchCfg> cands =
+                    tune_candidates(cfg.dim, cfg.dtype, cfg.halo, game);
                 hipEvent_t e0, e1;
                 HIPCHK(hipEventCreate(&e0));
                 HIPCHK(hipEventCreate(&e1));
@@ -613,8 +646,8 @@ int gather_field_stats(const sl_problem *p, const int8_t *target, const T *speed
     FieldStats init{};
     for (int i = 0; i < SL_MAX_COMP; ++i) init.first_node[i] = INT_MAX;
     HIPCHK(hipMemcpyAsync(fs_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_field_stats<T>(speed, cost, (const T *)p->drift, p->dim, target, N, n_comp,
-                                 fs_dev, s));
+    HIPCHK(launch_field_stats<T>(speed, speed_comps(p), cost, (const T *)p->drift, p->dim,
+                                 target, N, n_comp, fs_dev, s));
     HIPCHK(hipMemcpyAsync(host, fs_dev, sizeof(FieldStats), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return SL_OK;
@@ -661,7 +694,7 @@ int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **
     *wl = p->cost ? a.take<T>(N) : nullptr;
     T *qq = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
     if (q) *q = qq;
-    *ctrl = a.take<T>((size_t)p->m * p->dim);
+    *ctrl = a.take<T>((size_t)table_rows(p) * p->dim);
     *fs = a.take<FieldStats>(1);
     ex.reserve(a, 1, tiles);
     return SL_OK;
@@ -728,7 +761,9 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     d.beta = (T)beta;
     d.G = (T)p->v_ghost;
     for (int k = 0; k < 3; ++k) d.n[k] = k < p->dim ? p->n[k] : 1;
-    d.m = p->m;
+    d.m = table_rows(p);
+    d.m_inner = p->m;
+    d.speed_axes = speed_comps(p) > 1;
     d.bit = 0;
     Exec<T>::tiles_of(ex.cfg, p->n, p->dim, d.tiles);
     d.halo = H;
@@ -811,11 +846,11 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     const int nc = p->n_comp;
     const int tilesK = max_tiles(p->dim, SL_F64, cg.nK);
     P.gK_t = a.take<T>(cg.NK);
-    P.cK = a.take<double>(cg.NK);
+    P.cK = a.take<double>(cg.NK * (size_t)speed_comps(p));
     P.wlK = a.take<double>(cg.NK);
     P.qK = p->drift ? a.take<double>(cg.NK * (size_t)p->dim) : nullptr;
     P.gK = a.take<double>(cg.NK);
-    P.ctrlK = a.take<double>((size_t)p->m * p->dim);
+    P.ctrlK = a.take<double>((size_t)table_rows(p) * p->dim);
     P.tK = a.take<int8_t>(cg.NK);
     P.Vaux = a.take<double>((size_t)nc * 2 * cg.NK);
     P.Vpack = a.take<double>((size_t)nc * cg.NK);
@@ -827,7 +862,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     P.Vf = a.take<T>((size_t)nc * 2 * N);
     P.wl = p->cost ? a.take<T>(N) : nullptr;
     P.q = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
-    P.ctrl = a.take<T>((size_t)p->m * p->dim);
+    P.ctrl = a.take<T>((size_t)table_rows(p) * p->dim);
     P.fs = a.take<FieldStats>(1);
     P.counts = a.take<unsigned long long>(8);
     P.ex.reserve(a, nc, tiles * nc);
@@ -859,7 +894,8 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     double betaK, wK, emaxK;
     scheme_constants(p->lambda, cg.hK, p->disc, &betaK, &wK);
     if (p->speed)
-        HIPCHK(launch_sample_coarse<T>((const T *)p->speed, P.cK, p->n, cg.nK, p->dim, 1, 1.0, s));
+        HIPCHK(launch_sample_coarse<T>((const T *)p->speed, P.cK, p->n, cg.nK, p->dim,
+                                       speed_comps(p), 1.0, s));
     if (p->cost)
         HIPCHK(launch_sample_coarse<T>((const T *)p->cost, P.wlK, p->n, cg.nK, p->dim, 1, wK, s));
     if (p->g) HIPCHK(launch_gather_nearest<T>((const T *)p->g, P.gK_t, p->n, cg.nK, p->dim, s));
@@ -878,8 +914,8 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
         FieldStats init{};
         for (int i = 0; i < SL_MAX_COMP; ++i) init.first_node[i] = INT_MAX;
         HIPCHK(hipMemcpyAsync(P.fsK, &init, sizeof(init), hipMemcpyHostToDevice, s));
-        HIPCHK(launch_field_stats<double>(nullptr, nullptr, nullptr, p->dim, P.tK, cg.NK, nc,
-                                          P.fsK, s));
+        HIPCHK(launch_field_stats<double>(nullptr, 1, nullptr, nullptr, p->dim, P.tK, cg.NK,
+                                          nc, P.fsK, s));
         const int *first_fine = reinterpret_cast<const int *>(
             reinterpret_cast<const char *>(P.fs) + offsetof(FieldStats, first_node));
         const int *firstK = reinterpret_cast<const int *>(
@@ -924,7 +960,9 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
         d.beta = betaK;
         d.G = p->v_ghost;
         for (int k = 0; k < 3; ++k) d.n[k] = cg.nK[k];
-        d.m = p->m;
+        d.m = table_rows(p);
+        d.m_inner = p->m;
+        d.speed_axes = speed_comps(p) > 1;
         d.bit = i;
         Exec<double>::tiles_of(P.exK.cfg, cg.nK, p->dim, d.tiles);
         d.halo = HK;
@@ -1029,7 +1067,9 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
         d.beta = (T)beta;
         d.G = (T)p->v_ghost;
         for (int k = 0; k < 3; ++k) d.n[k] = k < p->dim ? p->n[k] : 1;
-        d.m = p->m;
+        d.m = table_rows(p);
+        d.m_inner = p->m;
+        d.speed_axes = speed_comps(p) > 1;
         d.bit = i;
         Exec<T>::tiles_of(P.ex.cfg, p->n, p->dim, d.tiles);
         d.halo = H;
@@ -1086,7 +1126,7 @@ void plan_adjoint(const sl_problem *p, int n_sets, Arena &a, AdjPlan<T> &P) {
     const size_t N = nodes_of(p);
     P.lam = a.take<T>((size_t)n_sets * N);
     P.acc = a.take<T>((size_t)n_sets * 2 * N);
-    P.ctrl = a.take<T>((size_t)p->m * p->dim);
+    P.ctrl = a.take<T>((size_t)table_rows(p) * p->dim);
     P.ads = a.take<AdjDesc<T>>(n_sets);
     P.st = a.take<SdState>(n_sets);
     P.cnt = a.take<ExecCounters>(1);
@@ -1186,6 +1226,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
             sd.beta = (T)beta;
             for (int k = 0; k < 3; ++k) sd.n[k] = hd[i].n[k];
             sd.m = p->m;
+            sd.m_inner = p->m;
             sd.bit = i;
             Exec<T>::tiles_of(cfg, sd.n, 2, sd.tiles);
             sd.halo = H;
@@ -1429,6 +1470,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.G = p->v_ghost;
             for (int k = 0; k < 3; ++k) sd.n[k] = d.nK[k];
             sd.m = p->m;
+            sd.m_inner = p->m;
             sd.bit = i;
             Exec<double>::tiles_of(B.exK.cfg, d.nK, dim, sd.tiles);
             sd.halo = HKq[q];
@@ -1471,6 +1513,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.G = (T)p->v_ghost;
             for (int k = 0; k < 3; ++k) sd.n[k] = d.n[k];
             sd.m = p->m;
+            sd.m_inner = p->m;
             sd.bit = i;
             Exec<T>::tiles_of(B.ex.cfg, d.n, dim, sd.tiles);
             sd.halo = Hq[q];
@@ -1526,8 +1569,8 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
-        if (probs[q].drift) return SL_ERR_UNSUPPORTED;
-        if (probs[q].m != probs[0].m && false) return SL_ERR_UNSUPPORTED;
+        if (probs[q].drift || is_game(&probs[q]) || probs[q].speed_axes)
+            return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
 }
@@ -1581,6 +1624,7 @@ int sl_solve(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_by
     if (rc) return rc;
     if ((rc = validate_solve_opts(o))) return rc;
     if (!V || !ws) return SL_ERR_INVALID_ARG;
+    if (is_game(p) && o->want_policy && policy) return SL_ERR_UNSUPPORTED;
     if (ws_bytes < sl_solve_workspace_size(p)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == SL_F32)
@@ -1625,6 +1669,7 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
     if ((rc = validate_ra(p, ra))) return rc;
     if ((rc = validate_solve_opts(o))) return rc;
     if (!member || !V || !ws) return SL_ERR_INVALID_ARG;
+    if (is_game(p) && o->want_policy && policy) return SL_ERR_UNSUPPORTED;
     if (ws_bytes < sl_isa_workspace_size(p, ra)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == SL_F32)
@@ -1689,7 +1734,7 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
-    if (p->drift) return SL_ERR_UNSUPPORTED;
+    if (p->drift || is_game(p) || p->speed_axes) return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

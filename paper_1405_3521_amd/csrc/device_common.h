@@ -21,6 +21,12 @@ template <>
 __device__ __forceinline__ float min_<float>(float a, float b) { return __builtin_fminf(a, b); }
 template <>
 __device__ __forceinline__ double min_<double>(double a, double b) { return __builtin_fmin(a, b); }
+template <typename T>
+__device__ __forceinline__ T max_(T a, T b) { return a > b ? a : b; }
+template <>
+__device__ __forceinline__ float max_<float>(float a, float b) { return __builtin_fmaxf(a, b); }
+template <>
+__device__ __forceinline__ double max_<double>(double a, double b) { return __builtin_fmax(a, b); }
 
 // Split a foot coordinate into the integer cell index (tile-local, >= 0) and the
 // fractional part.  FP32: local coordinate u > 0, so truncation is the floor and

@@ -34,10 +34,12 @@ struct SdDesc {
     const int8_t *target;       // per-node target id (>= 0: fixed node)
     const uint8_t *member;      // per-node set bitmask or nullptr (whole box)
     uint8_t *policy;            // per-node first minimising control (policy pass only)
-    const T *ctrl;              // m*dim control displacements e_kd = (h/dx_d) b_kd
+    const T *ctrl;              // m*dim displacements (h/dx_d)(a_kd - b_ld), row l*m_inner + k
     T wl_const, beta, G;
     int n[3];
-    int m;
+    int m;                      // table rows (pursuer controls x evader choices)
+    int m_inner;                // pursuer controls per evader choice (= m: control problem)
+    int speed_axes;             // 1: speed holds dim factors per node
     int bit;                    // member bit of this sd
     int tiles[3];               // tiles per axis
     int tile_offset;            // first global tile id of this sd
@@ -226,7 +228,7 @@ hipError_t launch_place_missing(int8_t *tK, T *gK, const T *g, const int *first_
                                 int n_comp, hipStream_t s);
 // One-pass input statistics (fs must be pre-initialised: zeros, first_node = INT_MAX).
 template <typename T>
-hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
+hipError_t launch_field_stats(const T *speed, int speed_comps, const T *cost, const T *drift, int dim,
                               const int8_t *target, size_t n, int n_comp, FieldStats *fs,
                               hipStream_t s);
 // Flip final_buf of every sd (after a policy pass).

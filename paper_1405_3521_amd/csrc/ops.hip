@@ -57,8 +57,9 @@ __global__ void k_absmax(const T *src, size_t n, unsigned long long *out) {
 // values (speed < 0, cost <= 0, non-finite), target counts, lowest node index per
 // target component, target ids out of range.
 template <typename T>
-__global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int dim,
-                              const int8_t *target, size_t n, int n_comp, FieldStats *fs) {
+__global__ void k_field_stats(const T *speed, int speed_comps, const T *cost, const T *drift,
+                              int dim, const int8_t *target, size_t n, int n_comp,
+                              FieldStats *fs) {
     double smax = 0.0, cmax = 0.0, dmax = 0.0;
     int bad_s = 0, bad_c = 0, ntar = 0, bad_t = 0;
     int first[SL_MAX_COMP];
@@ -67,8 +68,10 @@ __global__ void k_field_stats(const T *speed, const T *cost, const T *drift, int
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         if (speed) {
-            const double v = (double)speed[i];
-            if (!(v >= 0.0) || !(v < INFINITY)) ++bad_s; else smax = v > smax ? v : smax;
+            for (int c = 0; c < speed_comps; ++c) {
+                const double v = (double)speed[i * speed_comps + c];
+                if (!(v >= 0.0) || !(v < INFINITY)) ++bad_s; else smax = v > smax ? v : smax;
+            }
         }
         if (cost) {
             const double v = (double)cost[i];
@@ -508,15 +511,16 @@ template hipError_t launch_place_missing<float>(int8_t *, float *, const float *
 template hipError_t launch_place_missing<double>(int8_t *, double *, const double *, const int *, const int *, const int *, const int *, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_field_stats(const T *speed, const T *cost, const T *drift, int dim,
+hipError_t launch_field_stats(const T *speed, int speed_comps, const T *cost, const T *drift, int dim,
                               const int8_t *target, size_t n, int n_comp, FieldStats *fs,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_field_stats<T>, dim3(grid_for(n) < 512 ? grid_for(n) : 512),
-                       dim3(kOpThreads), 0, s, speed, cost, drift, dim, target, n, n_comp, fs);
+                       dim3(kOpThreads), 0, s, speed, speed_comps, cost, drift, dim, target, n,
+                       n_comp, fs);
     return hipGetLastError();
 }
-template hipError_t launch_field_stats<float>(const float *, const float *, const float *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
-template hipError_t launch_field_stats<double>(const double *, const double *, const double *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
+template hipError_t launch_field_stats<float>(const float *, int, const float *, const float *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
+template hipError_t launch_field_stats<double>(const double *, int, const double *, const double *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
 
 hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
                              double delta, uint8_t *memberK, uint8_t *labelK, hipStream_t s) {

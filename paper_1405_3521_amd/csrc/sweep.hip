@@ -1,8 +1,10 @@
 // Semi-Lagrangian sweep kernels for gfx950 (CDNA4).
 //
-// One sweep applies the SL operator (paper Sec. 3, (SL)/(Tdef), control case)
-//     V_new(j) = min_k  fma(beta, I[V](foot_jk), w l_j)
-// to every free member node of every active (sub-domain, tile) work item.
+// One sweep applies the SL operator (paper Sec. 3, (SL)/(Tdef))
+//     V_new(j) = max_l min_k  fma(beta, I[V](foot_j,lk), w l_j)
+// to every free member node of every active (sub-domain, tile) work item: the
+// table holds, per evader choice l, the pursuer's m_inner displacements; a control
+// problem has one block (l = 0) and the maximum is over one value.
 //
 // Mapping to the hardware
 //   * one work-group (4 wave64) per work item; the tile plus an H-cell halo
@@ -50,7 +52,8 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
     // S groups of kThreads threads share a tile: the same nodes, every S-th control
     // each (k = g, g + S, ...); group 0 takes the minimum over the groups' partial
     // results (exact, so the values do not depend on S; on ties the lowest control
-    // index wins, as in one pass).
+    // index wins, as in one pass).  Control problems only: a game (more than one
+    // evader block) runs with S = 1.
     constexpr int NT = kThreads * S;
     __shared__ T lds[LW * LH];
     __shared__ T part[S > 1 ? (S - 1) * TX * TY : 1];
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         __syncthreads();
 
         const int gx = x0 + tx;
-        T c[NPT], ux0[NPT], uy0[NPT], qx[NPT], qy[NPT], wl[NPT], best[NPT];
+        T cx[NPT], cy[NPT], ux0[NPT], uy0[NPT], qx[NPT], qy[NPT], wl[NPT], best[NPT];
         int arg[NPT];
         bool act[NPT];
         int any = 0;
@@ -111,7 +114,8 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
             const int ty = ty0 + r * RSTEP;
             const int gy = y0 + ty;
             act[r] = false;
-            c[r] = T(0);                        // inactive lanes: foot = own node
+            cx[r] = T(0);                       // inactive lanes: foot = own node
+            cy[r] = T(0);
             wl[r] = d.wl_const;
             T qxv = T(0), qyv = T(0);           // drift in index units
             if (gx < n0 && gy < n1) {
@@ -119,7 +123,14 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                 const bool inset = !mem || ((mem[j] >> bit) & 1);
                 act[r] = inset && d.target[j] < 0;
                 if (act[r]) {
-                    c[r] = d.speed ? d.speed[j] : T(1);
+                    if (!d.speed) {
+                        cx[r] = cy[r] = T(1);
+                    } else if (d.speed_axes) {
+                        cx[r] = d.speed[2 * j];
+                        cy[r] = d.speed[2 * j + 1];
+                    } else {
+                        cx[r] = cy[r] = d.speed[j];
+                    }
                     if (d.wl) wl[r] = d.wl[j];
                     if (d.drift) {
                         qxv = d.drift[2 * j];
@@ -144,6 +155,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         const T beta = d.beta;
         const T *__restrict__ ctrl = d.ctrl;
         const int m = d.m;
+        const int ma = d.m_inner > 0 ? d.m_inner : m;
         // Jacobi (local_iters == 0): one evaluation per node, written to the other
         // buffer.  Block-asynchronous (local_iters = k > 0): the tile iterates up to
         // k times on its own values in LDS, the halo as staged, while anything in it
@@ -156,22 +168,28 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         for (int li = 0; li < iters; ++li) {
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            best[r] = (T)INFINITY;
+            best[r] = -(T)INFINITY;
             arg[r] = 0;
         }
+        // evader blocks (maximum) of pursuer controls (minimum); with S groups the
+        // groups split the controls of each block (games use S = 1)
         if (__any(any)) {
+        for (int kb = 0; kb < m; kb += ma) {
+            T inner[NPT];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) inner[r] = (T)INFINITY;
 #pragma unroll 2
-            for (int k = grp; k < m; k += S) {
+            for (int k = kb + grp; k < kb + ma; k += S) {
                 const T ex = ctrl[2 * k], ey = ctrl[2 * k + 1];
 #pragma unroll
                 for (int r = 0; r < NPT; ++r) {
                     T ux, uy;
                     if (sizeof(T) == 4) {
-                        ux = fma_(c[r], ex, ux0[r]);
-                        uy = fma_(c[r], ey, uy0[r]);
+                        ux = fma_(cx[r], ex, ux0[r]);
+                        uy = fma_(cy[r], ey, uy0[r]);
                     } else {
-                        ux = ux0[r] + (ex * c[r] + qx[r]);
-                        uy = uy0[r] + (ey * c[r] + qy[r]);
+                        ux = ux0[r] + (ex * cx[r] + qx[r]);
+                        uy = uy0[r] + (ey * cy[r] + qy[r]);
                     }
                     int ix, iy;
                     T fx, fy;
@@ -194,15 +212,18 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                     const T acc = fma_(fy, b, ay * a);
                     const T cand = fma_(beta, acc, wl[r]);
                     if (POLICY) {
-                        if (cand < best[r]) {
-                            best[r] = cand;
+                        if (cand < inner[r]) {
+                            inner[r] = cand;
                             arg[r] = k;
                         }
                     } else {
-                        best[r] = min_(best[r], cand);
+                        inner[r] = min_(inner[r], cand);
                     }
                 }
             }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) best[r] = max_(best[r], inner[r]);
+        }
         }
         if (S > 1) {
             if (grp > 0) {
@@ -361,7 +382,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         __syncthreads();
 
         const int gx = x0 + tx, gy = y0 + ty;
-        T c[NPT], ux0[NPT], uy0[NPT], uz0[NPT], qx[NPT], qy[NPT], qz[NPT], wl[NPT], best[NPT];
+        T cx[NPT], cy[NPT], cz[NPT], ux0[NPT], uy0[NPT], uz0[NPT], qx[NPT], qy[NPT], qz[NPT];
+        T wl[NPT], best[NPT];
         int arg[NPT];
         bool act[NPT];
         int any = 0;
@@ -370,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
             const int tz = tz0 + r * ZSTEP;
             const int gz = z0 + tz;
             act[r] = false;
-            c[r] = T(0);                        // inactive lanes: foot = own node
+            cx[r] = cy[r] = cz[r] = T(0);       // inactive lanes: foot = own node
             wl[r] = d.wl_const;
             T qxv = T(0), qyv = T(0), qzv = T(0);
             if (gx < n0 && gy < n1 && gz < n2) {
@@ -378,7 +400,15 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                 const bool inset = !mem || ((mem[j] >> bit) & 1);
                 act[r] = inset && d.target[j] < 0;
                 if (act[r]) {
-                    c[r] = d.speed ? d.speed[j] : T(1);
+                    if (!d.speed) {
+                        cx[r] = cy[r] = cz[r] = T(1);
+                    } else if (d.speed_axes) {
+                        cx[r] = d.speed[3 * j];
+                        cy[r] = d.speed[3 * j + 1];
+                        cz[r] = d.speed[3 * j + 2];
+                    } else {
+                        cx[r] = cy[r] = cz[r] = d.speed[j];
+                    }
                     if (d.wl) wl[r] = d.wl[j];
                     if (d.drift) {
                         qxv = d.drift[3 * j];
@@ -405,6 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         const T beta = d.beta;
         const T *__restrict__ ctrl = d.ctrl;
         const int m = d.m;
+        const int ma = d.m_inner > 0 ? d.m_inner : m;
         // Jacobi or block-asynchronous local iterations, as in the 2D kernel
         const bool async = !POLICY && local_iters > 0;
         const int iters = async ? local_iters : 1;
@@ -414,23 +445,27 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         for (int li = 0; li < iters; ++li) {
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            best[r] = (T)INFINITY;
+            best[r] = -(T)INFINITY;
             arg[r] = 0;
         }
         if (__any(any)) {
-            for (int k = 0; k < m; ++k) {
+        for (int kb = 0; kb < m; kb += ma) {     // evader blocks, as in the 2D kernel
+            T inner[NPT];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) inner[r] = (T)INFINITY;
+            for (int k = kb; k < kb + ma; ++k) {
                 const T ex = ctrl[3 * k], ey = ctrl[3 * k + 1], ez = ctrl[3 * k + 2];
 #pragma unroll
                 for (int r = 0; r < NPT; ++r) {
                     T ux, uy, uz;
                     if (sizeof(T) == 4) {
-                        ux = fma_(c[r], ex, ux0[r]);
-                        uy = fma_(c[r], ey, uy0[r]);
-                        uz = fma_(c[r], ez, uz0[r]);
+                        ux = fma_(cx[r], ex, ux0[r]);
+                        uy = fma_(cy[r], ey, uy0[r]);
+                        uz = fma_(cz[r], ez, uz0[r]);
                     } else {
-                        ux = ux0[r] + (ex * c[r] + qx[r]);
-                        uy = uy0[r] + (ey * c[r] + qy[r]);
-                        uz = uz0[r] + (ez * c[r] + qz[r]);
+                        ux = ux0[r] + (ex * cx[r] + qx[r]);
+                        uy = uy0[r] + (ey * cy[r] + qy[r]);
+                        uz = uz0[r] + (ez * cz[r] + qz[r]);
                     }
                     int ix, iy, iz;
                     T fx, fy, fz;
@@ -453,15 +488,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     const T acc = fma_(fz, c1, az * c0);
                     const T cand = fma_(beta, acc, wl[r]);
                     if (POLICY) {
-                        if (cand < best[r]) {
-                            best[r] = cand;
+                        if (cand < inner[r]) {
+                            inner[r] = cand;
                             arg[r] = k;
                         }
                     } else {
-                        best[r] = min_(best[r], cand);
+                        inner[r] = min_(inner[r], cand);
                     }
                 }
             }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) best[r] = max_(best[r], inner[r]);
+        }
         }
         if (async) {
             int chg = 0;

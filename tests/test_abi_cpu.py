@@ -153,3 +153,47 @@ def test_drift_accepted_by_solves_and_rejected_by_batch_and_adjoint():
     st = S.SlStats()
     assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
                         C.byref(st), None) == -3
+
+
+def test_game_and_axis_speed_fields_are_validated():
+    """Differential games (m_b evader choices) and per-axis speed factors: the
+    workspace queries size a game's larger displacement table and reject malformed
+    fields; the batch and the adjoint, and a game with a policy output, report
+    SL_ERR_UNSUPPORTED before any device work."""
+    L = S.lib()
+    vb = 0.5 * np.stack([np.cos(np.arange(20)), np.sin(np.arange(20))], axis=1)
+    vbp = vb.ctypes.data_as(C.POINTER(C.c_double))
+    game, k1 = _problem(m_b=20, velocity_b=vbp)           # 80 table rows
+    ctrl, k2 = _problem()
+    assert L.sl_solve_workspace_size(C.byref(game)) > L.sl_solve_workspace_size(C.byref(ctrl))
+    for bad in (dict(m_b=3), dict(velocity_b=vbp), dict(m_b=-1, velocity_b=vbp),
+                dict(m_b=257, velocity_b=vbp), dict(speed_axes=1), dict(speed_axes=2)):
+        p, k = _problem(**bad)
+        assert L.sl_solve_workspace_size(C.byref(p)) == 0, bad
+    va = np.zeros((64, 2))
+    vbig = np.zeros((65, 2))
+    wide, k3 = _problem(m=64, velocity=va.ctypes.data_as(C.POINTER(C.c_double)), m_b=65,
+                        velocity_b=vbig.ctypes.data_as(C.POINTER(C.c_double)))
+    assert L.sl_solve_workspace_size(C.byref(wide)) == 0      # 64 * 65 rows > SL_MAX_TABLE
+    wide.m_b = 64
+    assert L.sl_solve_workspace_size(C.byref(wide)) > 0       # 64 * 64 = SL_MAX_TABLE
+    nan = np.array([[np.nan, 0.0]])
+    pn, k4 = _problem(m_b=1, velocity_b=nan.ctypes.data_as(C.POINTER(C.c_double)))
+    assert L.sl_solve_workspace_size(C.byref(pn)) == 0
+    axes, k5 = _problem(speed_axes=1, speed=C.c_void_p(0x3000))
+    assert L.sl_solve_workspace_size(C.byref(axes)) > 0
+    ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    assert L.sl_isa_workspace_size(C.byref(game), C.byref(ra)) > 0
+    for p in (game, axes):
+        assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) == 0
+        buf = C.create_string_buffer(64)
+        st = S.SlStats()
+        assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
+                            C.byref(st), None) == -3
+    buf = C.create_string_buffer(64)
+    o = S.SlSolveOpts()
+    o.tol, o.max_sweeps, o.want_policy = 0.0, 10, 1
+    st = S.SlStats()
+    assert L.sl_solve(C.byref(game), C.byref(o), buf, 64, buf, buf, C.byref(st), None) == -3
+    assert L.sl_solve_isa(C.byref(game), C.byref(ra), buf, C.byref(o), buf, 64, buf, None, buf,
+                          None, C.byref(st), None) == -3
