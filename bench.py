@@ -66,9 +66,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c3,c4,c5",
+    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe",
                     help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
-                         "c5 (adjoint 513^2); empty for none")
+                         "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
+                         "(pursuit-evasion game 513^2); empty for none")
     return ap.parse_args()
 
 
@@ -105,6 +106,54 @@ def leg_c3(steps: int, li: int):
             "set_fraction_max": float(np.mean([x["set_fraction_max"] for x in sts])),
             "sweep_ms_per_launch": ms_launch, "valu_tops": ach, "valu_frac": ach / PEAK_VALU_TOPS,
             "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"]}
+
+
+def _isa_leg_2d(p, steps: int, li: int, workload: str):
+    """ISA to sup-res<1e-6 of a 2D problem in FP32 (tuned kernels), timed per call,
+    with the sweep launches' VALU rate."""
+    import torch
+    import paper_1405_3521_amd as S
+    dp = S.to_device(p, torch.float32, "cuda:0")
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
+                  q=p.ra_q, tol=p.ra_tol, autotune=1)
+    opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1, local_iters=li)
+    S.isa(dp, ra, opts)
+    _sync()
+    t0 = time.perf_counter()
+    sts = [S.isa(dp, ra, opts)[-1] for _ in range(steps)]
+    _sync()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    nc = np.mean([x["node_control_updates"] for x in sts])
+    launches = np.mean([x["sweep_launches"] for x in sts])
+    ms_launch = np.sum([x["ms_sweeps"] for x in sts]) / np.sum([x["sweep_launches"] for x in sts])
+    ach = OPS_PER_NC_2D * nc / launches / (ms_launch / 1e3) / 1e12
+    return {"workload": workload, "time_to_converge_ms": ms,
+            "node_control_updates_per_s": nc / (ms / 1e3),
+            "sweep_launches": int(launches),
+            "ms_reconstruct": float(np.mean([x["ms_ra"] for x in sts])),
+            "set_fraction_max": float(np.mean([x["set_fraction_max"] for x in sts])),
+            "sweep_ms_per_launch": ms_launch, "valu_tops": ach, "valu_frac": ach / PEAK_VALU_TOPS,
+            "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"]}
+
+
+def leg_vdp(steps: int, li: int):
+    """Van der Pol target problem (drift + control on x2), 1025^2, 4 target slices."""
+    import workloads as W
+    p = W.vdp_problem(1025, split=4).with_(coarse_stride=8)
+    return _isa_leg_2d(p, steps, li, "Van der Pol 1025^2, drift (x2, (1-x1^2)x2-x1) + (0, a), "
+                                     "21 controls, l=|x|, capture disk r=0.2 in 4 slices, "
+                                     "ISA (RA on 129^2) to sup-res<1e-6")
+
+
+def leg_pe(steps: int, li: int):
+    """Pursuit-evasion game, 513^2: max over 9 evader choices of min over 32 pursuer
+    controls (288 table rows), per-axis speed (x2 + 1, 1), 4 capture arcs."""
+    import workloads as W
+    p = W.pursuit_evasion_problem(513, split=4, m_a=32, m_b=8).with_(coarse_stride=8)
+    return _isa_leg_2d(p, steps, li, "pursuit-evasion game 513^2, f = ((x2+1)(a1-b1), a2-b2), "
+                                     "a: 32 directions, b: 8 directions of length 1/2 and 0, "
+                                     "l = x1^2 + 0.1, capture disk r=0.2 in 4 arcs, ISA (RA on "
+                                     "65^2, C=1, M=3, q=1/2) to sup-res<1e-6")
 
 
 def leg_c4(steps: int, li: int):
@@ -350,7 +399,7 @@ def main():
     }
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
-        fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5}[leg]
+        fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe}[leg]
         t0 = time.perf_counter()
         legs[leg] = fn(max(1, min(args.steps, 3)), args.local_iters)
         print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

@@ -102,3 +102,41 @@ def test_drift_3d_fp64_bit_exact():
     Vo, _, _, _ = O.solve(p)
     assert st["converged"]
     assert np.array_equal(host(V), Vo)
+
+
+def _fixed_point_residuals(p, member, Vs):
+    """Largest |T(V_i) - V_i| of the oracle's FP64 operator over each set's free
+    nodes (one oracle sweep per set)."""
+    mem = host(member)
+    fixed = O.fixed_mask(p)
+    out = []
+    for i in range(p.n_comp):
+        dom = ((mem >> i) & 1).astype(np.uint8)
+        Vi = Vs[i].astype(np.float64)
+        TV, _ = O.apply_T(p, Vi, fixed=fixed, dom=dom)
+        on = dom.astype(bool) & (np.asarray(p.target) < 0)
+        out.append(float(np.abs(TV[on] - Vi[on]).max(initial=0.0)))
+    return out
+
+
+def test_full_size_vdp_benchmark_configuration():
+    """The benchmark's Van der Pol workload (1025^2, 4 slices, coarse 129^2) in the
+    launch configuration it times (tuned kernels, 4 local iterations): sets and
+    labels bit-exact against the oracle's reconstruction, and every set's FP32
+    values a fixed point of the oracle's FP64 operator up to FP32 rounding."""
+    p = W.vdp_problem(1025, split=4).with_(coarse_stride=8)
+    say("case: full-size vdp 1025")
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    ra.autotune = 1
+    member, label, _ = S.reconstruct(dp, ra)
+    rec = I.reconstruct(p)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
+    V, own, pol, Vs, st = S.solve_isa(dp, ra, member,
+                                      S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=1,
+                                                  local_iters=4), want_sets=True)
+    assert st["converged"]
+    r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
+    say("  fixed-point residuals", r, "launches", st["sweeps_max"])
+    assert max(r) <= 2e-6

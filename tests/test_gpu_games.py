@@ -151,3 +151,27 @@ def test_game_autotune_and_policy_rejection():
     with pytest.raises(S.SlError) as e:
         S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP, want_policy=True))
     assert e.value.status == -3
+
+
+def test_full_size_pursuit_evasion_benchmark_configuration():
+    """The benchmark's game workload (513^2, 32 x 9 controls, 4 arcs, coarse 65^2)
+    in the launch configuration it times (tuned kernels, 4 local iterations): sets
+    and labels bit-exact against the oracle's reconstruction, and every set's FP32
+    values a fixed point of the oracle's FP64 game operator up to FP32 rounding."""
+    from tests.test_gpu_drift import _fixed_point_residuals
+    p = W.pursuit_evasion_problem(513, split=4, m_a=32, m_b=8).with_(coarse_stride=8)
+    say("case: full-size pursuit-evasion 513")
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    ra.autotune = 1
+    member, label, _ = S.reconstruct(dp, ra)
+    rec = I.reconstruct(p)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
+    V, own, pol, Vs, st = S.solve_isa(dp, ra, member,
+                                      S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=1,
+                                                  local_iters=4), want_sets=True)
+    assert st["converged"]
+    r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
+    say("  fixed-point residuals", r, "launches", st["sweeps_max"])
+    assert max(r) <= 2e-6
