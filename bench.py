@@ -45,6 +45,10 @@ OPS_PER_NC_3D = 28
 # counters are stored in profiles/.
 DEFAULT_SWEEP_CONFIG = 10
 DEFAULT_LOCAL_ITERS = 4
+# Coarse FP64 pass: local iterations per tile and launch (measured per workload at
+# tol 0: 8 for the 2D workloads with 32-64 controls, 4 for 3D and for the long-
+# characteristic or many-control 2D ones)
+RA_LOCAL_ITERS = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_multitarget1025_hbm_counters.md")
 
 
@@ -78,6 +82,15 @@ def _sync():
     torch.cuda.synchronize()
 
 
+def ra_opts(p, autotune: int = 1, local: int = RA_LOCAL_ITERS):
+    """Reconstruction options of a workload: its coarse grid and threshold, tuned
+    FP64 kernels, block-asynchronous coarse sweeps to stagnation (tol 0: the same
+    FP64 fixed point, so the same sets and labels, as Jacobi sweeps)."""
+    import paper_1405_3521_amd as S
+    return S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
+                    q=p.ra_q, tol=p.ra_tol, autotune=autotune, local_iters=local)
+
+
 def leg_c3(steps: int, li: int):
     """3D anisotropic 257^3, 8 target balls, 128 controls: ISA to sup-res<1e-6."""
     import torch
@@ -85,8 +98,7 @@ def leg_c3(steps: int, li: int):
     import workloads as W
     p = W.c3_aniso3d()
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
-                  autotune=1)
+    ra = ra_opts(p, local=4)
     opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1, local_iters=li)
     S.isa(dp, ra, opts)
     _sync()
@@ -108,14 +120,13 @@ def leg_c3(steps: int, li: int):
             "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"]}
 
 
-def _isa_leg_2d(p, steps: int, li: int, workload: str):
+def _isa_leg_2d(p, steps: int, li: int, workload: str, ra_local: int = 4):
     """ISA to sup-res<1e-6 of a 2D problem in FP32 (tuned kernels), timed per call,
     with the sweep launches' VALU rate."""
     import torch
     import paper_1405_3521_amd as S
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
-                  q=p.ra_q, tol=p.ra_tol, autotune=1)
+    ra = ra_opts(p, local=ra_local)
     opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1, local_iters=li)
     S.isa(dp, ra, opts)
     _sync()
@@ -164,8 +175,7 @@ def leg_c4(steps: int, li: int):
     import workloads as W
     probs = W.c4_batch()
     dps = [S.to_device(p, torch.float32, "cuda:0") for p in probs]
-    ras = [S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
-                  autotune=1) for p in probs]
+    ras = [ra_opts(p) for p in probs]
     opts = S.SolveOpts(tol=1e-6, autotune=2, local_iters=li)
     S.solve_batched(dps, ras, opts)
     _sync()
@@ -179,15 +189,13 @@ def leg_c4(steps: int, li: int):
     # one call per problem, default kernels (no per-size tuning inside the timing)
     single = S.SolveOpts(tol=1e-6, local_iters=li)
     for dp, p in zip(dps, probs):
-        S.isa(dp, S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q,
-                           tol=p.ra_tol), single)
+        S.isa(dp, ra_opts(p, autotune=0), single)
     _sync()
     ms_single = (time.perf_counter() - t0) * 1e3
     # one solve call per sub-domain (the batch's sets, each solved on its own with
     # its own launches), after each problem's reconstruction
     members = out[1]
-    ras0 = [S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
-                     q=p.ra_q, tol=p.ra_tol) for p in probs]
+    ras0 = [ra_opts(p, autotune=0) for p in probs]
     n_sd = 0
     _sync()
     t0 = time.perf_counter()
@@ -217,8 +225,7 @@ def leg_c5(steps: int, li: int):
     import workloads as W
     p = W.c5_adjoint()
     dp = S.to_device(p, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol,
-                  autotune=1)
+    ra = ra_opts(p)
     member, label, _ = S.reconstruct(dp, ra)
     th_true = torch.as_tensor(p.meta["theta_true"], dtype=torch.float32, device="cuda:0")
     fwd_opts = S.SolveOpts(tol=1e-6, autotune=1, local_iters=li)
@@ -326,8 +333,7 @@ def main():
 
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
-    ra = S.RaOpts(coarse_stride=prob.coarse_stride, coarse_n=prob.coarse_n, C=prob.ra_C, M=prob.ra_M, q=prob.ra_q,
-                  tol=prob.ra_tol, autotune=1)
+    ra = ra_opts(prob)
     # --sweep-config k forces candidate k-1; 0 lets the warm-up step run the
     # autotuner (complete solves as trials) and the timed steps use its pick
     opts = S.SolveOpts(tol=1e-6, profile=True,

@@ -635,6 +635,8 @@ const Variant *variants(int *count) {
         make2d<float, 32, 16, 2>(), // 13: FP32 2D, controls split over 2 groups
         make2d<float, 32, 16, 4>(), // 14: ... over 4 groups
         make2d<float, 64, 8, 4>(),  // 15
+        make2d<double, 16, 16, 2>(), // 16: FP64 2D, controls split over 2 groups: more
+        make2d<double, 16, 16, 4>(), // 17: waves per tile for small (coarse) grids
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;

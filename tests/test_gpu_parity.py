@@ -119,12 +119,18 @@ def test_reconstruction_bit_exact(n):
     assert np.array_equal(host(label), rec.label)
 
 
-def test_reconstruction_full_size_c2_labels():
-    """Full C2 size (1025^2, coarse 129^2): labels and sets bit-exact."""
+@pytest.mark.parametrize("local", [0, 8])
+def test_reconstruction_full_size_c2_labels(local):
+    """Full C2 size (1025^2, coarse 129^2): labels and sets bit-exact, with Jacobi
+    coarse sweeps and with the benchmark's coarse configuration (tuned kernels,
+    8 local iterations per tile and launch, tol 0)."""
     p = W.c2_multitarget()
-    say("case: reconstruct full c2")
+    say("case: reconstruct full c2, coarse local iterations", local)
     dp = S.to_device(p, torch.float32)
-    member, label, st, mK, lK = S.reconstruct(dp, ra_of(p), want_coarse=True)
+    ra = ra_of(p)
+    ra.local_iters = local
+    ra.autotune = 1 if local else 0
+    member, label, st, mK, lK = S.reconstruct(dp, ra, want_coarse=True)
     probK = I.coarse_problem(p)
     mKo, lKo, _, _, _, _ = I.reconstruct_on(probK)
     assert np.array_equal(host(mK), mKo)

@@ -63,7 +63,7 @@ class Problem:
     ra_C: float = 0.5                    # RA threshold 2 (C dx^q + M dx); these
     ra_M: float = 0.5                    # defaults give delta = 2 dx of the coarse grid
     ra_q: float = 1.0
-    ra_tol: float = 1e-10                # coarse stopping tolerance (same on every side)
+    ra_tol: float = 0.0                  # coarse stopping tolerance (0: until nothing changes)
     velocity_b: Optional[np.ndarray] = None  # (mb, dim) evader's table (games); None -> control problem
     meta: dict = field(default_factory=dict)
 
