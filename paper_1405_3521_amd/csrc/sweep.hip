@@ -637,6 +637,9 @@ const Variant *variants(int *count) {
         make2d<float, 64, 8, 4>(),  // 15
         make2d<double, 16, 16, 2>(), // 16: FP64 2D, controls split over 2 groups: more
         make2d<double, 16, 16, 4>(), // 17: waves per tile for small (coarse) grids
+        make2d<float, 32, 8>(),      // 18: FP32 2D, one node per thread: finer skipping
+        make2d<float, 16, 16>(),     // 19: and twice the waves per active region
+        make2d<float, 32, 8, 2>(),   // 20
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;

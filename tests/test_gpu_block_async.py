@@ -44,9 +44,10 @@ def test_block_async_equals_jacobi_2d(n):
     ra = ra_of(p)
     member, _, _ = S.reconstruct(dp, ra)
     nc = S.lib().sl_tune_candidates(2, 0)
-    for cand in (1, 3, 10, 12, nc):                # 64x16 / 32x16 tiles, split controls
+    # 64x16 / 32x16 / 32x8 / 16x16 tiles, the three schedules, split controls
+    for cand in (1, 3, 10, 12, 13, 22, 25, nc):
         Vj, Vsj, stj = _isa_sets(dp, ra, member, autotune=-cand)
-        for k in (1, 4, 32):
+        for k in (1, 4, 8, 32):
             Va, Vsa, sta = _isa_sets(dp, ra, member, autotune=-cand, local_iters=k)
             say("case", n, "candidate", cand, "local iterations", k, "launches",
                 sta["sweeps_max"], "vs sweeps", stj["sweeps_max"])
@@ -78,14 +79,15 @@ def test_block_async_batched_equals_jacobi():
 
 
 def test_block_async_full_size_c2():
-    """The benchmark's problem in the benchmark's configuration."""
+    """The benchmark's problem in the benchmark's configuration (candidate 22:
+    32x8 tiles, one work-group per item; 8 local iterations)."""
     p = W.c2_multitarget()
     dp = S.to_device(p, torch.float32)
     ra = ra_of(p)
     member, _, _ = S.reconstruct(dp, ra)
-    Vj, Vsj, stj = _isa_sets(dp, ra, member, autotune=-12)
-    for k in (4, 16):
-        Va, Vsa, sta = _isa_sets(dp, ra, member, autotune=-12, local_iters=k)
+    Vj, Vsj, stj = _isa_sets(dp, ra, member, autotune=-22)
+    for k in (8, 16):
+        Va, Vsa, sta = _isa_sets(dp, ra, member, autotune=-22, local_iters=k)
         say("full size, local iterations", k, "launches", sta["sweeps_max"], "vs", stj["sweeps_max"])
         assert np.array_equal(Vsa, Vsj), k
 
@@ -98,9 +100,10 @@ def test_block_async_tolerance_stop_vs_oracle():
     ra = ra_of(p)
     Vbar, _, rec, _, _ = I.isa(p)
     member = torch.as_tensor(rec.member, device="cuda:0")
-    for k in (4, 16):
+    for k in (4, 8, 16):
         V, own, pol, Vs, st = S.solve_isa(dp, ra, member,
-                                          S.SolveOpts(tol=1e-6, max_sweeps=CAP, local_iters=k))
+                                          S.SolveOpts(tol=1e-6, max_sweeps=CAP, local_iters=k,
+                                                      autotune=-22))
         err = np.abs(host(V).astype(np.float64) - Vbar).max()
         say("tol 1e-6, local iterations", k, "sup err", err)
         assert st["converged"] and err <= 1e-5
