@@ -23,6 +23,16 @@ template <>
 __device__ __forceinline__ double min_<double>(double a, double b) { return __builtin_fmin(a, b); }
 template <typename T>
 __device__ __forceinline__ T max_(T a, T b) { return a > b ? a : b; }
+
+// Read-only table in the constant address space: uniform indices then compile to
+// scalar loads through the scalar data cache instead of vector memory loads (the
+// displacement table is not written while a sweep kernel runs).
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ const_ptr<T> as_const(const T *p) {
+    return (const_ptr<T>)(p);
+}
 template <>
 __device__ __forceinline__ float max_<float>(float a, float b) { return __builtin_fmaxf(a, b); }
 template <>

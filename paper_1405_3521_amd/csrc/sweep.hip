@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         }
         const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
         const T beta = d.beta;
-        const T *__restrict__ ctrl = d.ctrl;
+        const const_ptr<T> ctrl = as_const(d.ctrl);     // scalar loads
         const int m = d.m;
         const int ma = d.m_inner > 0 ? d.m_inner : m;
         // Jacobi (local_iters == 0): one evaluation per node, written to the other
@@ -195,7 +195,9 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                     T fx, fy;
                     Foot<T>::split(ux, ox, ix, fx);
                     Foot<T>::split(uy, oy, iy, fy);
-                    const int base = iy * LW + ix;
+                    // corners lie inside the staged tile (0 <= ix, iy < LW, LH): a
+                    // 24-bit multiply is exact and single-pass
+                    const int base = (int)__umul24((unsigned)iy, (unsigned)LW) + ix;
                     const T v00 = lds[base], v10 = lds[base + 1];
                     const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
                     // Q1 as nested one-axis interpolations fma(f, v1, (1-f) v0), x then
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         }
         const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
         const T beta = d.beta;
-        const T *__restrict__ ctrl = d.ctrl;
+        const const_ptr<T> ctrl = as_const(d.ctrl);     // scalar loads
         const int m = d.m;
         const int ma = d.m_inner > 0 ? d.m_inner : m;
         // Jacobi or block-asynchronous local iterations, as in the 2D kernel
@@ -472,7 +474,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     Foot<T>::split(ux, ox, ix, fx);
                     Foot<T>::split(uy, oy, iy, fy);
                     Foot<T>::split(uz, oz, iz, fz);
-                    const int base = (iz * LH + iy) * LW + ix;
+                    // corners lie inside the staged block: 24-bit products are exact
+                    const int base = (int)__umul24((unsigned)iz, (unsigned)PL) +
+                                     (int)__umul24((unsigned)iy, (unsigned)LW) + ix;
                     // nested one-axis interpolations, x, then y, then z (as in 2D)
                     const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
                     const T v000 = lds[base], v100 = lds[base + 1];
