@@ -17,6 +17,7 @@ bytes per node per sweep).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -72,10 +73,12 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe",
+    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,study,balance",
                     help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
                          "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
-                         "(pursuit-evasion game 513^2); empty for none")
+                         "(pursuit-evasion game 513^2), study (global solve vs ISA and the "
+                         "RA threshold on the headline problem), balance (refinement of the "
+                         "target split, Van der Pol); empty for none")
     return ap.parse_args()
 
 
@@ -167,6 +170,89 @@ def leg_pe(steps: int, li: int):
                                      "a: 32 directions, b: 8 directions of length 1/2 and 0, "
                                      "l = x1^2 + 0.1, capture disk r=0.2 in 4 arcs, ISA (RA on "
                                      "65^2, C=1, M=3, q=1/2) to sup-res<1e-6")
+
+
+def leg_study(steps: int, li: int):
+    """Decomposition study on the 1025^2 multi-target workload: the global solve
+    without decomposition against the ISA, and the ISA across RA thresholds
+    delta = f * 2 (C dx_K^q + M dx_K): set sizes (balance) against the sup
+    difference from the global solution (accuracy)."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    p = W.c2_multitarget()
+    dp = S.to_device(p, torch.float32, "cuda:0")
+    li = DEFAULT_LOCAL_ITERS
+    opts = S.SolveOpts(tol=1e-6, autotune=-DEFAULT_SWEEP_CONFIG, local_iters=li)
+
+    def timed(fn):
+        fn()
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        _sync()
+        return out, (time.perf_counter() - t0) / steps * 1e3
+
+    (Vg, _, stg), ms_g = timed(lambda: S.solve(dp, opts))
+    nK = (p.n[0] - 1) // p.coarse_stride + 1
+    dxK = 2.0 / (nK - 1)
+    delta0 = 2.0 * (p.ra_C * dxK ** p.ra_q + p.ra_M * dxK)
+    rows = []
+    for f in (0.125, 0.25, 0.5, 1.0, 2.0, 4.0):
+        ra = ra_opts(p)
+        ra.delta_override = f * delta0
+        (V, owner, member, label, _, _, st), ms = timed(lambda: S.isa(dp, ra, opts))
+        counts = torch.zeros(p.N, dtype=torch.int32, device="cuda:0")
+        for i in range(p.n_comp):
+            counts += ((member >> i) & 1).to(torch.int32)
+        rows.append({"delta_factor": f, "delta": f * delta0, "isa_ms": ms,
+                     "set_fraction_max": st["set_fraction_max"],
+                     "set_fraction_sum": float(counts.float().mean()),
+                     "node_control_updates": st["node_control_updates"],
+                     "sup_diff_vs_global": float((V - Vg).abs().max())})
+    return {"workload": "multitarget 1025^2 (the headline problem), global solve and ISA to "
+                        "sup-res<1e-6, headline kernel configuration",
+            "no_decomposition": {"ms": ms_g, "launches": stg["sweeps_max"],
+                                 "node_control_updates": stg["node_control_updates"]},
+            "isa_by_delta": rows}
+
+
+def leg_balance(steps: int, li: int):
+    """Recursive refinement of the target split (balance) on Van der Pol 1025^2
+    (RA on 129^2, C = M = 0.05, q = 1): from the whole capture disk as one
+    component, halve the component with the largest set up to 8 components; then
+    the ISA on the refined split against the paper's fixed 4-slice split."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    p1 = W.vdp_problem(1025, split=1).with_(coarse_stride=8, ra_C=0.05, ra_M=0.05)
+    p4 = W.vdp_problem(1025, split=4).with_(coarse_stride=8, ra_C=0.05, ra_M=0.05)
+    dp1 = S.to_device(p1, torch.float32, "cuda:0")
+    ra = ra_opts(p1, local=4)
+    S.refine_split(dp1, ra, 8)
+    _sync()
+    t0 = time.perf_counter()
+    tid, nc, hist, st = S.refine_split(dp1, ra, 8)
+    _sync()
+    ms_refine = (time.perf_counter() - t0) * 1e3
+    opts = S.SolveOpts(tol=1e-6, autotune=1, local_iters=li)
+    out = {}
+    for name, dp, n in (("refined", dataclasses.replace(dp1, target=tid, n_comp=nc), nc),
+                        ("fixed_4_slices", S.to_device(p4, torch.float32, "cuda:0"), 4)):
+        S.isa(dp, ra, opts)
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = S.isa(dp, ra, opts)
+        _sync()
+        out[name] = {"components": n, "isa_ms": (time.perf_counter() - t0) / steps * 1e3,
+                     "set_fraction_max": r[-1]["set_fraction_max"],
+                     "node_control_updates": r[-1]["node_control_updates"]}
+    return {"workload": "Van der Pol 1025^2, RA on 129^2 with C = M = 0.05, q = 1; refinement "
+                        "from one capture component to 8, ISA to sup-res<1e-6",
+            "refine_ms": ms_refine, "reconstructions": st["sweeps_max"],
+            "set_fraction_max_by_step": hist, **out}
 
 
 def leg_c4(steps: int, li: int):
@@ -407,7 +493,8 @@ def main():
     }
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
-        fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe}[leg]
+        fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
+              "study": leg_study, "balance": leg_balance}[leg]
         t0 = time.perf_counter()
         legs[leg] = fn(max(1, min(args.steps, 3)), LEG_LOCAL_ITERS)
         print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

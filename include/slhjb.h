@@ -220,6 +220,31 @@ int sl_reconstruct(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t w
                    uint8_t *member, uint8_t *label, uint8_t *member_K, uint8_t *label_K,
                    sl_stats *stats, void *stream);
 
+/* Workspace bytes needed by sl_refine_split (0 if the arguments are invalid). */
+size_t sl_refine_workspace_size(const sl_problem *p, const sl_ra_opts *ra, int max_comp);
+
+/* Recursive refinement of the division of Gamma for balance, the remedy the
+ * paper's conclusions propose for unbalanced sub-domains (Sec. 5, on the Van der
+ * Pol example of Sec. 4.1).  Starting from p->target (p->n_comp components), repeat: run the
+ * reconstruction (as sl_reconstruct); stop if there are max_comp components or
+ * the largest projected set holds at most frac_goal of the fine nodes; else halve
+ * the component whose set holds the most fine nodes (lowest index on ties) among
+ * those with at least two target nodes: along the grid axis on which its nodes
+ * span the most index positions (lowest axis on ties), order them by (index on
+ * that axis, flat index) and give the upper floor(count/2) the next free label.
+ * Every decision is integer, so the result is reproducible bit for bit.
+ * Inputs: p (its target ids are read, not written), ra, max_comp in
+ * [p->n_comp, SL_MAX_COMP], frac_goal in [0, 1].  Outputs: target_out (DEVICE, N
+ * int8, the refined ids; g is unchanged), *n_comp_out (HOST), frac_max (HOST,
+ * room for max_comp - p->n_comp + 1 doubles, may be NULL: the largest set
+ * fraction after each reconstruction).  stats: ms_ra = total time, sweeps_max =
+ * reconstructions done, ra_sweeps_max = most coarse sweeps of one auxiliary
+ * problem.  The target ids cross to the host once and each reconstruction's
+ * member mask once (N bytes each way per step). */
+int sl_refine_split(const sl_problem *p, const sl_ra_opts *ra, int max_comp, double frac_goal,
+                    void *ws, size_t ws_bytes, int8_t *target_out, int *n_comp_out,
+                    double *frac_max, sl_stats *stats, void *stream);
+
 /* ISA steps 3-4 (paper Sec. 4): value iteration of T on every set i (nodes with
  * bit i of `member`; non-members read v_ghost), all sets in one launch per
  * sweep, then V(j) = min over the sets containing j.  Inputs: member (DEVICE, N

@@ -312,3 +312,51 @@ def adjoint_isa(prob, member: np.ndarray, pols: List[np.ndarray], owner: np.ndar
         total += dLdl_i
         lams.append(lam_i)
     return total, lams
+
+
+def split_component(target: np.ndarray, n: tuple, comp: int, new_label: int) -> np.ndarray:
+    """Halve target component ``comp``: along the grid axis on which its nodes span
+    the most index positions (lowest axis on ties), order the nodes by (index on
+    that axis, flat index) and give the upper floor(count/2) of them ``new_label``."""
+    dim = len(n)
+    tid = np.asarray(target).copy()
+    nodes = np.flatnonzero(tid == comp)
+    idx = []
+    rem = nodes.copy()
+    for d in range(dim):
+        idx.append(rem % n[d])
+        rem //= n[d]
+    extent = [int(idx[d].max() - idx[d].min()) for d in range(dim)]
+    axis = int(np.argmax(extent))                     # first maximum: lowest axis
+    order = np.lexsort((nodes, idx[axis]))            # by axis index, then flat index
+    upper = nodes[order[len(nodes) - len(nodes) // 2:]]
+    tid[upper] = new_label
+    return tid
+
+
+def refine_split(prob, max_comp: int, frac_goal: float = 0.0):
+    """Recursive refinement of the division of Gamma for balance (the remedy the
+    paper's conclusions propose for unbalanced sets): after each reconstruction,
+    the component whose projected set holds the most fine nodes (lowest index on
+    ties) among those with at least two target nodes is halved
+    (``split_component``), until there are ``max_comp`` components or the largest
+    set fraction is at most ``frac_goal``.
+
+    Returns (target ids, component count, largest set fraction after each
+    reconstruction)."""
+    tid = np.asarray(prob.target).astype(np.int8).copy()
+    nc = int(prob.n_comp)
+    history = []
+    while True:
+        rec = reconstruct(prob.with_(target=tid, n_comp=nc))
+        counts = np.array([int(((rec.member >> i) & 1).sum()) for i in range(nc)])
+        history.append(float(counts.max()) / prob.N)
+        if nc >= max_comp or history[-1] <= frac_goal:
+            break
+        sizes = np.array([int((tid == i).sum()) for i in range(nc)])
+        cands = [i for i in sorted(range(nc), key=lambda i: (-counts[i], i)) if sizes[i] >= 2]
+        if not cands:
+            break
+        tid = split_component(tid, tuple(prob.n[:prob.dim]), cands[0], nc)
+        nc += 1
+    return tid, nc, history

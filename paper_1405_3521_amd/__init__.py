@@ -19,7 +19,8 @@ import numpy as np
 
 __all__ = [
     "DeviceProblem", "RaOpts", "SolveOpts", "lib", "lib_path", "to_device", "solve",
-    "reconstruct", "solve_isa", "isa", "adjoint", "solve_batched", "SlError", "HJBSolve",
+    "reconstruct", "solve_isa", "isa", "adjoint", "solve_batched", "refine_split", "SlError",
+    "HJBSolve",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -104,6 +105,12 @@ def lib():
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(SlStats),
                                      C.c_void_p]
         L.sl_reconstruct.restype = C.c_int
+        L.sl_refine_workspace_size.argtypes = [P(SlProblem), P(SlRaOpts), C.c_int]
+        L.sl_refine_workspace_size.restype = C.c_size_t
+        L.sl_refine_split.argtypes = [P(SlProblem), P(SlRaOpts), C.c_int, C.c_double, C.c_void_p,
+                                      C.c_size_t, C.c_void_p, P(C.c_int), P(C.c_double),
+                                      P(SlStats), C.c_void_p]
+        L.sl_refine_split.restype = C.c_int
         L.sl_solve_isa.argtypes = [P(SlProblem), P(SlRaOpts), C.c_void_p, P(SlSolveOpts),
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, P(SlStats), C.c_void_p]
@@ -273,6 +280,33 @@ def _ra(o: RaOpts) -> SlRaOpts:
     cn = tuple(o.coarse_n or ()) + (0, 0, 0)
     return SlRaOpts(o.coarse_stride, (C.c_int * 3)(*[int(x) for x in cn[:3]]), o.C, o.M, o.q,
                     o.delta_override, o.tol, o.max_sweeps, int(o.autotune), int(o.local_iters))
+
+
+def refine_split(p: DeviceProblem, ra: RaOpts, max_comp: int, frac_goal: float = 0.0,
+                 workspace=None):
+    """Recursive halving of the target components for balance (see sl_refine_split).
+    Returns (target ids as a device int8 tensor, component count, the largest set
+    fraction after each reconstruction, stats)."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    rao = _ra(ra)
+    ws_bytes = L.sl_refine_workspace_size(C.byref(cp), C.byref(rao), int(max_comp))
+    if ws_bytes == 0:
+        raise ValueError("invalid problem, reconstruction options or max_comp")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    tid = torch.empty(p.N, dtype=torch.int8, device=dev)
+    nc = C.c_int(0)
+    fr = (C.c_double * (int(max_comp) - p.n_comp + 1))()
+    st = SlStats()
+    rc = L.sl_refine_split(C.byref(cp), C.byref(rao), int(max_comp), float(frac_goal), _ptr(ws),
+                           ws.numel(), _ptr(tid), C.byref(nc), fr, C.byref(st), _stream())
+    if rc < 0:
+        raise SlError("sl_refine_split", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    return tid, nc.value, list(fr)[:d["sweeps_max"]], d
 
 
 def coarse_nodes(p, ra: RaOpts) -> tuple:

@@ -1661,6 +1661,113 @@ int sl_reconstruct(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t w
                                     stats, s);
 }
 
+size_t sl_refine_workspace_size(const sl_problem *p, const sl_ra_opts *ra, int max_comp) {
+    if (validate(p) != SL_OK || validate_ra(p, ra) != SL_OK) return 0;
+    if (max_comp < p->n_comp || max_comp > SL_MAX_COMP) return 0;
+    sl_problem q = *p;
+    q.n_comp = max_comp;
+    const size_t isa = sl_isa_workspace_size(&q, ra);
+    if (!isa) return 0;
+    const size_t N = nodes_of(p);
+    return ((isa + 255) & ~size_t(255)) + 2 * ((N + 255) & ~size_t(255)) + 256;
+}
+
+int sl_refine_split(const sl_problem *p, const sl_ra_opts *ra, int max_comp, double frac_goal,
+                    void *ws, size_t ws_bytes, int8_t *target_out, int *n_comp_out,
+                    double *frac_max, sl_stats *stats, void *stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if ((rc = validate_ra(p, ra))) return rc;
+    if (max_comp < p->n_comp || max_comp > SL_MAX_COMP) return SL_ERR_INVALID_ARG;
+    if (!(frac_goal >= 0.0 && frac_goal <= 1.0)) return SL_ERR_INVALID_ARG;
+    if (!ws || !target_out || !n_comp_out) return SL_ERR_INVALID_ARG;
+    if (ws_bytes < sl_refine_workspace_size(p, ra, max_comp)) return SL_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = nodes_of(p);
+    sl_problem q = *p;
+    q.n_comp = max_comp;
+    const size_t isa = (sl_isa_workspace_size(&q, ra) + 255) & ~size_t(255);
+    uint8_t *member = (uint8_t *)ws + isa;
+    uint8_t *label = member + ((N + 255) & ~size_t(255));
+    // the target ids live on the host between reconstructions (the split is a
+    // handful of integer decisions); every reconstruction runs on the device
+    std::vector<int8_t> ht(N);
+    std::vector<uint8_t> hm(N);
+    HIPCHK(hipMemcpyAsync(ht.data(), p->target, N, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int nc = p->n_comp, steps = 0, last = SL_OK;
+    long ra_sweeps = 0;
+    Timer tm;
+    tm.mark(0, s);
+    for (;;) {
+        HIPCHK(hipMemcpyAsync(target_out, ht.data(), N, hipMemcpyHostToDevice, s));
+        q = *p;
+        q.target = target_out;
+        q.n_comp = nc;
+        sl_stats st{};
+        last = p->dtype == SL_F32
+                   ? reconstruct_impl<float>(&q, ra, ws, isa, member, label, nullptr, nullptr, &st, s)
+                   : reconstruct_impl<double>(&q, ra, ws, isa, member, label, nullptr, nullptr, &st, s);
+        if (last < 0) return last;
+        ra_sweeps = std::max(ra_sweeps, st.ra_sweeps_max);
+        HIPCHK(hipMemcpyAsync(hm.data(), member, N, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        long counts[SL_MAX_COMP] = {0}, sizes[SL_MAX_COMP] = {0};
+        for (size_t j = 0; j < N; ++j) {
+            for (int i = 0; i < nc; ++i) counts[i] += (hm[j] >> i) & 1;
+            if (ht[j] >= 0 && ht[j] < nc) ++sizes[ht[j]];
+        }
+        long cmax = 0;
+        for (int i = 0; i < nc; ++i) cmax = std::max(cmax, counts[i]);
+        const double fmax = (double)cmax / (double)N;
+        if (frac_max) frac_max[steps] = fmax;
+        ++steps;
+        if (nc >= max_comp || fmax <= frac_goal) break;
+        // the largest set (lowest index on ties) whose component can be halved
+        int pick = -1;
+        for (int i = 0; i < nc; ++i)
+            if (sizes[i] >= 2 && (pick < 0 || counts[i] > counts[pick])) pick = i;
+        if (pick < 0) break;
+        // halve it along the axis of largest index extent (lowest axis on ties):
+        // nodes ordered by (index on that axis, flat index), the upper half relabelled
+        int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+        std::vector<std::pair<long long, long long>> nodes;
+        for (size_t j = 0; j < N; ++j) {
+            if (ht[j] != pick) continue;
+            long long r = (long long)j;
+            for (int d = 0; d < p->dim; ++d) {
+                const int id = (int)(r % p->n[d]);
+                r /= p->n[d];
+                lo[d] = std::min(lo[d], id);
+                hi[d] = std::max(hi[d], id);
+            }
+        }
+        int axis = 0;
+        for (int d = 1; d < p->dim; ++d)
+            if (hi[d] - lo[d] > hi[axis] - lo[axis]) axis = d;
+        long long stride = 1;
+        for (int d = 0; d < axis; ++d) stride *= p->n[d];
+        for (size_t j = 0; j < N; ++j)
+            if (ht[j] == pick) nodes.emplace_back(((long long)j / stride) % p->n[axis], (long long)j);
+        std::sort(nodes.begin(), nodes.end());
+        const size_t keep = nodes.size() - nodes.size() / 2;
+        for (size_t k = keep; k < nodes.size(); ++k) ht[(size_t)nodes[k].second] = (int8_t)nc;
+        ++nc;
+    }
+    tm.mark(1, s);
+    *n_comp_out = nc;
+    if (stats) {
+        *stats = sl_stats{};
+        stats->ms_ra = tm.ms(0, 1);
+        stats->ms_total = stats->ms_ra;
+        stats->ra_sweeps_max = ra_sweeps;
+        stats->n_subdomains = nc;
+        stats->sweeps_max = steps;
+        stats->set_fraction_max = frac_max ? frac_max[steps - 1] : 0.0;
+    }
+    return last;
+}
+
 int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
                  const sl_solve_opts *o, void *ws, size_t ws_bytes, void *V, uint8_t *owner,
                  uint8_t *policy, void *V_sets, sl_stats *stats, void *stream) {

@@ -197,3 +197,22 @@ def test_game_and_axis_speed_fields_are_validated():
     assert L.sl_solve(C.byref(game), C.byref(o), buf, 64, buf, buf, C.byref(st), None) == -3
     assert L.sl_solve_isa(C.byref(game), C.byref(ra), buf, C.byref(o), buf, 64, buf, None, buf,
                           None, C.byref(st), None) == -3
+
+
+def test_refine_split_argument_checks():
+    L = S.lib()
+    p, keep = _problem()
+    ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    assert L.sl_refine_workspace_size(C.byref(p), C.byref(ra), 4) > L.sl_isa_workspace_size(
+        C.byref(p), C.byref(ra))
+    assert L.sl_refine_workspace_size(C.byref(p), C.byref(ra), 0) == 0     # below n_comp
+    assert L.sl_refine_workspace_size(C.byref(p), C.byref(ra), 9) == 0     # above SL_MAX_COMP
+    buf = C.create_string_buffer(64)
+    nc = C.c_int(0)
+    st = S.SlStats()
+    assert L.sl_refine_split(C.byref(p), C.byref(ra), 4, 1.5, buf, 64, buf, C.byref(nc), None,
+                             C.byref(st), None) == -1                        # goal outside [0, 1]
+    assert L.sl_refine_split(C.byref(p), C.byref(ra), 4, 0.0, buf, 64, None, C.byref(nc), None,
+                             C.byref(st), None) == -1
+    assert L.sl_refine_split(C.byref(p), C.byref(ra), 4, 0.0, buf, 64, buf, C.byref(nc), None,
+                             C.byref(st), None) == -5                        # workspace too small
