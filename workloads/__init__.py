@@ -60,8 +60,9 @@ class Problem:
     disc: str = "exp"                    # "exp": beta=e^{-lam h}; "paper": beta=1/(1+lam h)
     coarse_stride: int = 1
     coarse_n: Optional[tuple] = None     # coarse nodes per axis; None -> every coarse_stride-th node
-    ra_C: float = 0.5                    # RA threshold 2 (C dx^q + M dx); these
-    ra_M: float = 0.5                    # defaults give delta = 2 dx of the coarse grid
+    ra_C: float = 0.5                    # RA threshold 2 (C dx^q + M dx); these defaults
+    ra_M: float = 0.5                    # give delta = 2 dx_K (the benchmark workloads take
+                                         # C = M = q = 1, delta = 4 dx_K)
     ra_q: float = 1.0
     ra_tol: float = 0.0                  # coarse stopping tolerance (0: until nothing changes)
     velocity_b: Optional[np.ndarray] = None  # (mb, dim) evader's table (games); None -> control problem
@@ -255,7 +256,8 @@ def c2_multitarget(n: int = 1025, m: int = 64, n_disks: int = 4, r: float = 0.05
     tid = ball_targets((n, n), (-1.0, -1.0), (1.0, 1.0), cen, r)
     return Problem(name=f"multitarget_{n}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                    velocity=controls_2d(m), target=tid, n_comp=n_disks, speed=c, v_ghost=1.0,
-                   coarse_stride=coarse_stride(n, dx, r), meta={"centres": cen, "r": r})
+                   coarse_stride=coarse_stride(n, dx, r), ra_C=1.0, ra_M=1.0, ra_q=1.0,
+                   meta={"centres": cen, "r": r})
 
 
 def c3_aniso3d(n: int = 257, m: int = 128, n_balls: int = 8, r: float = 0.04,
@@ -272,7 +274,8 @@ def c3_aniso3d(n: int = 257, m: int = 128, n_balls: int = 8, r: float = 0.04,
     tid = ball_targets((n, n, n), (-1.0,) * 3, (1.0,) * 3, cen, r)
     return Problem(name=f"aniso3d_{n}", dim=3, n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3,
                    velocity=vel, target=tid, n_comp=n_balls, speed=c, v_ghost=1.0,
-                   coarse_stride=coarse_stride(n, dx, r), meta={"centres": cen, "r": r, "M": M})
+                   coarse_stride=coarse_stride(n, dx, r), ra_C=1.0, ra_M=1.0, ra_q=1.0,
+                   meta={"centres": cen, "r": r, "M": M})
 
 
 def c4_batch(count: int = 512, seed: int = 404, n_min: int = 16, n_max: int = 512,
@@ -294,8 +297,8 @@ def c4_batch(count: int = 512, seed: int = 404, n_min: int = 16, n_max: int = 51
         nK = coarse_nodes_for(n, 2.0, r)
         out.append(Problem(name=f"batch{p}_{n}", dim=2, n=(n, n), lo=(-1.0, -1.0),
                            hi=(1.0, 1.0), velocity=controls_2d(m), target=tid, n_comp=k,
-                           speed=c, v_ghost=1.0, coarse_n=(nK, nK),
-                           meta={"centres": cen, "r": r}))
+                           speed=c, v_ghost=1.0, coarse_n=(nK, nK), ra_C=1.0, ra_M=1.0,
+                           ra_q=1.0, meta={"centres": cen, "r": r}))
     return out
 
 
@@ -316,7 +319,7 @@ def c5_adjoint(n: int = 513, m: int = 32, n_disks: int = 4, r: float = 0.05,
     return Problem(name=f"adjoint_{n}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                    velocity=controls_2d(m), target=tid, n_comp=n_disks,
                    cost=f32(np.exp(th)), v_ghost=2.0,
-                   coarse_stride=coarse_stride(n, dx, r),
+                   coarse_stride=coarse_stride(n, dx, r), ra_C=1.0, ra_M=1.0, ra_q=1.0,
                    meta={"theta": th, "theta_true": th_true, "obs": obs, "centres": cen})
 
 
