@@ -73,10 +73,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,study,balance",
+    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,kruzkov,study,balance",
                     help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
                          "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
-                         "(pursuit-evasion game 513^2), study (global solve vs ISA and the "
+                         "(pursuit-evasion game 513^2), kruzkov (weighted minimum time "
+                         "513^2), study (global solve vs ISA and the "
                          "RA threshold on the headline problem), balance (refinement of the "
                          "target split, Van der Pol); empty for none")
     return ap.parse_args()
@@ -170,6 +171,16 @@ def leg_pe(steps: int, li: int):
                                      "a: 32 directions, b: 8 directions of length 1/2 and 0, "
                                      "l = x1^2 + 0.1, capture disk r=0.2 in 4 arcs, ISA (RA on "
                                      "65^2, C=1, M=3, q=1/2) to sup-res<1e-6")
+
+
+def leg_kruzkov(steps: int, li: int):
+    """Weighted minimum time in its Kruzkov form (per-node discount exp(-h l)),
+    513^2, slowness field l, 4 disks."""
+    import workloads as W
+    return _isa_leg_2d(W.kruzkov_problem(), steps, li,
+                       "Kruzkov weighted minimum time 513^2, l = exp(0.5 g) (smoothed "
+                       "Gaussian g), unit speed, 32 controls, 4 disks, per-node discount "
+                       "exp(-h l), ISA (RA on 65^2) to sup-res<1e-6")
 
 
 def leg_study(steps: int, li: int):
@@ -494,7 +505,7 @@ def main():
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
         fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
-              "study": leg_study, "balance": leg_balance}[leg]
+              "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov}[leg]
         t0 = time.perf_counter()
         legs[leg] = fn(max(1, min(args.steps, 3)), LEG_LOCAL_ITERS)
         print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

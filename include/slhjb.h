@@ -16,7 +16,14 @@
  *   I = Q1 (bi/trilinear) interpolation on the Cartesian grid; corners outside
  *   the box or outside the current sub-domain read the ghost value v_ghost;
  *   target nodes keep g.  Discount: SL_DISC_EXP beta = exp(-lambda h),
- *   w = (1 - beta)/lambda;  SL_DISC_PAPER beta = 1/(1 + lambda h), w = h.
+ *   w = (1 - beta)/lambda;  SL_DISC_PAPER beta = 1/(1 + lambda h), w = h;
+ *   SL_DISC_KRUZKOV (the Kruzkov image v = 1 - exp(-J) of the weighted minimum
+ *   time J = integral of l, Sec. 2 with the discount carried by the cost): per node
+ *   beta_j = exp(-h l_j) and the cost term 1 - beta_j = -expm1(-h l_j), lambda
+ *   unused; the exponentials are evaluated on the host in binary64 (the fields
+ *   cross to the host once per call).  v_ghost should exceed 1 (e.g. 2) so that
+ *   V = v_ghost is a supersolution in floating point.  sl_solve_batched and
+ *   sl_adjoint return SL_ERR_UNSUPPORTED for it.
  * Fixed point by value iteration from V = v_ghost (a supersolution), which the
  * paper notes is a contraction (Sec. 3).
  *
@@ -60,7 +67,7 @@ typedef enum {
 } sl_status;
 
 typedef enum { SL_F32 = 0, SL_F64 = 1 } sl_dtype;
-typedef enum { SL_DISC_EXP = 0, SL_DISC_PAPER = 1 } sl_disc;
+typedef enum { SL_DISC_EXP = 0, SL_DISC_PAPER = 1, SL_DISC_KRUZKOV = 2 } sl_disc;
 
 /* One exit-time problem on a uniform box grid (paper Sec. 2-3). */
 typedef struct sl_problem {

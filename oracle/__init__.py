@@ -36,7 +36,7 @@ _U8P = C.POINTER(C.c_uint8)
 _I32P = C.POINTER(C.c_int32)
 _I64P = C.POINTER(C.c_int64)
 
-DISC = {"exp": 0, "paper": 1}
+DISC = {"exp": 0, "paper": 1, "kruzkov": 2}
 
 
 def lib():

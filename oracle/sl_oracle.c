@@ -21,7 +21,10 @@
  *   - foot at x + h f and cost added with +, minimum over the discrete controls
  *     (the printed signs of (Tdef) are inconsistent with the Hamiltonian (HJ));
  *   - discount: "exp"   beta = exp(-lam h),  w = (1 - beta)/lam   (default),
- *               "paper" beta = 1/(1 + lam h), w = h               ((Tdef) as printed);
+ *               "paper" beta = 1/(1 + lam h), w = h               ((Tdef) as printed),
+ *               "kruzkov" per node beta_j = exp(-h l_j), w l_j -> 1 - beta_j =
+ *               -expm1(-h l_j): the Kruzkov image v = 1 - exp(-J) of the weighted
+ *               minimum time J = integral of l along the trajectory (lam unused);
  *   - dynamics f(x, a_k, b_l) = drift(x) + S(x) (a_k - b_l), S(x) = c(x) times the
  *     identity, or diag(c_1(x), .., c_d(x)) when per-axis speed factors are given,
  *     evaluated in grid-index units:
@@ -61,6 +64,7 @@ typedef struct {
     const double *c;      /* speed per node (or per node and axis), or NULL (= 1) */
     int c_axes;           /* 1: c holds dim factors per node          */
     double *wl;           /* w * l_j per node                        */
+    double *bn;           /* per-node discount (Kruzkov form) or NULL */
     double beta;
     double G;
     const uint8_t *fixed; /* 1: value fixed (target node)            */
@@ -77,6 +81,9 @@ int orc_scheme_constants(double lam, double h, int disc, double *beta, double *w
     } else if (disc == 1) {          /* the printed (Tdef): 1/(1+lam h) and h    */
         *beta = 1.0 / (1.0 + lam * h);
         *w = h;
+    } else if (disc == 2) {          /* Kruzkov form with l = 1: exp(-h), 1 - exp(-h) */
+        *beta = exp(-h);
+        *w = -expm1(-h);
     } else {
         return -1;
     }
@@ -120,7 +127,16 @@ static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const
         for (long j = 0; j < P->N; ++j)
             for (int d = 0; d < dim; ++d) P->q[j * dim + d] = t[d] * drift[j * dim + d];
     }
-    for (long j = 0; j < P->N; ++j) P->wl[j] = w * (l ? l[j] : 1.0);
+    if (disc == 2 && l) {
+        P->bn = (double *)malloc(sizeof(double) * (size_t)P->N);
+        if (!P->bn) return -2;
+        for (long j = 0; j < P->N; ++j) {
+            P->bn[j] = exp(-h * l[j]);
+            P->wl[j] = -expm1(-h * l[j]);
+        }
+    } else {
+        for (long j = 0; j < P->N; ++j) P->wl[j] = w * (l ? l[j] : 1.0);
+    }
     P->c = c;
     P->c_axes = c_axes ? 1 : 0;
     P->beta = beta;
@@ -135,6 +151,7 @@ static void prob_free(orc_prob *P)
     free(P->e);
     free(P->q);
     free(P->wl);
+    free(P->bn);
 }
 
 static inline void node_index(const orc_prob *P, long j, long *ij)
@@ -232,7 +249,7 @@ static double apply_node(const orc_prob *P, long j, const double *V, int *arg)
             foot_fractions(P, j, ij, k, tau);
             for (int s = 0; s < K; ++s) val[s] = cidx[s] >= 0 ? V[cidx[s]] : P->G;
             double r = interp_q1(P->dim, tau, val);
-            double cand = fma(P->beta, r, P->wl[j]);
+            double cand = fma(P->bn ? P->bn[j] : P->beta, r, P->wl[j]);
             if (ik < 0 || cand < inner) {
                 inner = cand;
                 ik = k;
@@ -395,6 +412,7 @@ long orc_adjoint(int dim, const int *n, const double *lo, const double *hi, doub
                  double *dLdl, double tol, long max_iters, double *residual)
 {
     orc_prob P;
+    if (disc == 2) return -1;        /* the discount depends on l: not a linear adjoint in w l */
     int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, NULL, drift, lam, disc, 0.0,
                        fixed, dom);
     if (rc) { prob_free(&P); return rc; }
@@ -447,6 +465,7 @@ long orc_tangent(int dim, const int *n, const double *lo, const double *hi, doub
                  double tol, long max_iters, double *residual)
 {
     orc_prob P;
+    if (disc == 2) return -1;
     int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, dl, drift, lam, disc, 0.0,
                        fixed, dom);
     if (rc) { prob_free(&P); return rc; }

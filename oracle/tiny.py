@@ -29,11 +29,25 @@ import numpy as np
 
 
 def _consts(lam: float, h: float, disc: str) -> Tuple[Fr, Fr]:
+    if disc == "kruzkov":
+        raise ValueError("the Kruzkov form has a per-node discount: use _node_consts")
     if disc == "exp":
         beta = Fr(math.exp(-lam * h))
         return beta, (1 - beta) / Fr(lam)
     beta = 1 / (1 + Fr(lam) * Fr(h))
     return beta, Fr(h)
+
+
+def _node_consts(prob):
+    """Per free node (discount, cost term): the problem's constants times l_j, or for
+    the Kruzkov form beta_j = exp(-h l_j) and 1 - beta_j, from the same binary64
+    exponentials the scheme uses (math.exp, math.expm1)."""
+    lv = [1.0] * prob.N if prob.cost is None else [float(x) for x in prob.cost]
+    if prob.disc == "kruzkov":
+        h = float(prob.step)
+        return [(Fr(math.exp(-h * l)), Fr(-math.expm1(-h * l))) for l in lv]
+    beta, w = _consts(prob.lam, prob.step, prob.disc)
+    return [(beta, w * Fr(l)) for l in lv]
 
 
 def _floor(x: Fr) -> int:
@@ -126,11 +140,10 @@ def policy_iteration(prob, max_iter: int = 100, st=None, rows=None):
     ``rows`` is None).
 
     Returns (V as a list of Fractions over all nodes, policy array, iterations)."""
-    beta, w = _consts(prob.lam, prob.step, prob.disc)
+    bw = _node_consts(prob)
     G = Fr(float(prob.v_ghost))
     tgt = np.asarray(prob.target)
     gv = [Fr(0)] * prob.N if prob.g is None else [Fr(float(x)) for x in prob.g]
-    lv = [Fr(1)] * prob.N if prob.cost is None else [Fr(float(x)) for x in prob.cost]
     if st is None:
         st = exact_stencils(prob)
     free = sorted(st)
@@ -148,8 +161,9 @@ def policy_iteration(prob, max_iter: int = 100, st=None, rows=None):
         b = [Fr(0)] * nf
         for j in free:
             r = pos[j]
+            beta, wl = bw[j]
             A[r][r] += 1
-            b[r] += w * lv[j]
+            b[r] += wl
             for idx, wt in st[j][pol[j]]:
                 if idx < 0:
                     b[r] += beta * wt * G
@@ -168,7 +182,7 @@ def policy_iteration(prob, max_iter: int = 100, st=None, rows=None):
             acc = Fr(0)
             for idx, wt in st[j][k]:
                 acc += wt * (G if idx < 0 else V[idx])
-            return beta * acc + w * lv[j]
+            return bw[j][0] * acc + bw[j][1]
 
         changed = False
         for j in free:

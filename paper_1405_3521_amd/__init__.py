@@ -28,7 +28,7 @@ _LIB_PATH = os.path.join(_HERE, "_lib", "libslhjb.so")
 _LIB = None
 
 SL_OK, SL_NOT_CONVERGED = 0, 1
-DISC = {"exp": 0, "paper": 1}
+DISC = {"exp": 0, "paper": 1, "kruzkov": 2}
 
 
 class SlError(RuntimeError):

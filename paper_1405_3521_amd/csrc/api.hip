@@ -81,7 +81,8 @@ int validate(const sl_problem *p) {
     if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return SL_ERR_INVALID_ARG;
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return SL_ERR_INVALID_ARG;
     if (!std::isfinite(p->v_ghost)) return SL_ERR_INVALID_ARG;
-    if (p->disc != SL_DISC_EXP && p->disc != SL_DISC_PAPER) return SL_ERR_INVALID_ARG;
+    if (p->disc != SL_DISC_EXP && p->disc != SL_DISC_PAPER && p->disc != SL_DISC_KRUZKOV)
+        return SL_ERR_INVALID_ARG;
     if (p->dtype != SL_F32 && p->dtype != SL_F64) return SL_ERR_INVALID_ARG;
     return SL_OK;
 }
@@ -122,10 +123,35 @@ void scheme_constants(double lam, double h, int disc, double *beta, double *w) {
     if (disc == SL_DISC_EXP) {
         *beta = std::exp(-lam * h);
         *w = -std::expm1(-lam * h) / lam;
+    } else if (disc == SL_DISC_KRUZKOV) {     // the per-node form with l = 1
+        *beta = std::exp(-h);
+        *w = -std::expm1(-h);
     } else {
         *beta = 1.0 / (1.0 + lam * h);
         *w = h;
     }
+}
+
+// Per-node discount and cost term of the Kruzkov form, beta_j = exp(-h l_j) and
+// 1 - beta_j = -expm1(-h l_j), evaluated on the host in binary64 (the problem
+// statement's transcendentals; the running cost crosses to the host once).
+// wl may alias l.
+bool uses_node_discount(const sl_problem *p) { return p->disc == SL_DISC_KRUZKOV && p->cost; }
+
+template <typename T>
+int kruzkov_fields(const T *l, size_t n, double h, T *beta, T *wl, hipStream_t s) {
+    std::vector<T> hl(n), hb(n), hw(n);
+    HIPCHK(hipMemcpyAsync(hl.data(), l, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t j = 0; j < n; ++j) {
+        const double x = -h * (double)hl[j];
+        hb[j] = (T)std::exp(x);
+        hw[j] = (T)(-std::expm1(x));
+    }
+    HIPCHK(hipMemcpyAsync(beta, hb.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(wl, hw.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SL_OK;
 }
 
 // Displacements in cells per unit speed, row l*m + k: e_d = (h/dx_d) * (a_kd - b_ld)
@@ -685,13 +711,15 @@ int check_fields(const FieldStats &fs) {
 // ------------------------------------------------------------ global solve
 template <typename T>
 int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **ctrl,
-                FieldStats **fs, int variant, T **q = nullptr) {
+                FieldStats **fs, int variant, T **q = nullptr, T **bn = nullptr) {
     const size_t N = nodes_of(p);
     (void)variant;
     const int tiles = max_tiles(p->dim, p->dtype, p->n);
     Vb[0] = a.take<T>(N);
     Vb[1] = a.take<T>(N);
     *wl = p->cost ? a.take<T>(N) : nullptr;
+    T *bb = uses_node_discount(p) ? a.take<T>(N) : nullptr;
+    if (bn) *bn = bb;
     T *qq = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
     if (q) *q = qq;
     *ctrl = a.take<T>((size_t)table_rows(p) * p->dim);
@@ -709,9 +737,9 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     const int variant = default_variant(p->dim, p->dtype);
     Arena a{(char *)ws, ws_bytes};
     Exec<T> ex;
-    T *Vb[2], *wl, *ctrl, *q = nullptr;
+    T *Vb[2], *wl, *ctrl, *q = nullptr, *bn = nullptr;
     FieldStats *fs_dev;
-    plan_global<T>(p, a, ex, Vb, &wl, &ctrl, &fs_dev, variant, &q);
+    plan_global<T>(p, a, ex, Vb, &wl, &ctrl, &fs_dev, variant, &q, &bn);
     if (!a.fits()) return SL_ERR_WORKSPACE;
 
     FieldStats fs{};
@@ -738,7 +766,11 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
-    if (p->cost) HIPCHK((launch_scale_field<T, T>((const T *)p->cost, wl, N, w, s)));
+    if (uses_node_discount(p)) {
+        if ((rc = kruzkov_fields<T>((const T *)p->cost, N, p->h, bn, wl, s))) return rc;
+    } else if (p->cost) {
+        HIPCHK((launch_scale_field<T, T>((const T *)p->cost, wl, N, w, s)));
+    }
     auto reinit = [&](hipStream_t q) -> hipError_t {
         for (int b = 0; b < 2; ++b) {
             const hipError_t e = launch_init_values<T>(Vb[b], p->target, (const T *)p->g,
@@ -752,6 +784,7 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     d.V[1] = Vb[1];
     d.speed = (const T *)p->speed;
     d.wl = wl;
+    d.beta_n = bn;
     d.drift = q;
     d.target = p->target;
     d.member = nullptr;
@@ -823,6 +856,7 @@ struct IsaPlan {
     // coarse
     double *cK = nullptr, *wlK = nullptr, *gK = nullptr, *ctrlK = nullptr, *gK_src = nullptr;
     double *qK = nullptr;          // coarse drift in index units (NK * dim)
+    double *betaK = nullptr;       // coarse per-node discount (Kruzkov form)
     T *gK_t = nullptr;
     int8_t *tK = nullptr;
     double *Vaux = nullptr;        // n_comp * 2 * NK
@@ -834,6 +868,7 @@ struct IsaPlan {
     T *Vf = nullptr;               // n_comp * 2 * N
     T *wl = nullptr, *ctrl = nullptr;
     T *q = nullptr;                // fine drift in index units (N * dim)
+    T *bn = nullptr;               // fine per-node discount (Kruzkov form)
     FieldStats *fs = nullptr;
     unsigned long long *counts = nullptr;
     Exec<T> ex;
@@ -849,6 +884,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     P.cK = a.take<double>(cg.NK * (size_t)speed_comps(p));
     P.wlK = a.take<double>(cg.NK);
     P.qK = p->drift ? a.take<double>(cg.NK * (size_t)p->dim) : nullptr;
+    P.betaK = uses_node_discount(p) ? a.take<double>(cg.NK) : nullptr;
     P.gK = a.take<double>(cg.NK);
     P.ctrlK = a.take<double>((size_t)table_rows(p) * p->dim);
     P.tK = a.take<int8_t>(cg.NK);
@@ -862,6 +898,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     P.Vf = a.take<T>((size_t)nc * 2 * N);
     P.wl = p->cost ? a.take<T>(N) : nullptr;
     P.q = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
+    P.bn = uses_node_discount(p) ? a.take<T>(N) : nullptr;
     P.ctrl = a.take<T>((size_t)table_rows(p) * p->dim);
     P.fs = a.take<FieldStats>(1);
     P.counts = a.take<unsigned long long>(8);
@@ -896,8 +933,13 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     if (p->speed)
         HIPCHK(launch_sample_coarse<T>((const T *)p->speed, P.cK, p->n, cg.nK, p->dim,
                                        speed_comps(p), 1.0, s));
-    if (p->cost)
+    if (uses_node_discount(p)) {
+        // Q1 samples of l, then the Kruzkov discount and cost term at the coarse step
+        HIPCHK(launch_sample_coarse<T>((const T *)p->cost, P.wlK, p->n, cg.nK, p->dim, 1, 1.0, s));
+        if ((rc = kruzkov_fields<double>(P.wlK, cg.NK, cg.hK, P.betaK, P.wlK, s))) return rc;
+    } else if (p->cost) {
         HIPCHK(launch_sample_coarse<T>((const T *)p->cost, P.wlK, p->n, cg.nK, p->dim, 1, wK, s));
+    }
     if (p->g) HIPCHK(launch_gather_nearest<T>((const T *)p->g, P.gK_t, p->n, cg.nK, p->dim, s));
     if (p->drift) {
         // Q1 samples of the drift, then index units of the coarse step
@@ -951,6 +993,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
         d.V[1] = V0 + cg.NK;
         d.speed = p->speed ? P.cK : nullptr;
         d.wl = p->cost ? P.wlK : nullptr;
+        d.beta_n = P.betaK;
         d.drift = P.qK;
         d.target = P.tK;
         d.member = nullptr;
@@ -1040,7 +1083,11 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(P.ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
-    if (p->cost) HIPCHK((launch_scale_field<T, T>((const T *)p->cost, P.wl, N, w, s)));
+    if (uses_node_discount(p)) {
+        if ((rc = kruzkov_fields<T>((const T *)p->cost, N, p->h, P.bn, P.wl, s))) return rc;
+    } else if (p->cost) {
+        HIPCHK((launch_scale_field<T, T>((const T *)p->cost, P.wl, N, w, s)));
+    }
     auto reinit = [&](hipStream_t q) -> hipError_t {
         for (int i = 0; i < nc; ++i)
             for (int b = 0; b < 2; ++b) {
@@ -1058,6 +1105,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
         d.V[1] = V0 + N;
         d.speed = (const T *)p->speed;
         d.wl = P.wl;
+        d.beta_n = P.bn;
         d.drift = P.q;
         d.target = p->target;
         d.member = member;
@@ -1569,7 +1617,8 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
-        if (probs[q].drift || is_game(&probs[q]) || probs[q].speed_axes)
+        if (probs[q].drift || is_game(&probs[q]) || probs[q].speed_axes ||
+            probs[q].disc == SL_DISC_KRUZKOV)
             return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
@@ -1841,7 +1890,8 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
-    if (p->drift || is_game(p) || p->speed_axes) return SL_ERR_UNSUPPORTED;
+    if (p->drift || is_game(p) || p->speed_axes || p->disc == SL_DISC_KRUZKOV)
+        return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

@@ -30,6 +30,7 @@ struct SdDesc {
     T *V[2];                    // Jacobi double buffer
     const T *speed;             // per-node speed c(x) or nullptr (= 1)
     const T *wl;                // per-node w*l(x) or nullptr (= wl_const)
+    const T *beta_n;            // per-node discount (Kruzkov form) or nullptr (= beta)
     const T *drift;             // per-node (h/dx)*drift, dim values per node, or nullptr
     const int8_t *target;       // per-node target id (>= 0: fixed node)
     const uint8_t *member;      // per-node set bitmask or nullptr (whole box)

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         __syncthreads();
 
         const int gx = x0 + tx;
-        T cx[NPT], cy[NPT], ux0[NPT], uy0[NPT], qx[NPT], qy[NPT], wl[NPT], best[NPT];
+        T cx[NPT], cy[NPT], ux0[NPT], uy0[NPT], qx[NPT], qy[NPT], wl[NPT], bt[NPT], best[NPT];
         int arg[NPT];
         bool act[NPT];
         int any = 0;
@@ -117,6 +117,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
             cx[r] = T(0);                       // inactive lanes: foot = own node
             cy[r] = T(0);
             wl[r] = d.wl_const;
+            bt[r] = d.beta;
             T qxv = T(0), qyv = T(0);           // drift in index units
             if (gx < n0 && gy < n1) {
                 const size_t j = (size_t)gy * n0 + gx;
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                         cx[r] = cy[r] = d.speed[j];
                     }
                     if (d.wl) wl[r] = d.wl[j];
+                    if (d.beta_n) bt[r] = d.beta_n[j];
                     if (d.drift) {
                         qxv = d.drift[2 * j];
                         qyv = d.drift[2 * j + 1];
@@ -152,7 +154,6 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
             qy[r] = sizeof(T) == 4 ? T(0) : qyv;
         }
         const int ox = x0 - H, oy = y0 - H;     // tile-local origin (FP64 path)
-        const T beta = d.beta;
         const const_ptr<T> ctrl = as_const(d.ctrl);     // scalar loads
         const int m = d.m;
         const int ma = d.m_inner > 0 ? d.m_inner : m;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                     const T a = fma_(fx, v10, ax * v00);
                     const T b = fma_(fx, v11, ax * v01);
                     const T acc = fma_(fy, b, ay * a);
-                    const T cand = fma_(beta, acc, wl[r]);
+                    const T cand = fma_(bt[r], acc, wl[r]);
                     if (POLICY) {
                         if (cand < inner[r]) {
                             inner[r] = cand;
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
 
         const int gx = x0 + tx, gy = y0 + ty;
         T cx[NPT], cy[NPT], cz[NPT], ux0[NPT], uy0[NPT], uz0[NPT], qx[NPT], qy[NPT], qz[NPT];
-        T wl[NPT], best[NPT];
+        T wl[NPT], bt[NPT], best[NPT];
         int arg[NPT];
         bool act[NPT];
         int any = 0;
@@ -396,6 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
             act[r] = false;
             cx[r] = cy[r] = cz[r] = T(0);       // inactive lanes: foot = own node
             wl[r] = d.wl_const;
+            bt[r] = d.beta;
             T qxv = T(0), qyv = T(0), qzv = T(0);
             if (gx < n0 && gy < n1 && gz < n2) {
                 const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
@@ -412,6 +414,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                         cx[r] = cy[r] = cz[r] = d.speed[j];
                     }
                     if (d.wl) wl[r] = d.wl[j];
+                    if (d.beta_n) bt[r] = d.beta_n[j];
                     if (d.drift) {
                         qxv = d.drift[3 * j];
                         qyv = d.drift[3 * j + 1];
@@ -434,7 +437,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
             qz[r] = sizeof(T) == 4 ? T(0) : qzv;
         }
         const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
-        const T beta = d.beta;
         const const_ptr<T> ctrl = as_const(d.ctrl);     // scalar loads
         const int m = d.m;
         const int ma = d.m_inner > 0 ? d.m_inner : m;
@@ -490,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     const T c0 = fma_(fy, b0, ay * a0);
                     const T c1 = fma_(fy, b1, ay * a1);
                     const T acc = fma_(fz, c1, az * c0);
-                    const T cand = fma_(beta, acc, wl[r]);
+                    const T cand = fma_(bt[r], acc, wl[r]);
                     if (POLICY) {
                         if (cand < inner[r]) {
                             inner[r] = cand;

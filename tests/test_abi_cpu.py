@@ -216,3 +216,20 @@ def test_refine_split_argument_checks():
                              C.byref(st), None) == -1
     assert L.sl_refine_split(C.byref(p), C.byref(ra), 4, 0.0, buf, 64, buf, C.byref(nc), None,
                              C.byref(st), None) == -5                        # workspace too small
+
+
+def test_kruzkov_form_accepted_by_solves_rejected_by_batch_and_adjoint():
+    L = S.lib()
+    p, keep = _problem(disc=2, cost=C.c_void_p(0x4000))
+    q, keep2 = _problem(cost=C.c_void_p(0x4000))
+    # one more per-node field (the discount)
+    assert L.sl_solve_workspace_size(C.byref(p)) > L.sl_solve_workspace_size(C.byref(q))
+    bad, keep3 = _problem(disc=3)
+    assert L.sl_solve_workspace_size(C.byref(bad)) == 0
+    ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
+    assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) == 0
+    buf = C.create_string_buffer(64)
+    st = S.SlStats()
+    assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
+                        C.byref(st), None) == -3

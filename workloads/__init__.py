@@ -35,7 +35,7 @@ __all__ = [
     "coarse_nodes_for",
     "c1_eikonal", "c2_multitarget", "c3_aniso3d", "c4_batch", "c5_adjoint",
     "strip_problem", "box_distance_problem", "vdp_problem", "obs_nodes",
-    "circle_controls", "pursuit_evasion_problem", "strip_game_problem",
+    "circle_controls", "pursuit_evasion_problem", "strip_game_problem", "kruzkov_problem",
 ]
 
 
@@ -450,3 +450,21 @@ def strip_game_problem(n: int, evader=(-0.5, 0.5), thick: int = 4, n_y: int = 5)
     return Problem(name=f"strip_game_{n}", dim=2, n=nn, lo=lo, hi=hi, velocity=vel,
                    velocity_b=vb, target=tid, n_comp=1, h=2.0 * dx, v_ghost=4.0)
 
+
+
+def kruzkov_problem(n: int = 513, m: int = 32, n_disks: int = 4, r: float = 0.05,
+                    sigma: float = 0.1, seed_field: int = 106, seed_disks: int = 206) -> Problem:
+    """Weighted minimum time in its Kruzkov form (``disc = "kruzkov"``): unit speed,
+    running cost l = exp(0.5 g) (a slowness field; g a smoothed unit-variance
+    Gaussian field), ``n_disks`` capture disks of radius r, v = 1 - exp(-J) with J
+    the l-weighted travel time; v_ghost = 2 keeps the initial values a
+    supersolution in floating point."""
+    dx = 2.0 / (n - 1)
+    g = gaussian_field((n, n), sigma / dx, seed_field)
+    l = f32(np.exp(0.5 * g)).reshape(-1)
+    cen = separated_centres(n_disks, 2, 0.3, seed_disks)
+    tid = ball_targets((n, n), (-1.0, -1.0), (1.0, 1.0), cen, r)
+    return Problem(name=f"kruzkov_{n}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
+                   velocity=controls_2d(m), target=tid, n_comp=n_disks, cost=l, v_ghost=2.0,
+                   disc="kruzkov", coarse_stride=coarse_stride(n, dx, r), ra_C=1.0, ra_M=1.0,
+                   ra_q=1.0, meta={"centres": cen, "r": r})
