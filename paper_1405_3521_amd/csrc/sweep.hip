@@ -457,6 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
             T inner[NPT];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) inner[r] = (T)INFINITY;
+#pragma unroll 2
             for (int k = kb; k < kb + ma; ++k) {
                 const T ex = ctrl[3 * k], ey = ctrl[3 * k + 1], ez = ctrl[3 * k + 2];
 #pragma unroll
@@ -483,8 +484,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
                     const T v000 = lds[base], v100 = lds[base + 1];
                     const T v010 = lds[base + LW], v110 = lds[base + LW + 1];
-                    const T v001 = lds[base + PL], v101 = lds[base + PL + 1];
-                    const T v011 = lds[base + PL + LW], v111 = lds[base + PL + LW + 1];
+                    const T *__restrict__ up = lds + base + PL;   // the z + 1 plane
+                    const T v001 = up[0], v101 = up[1];
+                    const T v011 = up[LW], v111 = up[LW + 1];
                     const T a0 = fma_(fx, v100, ax * v000);
                     const T b0 = fma_(fx, v110, ax * v010);
                     const T a1 = fma_(fx, v101, ax * v001);
