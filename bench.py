@@ -46,8 +46,11 @@ OPS_PER_NC_3D = 28
 # to the one whose HBM counters are stored in profiles/.
 DEFAULT_SWEEP_CONFIG = 22
 DEFAULT_LOCAL_ITERS = 8
-# The other workloads' fine sweeps: 4 local iterations (measured on each)
-LEG_LOCAL_ITERS = 4
+# The other workloads' fine sweeps: local iterations per tile and launch, the
+# faster of 4 and 8 measured on each (3D and the 288-candidate game do more work
+# per evaluation, so their tiles settle in fewer iterations per launch)
+LEG_LOCAL_ITERS = {"c3": 4, "pe": 4}
+LEG_LOCAL_ITERS_DEFAULT = 8
 # Coarse FP64 pass: local iterations per tile and launch (measured per workload at
 # tol 0: 8 for the 2D workloads with 32-64 controls, 4 for 3D and for the long-
 # characteristic or many-control 2D ones)
@@ -507,7 +510,8 @@ def main():
         fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
               "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov}[leg]
         t0 = time.perf_counter()
-        legs[leg] = fn(max(1, min(args.steps, 3)), LEG_LOCAL_ITERS)
+        legs[leg] = fn(max(1, min(args.steps, 3)),
+                       LEG_LOCAL_ITERS.get(leg, LEG_LOCAL_ITERS_DEFAULT))
         print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if legs:
         res["legs"] = legs

@@ -163,7 +163,7 @@ def test_full_size_pursuit_evasion_benchmark_configuration():
     say("case: full-size pursuit-evasion 513")
     dp = S.to_device(p, torch.float32)
     ra = ra_of(p)
-    ra.autotune = 1
+    ra.autotune, ra.local_iters = 1, 4
     member, label, _ = S.reconstruct(dp, ra)
     rec = I.reconstruct(p)
     assert np.array_equal(host(member), rec.member)
