@@ -103,8 +103,9 @@ typedef struct sl_problem {
                                  the pair is (h/dx_d)(a_kd - b_ld), the difference taken
                                  first, in FP64.  sl_solve, sl_reconstruct and sl_solve_isa
                                  take games (without a policy: want_policy with a policy
-                                 buffer returns SL_ERR_UNSUPPORTED); sl_solve_batched and
-                                 sl_adjoint return SL_ERR_UNSUPPORTED.  The sub-domain
+                                 buffer returns SL_ERR_UNSUPPORTED), and so does
+                                 sl_solve_batched; sl_adjoint returns
+                                 SL_ERR_UNSUPPORTED.  The sub-domain
                                  method needs the decomposability condition of Sec. 2
                                  (the paper shows it for its pursuit-evasion example); the
                                  library does not check it.                             */

@@ -1397,7 +1397,7 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
         d.sd_coarse0 = nsd;
         d.sd_fine0 = nsd;
         nsd += p->n_comp;
-        ctrl_len += (size_t)p->m * dim;
+        ctrl_len += (size_t)table_rows(p) * dim;
         B.hblk_N[q + 1] = B.hblk_N[q] + blocks_for(d.N);
         B.hblk_NK[q + 1] = B.hblk_NK[q] + blocks_for(d.NK);
         B.hblk_aux[q + 1] = B.hblk_aux[q] + blocks_for((size_t)p->n_comp * d.NK);
@@ -1517,14 +1517,14 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.beta = betaK;
             sd.G = p->v_ghost;
             for (int k = 0; k < 3; ++k) sd.n[k] = d.nK[k];
-            sd.m = p->m;
+            sd.m = table_rows(p);
             sd.m_inner = p->m;
             sd.bit = i;
             Exec<double>::tiles_of(B.exK.cfg, d.nK, dim, sd.tiles);
             sd.halo = HKq[q];
             B.exK.host_sds.push_back(sd);
         }
-        coff += (size_t)p->m * dim;
+        coff += (size_t)table_rows(p) * dim;
     }
     int rc = SL_OK;
     long SK = 0;
@@ -1560,14 +1560,14 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.beta = (T)beta;
             sd.G = (T)p->v_ghost;
             for (int k = 0; k < 3; ++k) sd.n[k] = d.n[k];
-            sd.m = p->m;
+            sd.m = table_rows(p);
             sd.m_inner = p->m;
             sd.bit = i;
             Exec<T>::tiles_of(B.ex.cfg, d.n, dim, sd.tiles);
             sd.halo = Hq[q];
             B.ex.host_sds.push_back(sd);
         }
-        coff += (size_t)p->m * dim;
+        coff += (size_t)table_rows(p) * dim;
     }
     long S = 0;
     const int status = B.ex.solve_tuned(o->autotune, reinit, o->tol, o->max_sweeps,
@@ -1617,8 +1617,7 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
-        if (probs[q].drift || is_game(&probs[q]) || probs[q].speed_axes ||
-            probs[q].disc == SL_DISC_KRUZKOV)
+        if (probs[q].drift || probs[q].speed_axes || probs[q].disc == SL_DISC_KRUZKOV)
             return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;

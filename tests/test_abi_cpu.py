@@ -158,8 +158,8 @@ def test_drift_accepted_by_solves_and_rejected_by_batch_and_adjoint():
 def test_game_and_axis_speed_fields_are_validated():
     """Differential games (m_b evader choices) and per-axis speed factors: the
     workspace queries size a game's larger displacement table and reject malformed
-    fields; the batch and the adjoint, and a game with a policy output, report
-    SL_ERR_UNSUPPORTED before any device work."""
+    fields; the batch takes games but not per-axis speed; the adjoint, and a game
+    with a policy output, report SL_ERR_UNSUPPORTED before any device work."""
     L = S.lib()
     vb = 0.5 * np.stack([np.cos(np.arange(20)), np.sin(np.arange(20))], axis=1)
     vbp = vb.ctypes.data_as(C.POINTER(C.c_double))
@@ -184,8 +184,9 @@ def test_game_and_axis_speed_fields_are_validated():
     assert L.sl_solve_workspace_size(C.byref(axes)) > 0
     ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
     assert L.sl_isa_workspace_size(C.byref(game), C.byref(ra)) > 0
+    assert L.sl_batched_workspace_size(1, C.byref(game), C.byref(ra)) > 0     # games batch
+    assert L.sl_batched_workspace_size(1, C.byref(axes), C.byref(ra)) == 0
     for p in (game, axes):
-        assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) == 0
         buf = C.create_string_buffer(64)
         st = S.SlStats()
         assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,

@@ -175,3 +175,31 @@ def test_full_size_pursuit_evasion_benchmark_configuration():
     r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
     say("  fixed-point residuals", r, "launches", st["sweeps_max"])
     assert max(r) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batched_games_match_oracle(dtype):
+    """A batch of games of different sizes and splits (the pursuit-evasion controls
+    and cost with a scalar speed field, which the batch takes; per-axis factors it
+    does not), solved in one batched call: sets and labels bit-exact per problem,
+    FP64 values bit-exact, FP32 within 1e-5."""
+    probs = []
+    for k, (n, split, nK) in enumerate([(33, 1, 9), (49, 4, 13), (41, 4, 21), (57, 1, 15)]):
+        X = W.node_coords((n, n), (-1.0, -1.0), (1.0, 1.0))
+        probs.append(W.pursuit_evasion_problem(n, split=split, m_a=12, m_b=4)
+                     .with_(speed=W.f32(1.0 + 0.3 * X[:, 1] ** 2), coarse_n=(nK, nK),
+                            name=f"game_batch{k}"))
+    say("case: batched games", dtype, [p.n[0] for p in probs])
+    dps = [S.to_device(p, dtype) for p in probs]
+    Vs, mem, lab, own, per, tot = S.solve_batched(dps, [ra_of(p) for p in probs],
+                                                  S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    assert tot["converged"]
+    for p, V, m, l in zip(probs, Vs, mem, lab):
+        Vbar, owner, rec, _, _ = I.isa(p)
+        assert np.array_equal(host(m), rec.member), p.name
+        assert np.array_equal(host(l), rec.label), p.name
+        Vg = host(V).astype(np.float64)
+        if dtype == torch.float64:
+            assert np.array_equal(Vg, Vbar), p.name
+        else:
+            assert np.abs(Vg - Vbar).max() <= 1e-5, p.name
