@@ -150,7 +150,7 @@ class DeviceProblem:
     lam: float = 1.0
     h: float = 0.0
     v_ghost: float = 1.0
-    disc: str = "exp"
+    disc: str = "exp"               # "exp", "paper" or "kruzkov" (per-node exp(-h l); see slhjb.h)
     dtype: "object" = None          # torch.float32 / torch.float64
     velocity_b: Optional[np.ndarray] = None  # host (m_b, dim) float64: the evader's b_l (games)
     speed_axes: bool = False        # speed holds dim factors per node (node-major)

@@ -57,7 +57,7 @@ class Problem:
     lam: float = 1.0
     h: float = 0.0                       # 0 -> h = dx (first axis)
     v_ghost: float = 1.0
-    disc: str = "exp"                    # "exp": beta=e^{-lam h}; "paper": beta=1/(1+lam h)
+    disc: str = "exp"                    # "exp": beta=e^{-lam h}; "paper": beta=1/(1+lam h); "kruzkov": beta_j=e^{-h l_j}
     coarse_stride: int = 1
     coarse_n: Optional[tuple] = None     # coarse nodes per axis; None -> every coarse_stride-th node
     ra_C: float = 0.5                    # RA threshold 2 (C dx^q + M dx); these defaults
