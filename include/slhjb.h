@@ -84,8 +84,8 @@ typedef struct sl_problem {
                                  Control-affine dynamics (the Van der Pol example, Sec.
                                  4.1).  The foot is u_d = i_d + (e_kd c_j + q_jd) in index
                                  units, q_jd = (h/dx_d) drift_jd in FP64.  The halo covers
-                                 c|e| + |q|.  sl_solve, sl_reconstruct and sl_solve_isa take
-                                 it; sl_solve_batched and sl_adjoint return
+                                 c|e| + |q|.  sl_solve, sl_reconstruct, sl_solve_isa and
+                                 sl_solve_batched take it; sl_adjoint returns
                                  SL_ERR_UNSUPPORTED.                                   */
     const int8_t *target;     /* DEVICE, N: -1 free node, i in [0, n_comp) target of component i */
     const void *g;            /* DEVICE, N exit costs (read on target nodes) in `dtype`; NULL = 0 */
@@ -114,8 +114,7 @@ typedef struct sl_problem {
                                  1: speed holds dim factors per node (node-major, N*dim,
                                  each >= 0), S(x) = diag(c_1(x), .., c_d(x)); the coarse
                                  grid samples each factor by Q1.  Needs speed != NULL;
-                                 sl_solve_batched and sl_adjoint return
-                                 SL_ERR_UNSUPPORTED.                                   */
+                                 sl_adjoint returns SL_ERR_UNSUPPORTED.                */
 } sl_problem;
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */

@@ -1380,8 +1380,9 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
         d.N = nodes_of(p);
         d.NK = cg.NK;
         d.tK = a.take<int8_t>(cg.NK);
-        d.cK = p->speed ? a.take<double>(cg.NK) : nullptr;
+        d.cK = p->speed ? a.take<double>(cg.NK * (size_t)speed_comps(p)) : nullptr;
         d.wlK = p->cost ? a.take<double>(cg.NK) : nullptr;
+        d.qK = p->drift ? a.take<double>(cg.NK * (size_t)dim) : nullptr;
         d.gK = p->g ? a.take<double>(cg.NK) : nullptr;
         d.Vaux = a.take<double>((size_t)p->n_comp * 2 * cg.NK);
         d.memberK = a.take<uint8_t>(cg.NK);
@@ -1391,6 +1392,7 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
         d.owner = owner ? owner[q] : nullptr;
         d.Vf = a.take<T>((size_t)p->n_comp * 2 * d.N);
         d.wl = p->cost ? a.take<T>(d.N) : nullptr;
+        d.q = p->drift ? a.take<T>(d.N * (size_t)dim) : nullptr;
         int t[3];
         tilesK += max_tiles(dim, SL_F64, cg.nK) * p->n_comp;
         tiles += max_tiles(dim, p->dtype, p->n) * p->n_comp;
@@ -1438,7 +1440,11 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         ProbDesc<T> &d = B.hp[q];
         d.target = p->target;
         d.speed = (const T *)p->speed;
+        d.scomp = speed_comps(p);
         d.cost = (const T *)p->cost;
+        d.drift = (const T *)p->drift;
+        index_units(p, p->n, p->h, d.ut);
+        index_units(p, d.nK, coarse_geom(p, &ras[q]).hK, d.utK);
         d.g = (const T *)p->g;
         d.V = (T *)V[q];
         d.fs = B.fs + q;
@@ -1479,8 +1485,9 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         control_table(p, p->n, p->h, e, &emax);
         control_table(p, B.hp[q].nK, coarse_geom(p, &ras[q]).hK, eK, &emaxK);
         const double smax = p->speed ? bits_to_double(fs[q].speed_max) : 1.0;
-        Hq[q] = halo_for(smax, emax);
-        HKq[q] = halo_for(smax, emaxK);
+        const double hK = coarse_geom(p, &ras[q]).hK;
+        Hq[q] = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs[q]));
+        HKq[q] = halo_for(smax, emaxK, drift_reach(p, B.hp[q].nK, hK, fs[q]));
         H = std::max(H, Hq[q]);
         HK = std::max(HK, HKq[q]);
         for (double x : e) ctrl.push_back((T)x);
@@ -1510,6 +1517,8 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.V[0] = d.Vaux + (size_t)i * 2 * d.NK;
             sd.V[1] = sd.V[0] + d.NK;
             sd.speed = d.cK;
+            sd.speed_axes = d.scomp > 1;
+            sd.drift = d.qK;
             sd.wl = d.wlK;
             sd.target = d.tK;
             sd.ctrl = B.ctrlK + coff;
@@ -1552,6 +1561,8 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.V[0] = d.Vf + (size_t)i * 2 * d.N;
             sd.V[1] = sd.V[0] + d.N;
             sd.speed = (const T *)p->speed;
+            sd.speed_axes = d.scomp > 1;
+            sd.drift = d.q;
             sd.wl = d.wl;
             sd.target = p->target;
             sd.member = d.member;
@@ -1617,8 +1628,7 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
-        if (probs[q].drift || probs[q].speed_axes || probs[q].disc == SL_DISC_KRUZKOV)
-            return SL_ERR_UNSUPPORTED;
+        if (probs[q].disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
 }

@@ -43,19 +43,27 @@ __global__ __launch_bounds__(kB) void k_b_stats(const ProbDesc<T> *pd, const int
     const Seg sg = segment(blkp, np, chunk, 0);
     const ProbDesc<T> &d = pd[sg.p];
     const size_t end = sg.end < d.N ? sg.end : d.N;
-    double smax = 0.0, cmax = 0.0;
+    double smax = 0.0, cmax = 0.0, dmax = 0.0;
     int bad_s = 0, bad_c = 0, ntar = 0, bad_t = 0;
     int first[SL_MAX_COMP];
 #pragma unroll
     for (int c = 0; c < SL_MAX_COMP; ++c) first[c] = INT_MAX;
     for (size_t i = sg.begin + threadIdx.x; i < end; i += kB) {
         if (d.speed) {
-            const double v = (double)d.speed[i];
-            if (!(v >= 0.0) || !(v < INFINITY)) ++bad_s; else smax = v > smax ? v : smax;
+            for (int c = 0; c < d.scomp; ++c) {
+                const double v = (double)d.speed[i * d.scomp + c];
+                if (!(v >= 0.0) || !(v < INFINITY)) ++bad_s; else smax = v > smax ? v : smax;
+            }
         }
         if (d.cost) {
             const double v = (double)d.cost[i];
             if (!(v > 0.0) || !(v < INFINITY)) ++bad_c; else cmax = v > cmax ? v : cmax;
+        }
+        if (d.drift) {
+            for (int c = 0; c < d.dim; ++c) {
+                const double v = __builtin_fabs((double)d.drift[i * d.dim + c]);
+                if (!(v < INFINITY)) ++bad_s; else dmax = v > dmax ? v : dmax;
+            }
         }
         const int t = d.target[i];
         if (t >= 0) {
@@ -73,6 +81,7 @@ __global__ __launch_bounds__(kB) void k_b_stats(const ProbDesc<T> *pd, const int
     for (int off = 32; off >= 1; off >>= 1) {
         double o = __shfl_xor(smax, off, 64); smax = o > smax ? o : smax;
         o = __shfl_xor(cmax, off, 64); cmax = o > cmax ? o : cmax;
+        o = __shfl_xor(dmax, off, 64); dmax = o > dmax ? o : dmax;
         bad_s += __shfl_xor(bad_s, off, 64);
         bad_c += __shfl_xor(bad_c, off, 64);
         ntar += __shfl_xor(ntar, off, 64);
@@ -87,6 +96,7 @@ __global__ __launch_bounds__(kB) void k_b_stats(const ProbDesc<T> *pd, const int
         FieldStats *fs = d.fs;
         if (smax > 0.0) atomicMax(&fs->speed_max, (unsigned long long)__double_as_longlong(smax));
         if (cmax > 0.0) atomicMax(&fs->cost_max, (unsigned long long)__double_as_longlong(cmax));
+        if (dmax > 0.0) atomicMax(&fs->drift_max, (unsigned long long)__double_as_longlong(dmax));
         if (bad_s) atomicAdd(&fs->bad_speed, bad_s);
         if (bad_c) atomicAdd(&fs->bad_cost, bad_c);
         if (ntar) atomicAdd(&fs->n_target, ntar);
@@ -114,7 +124,13 @@ __global__ __launch_bounds__(kB) void k_b_coarse_prep(const ProbDesc<T> *pd, con
         const size_t j = ((size_t)ax[2].near * d.n[1] + ax[1].near) * d.n[0] + ax[0].near;
         const int t = d.target[j];
         d.tK[k] = (int8_t)t;
-        if (d.speed) d.cK[k] = 1.0 * sample_q1(d.speed, 1, 0, d.n[0], d.n[1], d.dim, ax);
+        if (d.speed)
+            for (int c = 0; c < d.scomp; ++c)
+                d.cK[k * d.scomp + c] = 1.0 * sample_q1(d.speed, d.scomp, c, d.n[0], d.n[1], d.dim, ax);
+        // drift: Q1 samples, then index units of the coarse step (FP64 products)
+        if (d.drift)
+            for (int c = 0; c < d.dim; ++c)
+                d.qK[k * d.dim + c] = d.utK[c] * (1.0 * sample_q1(d.drift, d.dim, c, d.n[0], d.n[1], d.dim, ax));
         if (d.cost) d.wlK[k] = d.wK * sample_q1(d.cost, 1, 0, d.n[0], d.n[1], d.dim, ax);
         if (d.g) d.gK[k] = (double)d.g[j];
         if (t >= 0 && t < d.n_comp) atomicMin(&d.fsK->first_node[t], (int)k);
@@ -237,6 +253,9 @@ __global__ __launch_bounds__(kB) void k_b_project_init(const ProbDesc<T> *pd, co
             V0[d.N + j] = v;
         }
         if (d.cost) d.wl[j] = (T)(d.w * (double)d.cost[j]);
+        if (d.drift)
+            for (int q = 0; q < dim; ++q)
+                d.q[j * dim + q] = (T)(d.ut[q] * (double)d.drift[j * dim + q]);
     }
 }
 

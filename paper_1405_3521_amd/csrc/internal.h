@@ -133,6 +133,12 @@ struct ProbDesc {
     T *V;                       // output
     FieldStats *fs, *fsK;
     int sd_coarse0, sd_fine0;
+    // control-affine dynamics and per-axis speed
+    const T *drift;             // N*dim drift or nullptr
+    int scomp;                  // values per node of speed (1, or dim per-axis factors)
+    double ut[3], utK[3];       // index units h/dx_d of the fine and the coarse grid
+    double *qK;                 // NK*dim coarse drift in index units
+    T *q;                       // N*dim fine drift in index units
 };
 
 enum BatchOp {

@@ -138,9 +138,9 @@ def test_binding_raises_without_library(monkeypatch, tmp_path):
         S.lib()
 
 
-def test_drift_accepted_by_solves_and_rejected_by_batch_and_adjoint():
+def test_drift_accepted_by_solves_and_batch_rejected_by_adjoint():
     """Control-affine dynamics with a drift: sl_solve / sl_reconstruct / sl_solve_isa
-    size a workspace for it; the batch and the adjoint report SL_ERR_UNSUPPORTED
+    and the batch size a workspace for it; the adjoint reports SL_ERR_UNSUPPORTED
     before any device work."""
     L = S.lib()
     p, keep = _problem(drift=C.c_void_p(0x2000))
@@ -148,7 +148,8 @@ def test_drift_accepted_by_solves_and_rejected_by_batch_and_adjoint():
     assert L.sl_solve_workspace_size(C.byref(p)) > L.sl_solve_workspace_size(C.byref(q))
     ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
-    assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) == 0
+    assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) > L.sl_batched_workspace_size(
+        1, C.byref(q), C.byref(ra))
     buf = C.create_string_buffer(64)
     st = S.SlStats()
     assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
@@ -158,8 +159,8 @@ def test_drift_accepted_by_solves_and_rejected_by_batch_and_adjoint():
 def test_game_and_axis_speed_fields_are_validated():
     """Differential games (m_b evader choices) and per-axis speed factors: the
     workspace queries size a game's larger displacement table and reject malformed
-    fields; the batch takes games but not per-axis speed; the adjoint, and a game
-    with a policy output, report SL_ERR_UNSUPPORTED before any device work."""
+    fields; the batch takes both; the adjoint, and a game with a policy output,
+    report SL_ERR_UNSUPPORTED before any device work."""
     L = S.lib()
     vb = 0.5 * np.stack([np.cos(np.arange(20)), np.sin(np.arange(20))], axis=1)
     vbp = vb.ctypes.data_as(C.POINTER(C.c_double))
@@ -185,7 +186,7 @@ def test_game_and_axis_speed_fields_are_validated():
     ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
     assert L.sl_isa_workspace_size(C.byref(game), C.byref(ra)) > 0
     assert L.sl_batched_workspace_size(1, C.byref(game), C.byref(ra)) > 0     # games batch
-    assert L.sl_batched_workspace_size(1, C.byref(axes), C.byref(ra)) == 0
+    assert L.sl_batched_workspace_size(1, C.byref(axes), C.byref(ra)) > 0     # and axis factors
     for p in (game, axes):
         buf = C.create_string_buffer(64)
         st = S.SlStats()

@@ -140,3 +140,26 @@ def test_full_size_vdp_benchmark_configuration():
     r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
     say("  fixed-point residuals", r, "launches", st["sweeps_max"])
     assert max(r) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batched_drift_matches_oracle(dtype):
+    """A batch of Van der Pol problems of different sizes and splits (drift) in one
+    batched call: sets and labels bit-exact per problem, FP64 values bit-exact,
+    FP32 within 1e-5."""
+    probs = [W.vdp_problem(n, split=s).with_(coarse_n=(nK, nK), name=f"vdp_batch{k}")
+             for k, (n, s, nK) in enumerate([(41, 4, 11), (57, 2, 15), (33, 1, 9), (65, 4, 17)])]
+    say("case: batched drift", dtype, [p.n[0] for p in probs])
+    dps = [S.to_device(p, dtype) for p in probs]
+    Vs, mem, lab, own, per, tot = S.solve_batched(dps, [ra_of(p) for p in probs],
+                                                  S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    assert tot["converged"]
+    for p, V, m, l in zip(probs, Vs, mem, lab):
+        Vbar, owner, rec, _, _ = I.isa(p)
+        assert np.array_equal(host(m), rec.member), p.name
+        assert np.array_equal(host(l), rec.label), p.name
+        Vg = host(V).astype(np.float64)
+        if dtype == torch.float64:
+            assert np.array_equal(Vg, Vbar), p.name
+        else:
+            assert np.abs(Vg - Vbar).max() <= 1e-5, p.name

@@ -203,3 +203,25 @@ def test_batched_games_match_oracle(dtype):
             assert np.array_equal(Vg, Vbar), p.name
         else:
             assert np.abs(Vg - Vbar).max() <= 1e-5, p.name
+
+
+def test_batched_games_with_axis_factors_match_oracle():
+    """Pursuit-evasion games with their per-axis speed factors (x2 + 1, 1), mixed
+    with a control problem, in one FP64 batch: bit-exact per problem."""
+    probs = [W.pursuit_evasion_problem(n, split=s, m_a=12, m_b=4).with_(coarse_n=(nK, nK),
+                                                                         name=f"pe_axes{k}")
+             for k, (n, s, nK) in enumerate([(33, 4, 9), (49, 1, 13)])]
+    X = W.node_coords((41, 41), (-1.0, -1.0), (1.0, 1.0))
+    ctrl = W.c2_multitarget(n=41, m=16)
+    probs.append(ctrl.with_(speed=W.f32(np.stack([np.asarray(ctrl.speed),
+                                                  1.0 + 0.1 * X[:, 0]], axis=1)),
+                            velocity_b=None, coarse_n=(11, 11), name="axes_control"))
+    dps = [S.to_device(p, torch.float64) for p in probs]
+    Vs, mem, lab, own, per, tot = S.solve_batched(dps, [ra_of(p) for p in probs],
+                                                  S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    assert tot["converged"]
+    for p, V, m, l in zip(probs, Vs, mem, lab):
+        Vbar, owner, rec, _, _ = I.isa(p)
+        assert np.array_equal(host(m), rec.member), p.name
+        assert np.array_equal(host(l), rec.label), p.name
+        assert np.array_equal(host(V), Vbar), p.name
