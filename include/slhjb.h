@@ -22,8 +22,8 @@
  *   beta_j = exp(-h l_j) and the cost term 1 - beta_j = -expm1(-h l_j), lambda
  *   unused; the exponentials are evaluated on the host in binary64 (the fields
  *   cross to the host once per call).  v_ghost should exceed 1 (e.g. 2) so that
- *   V = v_ghost is a supersolution in floating point.  sl_solve_batched and
- *   sl_adjoint return SL_ERR_UNSUPPORTED for it.
+ *   V = v_ghost is a supersolution in floating point.  sl_adjoint returns
+ *   SL_ERR_UNSUPPORTED for it.
  * Fixed point by value iteration from V = v_ghost (a supersolution), which the
  * paper notes is a contraction (Sec. 3).
  *

@@ -1353,6 +1353,10 @@ struct BatchPlan {
     Exec<double> exK;
     Exec<T> ex;
     int tot_sd = 0;
+    // Kruzkov form, per problem (nullptr otherwise): coarse discount, fine discount
+    // and fine cost term
+    std::vector<double *> betaK;
+    std::vector<T *> bn, wlk;
 };
 
 inline int blocks_for(size_t len) { return (int)((len + kChunk - 1) / kChunk); }
@@ -1365,6 +1369,9 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
     B.hblk_N.assign(np + 1, 0);
     B.hblk_NK.assign(np + 1, 0);
     B.hblk_aux.assign(np + 1, 0);
+    B.betaK.assign(np, nullptr);
+    B.bn.assign(np, nullptr);
+    B.wlk.assign(np, nullptr);
     int tilesK = 0, tiles = 0, nsd = 0;
     size_t ctrl_len = 0;
     for (int q = 0; q < np; ++q) {
@@ -1393,6 +1400,11 @@ int plan_batched(int np, const sl_problem *probs, const sl_ra_opts *ras, uint8_t
         d.Vf = a.take<T>((size_t)p->n_comp * 2 * d.N);
         d.wl = p->cost ? a.take<T>(d.N) : nullptr;
         d.q = p->drift ? a.take<T>(d.N * (size_t)dim) : nullptr;
+        if (uses_node_discount(p)) {
+            B.betaK[q] = a.take<double>(cg.NK);
+            B.bn[q] = a.take<T>(d.N);
+            B.wlk[q] = a.take<T>(d.N);
+        }
         int t[3];
         tilesK += max_tiles(dim, SL_F64, cg.nK) * p->n_comp;
         tiles += max_tiles(dim, p->dtype, p->n) * p->n_comp;
@@ -1454,7 +1466,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
         scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
         scheme_constants(p->lambda, coarse_geom(p, &ras[q]).hK, p->disc, &betaK, &wK);
         d.w = w;
-        d.wK = wK;
+        d.wK = uses_node_discount(p) ? 1.0 : wK;     // Kruzkov: wlK holds the samples of l
         double dxK = 0.0;
         for (int k = 0; k < dim; ++k)
             dxK = std::max(dxK, (p->hi[k] - p->lo[k]) / (double)(d.nK[k] - 1));
@@ -1499,6 +1511,16 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     // 2. coarse data, placement of missing components, auxiliary initial values
     HIPCHK(launch_batched<T>(kBatchCoarsePrep, B.pd, np, B.blk_NK, B.hblk_NK[np], kChunk, nullptr, nullptr, s));
     HIPCHK(launch_batched<T>(kBatchPlace, B.pd, np, nullptr, 1, kChunk, nullptr, nullptr, s));
+    // Kruzkov form: per-node discount and cost term on the host, coarse and fine
+    for (int q = 0; q < np; ++q) {
+        const sl_problem *p = &probs[q];
+        if (!uses_node_discount(p)) continue;
+        const ProbDesc<T> &d = B.hp[q];
+        int rk = kruzkov_fields<double>(d.wlK, d.NK, coarse_geom(p, &ras[q]).hK, B.betaK[q],
+                                        d.wlK, s);
+        if (!rk) rk = kruzkov_fields<T>((const T *)p->cost, d.N, p->h, B.bn[q], B.wlk[q], s);
+        if (rk) return rk;
+    }
     auto reinitK = [&](hipStream_t q) -> hipError_t {
         return launch_batched<T>(kBatchInitAux, B.pd, np, B.blk_aux, B.hblk_aux[np], kChunk,
                                  nullptr, nullptr, q);
@@ -1520,6 +1542,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.speed_axes = d.scomp > 1;
             sd.drift = d.qK;
             sd.wl = d.wlK;
+            sd.beta_n = B.betaK[q];
             sd.target = d.tK;
             sd.ctrl = B.ctrlK + coff;
             sd.wl_const = wK;
@@ -1563,7 +1586,8 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
             sd.speed = (const T *)p->speed;
             sd.speed_axes = d.scomp > 1;
             sd.drift = d.q;
-            sd.wl = d.wl;
+            sd.wl = B.wlk[q] ? B.wlk[q] : d.wl;
+            sd.beta_n = B.bn[q];
             sd.target = p->target;
             sd.member = d.member;
             sd.ctrl = B.ctrl + coff;
@@ -1628,7 +1652,6 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
-        if (probs[q].disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
 }

@@ -98,3 +98,28 @@ def test_full_size_kruzkov_benchmark_configuration():
     r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
     say("  fixed-point residuals", r, "launches", st["sweeps_max"])
     assert max(r) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batched_kruzkov_matches_oracle(dtype):
+    """A batch mixing Kruzkov problems of different sizes with a discounted control
+    problem: sets and labels bit-exact per problem, FP64 values bit-exact, FP32
+    within 1e-5."""
+    probs = [W.kruzkov_problem(n=n, m=16, n_disks=k).with_(coarse_n=(nK, nK),
+                                                           name=f"kruzkov_batch{n}")
+             for n, k, nK in ((49, 2, 17), (65, 4, 21), (33, 1, 11))]
+    probs.append(W.c2_multitarget(n=41, m=16).with_(coarse_n=(11, 11), name="discounted"))
+    say("case: batched kruzkov", dtype)
+    dps = [S.to_device(p, dtype) for p in probs]
+    Vs, mem, lab, own, per, tot = S.solve_batched(dps, [ra_of(p) for p in probs],
+                                                  S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    assert tot["converged"]
+    for p, V, m, l in zip(probs, Vs, mem, lab):
+        Vbar, owner, rec, _, _ = I.isa(p)
+        assert np.array_equal(host(m), rec.member), p.name
+        assert np.array_equal(host(l), rec.label), p.name
+        Vg = host(V).astype(np.float64)
+        if dtype == torch.float64:
+            assert np.array_equal(Vg, Vbar), p.name
+        else:
+            assert np.abs(Vg - Vbar).max() <= 1e-5, p.name
