@@ -84,9 +84,7 @@ typedef struct sl_problem {
                                  Control-affine dynamics (the Van der Pol example, Sec.
                                  4.1).  The foot is u_d = i_d + (e_kd c_j + q_jd) in index
                                  units, q_jd = (h/dx_d) drift_jd in FP64.  The halo covers
-                                 c|e| + |q|.  sl_solve, sl_reconstruct, sl_solve_isa and
-                                 sl_solve_batched take it; sl_adjoint returns
-                                 SL_ERR_UNSUPPORTED.                                   */
+                                 c|e| + |q|.  Every entry point takes it.              */
     const int8_t *target;     /* DEVICE, N: -1 free node, i in [0, n_comp) target of component i */
     const void *g;            /* DEVICE, N exit costs (read on target nodes) in `dtype`; NULL = 0 */
     int n_comp;               /* number of target components, 1..SL_MAX_COMP          */
@@ -113,8 +111,8 @@ typedef struct sl_problem {
     int speed_axes;           /* 0: speed holds one c(x) per node, S(x) = c(x) I;
                                  1: speed holds dim factors per node (node-major, N*dim,
                                  each >= 0), S(x) = diag(c_1(x), .., c_d(x)); the coarse
-                                 grid samples each factor by Q1.  Needs speed != NULL;
-                                 sl_adjoint returns SL_ERR_UNSUPPORTED.                */
+                                 grid samples each factor by Q1.  Needs speed != NULL.
+                                 Every entry point takes it.                           */
 } sl_problem;
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */
@@ -299,6 +297,9 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
  * after sl_solve), owner (DEVICE, N uint8: dL/dV(j) goes to set owner[j] only;
  * NULL: to every set), policy (DEVICE, n_sets*N uint8 controls from the forward
  * call with want_policy), dLdV (DEVICE, N in p->dtype).
+ * The feet are those of the forward scheme: per-axis speed factors and drift
+ * (index units, e c + q) are taken; games and the Kruzkov discount (the
+ * discount then depends on l, so V is not linear in l) return SL_ERR_UNSUPPORTED.
  * local_iters (0..1024): 0 = the Jacobi iteration above.  k > 0 in 2D, when the
  * foot reaches at most 8 cells: block-asynchronous tiles.  Every active 32x16 tile
  * stages lambda, the frozen feet and the inflow from its halo in on-chip memory,

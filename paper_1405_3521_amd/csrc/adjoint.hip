@@ -56,7 +56,6 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjDesc<T> *__restri
         ++nact;
         const int k = d.policy[j];
         if (ln == T(0) || k >= d.m) continue;
-        const T c = d.speed ? d.speed[j] : T(1);
         int ij[3], p[3];
         T tau[3];
         ij[0] = (int)(j % n0);
@@ -64,7 +63,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjDesc<T> *__restri
         ij[2] = (int)(j / ((size_t)n0 * n1));
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const T disp = c * d.ctrl[DIM * k + a];
+            // foot offset e c + q in index units, the forward sweep's order
+            const T c = !d.speed ? T(1) : (d.speed_axes ? d.speed[DIM * j + a] : d.speed[j]);
+            const T q = d.drift ? d.drift[DIM * j + a] : T(0);
+            const T disp = d.ctrl[DIM * k + a] * c + q;
             const T f = __builtin_floor(disp);
             tau[a] = disp - f;
             p[a] = ij[a] + (int)f;
@@ -165,8 +167,16 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
                     lv = lam[j];
                     const int k = d.policy[j];
                     if (k < d.m) {
-                        const T c = d.speed ? d.speed[j] : T(1);
-                        const T dx = c * d.ctrl[2 * k], dy = c * d.ctrl[2 * k + 1];
+                        T cx = T(1), cy = T(1), qx = T(0), qy = T(0);
+                        if (d.speed) {
+                            cx = d.speed_axes ? d.speed[2 * j] : d.speed[j];
+                            cy = d.speed_axes ? d.speed[2 * j + 1] : cx;
+                        }
+                        if (d.drift) {
+                            qx = d.drift[2 * j];
+                            qy = d.drift[2 * j + 1];
+                        }
+                        const T dx = d.ctrl[2 * k] * cx + qx, dy = d.ctrl[2 * k + 1] * cy + qy;
                         const T flx = floor_(dx), fly = floor_(dy);
                         fx = dx - flx;
                         fy = dy - fly;

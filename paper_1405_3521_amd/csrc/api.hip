@@ -1161,7 +1161,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
 // ------------------------------------------------------------------- adjoint
 template <typename T>
 struct AdjPlan {
-    T *lam = nullptr, *acc = nullptr, *ctrl = nullptr;
+    T *lam = nullptr, *acc = nullptr, *ctrl = nullptr, *q = nullptr;
     AdjDesc<T> *ads = nullptr;
     SdState *st = nullptr;
     ExecCounters *cnt = nullptr;
@@ -1175,6 +1175,7 @@ void plan_adjoint(const sl_problem *p, int n_sets, Arena &a, AdjPlan<T> &P) {
     P.lam = a.take<T>((size_t)n_sets * N);
     P.acc = a.take<T>((size_t)n_sets * 2 * N);
     P.ctrl = a.take<T>((size_t)table_rows(p) * p->dim);
+    P.q = p->drift ? a.take<T>(N * (size_t)p->dim) : nullptr;
     P.ads = a.take<AdjDesc<T>>(n_sets);
     P.st = a.take<SdState>(n_sets);
     P.cnt = a.take<ExecCounters>(1);
@@ -1209,6 +1210,11 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     std::vector<T> et(e.size());
     for (size_t i = 0; i < e.size(); ++i) et[i] = (T)e[i];
     HIPCHK(hipMemcpyAsync(P.ctrl, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice, s));
+    if (p->drift) {
+        double t[3];
+        index_units(p, p->n, p->h, t);
+        HIPCHK(launch_scale_drift<T>((const T *)p->drift, P.q, N, p->dim, t, s));
+    }
     HIPCHK(hipMemsetAsync(P.lam, 0, sizeof(T) * (size_t)n_sets * N, s));
     HIPCHK(hipMemsetAsync(P.acc, 0, sizeof(T) * (size_t)n_sets * 2 * N, s));
     std::vector<AdjDesc<T>> hd(n_sets);
@@ -1221,6 +1227,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         d.owner = member ? owner : nullptr;
         d.policy = policy + (size_t)i * N;
         d.speed = (const T *)p->speed;
+        d.drift = P.q;
         d.target = p->target;
         d.member = member;
         d.ctrl = P.ctrl;
@@ -1229,6 +1236,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         d.m = p->m;
         d.bit = i;
         d.set = i;
+        d.speed_axes = speed_comps(p) > 1;
     }
     HIPCHK(hipMemcpyAsync(P.ads, hd.data(), sizeof(AdjDesc<T>) * n_sets, hipMemcpyHostToDevice, s));
     std::vector<SdState> hs(n_sets);
@@ -1246,7 +1254,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     int *active = pinned().active;
     if (!active) return SL_ERR_HIP;
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
-    const int H = halo_for(smax, emax);
+    const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
     if (p->dim == 2 && local_iters > 0 && H <= adjoint_tiles_max_halo()) {
         // block-asynchronous tiles on the sweep executor
         LaunchCfg cfg{};
@@ -1267,6 +1275,8 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
             SdDesc<T> sd{};
             sd.V[0] = sd.V[1] = hd[i].lam;
             sd.speed = (const T *)p->speed;
+            sd.speed_axes = hd[i].speed_axes;
+            sd.drift = P.q;
             sd.target = p->target;
             sd.member = member;
             sd.policy = const_cast<uint8_t *>(policy + (size_t)i * N);
@@ -1922,8 +1932,7 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
-    if (p->drift || is_game(p) || p->speed_axes || p->disc == SL_DISC_KRUZKOV)
-        return SL_ERR_UNSUPPORTED;
+    if (is_game(p) || p->disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

@@ -103,7 +103,8 @@ struct AdjDesc {
     const T *g;                 // dL/dV per node
     const uint8_t *owner;       // set owning each node's value, or nullptr (all)
     const uint8_t *policy;      // frozen control index per node (>= m: none)
-    const T *speed;             // speed per node or nullptr (= 1)
+    const T *speed;             // speed per node (dim per node if speed_axes) or nullptr (= 1)
+    const T *drift;             // per-node drift in index units, dim per node, or nullptr
     const int8_t *target;       // target ids (>= 0: fixed, no adjoint)
     const uint8_t *member;      // set bitmask or nullptr
     const T *ctrl;              // m*dim control displacements
@@ -112,6 +113,7 @@ struct AdjDesc {
     int m;
     int bit;
     int set;
+    int speed_axes;             // speed holds one factor per axis
 };
 
 // One problem of a batch (device memory): its fine fields (caller's), its

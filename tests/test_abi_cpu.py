@@ -138,10 +138,11 @@ def test_binding_raises_without_library(monkeypatch, tmp_path):
         S.lib()
 
 
-def test_drift_accepted_by_solves_and_batch_rejected_by_adjoint():
-    """Control-affine dynamics with a drift: sl_solve / sl_reconstruct / sl_solve_isa
-    and the batch size a workspace for it; the adjoint reports SL_ERR_UNSUPPORTED
-    before any device work."""
+def test_drift_accepted_by_every_entry_point():
+    """Control-affine dynamics with a drift: sl_solve / sl_reconstruct / sl_solve_isa,
+    the batch and the adjoint size a workspace with room for the scaled drift; the
+    adjoint passes its argument checks and stops at the workspace size (-5) before
+    any device work."""
     L = S.lib()
     p, keep = _problem(drift=C.c_void_p(0x2000))
     q, keep2 = _problem()
@@ -150,17 +151,20 @@ def test_drift_accepted_by_solves_and_batch_rejected_by_adjoint():
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
     assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) > L.sl_batched_workspace_size(
         1, C.byref(q), C.byref(ra))
+    assert L.sl_adjoint_workspace_size(C.byref(p), 1) > L.sl_adjoint_workspace_size(
+        C.byref(q), 1)
     buf = C.create_string_buffer(64)
     st = S.SlStats()
     assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
-                        C.byref(st), None) == -3
+                        C.byref(st), None) == -5
 
 
 def test_game_and_axis_speed_fields_are_validated():
     """Differential games (m_b evader choices) and per-axis speed factors: the
     workspace queries size a game's larger displacement table and reject malformed
-    fields; the batch takes both; the adjoint, and a game with a policy output,
-    report SL_ERR_UNSUPPORTED before any device work."""
+    fields; the batch takes both; the adjoint takes axis factors (and stops at the
+    workspace size, -5) but not games, which, like a game with a policy output,
+    report SL_ERR_UNSUPPORTED (-3) before any device work."""
     L = S.lib()
     vb = 0.5 * np.stack([np.cos(np.arange(20)), np.sin(np.arange(20))], axis=1)
     vbp = vb.ctypes.data_as(C.POINTER(C.c_double))
@@ -187,11 +191,11 @@ def test_game_and_axis_speed_fields_are_validated():
     assert L.sl_isa_workspace_size(C.byref(game), C.byref(ra)) > 0
     assert L.sl_batched_workspace_size(1, C.byref(game), C.byref(ra)) > 0     # games batch
     assert L.sl_batched_workspace_size(1, C.byref(axes), C.byref(ra)) > 0     # and axis factors
-    for p in (game, axes):
+    for p, rc in ((game, -3), (axes, -5)):
         buf = C.create_string_buffer(64)
         st = S.SlStats()
         assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
-                            C.byref(st), None) == -3
+                            C.byref(st), None) == rc
     buf = C.create_string_buffer(64)
     o = S.SlSolveOpts()
     o.tol, o.max_sweeps, o.want_policy = 0.0, 10, 1

@@ -168,3 +168,97 @@ def test_autograd_gradient_against_fd(mode, li):
         an = float(grad @ d)
         say(f"  {mode} local {li}: fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
         assert abs(fd - an) <= 1e-3 * abs(fd)
+
+
+VARIANTS = {"swirl": dict(swirl=0.5), "axes": dict(axis_speed=True)}
+
+
+@pytest.mark.parametrize("li", LOCAL)
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_adjoint_drift_and_axis_speed(variant, dtype, tol, li):
+    """Feet shifted by a per-node drift, or stretched by per-axis speed factors:
+    the same bars as the plain adjoint."""
+    p = W.c5_adjoint(n=129, n_obs=1500, **VARIANTS[variant])
+    say("case: adjoint", variant, dtype, "local", li)
+    V, pol, _, _ = O.solve(p)
+    Vt, _, _, _ = O.solve(p.with_(cost=np.exp(p.meta["theta_true"])))
+    obs = p.meta["obs"]
+    gV = _obs_grad(p, V, Vt[obs], obs)
+    _, dLdl_o, it_o, _ = O.adjoint(p, pol, gV)
+    dp = S.to_device(p, dtype)
+    dLdl, st = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
+                         torch.as_tensor(gV, dtype=dtype, device=DEV),
+                         tol=gpu_tol(gV, dtype), local_iters=li)
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  rel l2", err, "launches", st["sweeps_max"], "oracle iters", it_o)
+    assert st["converged"]
+    assert err <= tol
+
+
+def test_adjoint_isa_swirl():
+    """Sets of the reconstruction with a drift; per-set adjoints summed."""
+    p = W.c5_adjoint(n=129, n_obs=1500, swirl=0.5)
+    say("case: isa adjoint with drift")
+    Vbar, owner, rec, Vs, _ = I.isa(p)
+    _, pols, _ = I.solve_subdomains(p, rec.member, want_policy=True)
+    Vt = I.isa(p.with_(cost=np.exp(p.meta["theta_true"])))[0]
+    obs = p.meta["obs"]
+    gV = _obs_grad(p, Vbar, Vt[obs], obs)
+    dLdl_o, _ = I.adjoint_isa(p, rec.member, pols, owner, gV)
+    dp = S.to_device(p, torch.float32)
+    pol_t = torch.as_tensor(np.concatenate([pol_u8(q) for q in pols]), device=DEV)
+    dLdl, st = S.adjoint(dp, pol_t, torch.as_tensor(gV, dtype=torch.float32, device=DEV),
+                         member=torch.as_tensor(rec.member, device=DEV),
+                         owner=torch.as_tensor(owner, device=DEV), tol=0.0, local_iters=4)
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  rel l2", err, "launches", st["sweeps_max"])
+    assert err <= 1e-4
+
+
+def test_adjoint_vdp_drift_field():
+    """Van der Pol dynamics (drift larger than the control), 257^2, a dense g."""
+    p = W.vdp_problem(257, split=1)
+    say("case: adjoint vdp 257")
+    V, pol, _, _ = O.solve(p)
+    gV = np.random.Generator(np.random.PCG64(11)).normal(size=p.N)
+    _, dLdl_o, _, _ = O.adjoint(p, pol, gV)
+    dp = S.to_device(p, torch.float32)
+    for li in LOCAL:
+        dLdl, st = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
+                             torch.as_tensor(gV, dtype=torch.float32, device=DEV),
+                             tol=0.0, local_iters=li)
+        err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+        say("  local", li, "rel l2", err, "launches", st["sweeps_max"])
+        assert st["converged"]
+        assert err <= 1e-4
+
+
+def test_autograd_gradient_with_drift_against_fd():
+    """theta -> V with a drift (GPU FP32, tiles) -> loss; gradient against central
+    differences of the oracle's FP64 loss."""
+    p = W.c5_adjoint(n=65, n_obs=300, swirl=0.5)
+    obs = p.meta["obs"]
+    Vobs = O.solve(p.with_(cost=np.exp(p.meta["theta_true"])))[0][obs]
+
+    def loss_o(theta):
+        return float(np.sum((O.solve(p.with_(cost=np.exp(theta)))[0][obs] - Vobs) ** 2))
+
+    dp = S.to_device(p, torch.float32)
+    ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=p.ra_tol)
+    theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device=DEV).requires_grad_(True)
+    opts = S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=4)
+    V = S.HJBSolve.apply(torch.exp(theta), dp, None, ra, opts, 0.0, 4)
+    loss = ((V[torch.as_tensor(obs, device=DEV)]
+             - torch.as_tensor(Vobs, dtype=torch.float32, device=DEV)) ** 2).sum()
+    loss.backward()
+    grad = theta.grad.detach().cpu().numpy().astype(np.float64)
+    th = p.meta["theta"]
+    rng = np.random.Generator(np.random.PCG64(706))
+    eps = 1e-6
+    for _ in range(4):
+        d = rng.normal(size=p.N)
+        fd = (loss_o(th + eps * d) - loss_o(th - eps * d)) / (2 * eps)
+        an = float(grad @ d)
+        say(f"  fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+        assert abs(fd - an) <= 1e-3 * abs(fd)

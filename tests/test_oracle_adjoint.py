@@ -13,9 +13,16 @@ import workloads as W
 from oracle import isa as I
 
 
-@pytest.fixture(scope="module")
-def prob():
-    return W.c5_adjoint(n=65, n_obs=300)
+VARIANTS = {
+    "plain": dict(),
+    "swirl": dict(swirl=0.5),          # drift: feet shift by q_j per node
+    "axes": dict(axis_speed=True),     # S(x) = diag(c_1, c_2)
+}
+
+
+@pytest.fixture(scope="module", params=list(VARIANTS))
+def prob(request):
+    return W.c5_adjoint(n=65, n_obs=300, **VARIANTS[request.param])
 
 
 def _linear_system(p, pol, dom=None):

@@ -304,9 +304,15 @@ def c4_batch(count: int = 512, seed: int = 404, n_min: int = 16, n_max: int = 51
 
 def c5_adjoint(n: int = 513, m: int = 32, n_disks: int = 4, r: float = 0.05,
                theta_sd: float = 0.1, seed_disks: int = 205, seed_theta: int = 105,
-               seed_obs: int = 505, seed_true: int = 605, n_obs: int = 2000) -> Problem:
+               seed_obs: int = 505, seed_true: int = 605, n_obs: int = 2000,
+               swirl: float = 0.0, axis_speed: bool = False) -> Problem:
     """2D learnable-cost problem: f = a, l = exp(theta) with theta i.i.d. N(0, sd^2),
-    V_ghost = 2.  ``meta`` holds theta, theta_true and the observation nodes."""
+    V_ghost = 2.  ``meta`` holds theta, theta_true and the observation nodes.
+
+    Variants of the same data: ``swirl`` > 0 adds the rotating drift
+    swirl * (-x2, x1) (f = drift + a; below 1 the unit controls still steer against
+    it everywhere in the box), ``axis_speed`` the per-axis speed factors
+    (1 + x1^2 / 2, 1 - x2^2 / 4), so S(x) = diag(c_1, c_2)."""
     N = n * n
     dx = 2.0 / (n - 1)
     cen = separated_centres(n_disks, 2, 0.3, seed_disks)
@@ -316,9 +322,19 @@ def c5_adjoint(n: int = 513, m: int = 32, n_disks: int = 4, r: float = 0.05,
     th = f32(th)
     th_true = f32(th_true)
     obs = obs_nodes(tid, n_obs, seed_obs)
-    return Problem(name=f"adjoint_{n}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
+    drift = speed = None
+    name = f"adjoint_{n}"
+    if swirl > 0.0 or axis_speed:
+        X = node_coords((n, n), (-1.0, -1.0), (1.0, 1.0))
+        if swirl > 0.0:
+            drift = f32(swirl * np.stack([-X[:, 1], X[:, 0]], axis=1))
+            name += f"_swirl{swirl}"
+        if axis_speed:
+            speed = f32(np.stack([1.0 + 0.5 * X[:, 0] ** 2, 1.0 - 0.25 * X[:, 1] ** 2], axis=1))
+            name += "_axes"
+    return Problem(name=name, dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                    velocity=controls_2d(m), target=tid, n_comp=n_disks,
-                   cost=f32(np.exp(th)), v_ghost=2.0,
+                   cost=f32(np.exp(th)), v_ghost=2.0, drift=drift, speed=speed,
                    coarse_stride=coarse_stride(n, dx, r), ra_C=1.0, ra_M=1.0, ra_q=1.0,
                    meta={"theta": th, "theta_true": th_true, "obs": obs, "centres": cen})
 
