@@ -37,6 +37,7 @@ _I32P = C.POINTER(C.c_int32)
 _I64P = C.POINTER(C.c_int64)
 
 DISC = {"exp": 0, "paper": 1, "kruzkov": 2}
+INTERP = {"q1": 0, "p1": 1}
 
 
 def lib():
@@ -49,7 +50,8 @@ def lib():
         L.orc_scheme_constants.argtypes = [C.c_double, C.c_double, C.c_int, _DP, _DP]
         L.orc_scheme_constants.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
-        common = [C.c_int, _IP, _DP, _DP, C.c_double, C.c_int, _DP, _DP, C.c_int, _DP, C.c_int]
+        common = [C.c_int, _IP, _DP, _DP, C.c_double, C.c_int, _DP, _DP, C.c_int, _DP, C.c_int,
+                  C.c_int]
         L.orc_apply.argtypes = common + [_DP, _DP, C.c_double, C.c_int, C.c_double, _U8P, _U8P,
                                          _DP, _DP, _I32P, C.c_int]
         L.orc_apply.restype = C.c_int
@@ -107,7 +109,8 @@ def _common(prob):
     mb = 0 if bb is None else int(bb.shape[0])
     keep = (n, lo, hi, b, c, bb)
     return keep, [prob.dim, _p(n, _IP), _p(lo, _DP), _p(hi, _DP), float(prob.step), prob.m,
-                  _p(b, _DP), _p(c, _DP), mb, _p(bb, _DP), c_axes]
+                  _p(b, _DP), _p(c, _DP), mb, _p(bb, _DP), c_axes,
+                  INTERP[getattr(prob, "interp", "q1")]]
 
 
 def max_threads() -> int:

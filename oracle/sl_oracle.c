@@ -13,7 +13,9 @@
  *   control problem's min_k)
  *   fixed (target) nodes keep their value, nodes outside the box or outside the
  *   solve domain read the ghost value G (the paper's ghost nodes, finite here).
- *   I is tensor-product linear (Q1) interpolation on the Cartesian grid.
+ *   I is tensor-product linear (Q1) interpolation on the Cartesian grid, or
+ *   piecewise linear (P1) interpolation on the Kuhn triangulation of its cells
+ *   (Sec. 3 states the scheme with P1 on a simplicial grid).
  *   The fixed point is found by the plain (Jacobi) iteration V <- T(V) (Sec. 3,
  *   "the fixed point ... is found through the iterative map", a contraction).
  *
@@ -39,7 +41,19 @@
  *     fma(tau, v1, (1 - tau) * v0); an implementation that follows the same order
  *     gets bit-identical FP64 results.  Every rounding step is monotone in the node
  *     values, and a constant field equal to a power of two (the ghost value) is
- *     reproduced exactly.
+ *     reproduced exactly;
+ *   - P1 on simplices: each cell is split into the d! Kuhn simplices, the simplex of
+ *     a point being fixed by the order of its fractions tau (descending; equal
+ *     fractions in increasing axis order, which does not change the value).  With
+ *     t_0 >= .. >= t_{d-1} the sorted fractions and v_0 .. v_d the vertices (v_0 the
+ *     cell's lower corner, each next one a step along the next sorted axis), the
+ *     barycentric weights are 1 - t_0, t_0 - t_1, .., t_{d-1}.  The value is taken
+ *     as nested one-dimensional interpolations from the far vertex inwards,
+ *       acc = v_d;  acc = lerp(t_i / t_{i-1}, v_i, acc) for i = d-1 .. 1;
+ *       value = lerp(t_0, v_0, acc),   lerp(s, a, b) = fma(s, b, (1 - s) * a),
+ *     (a ratio with t_{i-1} = 0 is 0), which expands to the barycentric form and
+ *     keeps the two properties above: every step is monotone in the vertex values
+ *     and a power-of-two constant is reproduced exactly.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
  */
@@ -63,6 +77,7 @@ typedef struct {
     double *q;            /* N*dim: (h/dx_d) * drift_jd, or NULL     */
     const double *c;      /* speed per node (or per node and axis), or NULL (= 1) */
     int c_axes;           /* 1: c holds dim factors per node          */
+    int interp;           /* 0: Q1 on cells; 1: P1 on Kuhn simplices  */
     double *wl;           /* w * l_j per node                        */
     double *bn;           /* per-node discount (Kruzkov form) or NULL */
     double beta;
@@ -92,12 +107,13 @@ int orc_scheme_constants(double lam, double h, int disc, double *beta, double *w
 
 static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const double *hi,
                      double h, int m, const double *b, const double *c, int mb,
-                     const double *bb, int c_axes, const double *l, const double *drift,
+                     const double *bb, int c_axes, int interp, const double *l, const double *drift,
                      double lam, int disc, double G, const uint8_t *fixed, const uint8_t *dom)
 {
     double beta, w, t[3];
     memset(P, 0, sizeof(*P));
     if (dim < 1 || dim > 3 || m < 1) return -1;
+    if (interp != 0 && interp != 1) return -1;
     if (bb ? mb < 1 : mb > 1) return -1;
     if (mb < 1) mb = 1;
     P->dim = dim;
@@ -139,6 +155,7 @@ static int prob_init(orc_prob *P, int dim, const int *n, const double *lo, const
     }
     P->c = c;
     P->c_axes = c_axes ? 1 : 0;
+    P->interp = interp;
     P->beta = beta;
     P->G = G;
     P->fixed = fixed;
@@ -180,7 +197,23 @@ static void foot_fractions(const orc_prob *P, long j, const long *ij, int k, dou
     }
 }
 
-/* Q1 stencil at the foot of control k from node j: corner node indices (-1 = ghost:
+/* Axes in the order of decreasing fraction, equal fractions in increasing axis
+ * order (insertion sort of at most three entries). */
+static void kuhn_order(int dim, const double *tau, int *ax)
+{
+    for (int d = 0; d < dim; ++d) {
+        int i = d;
+        while (i > 0 && tau[ax[i - 1]] < tau[d]) {
+            ax[i] = ax[i - 1];
+            --i;
+        }
+        ax[i] = d;
+    }
+}
+
+/* Interpolation stencil at the foot of control k from node j (Q1: the 2^dim cell
+ * corners, bit d = upper node on axis d; P1: the dim + 1 simplex vertices in order
+ * v_0 .. v_dim): corner node indices (-1 = ghost:
  * outside the box or outside the domain) and weights.  Returns the corner count. */
 static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx, double *wt)
 {
@@ -196,6 +229,35 @@ static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx,
         p[d] = (long)fl;
     }
     const int K = 1 << dim;
+    if (P->interp == 1) {
+        /* P1: the d + 1 vertices of the point's Kuhn simplex with their barycentric
+         * weights, then the unused slots as absent corners of weight 0 */
+        int ax[3];
+        kuhn_order(dim, tau, ax);
+        long pv[3] = {p[0], p[1], p[2]};
+        for (int s = 0; s <= dim; ++s) {
+            if (s > 0) pv[ax[s - 1]] += 1;
+            double w;
+            if (s == 0) w = 1.0 - tau[ax[0]];
+            else if (s < dim) w = tau[ax[s - 1]] - tau[ax[s]];
+            else w = tau[ax[dim - 1]];
+            long idx = 0, stride = 1;
+            int inside = 1;
+            for (int d = 0; d < dim; ++d) {
+                if (pv[d] < 0 || pv[d] >= P->n[d]) inside = 0;
+                idx += pv[d] * stride;
+                stride *= P->n[d];
+            }
+            if (inside && P->dom && !P->dom[idx]) inside = 0;
+            cidx[s] = inside ? idx : -1;
+            wt[s] = w;
+        }
+        for (int s = dim + 1; s < K; ++s) {
+            cidx[s] = -1;
+            wt[s] = 0.0;
+        }
+        return dim + 1;
+    }
     for (int s = 0; s < K; ++s) {
         double w = 0.0;
         long idx = 0, stride = 1;
@@ -214,6 +276,22 @@ static int stencil(const orc_prob *P, long j, const long *ij, int k, long *cidx,
         wt[s] = w;
     }
     return K;
+}
+
+/* P1 value at the foot from the vertex values val[0..dim] of its Kuhn simplex
+ * (stencil order): nested linear interpolations from the far vertex inwards. */
+static double interp_p1(int dim, const double *tau, const double *val)
+{
+    int ax[3];
+    kuhn_order(dim, tau, ax);
+    double acc = val[dim];
+    for (int i = dim - 1; i >= 0; --i) {
+        double s;
+        if (i == 0) s = tau[ax[0]];
+        else s = tau[ax[i - 1]] > 0.0 ? tau[ax[i]] / tau[ax[i - 1]] : 0.0;
+        acc = fma(s, acc, (1.0 - s) * val[i]);
+    }
+    return acc;
 }
 
 /* Q1 value at the foot from the corner values val[0..2^dim) (bit d of the corner
@@ -248,7 +326,8 @@ static double apply_node(const orc_prob *P, long j, const double *V, int *arg)
             int K = stencil(P, j, ij, k, cidx, wt);
             foot_fractions(P, j, ij, k, tau);
             for (int s = 0; s < K; ++s) val[s] = cidx[s] >= 0 ? V[cidx[s]] : P->G;
-            double r = interp_q1(P->dim, tau, val);
+            double r = P->interp == 1 ? interp_p1(P->dim, tau, val)
+                                      : interp_q1(P->dim, tau, val);
             double cand = fma(P->bn ? P->bn[j] : P->beta, r, P->wl[j]);
             if (ik < 0 || cand < inner) {
                 inner = cand;
@@ -321,13 +400,13 @@ int orc_max_threads(void)
 /* Apply T once: TV = T(V), policy (first minimising control, -1 on fixed or
  * non-domain nodes) optional.  Returns 0 or a negative error. */
 int orc_apply(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-              const double *b, const double *c, int mb, const double *bb, int c_axes,
+              const double *b, const double *c, int mb, const double *bb, int c_axes, int interp,
               const double *l, const double *drift, double lam, int disc, double G,
               const uint8_t *fixed, const uint8_t *dom, const double *V, double *TV,
               int32_t *policy, int nthreads)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, l, drift, lam, disc, G,
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, interp, l, drift, lam, disc, G,
                        fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     set_threads(nthreads);
@@ -342,13 +421,13 @@ int orc_apply(int dim, const int *n, const double *lo, const double *hi, double 
  * negative error.  On return V holds the last iterate, policy (optional) the
  * first minimising control of the last sweep. */
 long orc_solve(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-               const double *b, const double *c, int mb, const double *bb, int c_axes,
+               const double *b, const double *c, int mb, const double *bb, int c_axes, int interp,
                const double *l, const double *drift, double lam, int disc, double G,
                const uint8_t *fixed, const uint8_t *dom, double *V, int32_t *policy,
                double tol, long max_sweeps, double *residual, int nthreads)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, l, drift, lam, disc, G,
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, interp, l, drift, lam, disc, G,
                        fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     set_threads(nthreads);
@@ -373,12 +452,12 @@ long orc_solve(int dim, const int *n, const double *lo, const double *hi, double
 /* Interpolation stencil of the frozen policy: for every node j with policy[j] >= 0,
  * corner indices (-1 = ghost) and weights of I at its foot, 2^dim per node. */
 int orc_policy_stencil(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-                       const double *b, const double *c, int mb, const double *bb, int c_axes,
+                       const double *b, const double *c, int mb, const double *bb, int c_axes, int interp,
                        const double *drift, const uint8_t *dom, const int32_t *policy,
                        int64_t *cidx, double *wts)
 {
     orc_prob P;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, NULL, drift, 1.0, 0, 0.0,
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, interp, NULL, drift, 1.0, 0, 0.0,
                        NULL, dom);
     if (rc) { prob_free(&P); return rc; }
     const int K = 1 << dim;
@@ -406,14 +485,14 @@ int orc_policy_stencil(int dim, const int *n, const double *lo, const double *hi
  * max|lambda_new - lambda| <= tol.  Output: lam_out (N, zero off free nodes) and,
  * if dLdl != NULL, w * lambda.  Returns iterations or a negative error. */
 long orc_adjoint(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-                 const double *b, const double *c, int mb, const double *bb, int c_axes,
+                 const double *b, const double *c, int mb, const double *bb, int c_axes, int interp,
                  const double *drift, double lam, int disc, const uint8_t *fixed,
                  const uint8_t *dom, const int32_t *policy, const double *gV, double *lam_out,
                  double *dLdl, double tol, long max_iters, double *residual)
 {
     orc_prob P;
     if (disc == 2) return -1;        /* the discount depends on l: not a linear adjoint in w l */
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, NULL, drift, lam, disc, 0.0,
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, interp, NULL, drift, lam, disc, 0.0,
                        fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     double beta = P.beta, w;
@@ -459,14 +538,14 @@ long orc_adjoint(int dim, const int *n, const double *lo, const double *hi, doub
  * nodes (zero elsewhere), plain Jacobi from zero.  Used for the dot-product test
  * <lambda, w dl> = <gV, Vdot>.  Returns iterations or a negative error. */
 long orc_tangent(int dim, const int *n, const double *lo, const double *hi, double h, int m,
-                 const double *b, const double *c, int mb, const double *bb, int c_axes,
+                 const double *b, const double *c, int mb, const double *bb, int c_axes, int interp,
                  const double *drift, double lam, int disc, const uint8_t *fixed,
                  const uint8_t *dom, const int32_t *policy, const double *dl, double *Vdot,
                  double tol, long max_iters, double *residual)
 {
     orc_prob P;
     if (disc == 2) return -1;
-    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, dl, drift, lam, disc, 0.0,
+    int rc = prob_init(&P, dim, n, lo, hi, h, m, b, c, mb, bb, c_axes, interp, dl, drift, lam, disc, 0.0,
                        fixed, dom);
     if (rc) { prob_free(&P); return rc; }
     const long N = P.N;

@@ -5,7 +5,7 @@ scheme V = T(V) (paper Sec. 3, (SL)/(Tdef)): instead of iterating T, alternate
   * policy evaluation: solve the linear system V = beta P_pi V + w l (+ fixed and
     ghost contributions) exactly, in rational arithmetic, and
   * policy improvement: pi(j) = a minimiser of beta I[V](foot_k) + w l_j,
-until the policy is stable.  The foot positions and Q1 weights are evaluated
+until the policy is stable.  The foot positions and the Q1 (or P1) weights are evaluated
 exactly from the (binary64) problem data, so the only inexact inputs are the
 binary64 values of beta and w.  Only practical for grids of a few dozen free
 nodes.
@@ -65,6 +65,31 @@ def _table(prob):
             for b in np.asarray(vb) for a in A]
 
 
+def _kuhn_stencil(p, tau, n):
+    """P1 on the Kuhn simplex holding the point p + tau: its vertices start at the
+    cell's lower corner p and step one axis at a time, in the order of decreasing
+    fraction; the barycentric weights of the point are 1 - t_0, t_0 - t_1, ..,
+    t_{d-1} for the sorted fractions (exact rationals; a tie gives a zero weight,
+    so its order does not matter)."""
+    dim = len(p)
+    order = sorted(range(dim), key=lambda d: -tau[d])
+    t = [tau[d] for d in order]
+    w = [1 - t[0]] + [t[i - 1] - t[i] for i in range(1, dim)] + [t[dim - 1]]
+    v = list(p)
+    st = []
+    for i in range(dim + 1):
+        if i > 0:
+            v[order[i - 1]] += 1
+        inside = all(0 <= v[d] < n[d] for d in range(dim))
+        idx, stride = 0, 1
+        for d in range(dim):
+            idx += v[d] * stride
+            stride *= n[d]
+        if w[i] != 0:
+            st.append((idx if inside else -1, w[i]))
+    return st
+
+
 def exact_stencils(prob):
     """For every free node and table row: list of (corner index or -1, weight)."""
     dim, n = prob.dim, prob.n
@@ -98,6 +123,9 @@ def exact_stencils(prob):
             p = [_floor(x) for x in u]
             tau = [u[d] - p[d] for d in range(dim)]
             st = []
+            if getattr(prob, "interp", "q1") == "p1":
+                per_k.append(_kuhn_stencil(p, tau, n))
+                continue
             for s in range(1 << dim):
                 w = Fr(1)
                 idx, stride, inside = 0, 1, True

@@ -66,6 +66,7 @@ class Problem:
     ra_q: float = 1.0
     ra_tol: float = 0.0                  # coarse stopping tolerance (0: until nothing changes)
     velocity_b: Optional[np.ndarray] = None  # (mb, dim) evader's table (games); None -> control problem
+    interp: str = "q1"                   # "q1": Q1 on cells; "p1": P1 on the Kuhn simplices of each cell
     meta: dict = field(default_factory=dict)
 
     @property
