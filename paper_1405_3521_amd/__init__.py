@@ -29,6 +29,8 @@ _LIB = None
 
 SL_OK, SL_NOT_CONVERGED = 0, 1
 DISC = {"exp": 0, "paper": 1, "kruzkov": 2}
+INTERP = {"q1": 0, "p1": 1}
+ABI_VERSION = 5          # struct layout of slhjb.h
 
 
 class SlError(RuntimeError):
@@ -46,6 +48,7 @@ class SlProblem(C.Structure):
         ("n_comp", C.c_int), ("lambda_", C.c_double), ("h", C.c_double),
         ("v_ghost", C.c_double), ("disc", C.c_int), ("dtype", C.c_int),
         ("m_b", C.c_int), ("velocity_b", C.POINTER(C.c_double)), ("speed_axes", C.c_int),
+        ("interp", C.c_int),
     ]
 
 
@@ -92,6 +95,9 @@ def lib():
         L.sl_status_string.argtypes = [C.c_int]
         L.sl_status_string.restype = C.c_char_p
         L.sl_abi_version.restype = C.c_int
+        if L.sl_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{_LIB_PATH} has ABI {L.sl_abi_version()}, the binding "
+                               f"expects {ABI_VERSION}: rebuild it")
         L.sl_tune_candidates.argtypes = [C.c_int, C.c_int]
         L.sl_tune_candidates.restype = C.c_int
         L.sl_solve_workspace_size.argtypes = [P(SlProblem)]
@@ -154,6 +160,7 @@ class DeviceProblem:
     dtype: "object" = None          # torch.float32 / torch.float64
     velocity_b: Optional[np.ndarray] = None  # host (m_b, dim) float64: the evader's b_l (games)
     speed_axes: bool = False        # speed holds dim factors per node (node-major)
+    interp: str = "q1"              # "q1" (cells) or "p1" (Kuhn simplices; 2D)
 
     @property
     def N(self) -> int:
@@ -217,7 +224,7 @@ def to_device(prob, dtype=None, device: str = "cuda:0") -> DeviceProblem:
         else dev(np.asarray(prob.drift).reshape(-1), dtype),
         lam=float(prob.lam),
         h=float(getattr(prob, "step", 0.0) or prob.h), v_ghost=float(prob.v_ghost),
-        disc=prob.disc, dtype=dtype)
+        disc=prob.disc, dtype=dtype, interp=getattr(prob, "interp", "q1"))
 
 
 def _ptr(t):
@@ -268,6 +275,7 @@ def _cproblem(p: DeviceProblem):
     cp.m_b = 0 if vb is None else vb.shape[0]
     cp.velocity_b = None if vb is None else vb.ctypes.data_as(C.POINTER(C.c_double))
     cp.speed_axes = 1 if p.speed_axes else 0
+    cp.interp = INTERP[p.interp]
     return cp, (vel, vb)     # keep the host tables alive
 
 

@@ -84,6 +84,8 @@ int validate(const sl_problem *p) {
     if (p->disc != SL_DISC_EXP && p->disc != SL_DISC_PAPER && p->disc != SL_DISC_KRUZKOV)
         return SL_ERR_INVALID_ARG;
     if (p->dtype != SL_F32 && p->dtype != SL_F64) return SL_ERR_INVALID_ARG;
+    if (p->interp != SL_INTERP_Q1 && p->interp != SL_INTERP_P1) return SL_ERR_INVALID_ARG;
+    if (p->interp == SL_INTERP_P1 && p->dim != 2) return SL_ERR_UNSUPPORTED;
     return SL_OK;
 }
 
@@ -292,12 +294,12 @@ struct ChunkLoop {
 // Kernel configurations are chosen per problem shape by timing candidates on
 // the caller's problem; the winner is cached for the life of the process.
 struct TuneKey {
-    int dim, dtype, m, m_inner, halo, nsd, size_class, local_iters;
+    int dim, dtype, m, m_inner, halo, nsd, size_class, local_iters, interp;
     bool operator<(const TuneKey &o) const {
-        const int a[8] = {dim, dtype, m, m_inner, halo, nsd, size_class, local_iters};
-        const int b[8] = {o.dim,  o.dtype, o.m,          o.m_inner,
-                          o.halo, o.nsd,   o.size_class, o.local_iters};
-        return std::lexicographical_compare(a, a + 8, b, b + 8);
+        const int a[9] = {dim, dtype, m, m_inner, halo, nsd, size_class, local_iters, interp};
+        const int b[9] = {o.dim,  o.dtype, o.m,          o.m_inner,     o.halo,
+                          o.nsd,  o.size_class, o.local_iters, o.interp};
+        return std::lexicographical_compare(a, a + 9, b, b + 9);
     }
 };
 std::map<TuneKey, std::pair<int, int>> &tune_cache() {
@@ -310,18 +312,21 @@ std::mutex &tune_mutex() {
 }
 
 // Candidates for (dim, dtype); a game leaves out the variants that split the
-// controls over several thread groups.
-std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo, bool game = false) {
+// controls over several thread groups, P1 the variants without P1 kernels.
+std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo, bool game = false,
+                                       int interp = SL_INTERP_Q1) {
     LaunchCfg all[16];
     const int nv = sweep_variants(dim, all, 16);
     std::vector<LaunchCfg> out;
     for (int i = 0; i < nv && i < 16; ++i) {
         if (all[i].dtype != dtype) continue;
         if (game && all[i].threads > kThreads) continue;
+        if (interp == SL_INTERP_P1 && !sweep_has_p1(all[i].variant)) continue;
         for (int mode = 0; mode < 3; ++mode) {
             LaunchCfg c = all[i];
             c.halo = halo;
             c.mode = mode;
+            c.interp = interp;
             out.push_back(c);
         }
     }
@@ -516,7 +521,7 @@ struct Exec {
         for (const auto &d : host_sds) game = game || (d.m_inner > 0 && d.m_inner < d.m);
         if (autotune < 0) {                  // forced candidate (testing)
             const std::vector<LaunchCfg> cands =
-                tune_candidates(cfg.dim, cfg.dtype, cfg.halo, game);
+                tune_candidates(cfg.dim, cfg.dtype, cfg.halo, game, cfg.interp);
             const int k = -autotune - 1;
             if (k >= (int)cands.size()) return SL_ERR_INVALID_ARG;
             cfg = cands[k];
@@ -534,7 +539,8 @@ struct Exec {
                               cfg.halo,
                               (int)host_sds.size(),
                               sc,
-                              local_iters};
+                              local_iters,
+                              cfg.interp};
             bool found = false;
             std::pair<int, int> pick;
             {
@@ -547,7 +553,7 @@ struct Exec {
             }
             if (!found) {
                 const std::vector<LaunchCfg> cands =
-                    tune_candidates(cfg.dim, cfg.dtype, cfg.halo, game);
+                    tune_candidates(cfg.dim, cfg.dtype, cfg.halo, game, cfg.interp);
                 hipEvent_t e0, e1;
                 HIPCHK(hipEventCreate(&e0));
                 HIPCHK(hipEventCreate(&e1));
@@ -580,8 +586,9 @@ struct Exec {
                 std::lock_guard<std::mutex> lk(tune_mutex());
                 tune_cache()[key] = pick;
             }
-            const int halo = cfg.halo;
+            const int halo = cfg.halo, interp = cfg.interp;
             cfg = make_cfg(cfg.dim, cfg.dtype, halo, pick.first);
+            cfg.interp = interp;
             cfg.mode = pick.second;
             cfg.local_iters = local_iters;
             ms_sweeps = 0.0;
@@ -756,6 +763,7 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
     if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     ex.cfg = make_cfg(p->dim, p->dtype, H, variant);
+    ex.cfg.interp = p->interp;
     ex.cfg.local_iters = o->local_iters;
     if (p->drift) {
         double t[3];
@@ -975,6 +983,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     const int HK = halo_for(smax, emaxK, drift_reach(p, cg.nK, cg.hK, fs));
     if (HK > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.exK.cfg = make_cfg(p->dim, SL_F64, HK, default_variant(p->dim, SL_F64));
+    P.exK.cfg.interp = p->interp;
     P.exK.cfg.local_iters = ra->local_iters;
     auto reinit = [&](hipStream_t q) -> hipError_t {
         for (int i = 0; i < nc; ++i)
@@ -1074,6 +1083,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
     if (H > max_halo(p->dim)) return SL_ERR_UNSUPPORTED;
     P.ex.cfg = make_cfg(p->dim, p->dtype, H, default_variant(p->dim, p->dtype));
+    P.ex.cfg.interp = p->interp;
     P.ex.cfg.local_iters = o->local_iters;
     if (p->drift) {
         double t[3];
@@ -1662,6 +1672,7 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
+        if (probs[q].interp != SL_INTERP_Q1) return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
 }
@@ -1932,7 +1943,8 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
-    if (is_game(p) || p->disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
+    if (is_game(p) || p->disc == SL_DISC_KRUZKOV || p->interp != SL_INTERP_Q1)
+        return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

@@ -17,12 +17,28 @@ __device__ __forceinline__ double fma_<double>(double a, double b, double c) { r
 
 template <typename T>
 __device__ __forceinline__ T min_(T a, T b) { return a < b ? a : b; }
+
 template <>
 __device__ __forceinline__ float min_<float>(float a, float b) { return __builtin_fminf(a, b); }
 template <>
 __device__ __forceinline__ double min_<double>(double a, double b) { return __builtin_fmin(a, b); }
 template <typename T>
 __device__ __forceinline__ T max_(T a, T b) { return a > b ? a : b; }
+
+// t1 / t0 for the sorted fractions 0 <= t1 <= t0 of a P1 foot, 0 when t0 = 0:
+// FP64 divides exactly; FP32 multiplies by the reciprocal instruction and clamps
+// to 1 (any value in [0, 1] keeps the interpolation monotone and exact on
+// constants).
+template <typename T>
+__device__ __forceinline__ T simplex_ratio(T t1, T t0);
+template <>
+__device__ __forceinline__ float simplex_ratio<float>(float t1, float t0) {
+    return t0 > 0.f ? min_(t1 * __builtin_amdgcn_rcpf(t0), 1.f) : 0.f;
+}
+template <>
+__device__ __forceinline__ double simplex_ratio<double>(double t1, double t0) {
+    return t0 > 0.0 ? t1 / t0 : 0.0;
+}
 
 // Read-only table in the constant address space: uniform indices then compile to
 // scalar loads through the scalar data cache instead of vector memory loads (the

@@ -165,6 +165,7 @@ struct LaunchCfg {
     int threads;                // work-group size of the variant
     int local_iters;            // 0: Jacobi sweeps; k > 0: block-asynchronous, up to k
                                 // local iterations per tile and launch (in place)
+    int interp;                 // sl_interp of the kernels
 };
 
 // ---- launchers (sweep.hip) -------------------------------------------------
@@ -191,6 +192,8 @@ hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol,
 hipError_t sweep_set_attributes(LaunchCfg &cfg);
 // Supported tile shapes per (dim) for the autotuner; returns count.
 int sweep_variants(int dim, LaunchCfg *out, int cap);
+// Whether a variant has P1 kernels (2D).
+bool sweep_has_p1(int variant);
 
 // ---- launchers (ops.hip) ----------------------------------------------------
 template <typename T>

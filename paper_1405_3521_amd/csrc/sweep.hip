@@ -33,7 +33,7 @@ namespace {
 // ------------------------------------------------------------------ 2D kernel
 // Persistent: a resident grid of work-groups takes work items from a per-sweep
 // atomic queue until the list is exhausted.
-template <typename T, int TX, int TY, int H, bool POLICY, int S>
+template <typename T, int TX, int TY, int H, bool POLICY, int S, bool P1>
 __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
@@ -199,6 +199,19 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                     // corners lie inside the staged tile (0 <= ix, iy < LW, LH): a
                     // 24-bit multiply is exact and single-pass
                     const int base = (int)__umul24((unsigned)iy, (unsigned)LW) + ix;
+                    T acc;
+                    if (P1) {
+                        // P1 on the cell's Kuhn simplex: lower corner, one step
+                        // along the axis of the larger fraction (x on ties), the
+                        // upper corner; nested interpolations from the far vertex
+                        const bool xf = fx >= fy;
+                        const T t0 = xf ? fx : fy, t1 = xf ? fy : fx;
+                        const T v00 = lds[base], vm = lds[base + (xf ? 1 : LW)];
+                        const T v11 = lds[base + LW + 1];
+                        const T sr = simplex_ratio(t1, t0);
+                        const T in = fma_(sr, v11, (T(1) - sr) * vm);
+                        acc = fma_(t0, in, (T(1) - t0) * v00);
+                    } else {
                     const T v00 = lds[base], v10 = lds[base + 1];
                     const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
                     // Q1 as nested one-axis interpolations fma(f, v1, (1-f) v0), x then
@@ -212,7 +225,8 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
                     const T ax = T(1) - fx, ay = T(1) - fy;
                     const T a = fma_(fx, v10, ax * v00);
                     const T b = fma_(fx, v11, ax * v01);
-                    const T acc = fma_(fy, b, ay * a);
+                    acc = fma_(fy, b, ay * a);
+                    }
                     const T cand = fma_(bt[r], acc, wl[r]);
                     if (POLICY) {
                         if (cand < inner[r]) {
@@ -581,13 +595,18 @@ __global__ void k_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol, Exe
 struct Variant {
     int dim, dtype, tile[3], threads;
     const void *fn[kMaxHalo + 1][2];    // [H][policy]
+    const void *fn_p1[kMaxHalo + 1][2]; // P1 interpolation (2D; null where not built)
     size_t lds_bytes[kMaxHalo + 1];     // dynamic LDS (3D only)
 };
 
-template <typename T, int TX, int TY, int H, int S>
+template <typename T, int TX, int TY, int H, int S, bool WITH_P1>
 void fill2d(Variant &v) {
-    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S>;
-    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S>;
+    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S, false>;
+    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S, false>;
+    if (WITH_P1) {
+        v.fn_p1[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S, WITH_P1>;
+        v.fn_p1[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S, WITH_P1>;
+    }
     v.lds_bytes[H] = 0;
 }
 template <typename T, int TX, int TY, int TZ, int H>
@@ -597,19 +616,20 @@ void fill3d(Variant &v) {
     v.lds_bytes[H] = sizeof(T) * (size_t)(TX + 2 * H) * (TY + 2 * H) * (TZ + 2 * H);
 }
 
-template <typename T, int TX, int TY, int S = 1>
+template <typename T, int TX, int TY, int S = 1, bool P = false>
 Variant make2d() {
     Variant v{};
     v.dim = 2;
     v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = 1;
     v.threads = kThreads * S;
-    fill2d<T, TX, TY, 1, S>(v); fill2d<T, TX, TY, 2, S>(v); fill2d<T, TX, TY, 3, S>(v);
-    fill2d<T, TX, TY, 4, S>(v); fill2d<T, TX, TY, 5, S>(v); fill2d<T, TX, TY, 6, S>(v);
-    fill2d<T, TX, TY, 7, S>(v); fill2d<T, TX, TY, 8, S>(v); fill2d<T, TX, TY, 9, S>(v);
-    fill2d<T, TX, TY, 10, S>(v); fill2d<T, TX, TY, 11, S>(v); fill2d<T, TX, TY, 12, S>(v);
-    fill2d<T, TX, TY, 13, S>(v); fill2d<T, TX, TY, 14, S>(v); fill2d<T, TX, TY, 15, S>(v);
-    fill2d<T, TX, TY, 16, S>(v);
+    fill2d<T, TX, TY, 1, S, P>(v); fill2d<T, TX, TY, 2, S, P>(v); fill2d<T, TX, TY, 3, S, P>(v);
+    fill2d<T, TX, TY, 4, S, P>(v); fill2d<T, TX, TY, 5, S, P>(v); fill2d<T, TX, TY, 6, S, P>(v);
+    fill2d<T, TX, TY, 7, S, P>(v); fill2d<T, TX, TY, 8, S, P>(v); fill2d<T, TX, TY, 9, S, P>(v);
+    fill2d<T, TX, TY, 10, S, P>(v); fill2d<T, TX, TY, 11, S, P>(v);
+    fill2d<T, TX, TY, 12, S, P>(v); fill2d<T, TX, TY, 13, S, P>(v);
+    fill2d<T, TX, TY, 14, S, P>(v); fill2d<T, TX, TY, 15, S, P>(v);
+    fill2d<T, TX, TY, 16, S, P>(v);
     return v;
 }
 template <typename T, int TX, int TY, int TZ>
@@ -627,16 +647,16 @@ Variant make3d() {
 
 const Variant *variants(int *count) {
     static const Variant table[] = {
-        make2d<float, 64, 16>(),   // 0: default FP32 2D
+        make2d<float, 64, 16, 1, true>(),   // 0: default FP32 2D (also P1)
         make2d<float, 64, 8>(),    // 1
         make2d<float, 64, 4>(),    // 2
         make2d<float, 32, 16>(),   // 3
-        make2d<double, 64, 8>(),   // 4: FP64 2D
+        make2d<double, 64, 8, 1, true>(),   // 4: FP64 2D (also P1)
         make3d<float, 32, 8, 8>(), // 5: default FP32 3D
         make3d<float, 32, 8, 4>(), // 6
         make3d<float, 16, 16, 4>(),// 7
         make3d<double, 16, 8, 8>(),// 8: FP64 3D
-        make2d<double, 32, 8>(),   // 9: FP64 2D, small tiles (coarse grids)
+        make2d<double, 32, 8, 1, true>(),   // 9: FP64 2D, small tiles (coarse grids; also P1)
         make2d<double, 16, 16>(),  // 10
         make3d<double, 8, 8, 8>(), // 11: FP64 3D, small tiles
         make3d<double, 16, 8, 4>(),// 12
@@ -645,7 +665,7 @@ const Variant *variants(int *count) {
         make2d<float, 64, 8, 4>(),  // 15
         make2d<double, 16, 16, 2>(), // 16: FP64 2D, controls split over 2 groups: more
         make2d<double, 16, 16, 4>(), // 17: waves per tile for small (coarse) grids
-        make2d<float, 32, 8>(),      // 18: FP32 2D, one node per thread: finer skipping
+        make2d<float, 32, 8, 1, true>(),    // 18: FP32 2D, one node per thread: finer skipping (also P1)
         make2d<float, 16, 16>(),     // 19: and twice the waves per active region
         make2d<float, 32, 8, 2>(),   // 20
     };
@@ -669,10 +689,17 @@ int sweep_variants(int dim, LaunchCfg *out, int cap) {
             out[k].halo = 0;
             out[k].variant = i;
             out[k].threads = v[i].threads;
+            out[k].interp = SL_INTERP_Q1;
         }
         ++k;
     }
     return k;
+}
+
+bool sweep_has_p1(int variant) {
+    int nv = 0;
+    const Variant *vt = variants(&nv);
+    return variant >= 0 && variant < nv && vt[variant].dim == 2 && vt[variant].fn_p1[1][0];
 }
 
 static const void *sweep_fn(const LaunchCfg &cfg, int want_policy, size_t *lds) {
@@ -682,6 +709,7 @@ static const void *sweep_fn(const LaunchCfg &cfg, int want_policy, size_t *lds) 
     const Variant &v = vt[cfg.variant];
     if (cfg.halo > (v.dim == 2 ? kMaxHalo : kMaxHalo3D) || !v.fn[cfg.halo][0]) return nullptr;
     *lds = v.lds_bytes[cfg.halo];
+    if (cfg.interp == SL_INTERP_P1) return v.dim == 2 ? v.fn_p1[cfg.halo][want_policy ? 1 : 0] : nullptr;
     return v.fn[cfg.halo][want_policy ? 1 : 0];
 }
 

@@ -1,0 +1,133 @@
+"""P1 interpolation on the Kuhn simplices of each cell (2D) on the GPU against the
+oracle: FP64 bit-exact (the same nested evaluation and an exact division), FP32
+within 1e-5, sets and labels bit-exact, block-asynchronous sweeps equal to Jacobi
+bit for bit, and the 1025^2 multitarget workload in the benchmark's launch
+configuration a fixed point of the oracle's P1 operator."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1405_3521_amd as S
+import workloads as W
+from oracle import isa as I
+
+pytestmark = pytest.mark.gpu
+
+CAP = 50_000
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def ra_of(p):
+    return S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
+                    q=p.ra_q, tol=p.ra_tol)
+
+
+def p1(n, **kw):
+    return W.c2_multitarget(n=n, m=32, **kw).with_(interp="p1")
+
+
+@pytest.mark.parametrize("li", [0, 8])
+def test_p1_global_fp64_bit_exact(li):
+    p = p1(97)
+    say("case: p1 global fp64 97 local", li)
+    V, pol, st = S.solve(S.to_device(p, torch.float64),
+                         S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=li, want_policy=True))
+    Vo, pol_o, _, _ = O.solve(p)
+    assert st["converged"]
+    assert np.array_equal(host(V), Vo)
+    free = pol_o >= 0
+    assert np.array_equal(host(pol).astype(np.int64)[free], pol_o[free])
+
+
+def test_p1_global_fp32():
+    p = p1(129)
+    say("case: p1 global fp32 129")
+    V, _, st = S.solve(S.to_device(p, torch.float32), S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    Vo, _, _, _ = O.solve(p)
+    err = np.abs(host(V).astype(np.float64) - Vo).max()
+    say("  sup err", err)
+    assert st["converged"] and err <= 1e-5
+    # not the Q1 solution
+    Vq, _, _, _ = O.solve(p.with_(interp="q1"))
+    assert np.abs(Vq - Vo).max() > 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_p1_isa(dtype):
+    p = p1(129)
+    say("case: p1 isa 129", dtype)
+    dp = S.to_device(p, dtype)
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    Vbar, own_o, rec, Vs_o, _ = I.isa(p)
+    assert st["converged"]
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
+    if dtype == torch.float64:
+        assert np.array_equal(host(V), Vbar)
+    else:
+        err = np.abs(host(V).astype(np.float64) - Vbar).max()
+        say("  sup err", err)
+        assert err <= 1e-5
+
+
+def test_p1_block_async_equals_jacobi_and_tuned_configs():
+    p = p1(257)
+    say("case: p1 block-async 257")
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    member, _, _ = S.reconstruct(dp, ra)
+    Vj = S.solve_isa(dp, ra, member, S.SolveOpts(tol=0.0, max_sweeps=CAP), want_sets=True)
+    for k in (1, 8):
+        Va = S.solve_isa(dp, ra, member, S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=k),
+                         want_sets=True)
+        say("  local", k, "launches", Va[-1]["sweeps_max"], "vs", Vj[-1]["sweeps_max"])
+        assert torch.equal(Va[3], Vj[3])
+    # every P1 candidate of the tuner (FP32 tile-local coordinates differ in the
+    # last bits across tile shapes): within 1e-6 of the default
+    Vt = S.solve_isa(dp, ra, member, S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=1,
+                                                 local_iters=8), want_sets=True)
+    err = float((Vt[3] - Vj[3]).abs().max())
+    say("  tuned", Vt[-1].get("variant"), "err", err)
+    assert err <= 1e-6
+
+
+def test_p1_rejected_where_not_built():
+    p = p1(33)
+    dp = S.to_device(p, torch.float32)
+    V, pol, _ = S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP, want_policy=True))
+    with pytest.raises(S.SlError):
+        S.adjoint(dp, pol, torch.ones_like(V), tol=0.0)
+    with pytest.raises((S.SlError, ValueError)):
+        S.solve_batched([dp], [ra_of(p)])
+
+
+def test_full_size_p1_benchmark_configuration():
+    """The 1025^2 multitarget workload (64 controls, coarse 129^2) with P1, in the
+    benchmark's launch configuration (tuned kernels, 8 local iterations; coarse 8):
+    sets and labels bit-exact, every set's FP32 values a fixed point of the oracle's
+    FP64 P1 operator up to FP32 rounding."""
+    from tests.test_gpu_drift import _fixed_point_residuals
+    p = W.c2_multitarget().with_(interp="p1")
+    say("case: p1 full size 1025")
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    ra.autotune, ra.local_iters = 1, 8
+    member, label, _ = S.reconstruct(dp, ra)
+    rec = I.reconstruct(p)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
+    V, own, pol, Vs, st = S.solve_isa(dp, ra, member,
+                                      S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=1,
+                                                  local_iters=8), want_sets=True)
+    assert st["converged"]
+    r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
+    say("  fixed-point residuals", r, "launches", st["sweeps_max"])
+    assert max(r) <= 2e-6
