@@ -36,6 +36,10 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.3 T lane-ops/s
 # addressing), 2D: foot 2 fma, cell index 2, fraction 2, Q1 as nested one-axis
 # interpolations (1-tau 2, 3 mul, 3 fma), candidate 1 fma, min 1 -> 16
 OPS_PER_NC_2D = 16
+# P1 on the Kuhn simplex, the same rules: foot 2 fma, cell index 2, fraction 2,
+# simplex order (compare, 2 selects) 3, ratio t1/t0 (reciprocal, mul, clamp) 3,
+# nested interpolations (1-s 2, 2 mul, 2 fma) 6, candidate 1 fma, min 1 -> 20
+OPS_PER_NC_2D_P1 = 20
 # 3D: foot 3, index 3, fraction 3, Q1 (1-tau 3, 7 mul, 7 fma), candidate 1,
 #     min 1 -> 28
 OPS_PER_NC_3D = 28
@@ -76,11 +80,12 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,kruzkov,study,balance",
+    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,kruzkov,p1,study,balance",
                     help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
                          "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
                          "(pursuit-evasion game 513^2), kruzkov (weighted minimum time "
-                         "513^2), study (global solve vs ISA and the "
+                         "513^2), p1 (the headline workload with P1 interpolation), "
+                         "study (global solve vs ISA and the "
                          "RA threshold on the headline problem), balance (refinement of the "
                          "target split, Van der Pol); empty for none")
     return ap.parse_args()
@@ -129,7 +134,8 @@ def leg_c3(steps: int, li: int):
             "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"]}
 
 
-def _isa_leg_2d(p, steps: int, li: int, workload: str, ra_local: int = 4):
+def _isa_leg_2d(p, steps: int, li: int, workload: str, ra_local: int = 4,
+                ops_per_nc: int = OPS_PER_NC_2D):
     """ISA to sup-res<1e-6 of a 2D problem in FP32 (tuned kernels), timed per call,
     with the sweep launches' VALU rate."""
     import torch
@@ -146,7 +152,7 @@ def _isa_leg_2d(p, steps: int, li: int, workload: str, ra_local: int = 4):
     nc = np.mean([x["node_control_updates"] for x in sts])
     launches = np.mean([x["sweep_launches"] for x in sts])
     ms_launch = np.sum([x["ms_sweeps"] for x in sts]) / np.sum([x["sweep_launches"] for x in sts])
-    ach = OPS_PER_NC_2D * nc / launches / (ms_launch / 1e3) / 1e12
+    ach = ops_per_nc * nc / launches / (ms_launch / 1e3) / 1e12
     return {"workload": workload, "time_to_converge_ms": ms,
             "node_control_updates_per_s": nc / (ms / 1e3),
             "sweep_launches": int(launches),
@@ -184,6 +190,17 @@ def leg_kruzkov(steps: int, li: int):
                        "Kruzkov weighted minimum time 513^2, l = exp(0.5 g) (smoothed "
                        "Gaussian g), unit speed, 32 controls, 4 disks, per-node discount "
                        "exp(-h l), ISA (RA on 65^2) to sup-res<1e-6")
+
+
+def leg_p1(steps: int, li: int):
+    """The headline multitarget workload (1025^2, 64 controls, 4 disks) with P1
+    interpolation on the Kuhn simplices of each cell instead of Q1."""
+    import workloads as W
+    p = W.c2_multitarget().with_(interp="p1")
+    return _isa_leg_2d(p, steps, li,
+                       "multitarget 1025^2 with P1 (Kuhn simplices), 64 controls, 4 disks, "
+                       "ISA (RA on 129^2) to sup-res<1e-6", ra_local=RA_LOCAL_ITERS,
+                       ops_per_nc=OPS_PER_NC_2D_P1)
 
 
 def leg_study(steps: int, li: int):
@@ -508,7 +525,8 @@ def main():
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
         fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
-              "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov}[leg]
+              "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov,
+              "p1": leg_p1}[leg]
         t0 = time.perf_counter()
         legs[leg] = fn(max(1, min(args.steps, 3)),
                        LEG_LOCAL_ITERS.get(leg, LEG_LOCAL_ITERS_DEFAULT))
