@@ -71,10 +71,13 @@ typedef enum { SL_DISC_EXP = 0, SL_DISC_PAPER = 1, SL_DISC_KRUZKOV = 2 } sl_disc
 /* Interpolation I[V] at the foot (Sec. 3): Q1, tensor-product linear on the grid
  * cell; or P1, linear on the Kuhn simplex of the cell that holds the foot (the
  * simplex fixed by the order of the foot's fractions t, decreasing, equal ones in
- * increasing axis order).  P1 is evaluated as lerp(t_0, v_0, lerp(t_1/t_0, v_1,
- * v_2)) with lerp(s, a, b) = fma(s, b, (1 - s) a) and v_0, v_1, v_2 the simplex's
- * vertices from the cell's lower corner (a ratio with t_0 = 0 is 0); FP64 divides
- * exactly, FP32 uses the reciprocal instruction, clamped to 1. */
+ * increasing axis order).  P1 is evaluated as nested interpolations from the far
+ * vertex, in 2D lerp(t_0, v_0, lerp(t_1/t_0, v_1, v_2)), in 3D
+ * lerp(t_0, v_0, lerp(t_1/t_0, v_1, lerp(t_2/t_1, v_2, v_3))), with
+ * lerp(s, a, b) = fma(s, b, (1 - s) a) and v_0 .. v_d the simplex's vertices from
+ * the cell's lower corner, one sorted axis step at a time (a ratio with a zero
+ * denominator is 0); FP64 divides exactly, FP32 uses the reciprocal instruction,
+ * clamped to 1. */
 typedef enum { SL_INTERP_Q1 = 0, SL_INTERP_P1 = 1 } sl_interp;
 
 /* One exit-time problem on a uniform box grid (paper Sec. 2-3). */
@@ -122,8 +125,8 @@ typedef struct sl_problem {
                                  grid samples each factor by Q1.  Needs speed != NULL.
                                  Every entry point takes it.                           */
     int interp;               /* sl_interp.  SL_INTERP_P1 is taken by sl_solve,
-                                 sl_reconstruct and sl_solve_isa in 2D; 3D, the batch and
-                                 the adjoint return SL_ERR_UNSUPPORTED for it.          */
+                                 sl_reconstruct and sl_solve_isa (2D and 3D); the batch
+                                 and the adjoint return SL_ERR_UNSUPPORTED for it.      */
 } sl_problem;
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */

@@ -160,7 +160,7 @@ class DeviceProblem:
     dtype: "object" = None          # torch.float32 / torch.float64
     velocity_b: Optional[np.ndarray] = None  # host (m_b, dim) float64: the evader's b_l (games)
     speed_axes: bool = False        # speed holds dim factors per node (node-major)
-    interp: str = "q1"              # "q1" (cells) or "p1" (Kuhn simplices; 2D)
+    interp: str = "q1"              # "q1" (cells) or "p1" (Kuhn simplices)
 
     @property
     def N(self) -> int:

@@ -85,7 +85,6 @@ int validate(const sl_problem *p) {
         return SL_ERR_INVALID_ARG;
     if (p->dtype != SL_F32 && p->dtype != SL_F64) return SL_ERR_INVALID_ARG;
     if (p->interp != SL_INTERP_Q1 && p->interp != SL_INTERP_P1) return SL_ERR_INVALID_ARG;
-    if (p->interp == SL_INTERP_P1 && p->dim != 2) return SL_ERR_UNSUPPORTED;
     return SL_OK;
 }
 

@@ -192,7 +192,7 @@ hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol,
 hipError_t sweep_set_attributes(LaunchCfg &cfg);
 // Supported tile shapes per (dim) for the autotuner; returns count.
 int sweep_variants(int dim, LaunchCfg *out, int cap);
-// Whether a variant has P1 kernels (2D).
+// Whether a variant has P1 kernels.
 bool sweep_has_p1(int variant);
 
 // ---- launchers (ops.hip) ----------------------------------------------------

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
 }
 
 // ------------------------------------------------------------------ 3D kernel
-template <typename T, int TX, int TY, int TZ, int H, bool POLICY>
+template <typename T, int TX, int TY, int TZ, int H, bool POLICY, bool P1>
 __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
@@ -494,6 +494,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     // corners lie inside the staged block: 24-bit products are exact
                     const int base = (int)__umul24((unsigned)iz, (unsigned)PL) +
                                      (int)__umul24((unsigned)iy, (unsigned)LW) + ix;
+                    T acc;
+                    if (P1) {
+                        // P1 on the cell's Kuhn simplex: the fractions sorted in
+                        // decreasing order with their axis steps (a stable sort:
+                        // equal fractions keep the lower axis first), vertices
+                        // from the lower corner one sorted step at a time, nested
+                        // interpolations from the far vertex
+                        T t0 = fx, t1 = fy, t2 = fz;
+                        int o0 = 1, o1 = LW, o2 = PL;
+                        if (t1 > t0) { const T t = t0; t0 = t1; t1 = t; const int o = o0; o0 = o1; o1 = o; }
+                        if (t2 > t1) { const T t = t1; t1 = t2; t2 = t; const int o = o1; o1 = o2; o2 = o; }
+                        if (t1 > t0) { const T t = t0; t0 = t1; t1 = t; const int o = o0; o0 = o1; o1 = o; }
+                        const T v0 = lds[base], v1 = lds[base + o0], v2 = lds[base + o0 + o1];
+                        const T v3 = lds[base + 1 + LW + PL];
+                        const T s2 = simplex_ratio(t2, t1), s1 = simplex_ratio(t1, t0);
+                        const T i2 = fma_(s2, v3, (T(1) - s2) * v2);
+                        const T i1 = fma_(s1, i2, (T(1) - s1) * v1);
+                        acc = fma_(t0, i1, (T(1) - t0) * v0);
+                        (void)o2;
+                    } else {
                     // nested one-axis interpolations, x, then y, then z (as in 2D)
                     const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
                     const T v000 = lds[base], v100 = lds[base + 1];
@@ -507,7 +527,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                     const T b1 = fma_(fx, v111, ax * v011);
                     const T c0 = fma_(fy, b0, ay * a0);
                     const T c1 = fma_(fy, b1, ay * a1);
-                    const T acc = fma_(fz, c1, az * c0);
+                    acc = fma_(fz, c1, az * c0);
+                    }
                     const T cand = fma_(bt[r], acc, wl[r]);
                     if (POLICY) {
                         if (cand < inner[r]) {
@@ -595,7 +616,7 @@ __global__ void k_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol, Exe
 struct Variant {
     int dim, dtype, tile[3], threads;
     const void *fn[kMaxHalo + 1][2];    // [H][policy]
-    const void *fn_p1[kMaxHalo + 1][2]; // P1 interpolation (2D; null where not built)
+    const void *fn_p1[kMaxHalo + 1][2]; // P1 interpolation (null where not built)
     size_t lds_bytes[kMaxHalo + 1];     // dynamic LDS (3D only)
 };
 
@@ -609,10 +630,14 @@ void fill2d(Variant &v) {
     }
     v.lds_bytes[H] = 0;
 }
-template <typename T, int TX, int TY, int TZ, int H>
+template <typename T, int TX, int TY, int TZ, int H, bool WITH_P1>
 void fill3d(Variant &v) {
-    v.fn[H][0] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, false>;
-    v.fn[H][1] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, true>;
+    v.fn[H][0] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, false, false>;
+    v.fn[H][1] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, true, false>;
+    if (WITH_P1) {
+        v.fn_p1[H][0] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, false, WITH_P1>;
+        v.fn_p1[H][1] = (const void *)&k_sweep3d<T, TX, TY, TZ, H, true, WITH_P1>;
+    }
     v.lds_bytes[H] = sizeof(T) * (size_t)(TX + 2 * H) * (TY + 2 * H) * (TZ + 2 * H);
 }
 
@@ -632,16 +657,17 @@ Variant make2d() {
     fill2d<T, TX, TY, 16, S, P>(v);
     return v;
 }
-template <typename T, int TX, int TY, int TZ>
+template <typename T, int TX, int TY, int TZ, bool P = false>
 Variant make3d() {
     Variant v{};
     v.dim = 3;
     v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = TZ;
     v.threads = kThreads;
-    fill3d<T, TX, TY, TZ, 1>(v); fill3d<T, TX, TY, TZ, 2>(v); fill3d<T, TX, TY, TZ, 3>(v);
-    fill3d<T, TX, TY, TZ, 4>(v); fill3d<T, TX, TY, TZ, 5>(v); fill3d<T, TX, TY, TZ, 6>(v);
-    fill3d<T, TX, TY, TZ, 7>(v); fill3d<T, TX, TY, TZ, 8>(v);
+    fill3d<T, TX, TY, TZ, 1, P>(v); fill3d<T, TX, TY, TZ, 2, P>(v);
+    fill3d<T, TX, TY, TZ, 3, P>(v); fill3d<T, TX, TY, TZ, 4, P>(v);
+    fill3d<T, TX, TY, TZ, 5, P>(v); fill3d<T, TX, TY, TZ, 6, P>(v);
+    fill3d<T, TX, TY, TZ, 7, P>(v); fill3d<T, TX, TY, TZ, 8, P>(v);
     return v;
 }
 
@@ -652,13 +678,13 @@ const Variant *variants(int *count) {
         make2d<float, 64, 4>(),    // 2
         make2d<float, 32, 16>(),   // 3
         make2d<double, 64, 8, 1, true>(),   // 4: FP64 2D (also P1)
-        make3d<float, 32, 8, 8>(), // 5: default FP32 3D
+        make3d<float, 32, 8, 8, true>(),  // 5: default FP32 3D (also P1)
         make3d<float, 32, 8, 4>(), // 6
         make3d<float, 16, 16, 4>(),// 7
-        make3d<double, 16, 8, 8>(),// 8: FP64 3D
+        make3d<double, 16, 8, 8, true>(), // 8: FP64 3D (also P1)
         make2d<double, 32, 8, 1, true>(),   // 9: FP64 2D, small tiles (coarse grids; also P1)
         make2d<double, 16, 16>(),  // 10
-        make3d<double, 8, 8, 8>(), // 11: FP64 3D, small tiles
+        make3d<double, 8, 8, 8, true>(),  // 11: FP64 3D, small tiles (also P1)
         make3d<double, 16, 8, 4>(),// 12
         make2d<float, 32, 16, 2>(), // 13: FP32 2D, controls split over 2 groups
         make2d<float, 32, 16, 4>(), // 14: ... over 4 groups
@@ -699,7 +725,7 @@ int sweep_variants(int dim, LaunchCfg *out, int cap) {
 bool sweep_has_p1(int variant) {
     int nv = 0;
     const Variant *vt = variants(&nv);
-    return variant >= 0 && variant < nv && vt[variant].dim == 2 && vt[variant].fn_p1[1][0];
+    return variant >= 0 && variant < nv && vt[variant].fn_p1[1][0];
 }
 
 static const void *sweep_fn(const LaunchCfg &cfg, int want_policy, size_t *lds) {
@@ -709,7 +735,7 @@ static const void *sweep_fn(const LaunchCfg &cfg, int want_policy, size_t *lds) 
     const Variant &v = vt[cfg.variant];
     if (cfg.halo > (v.dim == 2 ? kMaxHalo : kMaxHalo3D) || !v.fn[cfg.halo][0]) return nullptr;
     *lds = v.lds_bytes[cfg.halo];
-    if (cfg.interp == SL_INTERP_P1) return v.dim == 2 ? v.fn_p1[cfg.halo][want_policy ? 1 : 0] : nullptr;
+    if (cfg.interp == SL_INTERP_P1) return v.fn_p1[cfg.halo][want_policy ? 1 : 0];
     return v.fn[cfg.halo][want_policy ? 1 : 0];
 }
 

@@ -243,8 +243,8 @@ def test_kruzkov_form_accepted_by_solves_and_batch_rejected_by_adjoint():
 
 
 def test_p1_interpolation_field_is_validated():
-    """interp: Q1 (0) or P1 (1).  P1 is sized by the 2D solves and the
-    reconstruction; 3D P1 and other values are refused by every workspace query,
+    """interp: Q1 (0) or P1 (1).  P1 is sized by the solves and the
+    reconstruction in 2D and 3D; other values are refused by every workspace query,
     the batch refuses P1, and the adjoint reports SL_ERR_UNSUPPORTED (-3) before
     any device work."""
     L = S.lib()
@@ -259,9 +259,9 @@ def test_p1_interpolation_field_is_validated():
     v3 = np.eye(3)
     p3, k4 = _problem(interp=1, dim=3, m=3, velocity=v3.ctypes.data_as(C.POINTER(C.c_double)))
     p3.n[2] = 9
-    assert L.sl_solve_workspace_size(C.byref(p3)) == 0
-    p3.interp = 0
     assert L.sl_solve_workspace_size(C.byref(p3)) > 0
+    p3.interp = 3
+    assert L.sl_solve_workspace_size(C.byref(p3)) == 0
     buf = C.create_string_buffer(64)
     st = S.SlStats()
     assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,

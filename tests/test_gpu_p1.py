@@ -1,4 +1,4 @@
-"""P1 interpolation on the Kuhn simplices of each cell (2D) on the GPU against the
+"""P1 interpolation on the Kuhn simplices of each cell (2D and 3D) on the GPU against the
 oracle: FP64 bit-exact (the same nested evaluation and an exact division), FP32
 within 1e-5, sets and labels bit-exact, block-asynchronous sweeps equal to Jacobi
 bit for bit, and the 1025^2 multitarget workload in the benchmark's launch
@@ -131,3 +131,51 @@ def test_full_size_p1_benchmark_configuration():
     r = _fixed_point_residuals(p, member, host(Vs).reshape(p.n_comp, p.N))
     say("  fixed-point residuals", r, "launches", st["sweeps_max"])
     assert max(r) <= 2e-6
+
+
+def p1_3d(n, m=26):
+    return W.c3_aniso3d(n=n, m=m, n_balls=2, r=0.2).with_(interp="p1")
+
+
+@pytest.mark.parametrize("li", [0, 4])
+def test_p1_3d_global_fp64_bit_exact(li):
+    p = p1_3d(25)
+    say("case: p1 3d global fp64 25 local", li)
+    V, _, st = S.solve(S.to_device(p, torch.float64),
+                       S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=li))
+    Vo, _, _, _ = O.solve(p)
+    assert st["converged"]
+    assert np.array_equal(host(V), Vo)
+
+
+def test_p1_3d_fp32_and_block_async():
+    p = p1_3d(33)
+    say("case: p1 3d fp32 33")
+    dp = S.to_device(p, torch.float32)
+    V, _, st = S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    Vo, _, _, _ = O.solve(p)
+    err = np.abs(host(V).astype(np.float64) - Vo).max()
+    say("  sup err", err)
+    assert st["converged"] and err <= 1e-5
+    assert np.abs(O.solve(p.with_(interp="q1"))[0] - Vo).max() > 1e-4
+    Va, _, sta = S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=4))
+    say("  local 4 launches", sta["sweeps_max"], "vs", st["sweeps_max"])
+    assert torch.equal(Va, V)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_p1_3d_isa(dtype):
+    p = p1_3d(33)
+    say("case: p1 3d isa 33", dtype)
+    dp = S.to_device(p, dtype)
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra_of(p), S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    Vbar, own_o, rec, Vs_o, _ = I.isa(p)
+    assert st["converged"]
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
+    if dtype == torch.float64:
+        assert np.array_equal(host(V), Vbar)
+    else:
+        err = np.abs(host(V).astype(np.float64) - Vbar).max()
+        say("  sup err", err)
+        assert err <= 1e-5
