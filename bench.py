@@ -43,6 +43,10 @@ OPS_PER_NC_2D_P1 = 20
 # 3D: foot 3, index 3, fraction 3, Q1 (1-tau 3, 7 mul, 7 fma), candidate 1,
 #     min 1 -> 28
 OPS_PER_NC_3D = 28
+# 3D P1: foot 3, index 3, fraction 3, sort (3 compare-swaps: compare, 2 selects) 9,
+#     ratios (2 x reciprocal, mul, clamp) 6, nested (3 x 1-s, mul, fma) 9,
+#     candidate 1, min 1 -> 35
+OPS_PER_NC_3D_P1 = 35
 # Headline sweep configuration: autotuner candidate 22 of the 2D FP32 kernels
 # (32x8 tiles, one node per thread, one work-group per item) with block-
 # asynchronous sweeps of up to 8 local iterations per tile and launch, the
@@ -53,7 +57,7 @@ DEFAULT_LOCAL_ITERS = 8
 # The other workloads' fine sweeps: local iterations per tile and launch, the
 # faster of 4 and 8 measured on each (3D and the 288-candidate game do more work
 # per evaluation, so their tiles settle in fewer iterations per launch)
-LEG_LOCAL_ITERS = {"c3": 4, "pe": 4}
+LEG_LOCAL_ITERS = {"c3": 4, "pe": 4, "p1_3d": 4}
 LEG_LOCAL_ITERS_DEFAULT = 8
 # Coarse FP64 pass: local iterations per tile and launch (measured per workload at
 # tol 0: 8 for the 2D workloads with 32-64 controls, 4 for 3D and for the long-
@@ -80,11 +84,12 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,kruzkov,p1,study,balance",
+    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,kruzkov,p1,p1_3d,study,balance",
                     help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
                          "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
                          "(pursuit-evasion game 513^2), kruzkov (weighted minimum time "
-                         "513^2), p1 (the headline workload with P1 interpolation), "
+                         "513^2), p1 / p1_3d (the headline / the 3D workload with P1 "
+                         "interpolation), "
                          "study (global solve vs ISA and the "
                          "RA threshold on the headline problem), balance (refinement of the "
                          "target split, Van der Pol); empty for none")
@@ -107,10 +112,25 @@ def ra_opts(p, autotune: int = 1, local: int = RA_LOCAL_ITERS):
 
 def leg_c3(steps: int, li: int):
     """3D anisotropic 257^3, 8 target balls, 128 controls: ISA to sup-res<1e-6."""
+    import workloads as W
+    return _isa_leg_3d(W.c3_aniso3d(), steps, li,
+                       "aniso3d 257^3, 8 balls r=0.04, 128 Fibonacci controls, SPD M "
+                       "(cond 4), ISA (RA on 65^3) to sup-res<1e-6")
+
+
+def leg_p1_3d(steps: int, li: int):
+    """The 3D workload with P1 interpolation on the Kuhn simplices of each cell."""
+    import workloads as W
+    return _isa_leg_3d(W.c3_aniso3d().with_(interp="p1"), steps, li,
+                       "aniso3d 257^3 with P1 (Kuhn simplices), 8 balls r=0.04, 128 "
+                       "Fibonacci controls, ISA (RA on 65^3) to sup-res<1e-6",
+                       OPS_PER_NC_3D_P1)
+
+
+def _isa_leg_3d(p, steps: int, li: int, workload: str, ops_per_nc: int = OPS_PER_NC_3D):
+    """ISA to sup-res<1e-6 of a 3D problem in FP32 (tuned kernels)."""
     import torch
     import paper_1405_3521_amd as S
-    import workloads as W
-    p = W.c3_aniso3d()
     dp = S.to_device(p, torch.float32, "cuda:0")
     ra = ra_opts(p, local=4)
     opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1, local_iters=li)
@@ -123,9 +143,8 @@ def leg_c3(steps: int, li: int):
     nc = np.mean([x["node_control_updates"] for x in sts])
     launches = np.mean([x["sweep_launches"] for x in sts])
     ms_launch = np.sum([x["ms_sweeps"] for x in sts]) / np.sum([x["sweep_launches"] for x in sts])
-    ach = OPS_PER_NC_3D * nc / launches / (ms_launch / 1e3) / 1e12
-    return {"workload": "aniso3d 257^3, 8 balls r=0.04, 128 Fibonacci controls, SPD M "
-                        "(cond 4), ISA (RA on 65^3) to sup-res<1e-6",
+    ach = ops_per_nc * nc / launches / (ms_launch / 1e3) / 1e12
+    return {"workload": workload,
             "time_to_converge_ms": ms, "node_control_updates_per_s": nc / (ms / 1e3),
             "sweeps": int(np.mean([x["sweeps_max"] for x in sts])),
             "ms_reconstruct": float(np.mean([x["ms_ra"] for x in sts])),
@@ -526,7 +545,7 @@ def main():
     for leg in [x for x in args.legs.split(",") if x]:
         fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
               "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov,
-              "p1": leg_p1}[leg]
+              "p1": leg_p1, "p1_3d": leg_p1_3d}[leg]
         t0 = time.perf_counter()
         legs[leg] = fn(max(1, min(args.steps, 3)),
                        LEG_LOCAL_ITERS.get(leg, LEG_LOCAL_ITERS_DEFAULT))
