@@ -679,8 +679,8 @@ const Variant *variants(int *count) {
         make2d<float, 32, 16>(),   // 3
         make2d<double, 64, 8, 1, true>(),   // 4: FP64 2D (also P1)
         make3d<float, 32, 8, 8, true>(),  // 5: default FP32 3D (also P1)
-        make3d<float, 32, 8, 4>(), // 6
-        make3d<float, 16, 16, 4>(),// 7
+        make3d<float, 32, 8, 4, true>(),  // 6 (also P1)
+        make3d<float, 16, 16, 4, true>(), // 7 (also P1)
         make3d<double, 16, 8, 8, true>(), // 8: FP64 3D (also P1)
         make2d<double, 32, 8, 1, true>(),   // 9: FP64 2D, small tiles (coarse grids; also P1)
         make2d<double, 16, 16>(),  // 10

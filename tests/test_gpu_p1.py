@@ -179,3 +179,27 @@ def test_p1_3d_isa(dtype):
         err = np.abs(host(V).astype(np.float64) - Vbar).max()
         say("  sup err", err)
         assert err <= 1e-5
+
+
+def test_p1_3d_tuned_configs():
+    """Every 3D P1 tuner candidate (forced one by one) is within 1e-5 of the
+    oracle, the FP32 parity bar.  Candidates are not compared bit for bit with each
+    other: FP32 foot coordinates are tile-local, so they round differently across
+    tile shapes (about 1e-6 apart here)."""
+    p = p1_3d(33)
+    say("case: p1 3d tuner candidates 33")
+    dp = S.to_device(p, torch.float32)
+    V0, _, _ = S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    Vo, _, _, _ = O.solve(p)
+    k = 1
+    while True:
+        try:
+            V, _, st = S.solve(dp, S.SolveOpts(tol=0.0, max_sweeps=CAP, autotune=-k, local_iters=4))
+        except S.SlError:
+            break
+        err = float((V - V0).abs().max())
+        err_o = np.abs(host(V).astype(np.float64) - Vo).max()
+        say("  candidate", k, "tile", st.get("tile"), "vs default", err, "vs oracle", err_o)
+        assert st["converged"] and err_o <= 1e-5
+        k += 1
+    assert k > 9            # 3 variants x 3 schedules
