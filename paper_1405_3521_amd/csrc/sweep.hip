@@ -685,7 +685,7 @@ const Variant *variants(int *count) {
         make2d<double, 32, 8, 1, true>(),   // 9: FP64 2D, small tiles (coarse grids; also P1)
         make2d<double, 16, 16>(),  // 10
         make3d<double, 8, 8, 8, true>(),  // 11: FP64 3D, small tiles (also P1)
-        make3d<double, 16, 8, 4>(),// 12
+        make3d<double, 16, 8, 4, true>(), // 12 (also P1)
         make2d<float, 32, 16, 2>(), // 13: FP32 2D, controls split over 2 groups
         make2d<float, 32, 16, 4>(), // 14: ... over 4 groups
         make2d<float, 64, 8, 4>(),  // 15

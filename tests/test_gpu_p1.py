@@ -203,3 +203,18 @@ def test_p1_3d_tuned_configs():
         assert st["converged"] and err_o <= 1e-5
         k += 1
     assert k > 9            # 3 variants x 3 schedules
+
+
+def test_p1_3d_isa_tuned_coarse_pass():
+    """The 3D reconstruction with the tuner over the FP64 P1 coarse kernels and
+    block-asynchronous coarse sweeps: sets and labels bit-exact (FP64 coordinates
+    are global, so every tile shape gives the same values)."""
+    p = p1_3d(33)
+    say("case: p1 3d tuned coarse 33")
+    dp = S.to_device(p, torch.float32)
+    ra = ra_of(p)
+    ra.autotune, ra.local_iters = 1, 4
+    member, label, _ = S.reconstruct(dp, ra)
+    rec = I.reconstruct(p)
+    assert np.array_equal(host(member), rec.member)
+    assert np.array_equal(host(label), rec.label)
