@@ -125,8 +125,9 @@ typedef struct sl_problem {
                                  grid samples each factor by Q1.  Needs speed != NULL.
                                  Every entry point takes it.                           */
     int interp;               /* sl_interp.  SL_INTERP_P1 is taken by sl_solve,
-                                 sl_reconstruct and sl_solve_isa (2D and 3D); the batch
-                                 and the adjoint return SL_ERR_UNSUPPORTED for it.      */
+                                 sl_reconstruct, sl_solve_isa (2D and 3D) and sl_adjoint
+                                 (its Jacobi iteration); sl_solve_batched returns
+                                 SL_ERR_UNSUPPORTED for it.                             */
 } sl_problem;
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */
@@ -315,7 +316,8 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
  * (index units, e c + q) are taken; games and the Kruzkov discount (the
  * discount then depends on l, so V is not linear in l) return SL_ERR_UNSUPPORTED.
  * local_iters (0..1024): 0 = the Jacobi iteration above.  k > 0 in 2D, when the
- * foot reaches at most 8 cells: block-asynchronous tiles.  Every active 32x16 tile
+ * foot reaches at most 8 cells and I[V] is Q1: block-asynchronous tiles.  With P1
+ * the scatter goes to the foot's simplex vertices with their barycentric weights.  Every active 32x16 tile
  * stages lambda, the frozen feet and the inflow from its halo in on-chip memory,
  * then repeats "lambda = g + inflow" up to k times while a node changes by more
  * than tol + 16 eps |lambda|, and writes back in place.  Tiles are revisited when

@@ -72,6 +72,40 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const AdjDesc<T> *__restri
             p[a] = ij[a] + (int)f;
         }
         const T bl = beta * ln;
+        if (d.interp == SL_INTERP_P1) {
+            // P1: the vertices of the foot's Kuhn simplex (lower corner, then one
+            // step along each axis in the order of decreasing fraction, equal
+            // fractions lower axis first) with their barycentric weights
+            int ax[3] = {0, 1, 2};
+#pragma unroll
+            for (int a = 1; a < DIM; ++a)
+                for (int b = a; b > 0 && tau[ax[b - 1]] < tau[ax[b]]; --b) {
+                    const int t = ax[b - 1];
+                    ax[b - 1] = ax[b];
+                    ax[b] = t;
+                }
+            int v[3] = {p[0], DIM > 1 ? p[1] : 0, DIM > 2 ? p[2] : 0};
+#pragma unroll
+            for (int s = 0; s <= DIM; ++s) {
+                if (s > 0) v[ax[s - 1]] += 1;
+                const T w = s == 0 ? T(1) - tau[ax[0]]
+                                   : (s < DIM ? tau[ax[s - 1]] - tau[ax[s]] : tau[ax[DIM - 1]]);
+                bool in = true;
+                size_t idx = 0, stride = 1;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int na = a == 0 ? n0 : (a == 1 ? n1 : n2);
+                    in = in && v[a] >= 0 && v[a] < na;
+                    idx += (size_t)(v[a] < 0 ? 0 : v[a]) * stride;
+                    stride *= (size_t)na;
+                }
+                if (!in || w == T(0)) continue;
+                if (d.target[idx] >= 0) continue;
+                if (mem && !((mem[idx] >> bit) & 1)) continue;
+                atomicAdd(&acc_out[idx], bl * w);
+            }
+            continue;
+        }
 #pragma unroll
         for (int q = 0; q < (1 << DIM); ++q) {
             T w = T(1);

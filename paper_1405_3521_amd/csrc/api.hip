@@ -1246,6 +1246,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         d.bit = i;
         d.set = i;
         d.speed_axes = speed_comps(p) > 1;
+        d.interp = p->interp;
     }
     HIPCHK(hipMemcpyAsync(P.ads, hd.data(), sizeof(AdjDesc<T>) * n_sets, hipMemcpyHostToDevice, s));
     std::vector<SdState> hs(n_sets);
@@ -1264,7 +1265,8 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     if (!active) return SL_ERR_HIP;
     const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
     const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
-    if (p->dim == 2 && local_iters > 0 && H <= adjoint_tiles_max_halo()) {
+    if (p->dim == 2 && local_iters > 0 && H <= adjoint_tiles_max_halo() &&
+        p->interp == SL_INTERP_Q1) {
         // block-asynchronous tiles on the sweep executor
         LaunchCfg cfg{};
         cfg.dim = 2;
@@ -1942,8 +1944,7 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
-    if (is_game(p) || p->disc == SL_DISC_KRUZKOV || p->interp != SL_INTERP_Q1)
-        return SL_ERR_UNSUPPORTED;
+    if (is_game(p) || p->disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

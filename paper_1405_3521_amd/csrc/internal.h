@@ -114,6 +114,7 @@ struct AdjDesc {
     int bit;
     int set;
     int speed_axes;             // speed holds one factor per axis
+    int interp;                 // sl_interp: the feet's stencil
 };
 
 // One problem of a batch (device memory): its fine fields (caller's), its

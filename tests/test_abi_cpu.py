@@ -245,8 +245,8 @@ def test_kruzkov_form_accepted_by_solves_and_batch_rejected_by_adjoint():
 def test_p1_interpolation_field_is_validated():
     """interp: Q1 (0) or P1 (1).  P1 is sized by the solves and the
     reconstruction in 2D and 3D; other values are refused by every workspace query,
-    the batch refuses P1, and the adjoint reports SL_ERR_UNSUPPORTED (-3) before
-    any device work."""
+    the batch refuses P1, and the adjoint takes it (and stops at the workspace
+    size, -5, before any device work)."""
     L = S.lib()
     p, k1 = _problem(interp=1)
     q, k2 = _problem()
@@ -265,4 +265,4 @@ def test_p1_interpolation_field_is_validated():
     buf = C.create_string_buffer(64)
     st = S.SlStats()
     assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
-                        C.byref(st), None) == -3
+                        C.byref(st), None) == -5
