@@ -125,9 +125,10 @@ typedef struct sl_problem {
                                  grid samples each factor by Q1.  Needs speed != NULL.
                                  Every entry point takes it.                           */
     int interp;               /* sl_interp.  SL_INTERP_P1 is taken by sl_solve,
-                                 sl_reconstruct, sl_solve_isa (2D and 3D) and sl_adjoint
-                                 (its Jacobi iteration); sl_solve_batched returns
-                                 SL_ERR_UNSUPPORTED for it.                             */
+                                 sl_reconstruct, sl_solve_isa (2D and 3D), sl_adjoint
+                                 (its Jacobi iteration) and sl_solve_batched, whose
+                                 problems must all share one interpolation (a mix
+                                 returns SL_ERR_UNSUPPORTED).                           */
 } sl_problem;
 
 /* Reconstruction algorithm options (paper Sec. 3, RA; Sec. 4, ISA steps 1-2). */

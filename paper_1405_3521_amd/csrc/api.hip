@@ -1548,6 +1548,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     };
     // 3. RA step 1 for every (problem, component): one launch per sweep
     B.exK.cfg = make_cfg(dim, SL_F64, HK, default_variant(dim, SL_F64));
+    B.exK.cfg.interp = probs[0].interp;
     B.exK.cfg.local_iters = ras[0].local_iters;
     size_t coff = 0;
     for (int q = 0; q < np; ++q) {
@@ -1593,6 +1594,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     tm.mark(1, s);
     // 5. ISA step 3 for every (problem, set): one launch per sweep
     B.ex.cfg = make_cfg(dim, probs[0].dtype, H, default_variant(dim, probs[0].dtype));
+    B.ex.cfg.interp = probs[0].interp;
     B.ex.cfg.local_iters = o->local_iters;
     coff = 0;
     for (int q = 0; q < np; ++q) {
@@ -1673,7 +1675,7 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
         if ((rc = validate_ra(&probs[q], &ras[q]))) return rc;
         if (probs[q].dim != probs[0].dim || probs[q].dtype != probs[0].dtype)
             return SL_ERR_UNSUPPORTED;
-        if (probs[q].interp != SL_INTERP_Q1) return SL_ERR_UNSUPPORTED;
+        if (probs[q].interp != probs[0].interp) return SL_ERR_UNSUPPORTED;
     }
     return SL_OK;
 }

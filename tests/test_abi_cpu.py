@@ -245,15 +245,18 @@ def test_kruzkov_form_accepted_by_solves_and_batch_rejected_by_adjoint():
 def test_p1_interpolation_field_is_validated():
     """interp: Q1 (0) or P1 (1).  P1 is sized by the solves and the
     reconstruction in 2D and 3D; other values are refused by every workspace query,
-    the batch refuses P1, and the adjoint takes it (and stops at the workspace
-    size, -5, before any device work)."""
+    the batch takes P1 but not a mix of P1 and Q1, and the adjoint takes it (and
+    stops at the workspace size, -5, before any device work)."""
     L = S.lib()
     p, k1 = _problem(interp=1)
     q, k2 = _problem()
     assert L.sl_solve_workspace_size(C.byref(p)) == L.sl_solve_workspace_size(C.byref(q)) > 0
     ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
     assert L.sl_isa_workspace_size(C.byref(p), C.byref(ra)) > 0
-    assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) == 0
+    assert L.sl_batched_workspace_size(1, C.byref(p), C.byref(ra)) > 0
+    pair = (S.SlProblem * 2)(p, q)                 # one interpolation per batch
+    ras = (S.SlRaOpts * 2)(ra, ra)
+    assert L.sl_batched_workspace_size(2, pair, ras) == 0
     bad, k3 = _problem(interp=2)
     assert L.sl_solve_workspace_size(C.byref(bad)) == 0
     v3 = np.eye(3)

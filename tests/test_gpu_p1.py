@@ -99,11 +99,31 @@ def test_p1_block_async_equals_jacobi_and_tuned_configs():
     assert err <= 1e-6
 
 
-def test_p1_rejected_by_the_batch():
-    p = p1(33)
-    dp = S.to_device(p, torch.float32)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_p1_batch_matches_oracle(dtype):
+    """A batch of P1 problems of different sizes (the batch's joint work lists
+    share one interpolation): sets and labels bit-exact per problem, FP64 values
+    bit-exact, FP32 within 1e-5; a batch mixing P1 and Q1 is refused."""
+    probs = [W.c2_multitarget(n=n, m=16, n_disks=k).with_(coarse_n=(nK, nK), interp="p1",
+                                                          name=f"p1_batch{n}")
+             for n, k, nK in ((49, 2, 17), (65, 4, 21), (33, 1, 11))]
+    say("case: batched p1", dtype)
+    dps = [S.to_device(p, dtype) for p in probs]
+    Vs, mem, lab, own, per, tot = S.solve_batched(dps, [ra_of(p) for p in probs],
+                                                  S.SolveOpts(tol=0.0, max_sweeps=CAP))
+    assert tot["converged"]
+    for p, V, m, l in zip(probs, Vs, mem, lab):
+        Vbar, owner, rec, _, _ = I.isa(p)
+        assert np.array_equal(host(m), rec.member), p.name
+        assert np.array_equal(host(l), rec.label), p.name
+        Vg = host(V).astype(np.float64)
+        if dtype == torch.float64:
+            assert np.array_equal(Vg, Vbar), p.name
+        else:
+            assert np.abs(Vg - Vbar).max() <= 1e-5, p.name
+    q = probs[0].with_(interp="q1")
     with pytest.raises((S.SlError, ValueError)):
-        S.solve_batched([dp], [ra_of(p)])
+        S.solve_batched([dps[0], S.to_device(q, dtype)], [ra_of(probs[0]), ra_of(q)])
 
 
 def _pol_u8(pol):
