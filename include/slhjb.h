@@ -54,6 +54,11 @@ extern "C" {
 #define SLHJB_ABI_VERSION 5
 #define SL_MAX_COMP 8
 #define SL_MAX_CONTROLS 256
+/* A policy output holds one control index per node in a byte and marks target and
+ * non-member nodes with 255, so the entry points that write or read a policy
+ * (sl_solve and sl_solve_isa with want_policy and a policy buffer, sl_adjoint)
+ * return SL_ERR_UNSUPPORTED for m above this. */
+#define SL_MAX_POLICY_CONTROLS 255
 #define SL_MAX_TABLE 4096     /* m * max(m_b, 1): displacement rows of a game       */
 
 typedef enum {

@@ -1730,6 +1730,7 @@ int sl_solve(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_by
     if ((rc = validate_solve_opts(o))) return rc;
     if (!V || !ws) return SL_ERR_INVALID_ARG;
     if (is_game(p) && o->want_policy && policy) return SL_ERR_UNSUPPORTED;
+    if (o->want_policy && policy && p->m > SL_MAX_POLICY_CONTROLS) return SL_ERR_UNSUPPORTED;
     if (ws_bytes < sl_solve_workspace_size(p)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == SL_F32)
@@ -1882,6 +1883,7 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
     if ((rc = validate_solve_opts(o))) return rc;
     if (!member || !V || !ws) return SL_ERR_INVALID_ARG;
     if (is_game(p) && o->want_policy && policy) return SL_ERR_UNSUPPORTED;
+    if (o->want_policy && policy && p->m > SL_MAX_POLICY_CONTROLS) return SL_ERR_UNSUPPORTED;
     if (ws_bytes < sl_isa_workspace_size(p, ra)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == SL_F32)
@@ -1947,6 +1949,7 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
     if (is_game(p) || p->disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
+    if (p->m > SL_MAX_POLICY_CONTROLS) return SL_ERR_UNSUPPORTED;
     const int n_sets = member ? p->n_comp : 1;
     if (ws_bytes < sl_adjoint_workspace_size(p, n_sets)) return SL_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;

@@ -103,6 +103,28 @@ def test_solve_argument_errors_before_device_work():
     assert L.sl_solve(C.byref(p), C.byref(opts), buf, 64, buf, None, C.byref(st), None) == -5
 
 
+def test_policy_byte_holds_at_most_255_controls():
+    """A policy byte marks target and non-member nodes with 255, so a policy output
+    (or an adjoint's policy input) with m = 256 controls is refused on the host;
+    m = 255 passes the check (and then fails on the too-small workspace)."""
+    L = S.lib()
+    st = S.SlStats()
+    buf = C.create_string_buffer(64)
+    want = S.SlSolveOpts(0.0, 100, 1, 0, 0, 0, 0)
+    ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    for m, code in ((256, -3), (255, -5)):
+        vel = np.stack([np.cos(np.arange(m)), np.sin(np.arange(m))], axis=1)
+        p, keep = _problem(m=m, velocity=vel.ctypes.data_as(C.POINTER(C.c_double)))
+        assert L.sl_solve(C.byref(p), C.byref(want), buf, 64, buf, buf, C.byref(st), None) == code
+        assert L.sl_solve_isa(C.byref(p), C.byref(ra), buf, C.byref(want), buf, 64, buf, None,
+                              buf, None, C.byref(st), None) == code
+        assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, 0.0, 10, 0, buf, 64,
+                            C.byref(st), None) == code
+        # without a policy buffer the control count may reach SL_MAX_CONTROLS
+        nopol = S.SlSolveOpts(0.0, 100, 0, 0, 0, 0, 0)
+        assert L.sl_solve(C.byref(p), C.byref(nopol), buf, 64, buf, None, C.byref(st), None) == -5
+
+
 def test_reconstruction_argument_errors():
     L = S.lib()
     p, keep = _problem()
