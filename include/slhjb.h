@@ -59,6 +59,9 @@ extern "C" {
  * (sl_solve and sl_solve_isa with want_policy and a policy buffer, sl_adjoint)
  * return SL_ERR_UNSUPPORTED for m above this. */
 #define SL_MAX_POLICY_CONTROLS 255
+/* Bytes of the device scratch array that sl_solve_noalloc uses as its workspace
+ * (one copy per device, held from the library's load until the process ends). */
+#define SL_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
 #define SL_MAX_TABLE 4096     /* m * max(m_b, 1): displacement rows of a game       */
 
 typedef enum {
@@ -68,7 +71,9 @@ typedef enum {
     SL_ERR_NO_TARGET = -2,    /* no target node (checked on the device)            */
     SL_ERR_UNSUPPORTED = -3,  /* dim, control count or component count out of range */
     SL_ERR_HIP = -4,          /* a HIP runtime call failed                          */
-    SL_ERR_WORKSPACE = -5     /* workspace smaller than the query says              */
+    SL_ERR_WORKSPACE = -5,    /* workspace smaller than the query says              */
+    SL_ERR_SCRATCH = -6       /* sl_solve_noalloc: the problem's workspace exceeds
+                                 SL_NOALLOC_SCRATCH_BYTES                             */
 } sl_status;
 
 typedef enum { SL_F32 = 0, SL_F64 = 1 } sl_dtype;
@@ -226,6 +231,26 @@ size_t sl_solve_workspace_size(const sl_problem *p);
  * v_ghost. */
 int sl_solve(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_bytes,
              void *V, uint8_t *policy, sl_stats *stats, void *stream);
+
+/* sl_solve without a workspace argument and without any allocation, for callers
+ * that cannot allocate memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc).  It runs the global solve of sl_solve with
+ * the same kernels and arguments, so its outputs equal sl_solve's bit for bit,
+ * and takes its workspace from a static device array of SL_NOALLOC_SCRATCH_BYTES
+ * bytes on the current device (the device the caller's stream belongs to must be
+ * current).  It calls no hipMalloc/hipFree, creates no events, streams or graphs
+ * (the sweep chunks are launched directly, not replayed from a captured graph),
+ * and polls convergence into host stack memory.
+ * Limits: sl_solve_workspace_size(p) must be at most SL_NOALLOC_SCRATCH_BYTES, else
+ * SL_ERR_SCRATCH (about 2.8 million FP32 nodes with a cost field, e.g. 1025^2 and
+ * 129^3); o->autotune must be <= 0 and o->profile 0 (both time with HIP events),
+ * else SL_ERR_INVALID_ARG; stats->ms_* are 0.  Every call on a device shares that
+ * device's array and every call re-initialises what it reads, so consecutive calls
+ * are independent, but calls that overlap in time on one device (other host
+ * threads or streams) race on the array and must be serialised by the caller.
+ * Arguments, outputs and other errors: as sl_solve. */
+int sl_solve_noalloc(const sl_problem *p, const sl_solve_opts *o, void *V, uint8_t *policy,
+                     sl_stats *stats, void *stream);
 
 /* Workspace bytes needed by sl_reconstruct / sl_solve_isa. */
 size_t sl_isa_workspace_size(const sl_problem *p, const sl_ra_opts *ra);

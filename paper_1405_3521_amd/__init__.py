@@ -19,6 +19,7 @@ import numpy as np
 
 __all__ = [
     "DeviceProblem", "RaOpts", "SolveOpts", "lib", "lib_path", "to_device", "solve",
+    "solve_noalloc",
     "reconstruct", "solve_isa", "isa", "adjoint", "solve_batched", "refine_split", "SlError",
     "HJBSolve",
 ]
@@ -105,6 +106,9 @@ def lib():
         L.sl_solve.argtypes = [P(SlProblem), P(SlSolveOpts), C.c_void_p, C.c_size_t, C.c_void_p,
                                C.c_void_p, P(SlStats), C.c_void_p]
         L.sl_solve.restype = C.c_int
+        L.sl_solve_noalloc.argtypes = [P(SlProblem), P(SlSolveOpts), C.c_void_p, C.c_void_p,
+                                       P(SlStats), C.c_void_p]
+        L.sl_solve_noalloc.restype = C.c_int
         L.sl_isa_workspace_size.argtypes = [P(SlProblem), P(SlRaOpts)]
         L.sl_isa_workspace_size.restype = C.c_size_t
         L.sl_reconstruct.argtypes = [P(SlProblem), P(SlRaOpts), C.c_void_p, C.c_size_t,
@@ -354,6 +358,30 @@ def solve(p: DeviceProblem, opts: SolveOpts = SolveOpts(), out=None, policy=None
                     C.byref(st), _stream())
     if rc < 0:
         raise SlError("sl_solve", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    return V, pol, d
+
+
+def solve_noalloc(p: DeviceProblem, opts: SolveOpts = SolveOpts(), out=None, policy=None):
+    """The global solve of ``solve`` through sl_solve_noalloc: the library takes its
+    workspace from its static device scratch instead of a caller workspace (see
+    slhjb.h for the size limit).  ``out`` and ``policy`` are the caller's output
+    tensors (allocated here when None).  Returns (V, policy or None, stats)."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    V = out if out is not None else torch.empty(p.N, dtype=p.dtype, device=dev)
+    _check_tensor(V, p.dtype, p.N, "out")
+    pol = policy
+    if opts.want_policy and pol is None:
+        pol = torch.full((p.N,), 255, dtype=torch.uint8, device=dev)
+    st = SlStats()
+    rc = L.sl_solve_noalloc(C.byref(cp), C.byref(_so(opts)), _ptr(V), _ptr(pol), C.byref(st),
+                            _stream())
+    if rc < 0:
+        raise SlError("sl_solve_noalloc", rc)
     d = st.as_dict()
     d["converged"] = rc == SL_OK
     return V, pol, d

@@ -21,6 +21,14 @@
 
 using namespace slhjb;
 
+// ------------------------------------------------------- no-allocation scratch
+// The workspace of sl_solve_noalloc: a file-scope device array that the code
+// object carries, so each device holds its own copy from module load until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its host
+// name is a stand-in, not a device address): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SL_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 // ------------------------------------------------------------------ workspace
@@ -231,10 +239,10 @@ hipStream_t capture_stream() {
 struct ChunkLoop {
     double ms = 0.0;         // HIP-event time of the chunks (profile)
     long launches = 0;
+    // `active`: host int the enqueued copy writes the active-set counter to
     template <class F>
     int run(F enqueue, long max_steps, int chunk, hipStream_t s, int use_graph, int profile,
-            long *done, int *status) {
-        int *active = pinned().active;
+            long *done, int *status, int *active) {
         if (!active) return SL_ERR_HIP;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
@@ -475,10 +483,14 @@ struct Exec {
     double ms_sweeps = 0.0;
     long sweep_launches = 0;
     int use_graph = 1;
+    // no_alloc: no graph capture, no events, and the convergence poll lands in a
+    // plain host int (no pinned allocation) -- the path of sl_solve_noalloc
+    int no_alloc = 0;
+    int poll_host = 0;
 
     int run(double tol, long max_sweeps, int check_every, int want_policy, hipStream_t s,
             long *sweeps_done, int profile = 0) {
-        int *active = pinned().active;
+        int *active = no_alloc ? &poll_host : pinned().active;
         if (!active) return SL_ERR_HIP;
         const int chunk = check_every > 0 ? check_every : 32;
         auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
@@ -493,7 +505,8 @@ struct Exec {
         ChunkLoop loop;
         long S = 0;
         int status = SL_NOT_CONVERGED;
-        int rc = loop.run(enqueue, max_sweeps, chunk, s, use_graph, profile, &S, &status);
+        int rc = loop.run(enqueue, max_sweeps, chunk, s, no_alloc ? 0 : use_graph,
+                          no_alloc ? 0 : profile, &S, &status, active);
         if (rc) return rc;
         ms_sweeps += loop.ms;
         sweep_launches += loop.launches;
@@ -652,9 +665,10 @@ void fill_cfg(sl_stats *stats, const LaunchCfg &c) {
 struct Timer {
     hipEvent_t e[4]{};
     bool ok = false;
-    Timer() {
-        ok = true;
-        for (auto &x : e) ok = ok && hipEventCreate(&x) == hipSuccess;
+    explicit Timer(bool on = true) {
+        ok = on;
+        if (on)
+            for (auto &x : e) ok = ok && hipEventCreate(&x) == hipSuccess;
     }
     ~Timer() {
         for (auto &x : e)
@@ -736,13 +750,14 @@ int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **
 
 template <typename T>
 int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_bytes,
-                 T *V, uint8_t *policy, sl_stats *stats, hipStream_t s) {
-    Timer tm;
+                 T *V, uint8_t *policy, sl_stats *stats, hipStream_t s, bool no_alloc = false) {
+    Timer tm(!no_alloc);
     tm.mark(0, s);
     const size_t N = nodes_of(p);
     const int variant = default_variant(p->dim, p->dtype);
     Arena a{(char *)ws, ws_bytes};
     Exec<T> ex;
+    ex.no_alloc = no_alloc ? 1 : 0;
     T *Vb[2], *wl, *ctrl, *q = nullptr, *bn = nullptr;
     FieldStats *fs_dev;
     plan_global<T>(p, a, ex, Vb, &wl, &ctrl, &fs_dev, variant, &q, &bn);
@@ -1339,7 +1354,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     ChunkLoop loop;
     long it = 0;
     int status = SL_NOT_CONVERGED;
-    if ((rc = loop.run(enqueue, max_iters, 32, s, 1, 0, &it, &status))) return rc;
+    if ((rc = loop.run(enqueue, max_iters, 32, s, 1, 0, &it, &status, active))) return rc;
     HIPCHK(launch_bookkeep(P.st, n_sets, 0, tol, P.cnt, 1, s, scale_rel));
     HIPCHK(launch_adjoint_combine<T>(P.ads, n_sets, p->target, N, (T)w, dLdl, s));
     tm.mark(2, s);
@@ -1680,6 +1695,27 @@ int validate_batch(int np, const sl_problem *probs, const sl_ra_opts *ras) {
     return SL_OK;
 }
 
+// ------------------------------------------------------- no-allocation scratch
+// Device address of `scratch` (declared at file scope above) on the current
+// device, taken once per device with that device current.
+constexpr int kMaxScratchDevices = 64;
+
+int noalloc_scratch(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices)
+        return SL_ERR_HIP;
+    static std::mutex mu;
+    static void *ptr[kMaxScratchDevices] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return SL_ERR_HIP;
+        ptr[dev] = q;
+    }
+    *out = ptr[dev];
+    return SL_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1694,6 +1730,8 @@ const char *sl_status_string(int status) {
     case SL_ERR_UNSUPPORTED: return "unsupported configuration";
     case SL_ERR_HIP: return "HIP runtime error";
     case SL_ERR_WORKSPACE: return "workspace too small";
+    case SL_ERR_SCRATCH:
+        return "problem needs more than the static scratch of the no-allocation entry point";
     default: return "unknown status";
     }
 }
@@ -1736,6 +1774,26 @@ int sl_solve(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_by
     if (p->dtype == SL_F32)
         return solve_global<float>(p, o, ws, ws_bytes, (float *)V, policy, stats, s);
     return solve_global<double>(p, o, ws, ws_bytes, (double *)V, policy, stats, s);
+}
+
+int sl_solve_noalloc(const sl_problem *p, const sl_solve_opts *o, void *V, uint8_t *policy,
+                     sl_stats *stats, void *stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if ((rc = validate_solve_opts(o))) return rc;
+    if (!V) return SL_ERR_INVALID_ARG;
+    if (o->autotune > 0 || o->profile) return SL_ERR_INVALID_ARG;   // both need HIP events
+    if (is_game(p) && o->want_policy && policy) return SL_ERR_UNSUPPORTED;
+    if (o->want_policy && policy && p->m > SL_MAX_POLICY_CONTROLS) return SL_ERR_UNSUPPORTED;
+    if (sl_solve_workspace_size(p) > SL_NOALLOC_SCRATCH_BYTES) return SL_ERR_SCRATCH;
+    void *ws = nullptr;
+    if ((rc = noalloc_scratch(&ws))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == SL_F32)
+        return solve_global<float>(p, o, ws, SL_NOALLOC_SCRATCH_BYTES, (float *)V, policy, stats,
+                                   s, true);
+    return solve_global<double>(p, o, ws, SL_NOALLOC_SCRATCH_BYTES, (double *)V, policy, stats,
+                                s, true);
 }
 
 size_t sl_isa_workspace_size(const sl_problem *p, const sl_ra_opts *ra) {

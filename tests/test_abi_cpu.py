@@ -35,7 +35,7 @@ def test_abi_version_matches_header():
 
 def test_status_strings():
     L = S.lib()
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert L.sl_status_string(code)
     assert b"unknown" in L.sl_status_string(42)
 
@@ -123,6 +123,35 @@ def test_policy_byte_holds_at_most_255_controls():
         # without a policy buffer the control count may reach SL_MAX_CONTROLS
         nopol = S.SlSolveOpts(0.0, 100, 0, 0, 0, 0, 0)
         assert L.sl_solve(C.byref(p), C.byref(nopol), buf, 64, buf, None, C.byref(st), None) == -5
+
+
+def test_noalloc_entry_point_host_checks():
+    """sl_solve_noalloc refuses, before any device work: problems whose workspace
+    exceeds the static scratch (SL_ERR_SCRATCH), the options that time with HIP
+    events (autotune > 0, profile), and everything sl_solve refuses."""
+    L = S.lib()
+    st = S.SlStats()
+    buf = C.create_string_buffer(64)
+    limit = 32 << 20
+    m = re.search(r"#define SL_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)",
+                  open(HEADER).read())
+    assert (int(m.group(1)) << int(m.group(2))) == limit
+    opts = S.SlSolveOpts(0.0, 100, 0, 0, 0, 0, 0)
+    big, keep = _problem()
+    big.n[0], big.n[1] = 2049, 2049
+    assert L.sl_solve_workspace_size(C.byref(big)) > limit
+    assert L.sl_solve_noalloc(C.byref(big), C.byref(opts), buf, None, C.byref(st), None) == -6
+    assert b"static scratch" in L.sl_status_string(-6)
+    small, keep2 = _problem()
+    assert L.sl_solve_workspace_size(C.byref(small)) <= limit
+    for bad in (S.SlSolveOpts(0.0, 100, 0, 0, 0, 1, 0), S.SlSolveOpts(0.0, 100, 0, 0, 1, 0, 0),
+                S.SlSolveOpts(-1.0, 100, 0, 0, 0, 0, 0)):
+        assert L.sl_solve_noalloc(C.byref(small), C.byref(bad), buf, None, C.byref(st),
+                                  None) == -1
+    assert L.sl_solve_noalloc(C.byref(small), C.byref(opts), None, None, C.byref(st), None) == -1
+    assert L.sl_solve_noalloc(None, C.byref(opts), buf, None, C.byref(st), None) == -1
+    q, keep3 = _problem(dim=1)
+    assert L.sl_solve_noalloc(C.byref(q), C.byref(opts), buf, None, C.byref(st), None) == -3
 
 
 def test_reconstruction_argument_errors():
