@@ -152,7 +152,8 @@ __device__ __forceinline__ double floor_<double>(double x) { return __builtin_fl
 template <typename T, int H>
 __global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
     const SdDesc<T> *__restrict__ sds, SdState *__restrict__ st, int n_sd,
-    const WorkItem *__restrict__ items, ExecCounters *__restrict__ cnt, int iter_rel,
+    const WorkItem *__restrict__ items, WorkItem *__restrict__ lists,
+    ExecCounters *__restrict__ cnt, int iter_rel,
     double tol, double scale_rel, int *__restrict__ stamp, int stamp_stride, int mode, int cls,
     int do_bookkeep, int local_iters) {
     constexpr int TX = kAdjTX, TY = kAdjTY;
@@ -167,7 +168,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
 
     const int iter = cnt->sweep_base + iter_rel;
     if (do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, iter, tol, cnt, 0, scale_rel);
-    const int n_items = cnt->class_items[cls];
+    const ItemList list = sweep_items(items, lists, stamp_stride, cnt, cls, iter, false);
+    const int n_items = list.n;
     const int slot = iter % 3;
     int *queue = &cnt->class_queue[cls][slot];
     const int tx = threadIdx.x % TX, ty0 = threadIdx.x / TX;
@@ -176,10 +178,9 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
     for (int item = mode == 1 ? next_item(queue) : (int)blockIdx.x; item < n_items;
          item = mode == 1 ? next_item(queue)
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
-        const WorkItem it = items[item];
+        const WorkItem it = list.items[item];
         SdState *sst = st + it.sd;
-        const int stp = stamp[(size_t)(iter & 1) * stamp_stride + it.tflat];
-        if (sd_skip(sst, iter, tol, scale_rel) || (iter > 0 && stp != iter)) continue;
+        if (sd_skip(sst, iter, tol, scale_rel)) continue;
         const SdDesc<T> &d = sds[it.sd];
         const int n0 = d.n[0], n1 = d.n[1];
         const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
@@ -334,9 +335,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
         block_max_to(lmax, &sst->scale[iter % 3]);
         const double bm = block_max_to(rmax, &sst->res[iter % 3]);
         (void)bm;
-        if (threadIdx.x == 0 && tile_changed)
-            stamp_neighbourhood<RX, RY, 0>(stamp + (size_t)((iter + 1) & 1) * stamp_stride,
-                                         d.tile_offset, it.t, d.tiles, iter + 1);
+        if (threadIdx.x < 64 && tile_changed)
+            stamp_and_list<RX, RY, 0>(stamp + (size_t)((iter + 1) & 1) * stamp_stride, it,
+                                      d.tile_offset, d.tiles, iter + 1,
+                                      lists + (size_t)((iter + 1) & 1) * stamp_stride,
+                                      &cnt->class_count[cls][(iter + 1) % 3]);
     }
     block_sum_to(nact, &cnt->nc_updates);
 }
@@ -391,8 +394,9 @@ hipError_t adjoint_tiles_set_attributes(LaunchCfg &cfg) {
 
 template <typename T>
 hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdState *st,
-                                int n_sd, const WorkItem *items, ExecCounters *cnt,
-                                int max_items, int iter_rel, double tol, double scale_rel,
+                                int n_sd, const WorkItem *items, WorkItem *lists,
+                                ExecCounters *cnt, int max_items, int iter_rel, double tol,
+                                double scale_rel,
                                 int *stamp, int stamp_stride, int cls, int do_bookkeep,
                                 hipStream_t s) {
     const void *fn = adjoint_tiles_fn<T>(cfg.halo);
@@ -401,14 +405,14 @@ hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdSt
     int mode = cfg.mode;
     if (mode && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
     int local_iters = cfg.local_iters;
-    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&cnt,
-                    (void *)&iter_rel, (void *)&tol, (void *)&scale_rel, (void *)&stamp,
+    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&lists,
+                    (void *)&cnt, (void *)&iter_rel, (void *)&tol, (void *)&scale_rel, (void *)&stamp,
                     (void *)&stamp_stride, (void *)&mode, (void *)&cls, (void *)&do_bookkeep,
                     (void *)&local_iters};
     return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, 0, s);
 }
-template hipError_t launch_adjoint_tiles<float>(const LaunchCfg &, const SdDesc<float> *, SdState *, int, const WorkItem *, ExecCounters *, int, int, double, double, int *, int, int, int, hipStream_t);
-template hipError_t launch_adjoint_tiles<double>(const LaunchCfg &, const SdDesc<double> *, SdState *, int, const WorkItem *, ExecCounters *, int, int, double, double, int *, int, int, int, hipStream_t);
+template hipError_t launch_adjoint_tiles<float>(const LaunchCfg &, const SdDesc<float> *, SdState *, int, const WorkItem *, WorkItem *, ExecCounters *, int, int, double, double, int *, int, int, int, hipStream_t);
+template hipError_t launch_adjoint_tiles<double>(const LaunchCfg &, const SdDesc<double> *, SdState *, int, const WorkItem *, WorkItem *, ExecCounters *, int, int, double, double, int *, int, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_adjoint_iter(int dim, const AdjDesc<T> *ads, SdState *st, int n_sets,

@@ -361,6 +361,7 @@ struct Exec {
     SdDesc<T> *sds = nullptr;       // device
     SdState *st = nullptr;          // device
     WorkItem *items = nullptr;      // device
+    WorkItem *lists = nullptr;      // device, 2 x tiles: active lists by sweep parity
     ExecCounters *cnt = nullptr;    // device
     int *prefix = nullptr;          // device
     int *stamp = nullptr;           // device, 2 x tiles: sweep each tile must be computed in
@@ -381,6 +382,7 @@ struct Exec {
         sds = a.take<SdDesc<T>>(nsd);
         st = a.take<SdState>(nsd);
         items = a.take<WorkItem>(tiles_total > 0 ? tiles_total : 1);
+        lists = a.take<WorkItem>(2 * (size_t)(tiles_total > 0 ? tiles_total : 1));
         cnt = a.take<ExecCounters>(1);
         prefix = a.take<int>(nsd);
         stamp_stride = tiles_total > 0 ? tiles_total : 1;
@@ -463,10 +465,12 @@ struct Exec {
             if (class_cap[c] == 0) continue;
             const hipError_t e =
                 kind == 1
-                    ? launch_adjoint_tiles<T>(ccfg[c], sds, st, n_sd, items + class_off[c], cnt,
+                    ? launch_adjoint_tiles<T>(ccfg[c], sds, st, n_sd, items + class_off[c],
+                                              lists + class_off[c], cnt,
                                               class_cap[c], sweep_rel, tol, scale_rel, stamp,
                                               stamp_stride, (int)c, first ? 1 : 0, q)
-                    : launch_sweep(ccfg[c], sds, st, n_sd, items + class_off[c], cnt,
+                    : launch_sweep(ccfg[c], sds, st, n_sd, items + class_off[c],
+                                   lists + class_off[c], cnt,
                                    class_cap[c], sweep_rel, tol, want_policy, stamp,
                                    stamp_stride, (int)c, first ? 1 : 0, q);
             if (e != hipSuccess) return e;

@@ -139,26 +139,66 @@ __device__ __forceinline__ double sample_q1(const T *f, int comps, int q, int n0
 // equal its old ones, and the output buffer already holds them (it holds the
 // iterate of sweep s-1, equal to that of sweep s).  A tile that changes in sweep
 // s therefore stamps every tile of its neighbourhood (itself included) with s+1,
-// and sweep s computes a tile iff its stamp is s.  The stamps are double buffered
-// by sweep parity: sweep s reads stamp[s & 1], written only in sweep s-1, and
-// writes stamp[(s+1) & 1], so every wave of a work-group reads the same value and
-// takes the same decision.  Concurrent writers store the same value.
+// and sweep s computes exactly the tiles stamped s.  The stamps are double
+// buffered by sweep parity (sweep s writes stamp[(s+1) & 1]).
+//
+// Active lists.  The first writer of stamp s+1 on a tile (atomic exchange) also
+// appends the tile's work item to the active list of sweep s+1 (one list per
+// sweep parity and halo class, its length in class_count[cls][(s+1) % 3]).
+// Sweep s > 0 launches over that list only, so the work-groups that do work are
+// the first ones of the grid: the hardware spreads them evenly over the compute
+// units, instead of leaving them wherever they happen to fall among thousands of
+// skipped tiles.  Sweep 0 takes every item of the class.
+//
+// Called by every lane of wave 0 of the work-group: one lane per neighbour tile.
 template <int RX, int RY, int RZ>
-__device__ __forceinline__ void stamp_neighbourhood(int *next, int off, const int *t,
-                                                    const int *nt, int s) {
-    for (int dz = -RZ; dz <= RZ; ++dz) {
-        const int z = t[2] + dz;
-        if (z < 0 || z >= nt[2]) continue;
-        for (int dy = -RY; dy <= RY; ++dy) {
-            const int y = t[1] + dy;
-            if (y < 0 || y >= nt[1]) continue;
-            for (int dx = -RX; dx <= RX; ++dx) {
-                const int x = t[0] + dx;
-                if (x < 0 || x >= nt[0]) continue;
-                next[off + (z * nt[1] + y) * nt[0] + x] = s;
-            }
+__device__ __forceinline__ void stamp_and_list(int *next_stamp, const WorkItem &it, int off,
+                                               const int *nt, int s, WorkItem *next_list,
+                                               int *next_count) {
+    constexpr int NX = 2 * RX + 1, NY = 2 * RY + 1, NZ = 2 * RZ + 1;
+    static_assert(NX * NY * NZ <= 64, "neighbourhood larger than a wave");
+    const int lane = (int)(threadIdx.x & 63);
+    bool fresh = false;
+    int x = 0, y = 0, z = 0, idx = 0;
+    if (lane < NX * NY * NZ) {
+        x = it.t[0] + lane % NX - RX;
+        y = it.t[1] + (lane / NX) % NY - RY;
+        z = it.t[2] + lane / (NX * NY) - RZ;
+        if (x >= 0 && x < nt[0] && y >= 0 && y < nt[1] && z >= 0 && z < nt[2]) {
+            idx = off + (z * nt[1] + y) * nt[0] + x;
+            fresh = atomicExch(&next_stamp[idx], s) != s;
         }
     }
+    const unsigned long long mask = __ballot(fresh);
+    if (!mask) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(next_count, (int)__popcll(mask));
+    base = __shfl(base, 0, 64);
+    if (fresh) {
+        WorkItem w;
+        w.sd = it.sd;
+        w.t[0] = x;
+        w.t[1] = y;
+        w.t[2] = z;
+        w.tflat = idx;
+        w.pad[0] = w.pad[1] = w.pad[2] = 0;
+        next_list[base + (int)__popcll(mask & ((1ull << lane) - 1ull))] = w;
+    }
+}
+
+// The work items of sweep `sweep` of halo class `cls`: every item of the class
+// (sweep 0, and passes that visit every tile), else the class's active list.
+// `lists` points at the class's segment of the parity-0 list; the parity-1 list
+// starts `list_stride` items later.
+struct ItemList {
+    const WorkItem *items;
+    int n;
+};
+__device__ __forceinline__ ItemList sweep_items(const WorkItem *items, const WorkItem *lists,
+                                                int list_stride, const ExecCounters *cnt,
+                                                int cls, int sweep, bool every) {
+    if (every || sweep == 0) return {items, cnt->class_items[cls]};
+    return {lists + (size_t)(sweep & 1) * list_stride, cnt->class_count[cls][sweep % 3]};
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -244,7 +284,11 @@ __device__ void bookkeep_block(SdState *st, int n_sd, int sweep, double tol,
         s.scale[(sweep + 1) % 3] = 0ull;
     }
     __syncthreads();
-    if (threadIdx.x < kMaxClasses) cnt->class_queue[threadIdx.x][(sweep + 1) % 3] = 0;
+    if (threadIdx.x < kMaxClasses) {
+        cnt->class_queue[threadIdx.x][(sweep + 1) % 3] = 0;
+        // the active lists that sweep `sweep` + 1 fills (read by `sweep` + 2)
+        cnt->class_count[threadIdx.x][(sweep + 2) % 3] = 0;
+    }
     if (threadIdx.x == 0) cnt->n_active = active;   // queues of the next sweep reset above
 }
 

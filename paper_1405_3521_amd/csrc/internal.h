@@ -81,6 +81,7 @@ struct ExecCounters {
     int pad2;
     int class_items[kMaxClasses];      // work items per halo class
     int class_queue[kMaxClasses][3];   // per-class, per-sweep work-queue heads
+    int class_count[kMaxClasses][3];   // per-class, per-sweep active-list lengths
 };
 
 // Input statistics gathered on the device in one pass (see launch_field_stats).
@@ -179,7 +180,7 @@ struct LaunchCfg {
 // `items` is the segment of halo class `cls` (capacity max_items); only the
 // launch with do_bookkeep runs the convergence bookkeeping of the sweep.
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
-                        const WorkItem *items, ExecCounters *cnt, int max_items,
+                        const WorkItem *items, WorkItem *lists, ExecCounters *cnt, int max_items,
                         int sweep_rel, double tol, int want_policy, int *stamp,
                         int stamp_stride, int cls, int do_bookkeep, hipStream_t s);
 // Bookkeeping before sweep cnt->sweep_base + sweep_rel (marks sds converged,
@@ -283,8 +284,9 @@ hipError_t launch_adjoint_iter(int dim, const AdjDesc<T> *ads, SdState *st, int 
 // LDS, the halo's inflow as staged, and writes back in place.
 template <typename T>
 hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdState *st,
-                                int n_sd, const WorkItem *items, ExecCounters *cnt,
-                                int max_items, int iter_rel, double tol, double scale_rel,
+                                int n_sd, const WorkItem *items, WorkItem *lists,
+                                ExecCounters *cnt, int max_items, int iter_rel, double tol,
+                                double scale_rel,
                                 int *stamp, int stamp_stride, int cls, int do_bookkeep,
                                 hipStream_t s);
 hipError_t adjoint_tiles_set_attributes(LaunchCfg &cfg);

@@ -37,6 +37,7 @@ template <typename T, int TX, int TY, int H, bool POLICY, int S, bool P1>
 __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
+                                                      WorkItem *__restrict__ lists,
                                                       ExecCounters *__restrict__ cnt,
                                                       int sweep_rel, double tol,
                                                       int *__restrict__ stamp,
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
     __shared__ int parg[(S > 1 && POLICY) ? (S - 1) * TX * TY : 1];
 
     if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
-    const int n_items = cnt->class_items[cls];
+    const ItemList list = sweep_items(items, lists, stamp_stride, cnt, cls, sweep, POLICY);
+    const int n_items = list.n;
     const int grp = S > 1 ? (int)threadIdx.x / kThreads : 0;
     const int lt = S > 1 ? (int)threadIdx.x % kThreads : (int)threadIdx.x;
     const int tx = lt % TX;
@@ -74,12 +76,9 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
     for (int item = mode == 1 ? next_item(queue) : (int)blockIdx.x; item < n_items;
          item = mode == 1 ? next_item(queue)
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
-        const WorkItem it = items[item];
+        const WorkItem it = list.items[item];
         SdState *sst = st + it.sd;
-        if (!POLICY) {
-            const int stp = stamp[(size_t)(sweep & 1) * stamp_stride + it.tflat];
-            if (sd_skip(sst, sweep, tol) || (sweep > 0 && stp != sweep)) continue;
-        }
+        if (!POLICY && sd_skip(sst, sweep, tol)) continue;
         const SdDesc<T> &d = sds[it.sd];
         const int n0 = d.n[0], n1 = d.n[1];
         const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
@@ -319,9 +318,11 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
         nact += na * (unsigned)m;
         if (!POLICY) {
             const double bm = block_max_to<NT>(rmax, &sst->res[sweep % 3]);
-            if (threadIdx.x == 0 && bm > 0.0)
-                stamp_neighbourhood<RX, RY, 0>(stamp + (size_t)((sweep + 1) & 1) * stamp_stride,
-                                             d.tile_offset, it.t, d.tiles, sweep + 1);
+            if (threadIdx.x < 64 && __shfl(bm, 0, 64) > 0.0)
+                stamp_and_list<RX, RY, 0>(stamp + (size_t)((sweep + 1) & 1) * stamp_stride, it,
+                                          d.tile_offset, d.tiles, sweep + 1,
+                                          lists + (size_t)((sweep + 1) & 1) * stamp_stride,
+                                          &cnt->class_count[cls][(sweep + 1) % 3]);
         }
     }
     if (!POLICY) block_sum_to<NT>(nact, &cnt->nc_updates);
@@ -332,6 +333,7 @@ template <typename T, int TX, int TY, int TZ, int H, bool POLICY, bool P1>
 __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
+                                                      WorkItem *__restrict__ lists,
                                                       ExecCounters *__restrict__ cnt,
                                                       int sweep_rel, double tol,
                                                       int *__restrict__ stamp,
@@ -352,7 +354,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
     T *lds = reinterpret_cast<T *>(lds_raw);
 
     if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
-    const int n_items = cnt->class_items[cls];
+    const ItemList list = sweep_items(items, lists, stamp_stride, cnt, cls, sweep, POLICY);
+    const int n_items = list.n;
     const int tx = threadIdx.x % TX;
     const int ty = (threadIdx.x / TX) % TY;
     const int tz0 = threadIdx.x / TXY;
@@ -365,12 +368,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
     for (int item = mode == 1 ? next_item(queue) : (int)blockIdx.x; item < n_items;
          item = mode == 1 ? next_item(queue)
                           : (mode == 2 ? item + (int)gridDim.x : n_items)) {
-        const WorkItem it = items[item];
+        const WorkItem it = list.items[item];
         SdState *sst = st + it.sd;
-        if (!POLICY) {
-            const int stp = stamp[(size_t)(sweep & 1) * stamp_stride + it.tflat];
-            if (sd_skip(sst, sweep, tol) || (sweep > 0 && stp != sweep)) continue;
-        }
+        if (!POLICY && sd_skip(sst, sweep, tol)) continue;
         const SdDesc<T> &d = sds[it.sd];
         const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
         const int x0 = it.t[0] * TX, y0 = it.t[1] * TY, z0 = it.t[2] * TZ;
@@ -591,9 +591,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
         nact += na * (unsigned)m;
         if (!POLICY) {
             const double bm = block_max_to(rmax, &sst->res[sweep % 3]);
-            if (threadIdx.x == 0 && bm > 0.0)
-                stamp_neighbourhood<RX, RY, RZ>(stamp + (size_t)((sweep + 1) & 1) * stamp_stride,
-                                             d.tile_offset, it.t, d.tiles, sweep + 1);
+            if (threadIdx.x < 64 && __shfl(bm, 0, 64) > 0.0)
+                stamp_and_list<RX, RY, RZ>(stamp + (size_t)((sweep + 1) & 1) * stamp_stride, it,
+                                           d.tile_offset, d.tiles, sweep + 1,
+                                           lists + (size_t)((sweep + 1) & 1) * stamp_stride,
+                                           &cnt->class_count[cls][(sweep + 1) % 3]);
         }
     }
     if (!POLICY) block_sum_to(nact, &cnt->nc_updates);
@@ -768,7 +770,7 @@ hipError_t sweep_set_attributes(LaunchCfg &cfg) {
 }
 
 hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int n_sd,
-                        const WorkItem *items, ExecCounters *cnt, int max_items,
+                        const WorkItem *items, WorkItem *lists, ExecCounters *cnt, int max_items,
                         int sweep, double tol, int want_policy, int *stamp,
                         int stamp_stride, int cls, int do_bookkeep, hipStream_t s) {
     size_t lds = 0;
@@ -778,8 +780,8 @@ hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int 
     int persistent = cfg.mode;
     if (persistent && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
     int local_iters = want_policy ? 0 : cfg.local_iters;
-    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&cnt,
-                    (void *)&sweep, (void *)&tol, (void *)&stamp, (void *)&stamp_stride,
+    void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&lists,
+                    (void *)&cnt, (void *)&sweep, (void *)&tol, (void *)&stamp, (void *)&stamp_stride,
                     (void *)&persistent, (void *)&cls, (void *)&do_bookkeep,
                     (void *)&local_iters};
     return hipLaunchKernel(fn, dim3(grid), dim3(cfg.threads > 0 ? cfg.threads : kThreads), args,
