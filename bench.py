@@ -9,7 +9,7 @@ Prints ONE JSON line (see the fields below).  `value` is node*control updates
 per second over the whole step (updates actually computed / step wall time);
 `time_to_converge_ms` is the step time.  The `roofline` object reports the
 dominant kernel (the sweep) against the FP32 VALU peak: it is bound by vector
-ALU work, not by HBM (about 20 VALU operations per node*control against 13
+ALU work, not by HBM (20 VALU lane-operations per node*control against 13
 bytes per node per sweep).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -32,27 +32,34 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # FP32 vector ALU without packed math: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.3 T lane-ops/s
-# Algorithmic lane operations per node*control (the scheme's arithmetic, no
-# addressing), 2D: foot 2 fma, cell index 2, fraction 2, Q1 as nested one-axis
-# interpolations (1-tau 2, 3 mul, 3 fma), candidate 1 fma, min 1 -> 16
-OPS_PER_NC_2D = 16
-# P1 on the Kuhn simplex, the same rules: foot 2 fma, cell index 2, fraction 2,
-# simplex order (compare, 2 selects) 3, ratio t1/t0 (reciprocal, mul, clamp) 3,
-# nested interpolations (1-s 2, 2 mul, 2 fma) 6, candidate 1 fma, min 1 -> 20
-OPS_PER_NC_2D_P1 = 20
-# 3D: foot 3, index 3, fraction 3, Q1 (1-tau 3, 7 mul, 7 fma), candidate 1,
-#     min 1 -> 28
-OPS_PER_NC_3D = 28
-# 3D P1: foot 3, index 3, fraction 3, sort (3 compare-swaps: compare, 2 selects) 9,
-#     ratios (2 x reciprocal, mul, clamp) 6, nested (3 x 1-s, mul, fma) 9,
-#     candidate 1, min 1 -> 35
-OPS_PER_NC_3D_P1 = 35
-# Headline sweep configuration: autotuner candidate 22 of the 2D FP32 kernels
-# (32x8 tiles, one node per thread, one work-group per item) with block-
-# asynchronous sweeps of up to 8 local iterations per tile and launch, the
-# fastest measured for this workload; forcing it keeps the timed kernel identical
-# to the one whose HBM counters are stored in profiles/.
-DEFAULT_SWEEP_CONFIG = 22
+# Lane operations per node*control, the hot-path scope's count for the scheme's
+# arithmetic with the cell index: 2D Q1 -> 20, 3D Q1 -> 40.  Our evaluation order
+# needs fewer: 2D foot 2 fma, cell index 2, fraction 2, LDS address 2, Q1 as
+# nested one-axis interpolations 8 (1-tau 2, 3 mul, 3 fma), candidate 1 fma,
+# min 1 = 18, and the built loop issues 17.5 VALU instructions per node*control
+# (two controls share one v_min3); so `frac` at 20 ops can exceed the kernel's
+# VALU issue fraction by up to 20/17.5, and the issue fraction measured with
+# SQ counters is stored beside it in profiles/.
+OPS_PER_NC_2D = 20
+# P1 on the Kuhn simplex: the 8 lane-ops of the nested Q1 become simplex order 3
+# (compare, 2 selects), ratio t1/t0 3 (reciprocal, mul, clamp) and the nested
+# P1 6 (1-s 2, 2 mul, 2 fma) -> 20 - 8 + 12 = 24
+OPS_PER_NC_2D_P1 = 24
+# 3D Q1 -> 40 (ours: foot 3, index 3, fraction 3, address 3, Q1 17 (1-tau 3,
+# 7 mul, 7 fma), candidate 1, min 1 = 31; the built loop issues 33.5)
+OPS_PER_NC_3D = 40
+# 3D P1: Q1's 17 become sort 9 (3 compare-swaps), ratios 6, nested 9 -> 40 - 17 + 24
+OPS_PER_NC_3D_P1 = 47
+# Revision of the headline sweep kernel whose HBM counters are stored in
+# profiles/ (the traffic figure is reported only while the kernel is unchanged)
+SWEEP_KERNEL_REV = 2
+# Headline sweep configuration: autotuner candidate 24 of the 2D FP32 kernels
+# (32x8 tiles, one node per thread, a resident grid walking the sweep's active
+# list with a grid stride) with block-asynchronous sweeps of up to 8 local
+# iterations per tile and launch, the fastest measured for this workload;
+# forcing it keeps the timed kernel identical to the one whose HBM counters are
+# stored in profiles/.
+DEFAULT_SWEEP_CONFIG = 24
 DEFAULT_LOCAL_ITERS = 8
 # The other workloads' fine sweeps: local iterations per tile and launch, the
 # faster of 4 and 8 measured on each (3D and the 288-candidate game do more work
@@ -74,6 +81,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-c2-n", type=int, default=257,
+                    help="grid of the multitarget problem whose oracle time-to-converge the "
+                         "CPU baseline reports (0: none)")
     ap.add_argument("--sweep-config", type=int, default=DEFAULT_SWEEP_CONFIG,
                     help="sweep kernel configuration for the headline workload: k > 0 forces "
                          "autotuner candidate k-1 (sl_tune_candidates order), 0 runs the "
@@ -81,11 +91,18 @@ def parse():
     ap.add_argument("--local-iters", type=int, default=DEFAULT_LOCAL_ITERS,
                     help="0: Jacobi sweeps; k > 0: block-asynchronous sweeps, up to k local "
                          "iterations per tile and launch (same fixed point)")
+    ap.add_argument("--ra-local-iters", type=int, default=RA_LOCAL_ITERS,
+                    help="coarse FP64 pass of the headline: local iterations per tile and "
+                         "launch (0: Jacobi sweeps); to stagnation either way")
+    ap.add_argument("--ra-config", type=int, default=0,
+                    help="coarse FP64 pass of the headline: k > 0 forces coarse candidate k-1 "
+                         "(sl_tune_candidates order), 0 lets the autotuner pick")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c3,c4,c5,vdp,pe,kruzkov,p1,p1_3d,study,balance",
-                    help="extra workloads to report: c3 (3D 257^3), c4 (512-problem batch), "
+    ap.add_argument("--legs", default="c1,c3,c4,c5,vdp,pe,kruzkov,p1,p1_3d,study,balance",
+                    help="extra workloads to report: c1 (FP64 eikonal 101^2 to 1e-10), "
+                         "c3 (3D 257^3), c4 (512-problem batch), "
                          "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
                          "(pursuit-evasion game 513^2), kruzkov (weighted minimum time "
                          "513^2), p1 / p1_3d (the headline / the 3D workload with P1 "
@@ -108,6 +125,38 @@ def ra_opts(p, autotune: int = 1, local: int = RA_LOCAL_ITERS):
     import paper_1405_3521_amd as S
     return S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
                     q=p.ra_q, tol=p.ra_tol, autotune=autotune, local_iters=local)
+
+
+def leg_c1(steps: int, li: int):
+    """Eikonal 101^2 in FP64 (point target, 32 controls, h = dx): the global solve
+    to sup-change < 1e-10, Jacobi sweeps (the oracle's iteration, so the same
+    iterate and sweep count), and the tuned block-asynchronous solve to the same
+    tolerance."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    p = W.c1_eikonal(101)
+    dp = S.to_device(p, torch.float64, "cuda:0")
+    out = {"workload": "eikonal 101^2, point target, 32 controls, FP64, global solve to "
+                       "sup-change < 1e-10"}
+    for name, opts in (("jacobi", S.SolveOpts(tol=1e-10, profile=True)),
+                       ("block_async", S.SolveOpts(tol=1e-10, profile=True, autotune=1,
+                                                   local_iters=li))):
+        S.solve(dp, opts)
+        _sync()
+        t0 = time.perf_counter()
+        sts = [S.solve(dp, opts)[-1] for _ in range(steps)]
+        _sync()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        nc = np.mean([x["node_control_updates"] for x in sts])
+        launches = np.mean([x["sweep_launches"] for x in sts])
+        ms_launch = np.sum([x["ms_sweeps"] for x in sts]) / np.sum([x["sweep_launches"] for x in sts])
+        ach = OPS_PER_NC_2D * nc / launches / (ms_launch / 1e3) / 1e12
+        out[name] = {"time_to_converge_ms": ms, "sweeps": int(np.mean([x["sweeps_max"] for x in sts])),
+                     "node_control_updates_per_s": nc / (ms / 1e3),
+                     "sweep_ms_per_launch": ms_launch, "valu_tops": ach,
+                     "valu_frac": ach / PEAK_VALU_TOPS}
+    return out
 
 
 def leg_c3(steps: int, li: int):
@@ -412,12 +461,13 @@ def stored_traffic(st, nc_per_launch):
                 k, v = kv.split("=")
                 rec[k] = v
     want = f"{st['tile'][0]}x{st['tile'][1]}/mode{st['mode']}/local{st.get('local_iters', 0)}"
-    if rec.get("config") != want or "bytes_per_launch" not in rec:
+    if (rec.get("config") != want or "bytes_per_launch" not in rec
+            or rec.get("kernel_rev") != str(SWEEP_KERNEL_REV)):
         return None
     return float(rec["bytes_per_launch"])
 
 
-def cpu_baseline(prob, budget_s: float):
+def cpu_baseline(prob, budget_s: float, c2_n: int = 257):
     """The FP64 oracle on a bounded sample of the same workload: plain Jacobi
     sweeps of the global 1025^2 problem from the ghost value, as many as fit in
     about ``budget_s`` seconds on all host threads, then a shorter sample on one
@@ -445,7 +495,36 @@ def cpu_baseline(prob, budget_s: float):
             "value_1_thread": nc_per_sweep * s1 / dt1,
             "sample": f"{sweeps} Jacobi sweeps of the global {prob.n[0]}^2 problem "
                       f"({nc_per_sweep:.3g} node*control each), FP64, OpenMP over nodes on all "
-                      f"host threads; {s1} sweeps on one thread for value_1_thread"}
+                      f"host threads; {s1} sweeps on one thread for value_1_thread",
+            "time_to_converge": oracle_time_to_converge(c2_n)}
+
+
+def oracle_time_to_converge(c2_n: int):
+    """The oracle's whole solves, as the GPU legs run them: the FP64 eikonal 101^2
+    to sup-change < 1e-10, and the multitarget workload at c2_n^2 (64 controls, 4
+    disks) as the ISA: reconstruction to stagnation, every set to sup-change
+    < 1e-6, assembly."""
+    import oracle as O
+    import workloads as W
+    from oracle import isa as I
+    out = {}
+    p = W.c1_eikonal(101)
+    t0 = time.perf_counter()
+    _, _, sw, _ = O.solve(p, tol=1e-10)
+    out["c1_101_fp64_ms"] = (time.perf_counter() - t0) * 1e3
+    out["c1_101_sweeps"] = sw
+    if c2_n > 0:
+        q = W.c2_multitarget(n=c2_n, m=64)
+        t0 = time.perf_counter()
+        rec = I.reconstruct(q)
+        t1 = time.perf_counter()
+        Vs, sw = I.solve_subdomains(q, rec.member, tol=1e-6)
+        I.assemble(Vs, rec.member, q.v_ghost)
+        t2 = time.perf_counter()
+        out[f"c2_{c2_n}_isa_ms"] = (t2 - t0) * 1e3
+        out[f"c2_{c2_n}_reconstruct_ms"] = (t1 - t0) * 1e3
+        out[f"c2_{c2_n}_sweeps_max"] = int(max(sw))
+    return out
 
 
 def main():
@@ -471,7 +550,8 @@ def main():
 
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
-    ra = ra_opts(prob)
+    ra = ra_opts(prob, autotune=-args.ra_config if args.ra_config > 0 else 1,
+                 local=args.ra_local_iters)
     # --sweep-config k forces candidate k-1; 0 lets the warm-up step run the
     # autotuner (complete solves as trials) and the timed steps use its pick
     opts = S.SolveOpts(tol=1e-6, profile=True,
@@ -544,7 +624,7 @@ def main():
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
         fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
-              "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov,
+              "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov, "c1": leg_c1,
               "p1": leg_p1, "p1_3d": leg_p1_3d}[leg]
         t0 = time.perf_counter()
         legs[leg] = fn(max(1, min(args.steps, 3)),
@@ -555,7 +635,7 @@ def main():
     if "c5" in legs:
         res["adjoint_grads_per_s"] = legs["c5"]["grads_per_s"]
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, args.cpu_c2_n)
     print(json.dumps(res), flush=True)
 
 

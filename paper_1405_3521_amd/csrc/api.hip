@@ -200,10 +200,10 @@ int default_variant(int dim, int dtype) {
 }
 
 LaunchCfg make_cfg(int dim, int dtype, int halo, int variant) {
-    LaunchCfg all[16];
-    const int nv = sweep_variants(dim, all, 16);
+    LaunchCfg all[kMaxVariants];
+    const int nv = sweep_variants(dim, all, kMaxVariants);
     LaunchCfg c{};
-    for (int i = 0; i < nv && i < 16; ++i)
+    for (int i = 0; i < nv && i < kMaxVariants; ++i)
         if (all[i].variant == variant) c = all[i];
     c.halo = halo;
     c.mode = 0;
@@ -231,21 +231,59 @@ hipStream_t capture_stream() {
     return cs;
 }
 
+// Instantiated chunk graphs kept across calls, keyed by everything their launches
+// take as arguments (device pointers, sizes, kernel configurations, tolerance), so
+// a call that repeats an earlier call's launches -- the same problem shape in the
+// same workspace -- replays the earlier graph without capturing it again.  The
+// node fields themselves are not in the key: kernels read them through the
+// descriptors, which every call uploads.  Bounded: the oldest entry is destroyed
+// when the cache is full.
+struct GraphCache {
+    static constexpr size_t kMax = 16;
+    std::vector<std::pair<std::vector<unsigned long long>, hipGraphExec_t>> entries;
+    std::mutex mu;
+    hipGraphExec_t find(const std::vector<unsigned long long> &key) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &e : entries)
+            if (e.first == key) return e.second;
+        return nullptr;
+    }
+    void insert(std::vector<unsigned long long> key, hipGraphExec_t exec) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (entries.size() >= kMax) {
+            (void)hipGraphExecDestroy(entries.front().second);
+            entries.erase(entries.begin());
+        }
+        entries.emplace_back(std::move(key), exec);
+    }
+};
+GraphCache &graph_cache() {
+    static GraphCache c;
+    return c;
+}
+
 // Runs `enqueue(stream, todo)` -- `todo` iterations, then a bookkeeping launch
 // that advances the device-side iteration base, then a copy of the active-set
 // counter to pinned host memory -- in chunks until the counter is zero or
-// max_steps iterations are done.  Full chunks are captured once as a hipGraph
-// and replayed on the caller's stream; a short last chunk is launched directly.
+// max_steps iterations are done.  Full chunks are captured as a hipGraph and
+// replayed on the caller's stream (from the graph cache when `key` is given);
+// a short last chunk is launched directly.
 struct ChunkLoop {
     double ms = 0.0;         // HIP-event time of the chunks (profile)
     long launches = 0;
     // `active`: host int the enqueued copy writes the active-set counter to
     template <class F>
     int run(F enqueue, long max_steps, int chunk, hipStream_t s, int use_graph, int profile,
-            long *done, int *status, int *active) {
+            long *done, int *status, int *active,
+            const std::vector<unsigned long long> *key = nullptr) {
         if (!active) return SL_ERR_HIP;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
+        bool cached = false;
+        if (use_graph && key) {
+            exec = graph_cache().find(*key);
+            cached = exec != nullptr;
+        }
         hipEvent_t ev[2] = {nullptr, nullptr};
         int rc = SL_OK;
         long S = 0;
@@ -269,6 +307,10 @@ struct ChunkLoop {
                         rc = SL_ERR_HIP;
                         break;
                     }
+                    if (key) {
+                        graph_cache().insert(*key, exec);
+                        cached = true;
+                    }
                 }
                 if (hipGraphLaunch(exec, s) != hipSuccess) { rc = SL_ERR_HIP; break; }
             } else if (enqueue(s, todo) != hipSuccess) {
@@ -288,7 +330,7 @@ struct ChunkLoop {
                 break;
             }
         }
-        if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec && !cached) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -322,12 +364,12 @@ std::mutex &tune_mutex() {
 // controls over several thread groups, P1 the variants without P1 kernels.
 std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo, bool game = false,
                                        int interp = SL_INTERP_Q1) {
-    LaunchCfg all[16];
-    const int nv = sweep_variants(dim, all, 16);
+    LaunchCfg all[kMaxVariants];
+    const int nv = sweep_variants(dim, all, kMaxVariants);
     std::vector<LaunchCfg> out;
-    for (int i = 0; i < nv && i < 16; ++i) {
+    for (int i = 0; i < nv && i < kMaxVariants; ++i) {
         if (all[i].dtype != dtype) continue;
-        if (game && all[i].threads > kThreads) continue;
+        if (game && all[i].groups > 1) continue;
         if (interp == SL_INTERP_P1 && !sweep_has_p1(all[i].variant)) continue;
         for (int mode = 0; mode < 3; ++mode) {
             LaunchCfg c = all[i];
@@ -342,10 +384,10 @@ std::vector<LaunchCfg> tune_candidates(int dim, int dtype, int halo, bool game =
 
 // Most tiles any variant of (dim, dtype) needs on a grid of n nodes.
 int max_tiles(int dim, int dtype, const int *n) {
-    LaunchCfg all[16];
-    const int nv = sweep_variants(dim, all, 16);
+    LaunchCfg all[kMaxVariants];
+    const int nv = sweep_variants(dim, all, kMaxVariants);
     int best = 1;
-    for (int i = 0; i < nv && i < 16; ++i) {
+    for (int i = 0; i < nv && i < kMaxVariants; ++i) {
         if (all[i].dtype != dtype) continue;
         int tot = 1;
         for (int d = 0; d < dim; ++d) tot *= (n[d] + all[i].tile[d] - 1) / all[i].tile[d];
@@ -506,11 +548,33 @@ struct Exec {
             if (e != hipSuccess) return e;
             return hipMemcpyAsync(active, &cnt->n_active, sizeof(int), hipMemcpyDeviceToHost, q);
         };
+        // everything the chunk's launches take as arguments
+        std::vector<unsigned long long> key;
+        auto put = [&key](const void *p) { key.push_back((unsigned long long)(uintptr_t)p); };
+        auto putd = [&key](double v) {
+            unsigned long long b;
+            std::memcpy(&b, &v, sizeof(b));
+            key.push_back(b);
+        };
+        key.push_back((unsigned long long)kind);
+        key.push_back((unsigned long long)n_sd);
+        key.push_back((unsigned long long)stamp_stride);
+        key.push_back((unsigned long long)chunk);
+        put(sds); put(st); put(items); put(lists); put(cnt); put(stamp); put(active);
+        putd(tol);
+        putd(scale_rel);
+        for (size_t c = 0; c < ccfg.size(); ++c) {
+            const LaunchCfg &g = ccfg[c];
+            for (int v : {g.dim, g.dtype, g.tile[0], g.tile[1], g.tile[2], g.halo, g.variant,
+                          g.mode, g.threads, g.grid_cap, g.local_iters, g.interp, class_off[c],
+                          class_cap[c]})
+                key.push_back((unsigned long long)(long long)v);
+        }
         ChunkLoop loop;
         long S = 0;
         int status = SL_NOT_CONVERGED;
         int rc = loop.run(enqueue, max_sweeps, chunk, s, no_alloc ? 0 : use_graph,
-                          no_alloc ? 0 : profile, &S, &status, active);
+                          no_alloc ? 0 : profile, &S, &status, active, &key);
         if (rc) return rc;
         ms_sweeps += loop.ms;
         sweep_launches += loop.launches;

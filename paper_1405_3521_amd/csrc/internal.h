@@ -23,6 +23,7 @@ constexpr int kMaxHalo = 16;           // largest supported halo (cells), 2D
 constexpr int kMaxHalo3D = 8;          // largest supported halo (cells), 3D
 constexpr int kMaxClasses = 16;        // halo classes per executor (one launch each per sweep)
 constexpr int kThreads = 256;          // threads per sweep work-group (4 waves)
+constexpr int kMaxVariants = 32;       // sweep kernel variants of one dimension
 
 // Per-sub-domain description (device memory, read-only during a sweep).
 template <typename T>
@@ -165,6 +166,7 @@ struct LaunchCfg {
     int mode;                   // 0: one work-group per item; 1: resident grid + atomic
                                 // work queue; 2: resident grid + static grid stride
     int threads;                // work-group size of the variant
+    int groups;                 // thread groups sharing a tile's controls (1: none)
     int local_iters;            // 0: Jacobi sweeps; k > 0: block-asynchronous, up to k
                                 // local iterations per tile and launch (in place)
     int interp;                 // sl_interp of the kernels

@@ -33,8 +33,8 @@ namespace {
 // ------------------------------------------------------------------ 2D kernel
 // Persistent: a resident grid of work-groups takes work items from a per-sweep
 // atomic queue until the list is exhausted.
-template <typename T, int TX, int TY, int H, bool POLICY, int S, bool P1>
-__global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
+template <typename T, int TX, int TY, int H, bool POLICY, int S, bool P1, int GT>
+__global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict__ sds,
                                                       SdState *__restrict__ st, int n_sd,
                                                       const WorkItem *__restrict__ items,
                                                       WorkItem *__restrict__ lists,
@@ -46,16 +46,16 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
     const int sweep = cnt->sweep_base + sweep_rel;
     constexpr int LW = TX + 2 * H;
     constexpr int LH = TY + 2 * H;
-    constexpr int RSTEP = kThreads / TX;
+    constexpr int RSTEP = GT / TX;
     constexpr int NPT = TY / RSTEP;
     constexpr int RX = (H + TX - 1) / TX, RY = (H + TY - 1) / TY;
-    static_assert(kThreads % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
-    // S groups of kThreads threads share a tile: the same nodes, every S-th control
+    static_assert(GT % 64 == 0 && GT % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
+    // S groups of GT threads share a tile: the same nodes, every S-th control
     // each (k = g, g + S, ...); group 0 takes the minimum over the groups' partial
     // results (exact, so the values do not depend on S; on ties the lowest control
     // index wins, as in one pass).  Control problems only: a game (more than one
     // evader block) runs with S = 1.
-    constexpr int NT = kThreads * S;
+    constexpr int NT = GT * S;
     __shared__ T lds[LW * LH];
     __shared__ T part[S > 1 ? (S - 1) * TX * TY : 1];
     __shared__ int parg[(S > 1 && POLICY) ? (S - 1) * TX * TY : 1];
@@ -63,8 +63,8 @@ __global__ __launch_bounds__(kThreads * S) void k_sweep2d(const SdDesc<T> *__res
     if (!POLICY && do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, sweep, tol, cnt, 0);
     const ItemList list = sweep_items(items, lists, stamp_stride, cnt, cls, sweep, POLICY);
     const int n_items = list.n;
-    const int grp = S > 1 ? (int)threadIdx.x / kThreads : 0;
-    const int lt = S > 1 ? (int)threadIdx.x % kThreads : (int)threadIdx.x;
+    const int grp = S > 1 ? (int)threadIdx.x / GT : 0;
+    const int lt = S > 1 ? (int)threadIdx.x % GT : (int)threadIdx.x;
     const int tx = lt % TX;
     const int ty0 = lt / TX;
     unsigned nact = 0;
@@ -616,19 +616,19 @@ __global__ void k_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol, Exe
 
 
 struct Variant {
-    int dim, dtype, tile[3], threads;
+    int dim, dtype, tile[3], threads, groups;
     const void *fn[kMaxHalo + 1][2];    // [H][policy]
     const void *fn_p1[kMaxHalo + 1][2]; // P1 interpolation (null where not built)
     size_t lds_bytes[kMaxHalo + 1];     // dynamic LDS (3D only)
 };
 
-template <typename T, int TX, int TY, int H, int S, bool WITH_P1>
+template <typename T, int TX, int TY, int H, int S, bool WITH_P1, int GT>
 void fill2d(Variant &v) {
-    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S, false>;
-    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S, false>;
+    v.fn[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S, false, GT>;
+    v.fn[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S, false, GT>;
     if (WITH_P1) {
-        v.fn_p1[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S, WITH_P1>;
-        v.fn_p1[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S, WITH_P1>;
+        v.fn_p1[H][0] = (const void *)&k_sweep2d<T, TX, TY, H, false, S, WITH_P1, GT>;
+        v.fn_p1[H][1] = (const void *)&k_sweep2d<T, TX, TY, H, true, S, WITH_P1, GT>;
     }
     v.lds_bytes[H] = 0;
 }
@@ -643,20 +643,22 @@ void fill3d(Variant &v) {
     v.lds_bytes[H] = sizeof(T) * (size_t)(TX + 2 * H) * (TY + 2 * H) * (TZ + 2 * H);
 }
 
-template <typename T, int TX, int TY, int S = 1, bool P = false>
+// GT threads per control group (kThreads unless the tile has fewer nodes), S groups
+template <typename T, int TX, int TY, int S = 1, bool P = false, int GT = kThreads>
 Variant make2d() {
     Variant v{};
     v.dim = 2;
     v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = 1;
-    v.threads = kThreads * S;
-    fill2d<T, TX, TY, 1, S, P>(v); fill2d<T, TX, TY, 2, S, P>(v); fill2d<T, TX, TY, 3, S, P>(v);
-    fill2d<T, TX, TY, 4, S, P>(v); fill2d<T, TX, TY, 5, S, P>(v); fill2d<T, TX, TY, 6, S, P>(v);
-    fill2d<T, TX, TY, 7, S, P>(v); fill2d<T, TX, TY, 8, S, P>(v); fill2d<T, TX, TY, 9, S, P>(v);
-    fill2d<T, TX, TY, 10, S, P>(v); fill2d<T, TX, TY, 11, S, P>(v);
-    fill2d<T, TX, TY, 12, S, P>(v); fill2d<T, TX, TY, 13, S, P>(v);
-    fill2d<T, TX, TY, 14, S, P>(v); fill2d<T, TX, TY, 15, S, P>(v);
-    fill2d<T, TX, TY, 16, S, P>(v);
+    v.threads = GT * S;
+    v.groups = S;
+    fill2d<T, TX, TY, 1, S, P, GT>(v); fill2d<T, TX, TY, 2, S, P, GT>(v); fill2d<T, TX, TY, 3, S, P, GT>(v);
+    fill2d<T, TX, TY, 4, S, P, GT>(v); fill2d<T, TX, TY, 5, S, P, GT>(v); fill2d<T, TX, TY, 6, S, P, GT>(v);
+    fill2d<T, TX, TY, 7, S, P, GT>(v); fill2d<T, TX, TY, 8, S, P, GT>(v); fill2d<T, TX, TY, 9, S, P, GT>(v);
+    fill2d<T, TX, TY, 10, S, P, GT>(v); fill2d<T, TX, TY, 11, S, P, GT>(v);
+    fill2d<T, TX, TY, 12, S, P, GT>(v); fill2d<T, TX, TY, 13, S, P, GT>(v);
+    fill2d<T, TX, TY, 14, S, P, GT>(v); fill2d<T, TX, TY, 15, S, P, GT>(v);
+    fill2d<T, TX, TY, 16, S, P, GT>(v);
     return v;
 }
 template <typename T, int TX, int TY, int TZ, bool P = false>
@@ -666,6 +668,7 @@ Variant make3d() {
     v.dtype = sizeof(T) == 4 ? SL_F32 : SL_F64;
     v.tile[0] = TX; v.tile[1] = TY; v.tile[2] = TZ;
     v.threads = kThreads;
+    v.groups = 1;
     fill3d<T, TX, TY, TZ, 1, P>(v); fill3d<T, TX, TY, TZ, 2, P>(v);
     fill3d<T, TX, TY, TZ, 3, P>(v); fill3d<T, TX, TY, TZ, 4, P>(v);
     fill3d<T, TX, TY, TZ, 5, P>(v); fill3d<T, TX, TY, TZ, 6, P>(v);
@@ -696,6 +699,12 @@ const Variant *variants(int *count) {
         make2d<float, 32, 8, 1, true>(),    // 18: FP32 2D, one node per thread: finer skipping (also P1)
         make2d<float, 16, 16>(),     // 19: and twice the waves per active region
         make2d<float, 32, 8, 2>(),   // 20
+        // tiles of fewer than 256 nodes (control groups of 128 or 64 threads): more
+        // tiles for small grids, so a launch spreads over every compute unit and a
+        // lone tile's local iterations take less time (the coarse FP64 pass)
+        make2d<double, 16, 8, 4, false, 128>(),   // 21
+        make2d<double, 8, 8, 4, false, 64>(),     // 22
+        make2d<float, 16, 8, 2, false, 128>(),    // 23
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;
@@ -717,6 +726,7 @@ int sweep_variants(int dim, LaunchCfg *out, int cap) {
             out[k].halo = 0;
             out[k].variant = i;
             out[k].threads = v[i].threads;
+            out[k].groups = v[i].groups;
             out[k].interp = SL_INTERP_Q1;
         }
         ++k;
