@@ -331,30 +331,34 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
 
 /* Gradient of a loss on V with respect to the running cost l, with the argmin
  * controls frozen (the fixed point is then linear in l: V = beta P V + w l + c on
- * free nodes).  Solves lambda = g + beta P^T lambda by Jacobi iteration with a
- * scatter of beta * (Q1 weight) * lambda to the free corners of each node's foot
- * (float atomics, so the summation order varies run to run), until the test
- * below holds or max_iters; then dLdl = w * sum over sets of
- * lambda.  Because the summation order varies between iterations, the state
- * settles only to within a few ulps, so the stopping test is
- * max|lambda_new - lambda| <= tol + 16 eps max|lambda_new| (eps of p->dtype);
- * tol = 0 therefore means "until the change is at rounding level".
+ * free nodes).  Solves lambda = g + beta P^T lambda, then dLdl = w * sum over sets
+ * of lambda.  P^T is applied as a gather: for every node c, the sum of
+ * w_c(j) lambda(j) over the free member nodes j whose frozen foot has c in its
+ * interpolation stencil (Q1 cell corners, or the P1 simplex vertices), in a fixed
+ * order of j; no atomics touch the adjoint state.
  * Inputs: member (DEVICE, N uint8 set bitmask, or NULL: one set = whole grid, as
  * after sl_solve), owner (DEVICE, N uint8: dL/dV(j) goes to set owner[j] only;
  * NULL: to every set), policy (DEVICE, n_sets*N uint8 controls from the forward
- * call with want_policy), dLdV (DEVICE, N in p->dtype).
- * The feet are those of the forward scheme: per-axis speed factors and drift
- * (index units, e c + q) are taken; games and the Kruzkov discount (the
+ * call with want_policy; m <= SL_MAX_POLICY_CONTROLS), dLdV (DEVICE, N in
+ * p->dtype).  The feet are those of the forward scheme: per-axis speed factors
+ * and drift (index units, e c + q) are taken; games and the Kruzkov discount (the
  * discount then depends on l, so V is not linear in l) return SL_ERR_UNSUPPORTED.
- * local_iters (0..1024): 0 = the Jacobi iteration above.  k > 0 in 2D, when the
- * foot reaches at most 8 cells and I[V] is Q1: block-asynchronous tiles.  With P1
- * the scatter goes to the foot's simplex vertices with their barycentric weights.  Every active 32x16 tile
- * stages lambda, the frozen feet and the inflow from its halo in on-chip memory,
- * then repeats "lambda = g + inflow" up to k times while a node changes by more
- * than tol + 16 eps |lambda|, and writes back in place.  Tiles are revisited when
- * a neighbour changed.  The iteration has nonnegative coefficients and spectral
- * radius <= beta < 1, so any update order converges to the same lambda (up to
- * rounding).  Otherwise the Jacobi iteration runs; max_iters counts launches.
+ * Iteration (tiles of 32x16 nodes in 2D, 8x8x4 in 3D, when the feet reach at
+ * most 8 cells in 2D and 5 in 3D):
+ *   local_iters = 0: Jacobi: every launch evaluates each active tile once from
+ *     one buffer into the other; a tile is revisited when a node of its
+ *     neighbourhood changed, so the iterates are exactly those of the Jacobi
+ *     iteration and the result is reproducible bit for bit (deterministic mode);
+ *   local_iters = k > 0 (<= 1024): block-asynchronous: every active tile repeats
+ *     the gather up to k times in on-chip memory, its halo as staged, and writes
+ *     back in place; tiles see their neighbours' latest values, so the order of
+ *     updates, and the result at rounding level, depends on scheduling.
+ *   With longer feet the Jacobi iteration runs over the whole grid as a scatter
+ *   with float atomics (the summation order then varies run to run).
+ *   The iteration has nonnegative coefficients and spectral radius <= beta < 1,
+ *   so every order converges to the same lambda (up to rounding).  Stop: the
+ *   largest change of one evaluation <= tol + 16 eps max|lambda| (eps of
+ *   p->dtype, the rounding level of the sums), or max_iters launches.
  * Output: dLdl (DEVICE, N in p->dtype; 0 on target nodes). */
 int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
                const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,

@@ -139,40 +139,133 @@ __device__ __forceinline__ float floor_<float>(float x) { return __builtin_floor
 template <>
 __device__ __forceinline__ double floor_<double>(double x) { return __builtin_floor(x); }
 
-// Block-asynchronous adjoint, 2D, one (set, tile) work item per work-group step.
-// The tile plus an H-cell halo is staged in LDS: lambda (0 off the set's free
-// nodes), and for every node its frozen foot cell (region coordinates of the
-// lower corner, -1 when none of its corners lies in the tile) with the Q1
-// fractions.  The inflow from halo nodes is pushed once (LDS float atomics);
-// then up to local_iters times: push the tile's own lambda, lambda = g + inflow,
-// while some node changes by more than tol + scale_rel * |lambda| (the atomics
-// reorder sums, so smaller changes are rounding).  The linear iteration has
-// nonnegative coefficients and spectral radius <= beta < 1, so every order of
-// updates converges to the same solution (up to rounding).
-template <typename T, int H>
-__global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
+// Tile shapes of the gather adjoint and the most in-stencil entries a tile node
+// keeps on chip (a node with more is summed by rescanning its neighbourhood).
+template <int DIM>
+struct AdjTile;
+template <>
+struct AdjTile<2> {
+    static constexpr int X = kAdjTX, Y = kAdjTY, Z = 1, K = 12;
+};
+template <>
+struct AdjTile<3> {
+    static constexpr int X = kAdjTX3, Y = kAdjTY3, Z = kAdjTZ3, K = 24;
+};
+
+// The frozen foot of free member node j (region coordinates l of the node): the
+// lower corner of its cell in region coordinates and the fractions, exactly as
+// the forward scheme places it (u_a = i_a + (e_a c_a + q_a), split by floor).
+template <typename T, int DIM>
+__device__ __forceinline__ bool adj_foot(const SdDesc<T> &d, size_t j, const int *l, int *p,
+                                         T *tau) {
+    const int k = d.policy[j];
+    if (k >= d.m) return false;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T c = !d.speed ? T(1) : (d.speed_axes ? d.speed[(size_t)DIM * j + a] : d.speed[j]);
+        const T q = d.drift ? d.drift[(size_t)DIM * j + a] : T(0);
+        const T disp = d.ctrl[DIM * k + a] * c + q;
+        const T f = floor_(disp);
+        tau[a] = disp - f;
+        p[a] = l[a] + (int)f;
+    }
+    return true;
+}
+
+// The interpolation stencil of a foot: fn(vertex region coordinates, weight) for
+// every vertex with a nonzero weight.  Q1: the 2^DIM cell corners with product
+// weights in axis order.  P1: the vertices of the foot's Kuhn simplex (lower
+// corner, then one step along each axis in the order of decreasing fraction,
+// equal fractions lower axis first) with their barycentric weights.
+template <typename T, int DIM, class F>
+__device__ __forceinline__ void adj_stencil(int interp, const int *p, const T *tau, F fn) {
+    if (interp == SL_INTERP_P1) {
+        int ax[3] = {0, 1, 2};
+#pragma unroll
+        for (int a = 1; a < DIM; ++a)
+            for (int b = a; b > 0 && tau[ax[b - 1]] < tau[ax[b]]; --b) {
+                const int t = ax[b - 1];
+                ax[b - 1] = ax[b];
+                ax[b] = t;
+            }
+        int v[3] = {p[0], DIM > 1 ? p[1] : 0, DIM > 2 ? p[2] : 0};
+#pragma unroll
+        for (int s = 0; s <= DIM; ++s) {
+            if (s > 0) v[ax[s - 1]] += 1;
+            const T w = s == 0 ? T(1) - tau[ax[0]]
+                               : (s < DIM ? tau[ax[s - 1]] - tau[ax[s]] : tau[ax[DIM - 1]]);
+            if (w != T(0)) fn(v, w);
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) {
+        T w = T(1);
+        int v[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int bq = (q >> a) & 1;
+            w = w * (bq ? tau[a] : T(1) - tau[a]);
+            v[a] = p[a] + bq;
+        }
+        if (w != T(0)) fn(v, w);
+    }
+}
+
+// Gather (pull) adjoint over tiles, 2D and 3D, no atomics on the adjoint state.
+//
+// lambda(c) = g(c) + beta * sum over the free member nodes j whose frozen foot
+// has c in its stencil of w_c(j) lambda(j): the transposed stencil.  For each
+// work item the tile plus an H-node halo (every node whose foot can reach the
+// tile) is staged in LDS; every region node pushes (j, w_c(j)) into the entry
+// list of each tile node c of its stencil (LDS counters give the slots), and
+// each list is then sorted by source, so the sum runs in a fixed order and the
+// result does not depend on the push order.  A node with more than K entries is
+// summed by rescanning its neighbourhood in the same source order.  Then up to
+// local_iters times: every tile node gathers from its list (halo values as
+// staged), the new values are written after a barrier, and the tile stops when
+// no node changed by more than tol + scale_rel |lambda|.
+//
+// local_iters = 0: one evaluation per launch from buffer it & 1 into the other
+// buffer (Jacobi); a tile is revisited when a node of its neighbourhood changed
+// at all, so skipped tiles already hold their values in both buffers and the
+// iterates are those of the plain Jacobi iteration, reproducible bit for bit.
+// local_iters > 0: block-asynchronous in place (both buffers are one array): a
+// tile sees its neighbours' latest values when it stages them, so the order of
+// updates, and the result at rounding level, depends on scheduling.  The
+// iteration has nonnegative coefficients and spectral radius <= beta < 1, so
+// every order converges to the same solution.
+template <typename T, int DIM, int H>
+__global__ __launch_bounds__(kThreads) void k_adjoint_pull(
     const SdDesc<T> *__restrict__ sds, SdState *__restrict__ st, int n_sd,
     const WorkItem *__restrict__ items, WorkItem *__restrict__ lists,
-    ExecCounters *__restrict__ cnt, int iter_rel,
-    double tol, double scale_rel, int *__restrict__ stamp, int stamp_stride, int mode, int cls,
-    int do_bookkeep, int local_iters) {
-    constexpr int TX = kAdjTX, TY = kAdjTY;
-    constexpr int LW = TX + 2 * H, LH = TY + 2 * H, NR = LW * LH, NT = TX * TY;
-    constexpr int RSTEP = kThreads / TX, NPT = TY / RSTEP;
+    ExecCounters *__restrict__ cnt, int iter_rel, double tol, double scale_rel,
+    int *__restrict__ stamp, int stamp_stride, int mode, int cls, int do_bookkeep,
+    int local_iters) {
+    using TT = AdjTile<DIM>;
+    constexpr int TX = TT::X, TY = TT::Y, TZ = TT::Z, K = TT::K;
+    constexpr int HZ = DIM == 3 ? H : 0;
+    constexpr int LW = TX + 2 * H, LH = TY + 2 * H, LD = TZ + 2 * HZ;
+    constexpr int NR = LW * LH * LD, NT = TX * TY * TZ;
+    constexpr int NPT = NT / kThreads;
     constexpr int RX = (H + TX - 1) / TX, RY = (H + TY - 1) / TY;
-    static_assert(kThreads % TX == 0 && TY % RSTEP == 0, "tile/thread mismatch");
-    __shared__ T lam_l[NR];
-    __shared__ int cell_l[NR];
-    __shared__ T fx_l[NR], fy_l[NR];
-    __shared__ T acc_h[NT], acc_t[NT];
+    constexpr int RZ = DIM == 3 ? (H + TZ - 1) / TZ : 0;
+    static_assert(NT % kThreads == 0 && NPT >= 1, "tile/thread mismatch");
+    static_assert(NR < 32768, "region offsets must fit in 16 bits");
+    extern __shared__ unsigned char lds_raw[];
+    T *lam_l = reinterpret_cast<T *>(lds_raw);                 // NR region values
+    T *ent_w = lam_l + NR;                                     // NT * K weights
+    short *ent_s = reinterpret_cast<short *>(ent_w + NT * K);  // NT * K sources
+    int *cnt_l = reinterpret_cast<int *>(ent_s + NT * K);      // NT entry counts
+    unsigned char *fr_l = reinterpret_cast<unsigned char *>(cnt_l + NT);  // NT free flags
 
     const int iter = cnt->sweep_base + iter_rel;
     if (do_bookkeep && blockIdx.x == 0) bookkeep_block(st, n_sd, iter, tol, cnt, 0, scale_rel);
     const ItemList list = sweep_items(items, lists, stamp_stride, cnt, cls, iter, false);
     const int n_items = list.n;
-    const int slot = iter % 3;
-    int *queue = &cnt->class_queue[cls][slot];
-    const int tx = threadIdx.x % TX, ty0 = threadIdx.x / TX;
+    int *queue = &cnt->class_queue[cls][iter % 3];
+    const bool jacobi = local_iters <= 0;
+    const int iters = jacobi ? 1 : local_iters;
     unsigned nact = 0;
 
     for (int item = mode == 1 ? next_item(queue) : (int)blockIdx.x; item < n_items;
@@ -182,171 +275,188 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_tiles(
         SdState *sst = st + it.sd;
         if (sd_skip(sst, iter, tol, scale_rel)) continue;
         const SdDesc<T> &d = sds[it.sd];
-        const int n0 = d.n[0], n1 = d.n[1];
-        const int x0 = it.t[0] * TX, y0 = it.t[1] * TY;
-        const int ox = x0 - H, oy = y0 - H;
-        T *__restrict__ lam = d.V[0];
+        const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+        const int o[3] = {it.t[0] * TX - H, it.t[1] * TY - H, it.t[2] * TZ - HZ};
+        const int src = jacobi ? (iter & 1) : 0;
+        const T *__restrict__ Vin = d.V[src];
+        T *__restrict__ Vout = d.V[src ^ 1];
         const uint8_t *__restrict__ mem = d.member;
         const int bit = d.bit;
         const T beta = d.beta;
+        auto free_at = [&](size_t j) -> bool {
+            return d.target[j] < 0 && (!mem || ((mem[j] >> bit) & 1));
+        };
 
         __syncthreads();                 // LDS of the previous item is no longer read
         for (int q = threadIdx.x; q < NR; q += kThreads) {
-            const int ly = q / LW, lx = q - ly * LW;
-            const int gx = ox + lx, gy = oy + ly;
-            T lv = T(0), fx = T(0), fy = T(0);
-            int cb = -1;
-            if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1) {
-                const size_t j = (size_t)gy * n0 + gx;
-                if (d.target[j] < 0 && (!mem || ((mem[j] >> bit) & 1))) {
-                    lv = lam[j];
-                    const int k = d.policy[j];
-                    if (k < d.m) {
-                        T cx = T(1), cy = T(1), qx = T(0), qy = T(0);
-                        if (d.speed) {
-                            cx = d.speed_axes ? d.speed[2 * j] : d.speed[j];
-                            cy = d.speed_axes ? d.speed[2 * j + 1] : cx;
-                        }
-                        if (d.drift) {
-                            qx = d.drift[2 * j];
-                            qy = d.drift[2 * j + 1];
-                        }
-                        const T dx = d.ctrl[2 * k] * cx + qx, dy = d.ctrl[2 * k + 1] * cy + qy;
-                        const T flx = floor_(dx), fly = floor_(dy);
-                        fx = dx - flx;
-                        fy = dy - fly;
-                        const int px = lx + (int)flx, py = ly + (int)fly;
-                        if (px + 1 >= H && px < H + TX && py + 1 >= H && py < H + TY)
-                            cb = py * LW + px;
-                    }
-                }
+            const int lx = q % LW, ly = (q / LW) % LH, lz = q / (LW * LH);
+            const int gx = o[0] + lx, gy = o[1] + ly, gz = o[2] + lz;
+            T lv = T(0);
+            if ((unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                (unsigned)gz < (unsigned)n2) {
+                const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+                if (free_at(j)) lv = Vin[j];
             }
             lam_l[q] = lv;
-            cell_l[q] = cb;
-            fx_l[q] = fx;
-            fy_l[q] = fy;
         }
-        for (int i = threadIdx.x; i < NT; i += kThreads) acc_h[i] = T(0);
+        for (int i = threadIdx.x; i < NT; i += kThreads) {
+            const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+            const int gx = o[0] + H + x, gy = o[1] + H + y, gz = o[2] + HZ + z;
+            bool f = false;
+            if (gx < n0 && gy < n1 && gz < n2) f = free_at(((size_t)gz * n1 + gy) * n0 + gx);
+            fr_l[i] = f ? 1 : 0;
+            cnt_l[i] = 0;
+        }
         __syncthreads();
-        // inflow from the halo (fixed for this launch)
+        // transposed stencil: every region node pushes its entries to the tile
         for (int q = threadIdx.x; q < NR; q += kThreads) {
-            const int ly = q / LW, lx = q - ly * LW;
-            if (lx >= H && lx < H + TX && ly >= H && ly < H + TY) continue;
-            {
-                const int cb = cell_l[q];
-                const T lv = lam_l[q];
-                if (cb >= 0 && lv != T(0)) {
-                    const int py = cb / LW, px = cb - py * LW;
-                    const T fx = fx_l[q], fy = fy_l[q];
-                    const T bl = beta * lv;
+            const int l[3] = {q % LW, (q / LW) % LH, q / (LW * LH)};
+            const int gx = o[0] + l[0], gy = o[1] + l[1], gz = o[2] + l[2];
+            if ((unsigned)gx >= (unsigned)n0 || (unsigned)gy >= (unsigned)n1 ||
+                (unsigned)gz >= (unsigned)n2)
+                continue;
+            const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+            if (!free_at(j)) continue;
+            int p[3] = {0, 0, 0};
+            T tau[3] = {T(0), T(0), T(0)};
+            if (!adj_foot<T, DIM>(d, j, l, p, tau)) continue;
+            adj_stencil<T, DIM>(d.interp, p, tau, [&](const int *v, T w) {
+                const int x = v[0] - H, y = v[1] - H, z = DIM == 3 ? v[2] - HZ : 0;
+                if ((unsigned)x >= (unsigned)TX || (unsigned)y >= (unsigned)TY ||
+                    (unsigned)z >= (unsigned)TZ)
+                    return;
+                const int ti = (z * TY + y) * TX + x;
+                if (!fr_l[ti]) return;
+                const int slot = atomicAdd(&cnt_l[ti], 1);
+                if (slot < K) {
+                    ent_s[ti * K + slot] = (short)q;
+                    ent_w[ti * K + slot] = w;
+                }
+            });
+        }
+        __syncthreads();
+        // this thread's tile nodes: sorted entry lists, owner-routed g
+        T gv[NPT];
+        int ne[NPT];
+        int qn[NPT];
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const int cy = py + b;
-                        if (cy < H || cy >= H + TY) continue;
-                        const T wy = b ? fy : T(1) - fy;
-#pragma unroll
-                        for (int a2 = 0; a2 < 2; ++a2) {
-                            const int cx = px + a2;
-                            if (cx < H || cx >= H + TX) continue;
-                            const T w = (a2 ? fx : T(1) - fx) * wy;
-                            if (w != T(0)) atomicAdd(&acc_h[(cy - H) * TX + (cx - H)], bl * w);
-                        }
+        for (int r = 0; r < NPT; ++r) {
+            const int i = threadIdx.x + r * kThreads;
+            const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+            qn[r] = ((z + HZ) * LH + (y + H)) * LW + (x + H);
+            gv[r] = T(0);
+            ne[r] = -1;
+            if (!fr_l[i]) continue;
+            const size_t j = ((size_t)(o[2] + HZ + z) * n1 + (o[1] + H + y)) * n0 + (o[0] + H + x);
+            if (!d.owner || d.owner[j] == d.set) gv[r] = d.g[j];
+            ne[r] = cnt_l[i];
+            if (ne[r] <= K) {
+                for (int a = 1; a < ne[r]; ++a) {        // insertion sort by source
+                    const short ks = ent_s[i * K + a];
+                    const T kw = ent_w[i * K + a];
+                    int b = a - 1;
+                    while (b >= 0 && ent_s[i * K + b] > ks) {
+                        ent_s[i * K + b + 1] = ent_s[i * K + b];
+                        ent_w[i * K + b + 1] = ent_w[i * K + b];
+                        --b;
                     }
+                    ent_s[i * K + b + 1] = ks;
+                    ent_w[i * K + b + 1] = kw;
                 }
             }
         }
-        // this thread's tile nodes: free flag and owner-routed g
-        T gv[NPT];
-        bool fr[NPT];
-#pragma unroll
-        for (int r = 0; r < NPT; ++r) {
-            const int ty = ty0 + r * RSTEP;
-            const int gx = x0 + tx, gy = y0 + ty;
-            fr[r] = false;
-            gv[r] = T(0);
-            if (gx < n0 && gy < n1) {
-                const size_t j = (size_t)gy * n0 + gx;
-                fr[r] = d.target[j] < 0 && (!mem || ((mem[j] >> bit) & 1));
-                if (fr[r] && (!d.owner || d.owner[j] == d.set)) gv[r] = d.g[j];
-            }
-        }
-        const int iters = local_iters > 0 ? local_iters : 1;
         double rmax = 0.0, lmax = 0.0;
         unsigned na = 0;
         bool tile_changed = false;
         for (int li = 0; li < iters; ++li) {
-            for (int i = threadIdx.x; i < NT; i += kThreads) acc_t[i] = T(0);
-            __syncthreads();             // acc_t cleared; lambda of the last iteration written
+            T nv[NPT];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
-                const int q = (ty0 + r * RSTEP + H) * LW + tx + H;
-                {
-                const int cb = cell_l[q];
-                const T lv = lam_l[q];
-                if (cb >= 0 && lv != T(0)) {
-                    const int py = cb / LW, px = cb - py * LW;
-                    const T fx = fx_l[q], fy = fy_l[q];
-                    const T bl = beta * lv;
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const int cy = py + b;
-                        if (cy < H || cy >= H + TY) continue;
-                        const T wy = b ? fy : T(1) - fy;
-#pragma unroll
-                        for (int a2 = 0; a2 < 2; ++a2) {
-                            const int cx = px + a2;
-                            if (cx < H || cx >= H + TX) continue;
-                            const T w = (a2 ? fx : T(1) - fx) * wy;
-                            if (w != T(0)) atomicAdd(&acc_t[(cy - H) * TX + (cx - H)], bl * w);
-                        }
-                    }
+                nv[r] = T(0);
+                if (ne[r] < 0) continue;
+                const int i = threadIdx.x + r * kThreads;
+                T acc = T(0);
+                if (ne[r] <= K) {
+                    for (int e = 0; e < ne[r]; ++e)
+                        acc = fma_(ent_w[i * K + e], lam_l[ent_s[i * K + e]], acc);
+                } else {
+                    // more entries than fit: rescan the neighbourhood in source order
+                    const int c[3] = {qn[r] % LW, (qn[r] / LW) % LH, qn[r] / (LW * LH)};
+                    const int zl = DIM == 3 ? max(c[2] - H - 1, 0) : 0;
+                    const int zh = DIM == 3 ? min(c[2] + H, LD - 1) : 0;
+                    for (int lz = zl; lz <= zh; ++lz)
+                        for (int ly = max(c[1] - H - 1, 0); ly <= min(c[1] + H, LH - 1); ++ly)
+                            for (int lx = max(c[0] - H - 1, 0); lx <= min(c[0] + H, LW - 1); ++lx) {
+                                const int l[3] = {lx, ly, lz};
+                                const int gx = o[0] + lx, gy = o[1] + ly, gz = o[2] + lz;
+                                if ((unsigned)gx >= (unsigned)n0 || (unsigned)gy >= (unsigned)n1 ||
+                                    (unsigned)gz >= (unsigned)n2)
+                                    continue;
+                                const size_t j = ((size_t)gz * n1 + gy) * n0 + gx;
+                                if (!free_at(j)) continue;
+                                int p[3] = {0, 0, 0};
+                                T tau[3] = {T(0), T(0), T(0)};
+                                if (!adj_foot<T, DIM>(d, j, l, p, tau)) continue;
+                                const T lq = lam_l[(lz * LH + ly) * LW + lx];
+                                adj_stencil<T, DIM>(d.interp, p, tau, [&](const int *v, T w) {
+                                    if (v[0] == c[0] && v[1] == c[1] && (DIM == 2 || v[2] == c[2]))
+                                        acc = fma_(w, lq, acc);
+                                });
+                            }
                 }
+                nv[r] = fma_(beta, acc, gv[r]);
             }
-            }
-            __syncthreads();             // every push of this iteration is done
+            __syncthreads();             // every gather of this iteration is done
             int chg = 0;
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
-                if (!fr[r]) continue;
-                const int i = (ty0 + r * RSTEP) * TX + tx;
-                const int q = (ty0 + r * RSTEP + H) * LW + tx + H;
-                const T lo = lam_l[q];
-                const T ln = gv[r] + (acc_h[i] + acc_t[i]);
-                const double dv = __builtin_fabs((double)ln - (double)lo);
-                const double al = __builtin_fabs((double)ln);
+                if (ne[r] < 0) continue;
+                const T lo = lam_l[qn[r]];
+                const double dv = __builtin_fabs((double)nv[r] - (double)lo);
+                const double al = __builtin_fabs((double)nv[r]);
                 rmax = dv > rmax ? dv : rmax;
                 lmax = al > lmax ? al : lmax;
-                chg |= dv > tol + scale_rel * al;
-                lam_l[q] = ln;
+                chg |= jacobi ? (nv[r] != lo) : (dv > tol + scale_rel * al);
+                lam_l[qn[r]] = nv[r];
                 ++na;
             }
             if (!__syncthreads_or(chg)) break;
             tile_changed = true;
         }
-        if (tile_changed) {
+        if (jacobi || tile_changed) {
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
-                if (!fr[r]) continue;
-                const int ty = ty0 + r * RSTEP;
-                lam[(size_t)(y0 + ty) * n0 + x0 + tx] = lam_l[(ty + H) * LW + tx + H];
+                if (ne[r] < 0) continue;
+                const int i = threadIdx.x + r * kThreads;
+                const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+                Vout[((size_t)(o[2] + HZ + z) * n1 + (o[1] + H + y)) * n0 + (o[0] + H + x)] =
+                    lam_l[qn[r]];
             }
         }
         nact += na;
         block_max_to(lmax, &sst->scale[iter % 3]);
-        const double bm = block_max_to(rmax, &sst->res[iter % 3]);
-        (void)bm;
+        (void)block_max_to(rmax, &sst->res[iter % 3]);
         if (threadIdx.x < 64 && tile_changed)
-            stamp_and_list<RX, RY, 0>(stamp + (size_t)((iter + 1) & 1) * stamp_stride, it,
-                                      d.tile_offset, d.tiles, iter + 1,
-                                      lists + (size_t)((iter + 1) & 1) * stamp_stride,
-                                      &cnt->class_count[cls][(iter + 1) % 3]);
+            stamp_and_list<RX, RY, RZ>(stamp + (size_t)((iter + 1) & 1) * stamp_stride, it,
+                                       d.tile_offset, d.tiles, iter + 1,
+                                       lists + (size_t)((iter + 1) & 1) * stamp_stride,
+                                       &cnt->class_count[cls][(iter + 1) % 3]);
     }
     block_sum_to(nact, &cnt->nc_updates);
 }
 
+template <typename T, int DIM, int H>
+constexpr size_t adj_lds_bytes() {
+    using TT = AdjTile<DIM>;
+    constexpr int HZ = DIM == 3 ? H : 0;
+    constexpr size_t NR = (size_t)(TT::X + 2 * H) * (TT::Y + 2 * H) * (TT::Z + 2 * HZ);
+    constexpr size_t NT = (size_t)TT::X * TT::Y * TT::Z;
+    return NR * sizeof(T) + NT * TT::K * (sizeof(T) + sizeof(short)) + NT * sizeof(int) + NT;
+}
+
 template <typename T>
-__global__ void k_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_t *target,
-                                  size_t N, T w, T *dLdl) {
+__global__ void k_adjoint_combine(const AdjDesc<T> *ads, const SdState *st, int n_sets,
+                                  const int8_t *target, size_t N, T w, T *dLdl) {
     for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
          j += (size_t)gridDim.x * blockDim.x) {
         T s = T(0);
@@ -354,38 +464,69 @@ __global__ void k_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_
             for (int i = 0; i < n_sets; ++i) {
                 const AdjDesc<T> &d = ads[i];
                 if (d.member && !((d.member[j] >> d.bit) & 1)) continue;
-                s += d.lam[j];
+                s += (st[i].final_buf ? d.lam2 : d.lam)[j];
             }
         dLdl[j] = w * s;
     }
 }
 
-// Instances of the adjoint tile kernel per halo (2D; H <= kMaxAdjHalo).
+// Instances of the gather adjoint per dimension and halo.
 constexpr int kMaxAdjHalo = 8;
+constexpr int kMaxAdjHalo3D = 5;
+template <typename T, int DIM, int H>
+void adj_entry(const void **fn, size_t *lds) {
+    fn[H] = (const void *)&k_adjoint_pull<T, DIM, H>;
+    lds[H] = adj_lds_bytes<T, DIM, H>();
+}
+struct AdjTable {
+    const void *fn[kMaxAdjHalo + 1] = {};
+    size_t lds[kMaxAdjHalo + 1] = {};
+};
+template <typename T, int DIM>
+const AdjTable &adjoint_table() {
+    static const AdjTable t = [] {
+        AdjTable a;
+        adj_entry<T, DIM, 1>(a.fn, a.lds);
+        adj_entry<T, DIM, 2>(a.fn, a.lds);
+        adj_entry<T, DIM, 3>(a.fn, a.lds);
+        adj_entry<T, DIM, 4>(a.fn, a.lds);
+        adj_entry<T, DIM, 5>(a.fn, a.lds);
+        if constexpr (DIM == 2) {
+            adj_entry<T, DIM, 6>(a.fn, a.lds);
+            adj_entry<T, DIM, 7>(a.fn, a.lds);
+            adj_entry<T, DIM, 8>(a.fn, a.lds);
+        }
+        return a;
+    }();
+    return t;
+}
 template <typename T>
-const void *adjoint_tiles_fn(int H) {
-    static const void *const table[kMaxAdjHalo + 1] = {
-        nullptr,
-        (const void *)&k_adjoint_tiles<T, 1>, (const void *)&k_adjoint_tiles<T, 2>,
-        (const void *)&k_adjoint_tiles<T, 3>, (const void *)&k_adjoint_tiles<T, 4>,
-        (const void *)&k_adjoint_tiles<T, 5>, (const void *)&k_adjoint_tiles<T, 6>,
-        (const void *)&k_adjoint_tiles<T, 7>, (const void *)&k_adjoint_tiles<T, 8>};
-    return (H >= 1 && H <= kMaxAdjHalo) ? table[H] : nullptr;
+const void *adjoint_tiles_fn(int dim, int H, size_t *lds) {
+    if (H < 1 || H > (dim == 2 ? kMaxAdjHalo : kMaxAdjHalo3D)) return nullptr;
+    const AdjTable &t = dim == 2 ? adjoint_table<T, 2>() : adjoint_table<T, 3>();
+    *lds = t.lds[H];
+    return t.fn[H];
 }
 
 }  // namespace
 
-int adjoint_tiles_max_halo() { return kMaxAdjHalo; }
+int adjoint_tiles_max_halo(int dim) { return dim == 2 ? kMaxAdjHalo : kMaxAdjHalo3D; }
 
 hipError_t adjoint_tiles_set_attributes(LaunchCfg &cfg) {
-    const void *fn = cfg.dtype == SL_F32 ? adjoint_tiles_fn<float>(cfg.halo)
-                                         : adjoint_tiles_fn<double>(cfg.halo);
+    size_t lds = 0;
+    const void *fn = cfg.dtype == SL_F32 ? adjoint_tiles_fn<float>(cfg.dim, cfg.halo, &lds)
+                                         : adjoint_tiles_fn<double>(cfg.dim, cfg.halo, &lds);
     if (!fn) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        const hipError_t e =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     int dev = 0, n_cu = 256, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         n_cu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     cfg.grid_cap = per_cu * n_cu;
@@ -399,7 +540,8 @@ hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdSt
                                 double scale_rel,
                                 int *stamp, int stamp_stride, int cls, int do_bookkeep,
                                 hipStream_t s) {
-    const void *fn = adjoint_tiles_fn<T>(cfg.halo);
+    size_t lds = 0;
+    const void *fn = adjoint_tiles_fn<T>(cfg.dim, cfg.halo, &lds);
     if (!fn) return hipErrorInvalidValue;
     int grid = max_items > 0 ? max_items : 1;
     int mode = cfg.mode;
@@ -409,7 +551,7 @@ hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdSt
                     (void *)&cnt, (void *)&iter_rel, (void *)&tol, (void *)&scale_rel, (void *)&stamp,
                     (void *)&stamp_stride, (void *)&mode, (void *)&cls, (void *)&do_bookkeep,
                     (void *)&local_iters};
-    return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s);
 }
 template hipError_t launch_adjoint_tiles<float>(const LaunchCfg &, const SdDesc<float> *, SdState *, int, const WorkItem *, WorkItem *, ExecCounters *, int, int, double, double, int *, int, int, int, hipStream_t);
 template hipError_t launch_adjoint_tiles<double>(const LaunchCfg &, const SdDesc<double> *, SdState *, int, const WorkItem *, WorkItem *, ExecCounters *, int, int, double, double, int *, int, int, int, hipStream_t);
@@ -431,15 +573,15 @@ template hipError_t launch_adjoint_iter<float>(int, const AdjDesc<float> *, SdSt
 template hipError_t launch_adjoint_iter<double>(int, const AdjDesc<double> *, SdState *, int, int, ExecCounters *, int, double, double, hipStream_t);
 
 template <typename T>
-hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_t *target,
-                                  size_t N, T w, T *dLdl, hipStream_t s) {
+hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, const SdState *st, int n_sets,
+                                  const int8_t *target, size_t N, T w, T *dLdl, hipStream_t s) {
     size_t g = (N + kThreads - 1) / kThreads;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_adjoint_combine<T>, dim3((unsigned)g), dim3(kThreads), 0, s, ads,
+    hipLaunchKernelGGL(k_adjoint_combine<T>, dim3((unsigned)g), dim3(kThreads), 0, s, ads, st,
                        n_sets, target, N, w, dLdl);
     return hipGetLastError();
 }
-template hipError_t launch_adjoint_combine<float>(const AdjDesc<float> *, int, const int8_t *, size_t, float, float *, hipStream_t);
-template hipError_t launch_adjoint_combine<double>(const AdjDesc<double> *, int, const int8_t *, size_t, double, double *, hipStream_t);
+template hipError_t launch_adjoint_combine<float>(const AdjDesc<float> *, const SdState *, int, const int8_t *, size_t, float, float *, hipStream_t);
+template hipError_t launch_adjoint_combine<double>(const AdjDesc<double> *, const SdState *, int, const int8_t *, size_t, double, double *, hipStream_t);
 
 }  // namespace slhjb

@@ -1258,7 +1258,7 @@ struct AdjPlan {
     SdState *st = nullptr;
     ExecCounters *cnt = nullptr;
     FieldStats *fs = nullptr;
-    Exec<T> ex;                      // block-asynchronous tile path (2D)
+    Exec<T> ex;                      // gather tile path
 };
 
 template <typename T>
@@ -1272,10 +1272,12 @@ void plan_adjoint(const sl_problem *p, int n_sets, Arena &a, AdjPlan<T> &P) {
     P.st = a.take<SdState>(n_sets);
     P.cnt = a.take<ExecCounters>(1);
     P.fs = a.take<FieldStats>(1);
-    if (p->dim == 2) {
-        const int tiles = ((p->n[0] + kAdjTX - 1) / kAdjTX) * ((p->n[1] + kAdjTY - 1) / kAdjTY);
-        P.ex.reserve(a, n_sets, tiles * n_sets);
-    }
+    const int tiles = p->dim == 2
+                          ? ((p->n[0] + kAdjTX - 1) / kAdjTX) * ((p->n[1] + kAdjTY - 1) / kAdjTY)
+                          : ((p->n[0] + kAdjTX3 - 1) / kAdjTX3) *
+                                ((p->n[1] + kAdjTY3 - 1) / kAdjTY3) *
+                                ((p->n[2] + kAdjTZ3 - 1) / kAdjTZ3);
+    P.ex.reserve(a, n_sets, tiles * n_sets);
 }
 
 template <typename T>
@@ -1313,6 +1315,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     for (int i = 0; i < n_sets; ++i) {
         AdjDesc<T> &d = hd[i];
         d.lam = P.lam + (size_t)i * N;
+        d.lam2 = d.lam;
         d.acc[0] = P.acc + (size_t)i * 2 * N;
         d.acc[1] = d.acc[0] + N;
         d.g = dLdV;
@@ -1331,6 +1334,13 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         d.speed_axes = speed_comps(p) > 1;
         d.interp = p->interp;
     }
+    const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
+    const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
+    // the gather tile path when the feet stay within its halo; otherwise the
+    // Jacobi scatter over the whole grid
+    const bool tiles = H <= adjoint_tiles_max_halo(p->dim);
+    if (tiles && local_iters == 0)          // Jacobi: the second buffer is the acc area
+        for (int i = 0; i < n_sets; ++i) hd[i].lam2 = hd[i].acc[0];
     HIPCHK(hipMemcpyAsync(P.ads, hd.data(), sizeof(AdjDesc<T>) * n_sets, hipMemcpyHostToDevice, s));
     std::vector<SdState> hs(n_sets);
     for (auto &x : hs) {
@@ -1346,17 +1356,14 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     bps = std::max(1, std::min(bps, 2048));
     int *active = pinned().active;
     if (!active) return SL_ERR_HIP;
-    const double smax = p->speed ? bits_to_double(fs.speed_max) : 1.0;
-    const int H = halo_for(smax, emax, drift_reach(p, p->n, p->h, fs));
-    if (p->dim == 2 && local_iters > 0 && H <= adjoint_tiles_max_halo() &&
-        p->interp == SL_INTERP_Q1) {
-        // block-asynchronous tiles on the sweep executor
+    if (tiles) {
+        // gather tiles on the sweep executor
         LaunchCfg cfg{};
-        cfg.dim = 2;
+        cfg.dim = p->dim;
         cfg.dtype = p->dtype;
-        cfg.tile[0] = kAdjTX;
-        cfg.tile[1] = kAdjTY;
-        cfg.tile[2] = 1;
+        cfg.tile[0] = p->dim == 2 ? kAdjTX : kAdjTX3;
+        cfg.tile[1] = p->dim == 2 ? kAdjTY : kAdjTY3;
+        cfg.tile[2] = p->dim == 2 ? 1 : kAdjTZ3;
         cfg.halo = H;
         cfg.variant = -1;
         cfg.threads = kThreads;
@@ -1367,7 +1374,8 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         P.ex.host_sds.clear();
         for (int i = 0; i < n_sets; ++i) {
             SdDesc<T> sd{};
-            sd.V[0] = sd.V[1] = hd[i].lam;
+            sd.V[0] = hd[i].lam;
+            sd.V[1] = hd[i].lam2;
             sd.speed = (const T *)p->speed;
             sd.speed_axes = hd[i].speed_axes;
             sd.drift = P.q;
@@ -1380,8 +1388,9 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
             sd.m = p->m;
             sd.m_inner = p->m;
             sd.bit = i;
-            Exec<T>::tiles_of(cfg, sd.n, 2, sd.tiles);
+            Exec<T>::tiles_of(cfg, sd.n, p->dim, sd.tiles);
             sd.halo = H;
+            sd.interp = p->interp;
             sd.g = dLdV;
             sd.owner = member ? owner : nullptr;
             sd.set = i;
@@ -1392,7 +1401,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         long it = 0;
         const int status = P.ex.run(tol, max_iters, 32, 0, s, &it, 0);
         if (status < 0) return status;
-        HIPCHK(launch_adjoint_combine<T>(P.ads, n_sets, p->target, N, (T)w, dLdl, s));
+        HIPCHK(launch_adjoint_combine<T>(P.ads, P.ex.st, n_sets, p->target, N, (T)w, dLdl, s));
         tm.mark(2, s);
         std::vector<SdState> hs2;
         unsigned long long nc = 0;
@@ -1424,7 +1433,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     int status = SL_NOT_CONVERGED;
     if ((rc = loop.run(enqueue, max_iters, 32, s, 1, 0, &it, &status, active))) return rc;
     HIPCHK(launch_bookkeep(P.st, n_sets, 0, tol, P.cnt, 1, s, scale_rel));
-    HIPCHK(launch_adjoint_combine<T>(P.ads, n_sets, p->target, N, (T)w, dLdl, s));
+    HIPCHK(launch_adjoint_combine<T>(P.ads, P.st, n_sets, p->target, N, (T)w, dLdl, s));
     tm.mark(2, s);
     ExecCounters c{};
     HIPCHK(hipMemcpyAsync(hs.data(), P.st, sizeof(SdState) * n_sets, hipMemcpyDeviceToHost, s));

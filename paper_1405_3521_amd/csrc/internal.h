@@ -51,6 +51,7 @@ struct SdDesc {
     const T *g;                 // dL/dV per node
     const uint8_t *owner;       // set owning each node's value, or nullptr (all sets)
     int set;                    // this sd's set index (compared with owner)
+    int interp;                 // sl_interp of the frozen feet's stencil
 };
 
 // Per-sub-domain convergence state (device memory).
@@ -101,6 +102,8 @@ struct FieldStats {
 template <typename T>
 struct AdjDesc {
     T *lam;                     // adjoint state per node
+    T *lam2;                    // second Jacobi buffer of the tile path (= lam otherwise);
+                                // the set's final_buf picks the one holding the result
     T *acc[2];                  // inflow accumulators (ping-pong)
     const T *g;                 // dL/dV per node
     const uint8_t *owner;       // set owning each node's value, or nullptr (all)
@@ -281,9 +284,10 @@ template <typename T>
 hipError_t launch_adjoint_iter(int dim, const AdjDesc<T> *ads, SdState *st, int n_sets,
                                int blocks_per_set, ExecCounters *cnt, int iter_rel, double tol,
                                double scale_rel, hipStream_t s);
-// Block-asynchronous adjoint over the tile work items of an executor (2D): every
-// active tile iterates lambda = g + beta P^T lambda up to local_iters times in
-// LDS, the halo's inflow as staged, and writes back in place.
+// Gather adjoint over the tile work items of an executor (2D and 3D): every
+// active tile gathers lambda = g + beta P^T lambda through its transposed
+// stencil, once per launch into the other buffer (local_iters = 0, Jacobi) or up
+// to local_iters times in LDS, writing back in place.
 template <typename T>
 hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdState *st,
                                 int n_sd, const WorkItem *items, WorkItem *lists,
@@ -292,11 +296,12 @@ hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdSt
                                 int *stamp, int stamp_stride, int cls, int do_bookkeep,
                                 hipStream_t s);
 hipError_t adjoint_tiles_set_attributes(LaunchCfg &cfg);
-int adjoint_tiles_max_halo();
-// Tile shape of the adjoint tile kernel.
+int adjoint_tiles_max_halo(int dim);
+// Tile shapes of the gather adjoint: 2D 32x16, 3D 8x8x4.
 constexpr int kAdjTX = 32, kAdjTY = 16;
+constexpr int kAdjTX3 = 8, kAdjTY3 = 8, kAdjTZ3 = 4;
 template <typename T>
-hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, int n_sets, const int8_t *target,
-                                  size_t N, T w, T *dLdl, hipStream_t s);
+hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, const SdState *st, int n_sets,
+                                  const int8_t *target, size_t N, T w, T *dLdl, hipStream_t s);
 
 }  // namespace slhjb

@@ -262,3 +262,82 @@ def test_autograd_gradient_with_drift_against_fd():
         an = float(grad @ d)
         say(f"  fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
         assert abs(fd - an) <= 1e-3 * abs(fd)
+
+
+# --------------------------------------------------- gather tiles, determinism
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
+def test_adjoint_jacobi_mode_is_deterministic(dtype, tol):
+    """local_iters = 0 (Jacobi gather over tiles, no atomics): two calls give the
+    same bits, global and with sets; both match the oracle's adjoint."""
+    p = W.c5_adjoint(n=129, n_obs=1500)
+    say("case: deterministic adjoint", dtype)
+    Vbar, owner, rec, Vs, _ = I.isa(p)
+    _, pols, _ = I.solve_subdomains(p, rec.member, want_policy=True)
+    gV = np.random.Generator(np.random.PCG64(17)).normal(size=p.N)
+    dLdl_o, _ = I.adjoint_isa(p, rec.member, pols, owner, gV)
+    dp = S.to_device(p, dtype)
+    pol_t = torch.as_tensor(np.concatenate([pol_u8(q) for q in pols]), device=DEV)
+    args = dict(member=torch.as_tensor(rec.member, device=DEV),
+                owner=torch.as_tensor(owner, device=DEV), tol=0.0, local_iters=0)
+    g_t = torch.as_tensor(gV, dtype=dtype, device=DEV)
+    a, st = S.adjoint(dp, pol_t, g_t, **args)
+    b, _ = S.adjoint(dp, pol_t, g_t, **args)
+    assert st["converged"]
+    assert torch.equal(a, b)
+    err = rel_l2(a.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  rel l2", err, "launches", st["sweeps_max"])
+    assert err <= tol
+
+
+def _adjoint_3d(n=25, seed=3):
+    p = W.c3_aniso3d(n=n, m=32, n_balls=3, r=0.15)
+    th = np.random.Generator(np.random.PCG64(seed)).normal(0.0, 0.1, p.N)
+    return p.with_(cost=W.f32(np.exp(th)), v_ghost=2.0)
+
+
+@pytest.mark.parametrize("li", LOCAL)
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
+def test_adjoint_3d_tiles(dtype, tol, li):
+    """3D gather tiles (8x8x4 nodes, halo as the feet need), Jacobi and
+    block-asynchronous, against the oracle's adjoint; with sets too."""
+    p = _adjoint_3d()
+    say("case: 3d adjoint tiles", dtype, "local", li)
+    V, pol, _, _ = O.solve(p)
+    gV = np.random.Generator(np.random.PCG64(19)).normal(size=p.N)
+    _, dLdl_o, _, _ = O.adjoint(p, pol, gV)
+    dp = S.to_device(p, dtype)
+    dLdl, st = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
+                         torch.as_tensor(gV, dtype=dtype, device=DEV), tol=0.0, local_iters=li)
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  global rel l2", err, "launches", st["sweeps_max"])
+    assert st["converged"] and err <= tol
+    Vbar, owner, rec, Vs, _ = I.isa(p)
+    _, pols, _ = I.solve_subdomains(p, rec.member, want_policy=True)
+    dLdl_o, _ = I.adjoint_isa(p, rec.member, pols, owner, gV)
+    dLdl, st = S.adjoint(dp, torch.as_tensor(np.concatenate([pol_u8(q) for q in pols]), device=DEV),
+                         torch.as_tensor(gV, dtype=dtype, device=DEV),
+                         member=torch.as_tensor(rec.member, device=DEV),
+                         owner=torch.as_tensor(owner, device=DEV), tol=0.0, local_iters=li)
+    err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+    say("  sets rel l2", err, "launches", st["sweeps_max"])
+    assert st["converged"] and err <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
+def test_adjoint_long_feet_scatter_path(dtype, tol):
+    """Feet longer than the tiles' halo (speed 8.5, so 9 cells in 2D) take the
+    whole-grid Jacobi scatter: same bars."""
+    p = W.c5_adjoint(n=97, n_obs=500)
+    p = p.with_(speed=W.f32(np.full(p.N, 8.5)))
+    say("case: adjoint scatter path", dtype)
+    V, pol, _, _ = O.solve(p)
+    gV = np.random.Generator(np.random.PCG64(23)).normal(size=p.N)
+    _, dLdl_o, _, _ = O.adjoint(p, pol, gV)
+    dp = S.to_device(p, dtype)
+    for li in LOCAL:
+        dLdl, st = S.adjoint(dp, torch.as_tensor(pol_u8(pol), device=DEV),
+                             torch.as_tensor(gV, dtype=dtype, device=DEV), tol=0.0,
+                             local_iters=li)
+        err = rel_l2(dLdl.cpu().numpy().astype(np.float64), dLdl_o)
+        say("  local", li, "rel l2", err, "launches", st["sweeps_max"])
+        assert st["converged"] and err <= tol
