@@ -97,10 +97,15 @@ def parse():
     ap.add_argument("--ra-config", type=int, default=0,
                     help="coarse FP64 pass of the headline: k > 0 forces coarse candidate k-1 "
                          "(sl_tune_candidates order), 0 lets the autotuner pick")
+    ap.add_argument("--leg-local-iters", default="",
+                    help="override the fine local iterations of legs, e.g. c5=16,c3=8")
+    ap.add_argument("--adj-local-iters", type=int, default=16,
+                    help="gradient leg: local iterations of the adjoint tiles (-1: as the "
+                         "forward's; 0: the deterministic Jacobi mode)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference "
                          "kernel for scaling the HBM byte counters)")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,vdp,pe,kruzkov,p1,p1_3d,study,balance",
+    ap.add_argument("--legs", default="c1,c3,c4,c5,vdp,pe,kruzkov,p1,p1_3d,study,balance,tables",
                     help="extra workloads to report: c1 (FP64 eikonal 101^2 to 1e-10), "
                          "c3 (3D 257^3), c4 (512-problem batch), "
                          "c5 (adjoint 513^2), vdp (Van der Pol drift 1025^2), pe "
@@ -109,7 +114,8 @@ def parse():
                          "interpolation), "
                          "study (global solve vs ISA and the "
                          "RA threshold on the headline problem), balance (refinement of the "
-                         "target split, Van der Pol); empty for none")
+                         "target split, Van der Pol), tables (the paper's Tables 1-5 on "
+                         "this GPU); empty for none")
     return ap.parse_args()
 
 
@@ -317,6 +323,126 @@ def leg_study(steps: int, li: int):
             "isa_by_delta": rows}
 
 
+def leg_tables(steps: int, li: int):
+    """Analogues of the paper's tables (Sec. 4.1) measured on MI355X.
+
+    tab1: distance function (4 edges, delta = dx_K), RA on coarse grids of N^2
+          cells under a 1025^2 fine grid: time and largest set (coarse and fine).
+    tab2: distance function, global solve (ND) against the ISA (RA on 20^2 cells)
+          from 25^2 to 1025^2 nodes, FP32 to sup-res < 1e-6.
+    tab3: distance function, sup and mean error against the closed form
+          1 - exp(-(1 - max|x_i|)) on 51^2, 101^2, 201^2 nodes: global solve and
+          the ISA with 2, 4 and 8 boundary pieces (FP64, to stagnation).
+    tab4: Van der Pol (4 slices), RA on coarse grids under a 401^2 fine grid:
+          time and largest set.
+    tab5: Van der Pol, sup and mean error against the oracle's 401^2 solution
+          (tests/golden/vdp_401.npz) at coincident nodes reachable in the
+          reference: global solve and the ISA with 2, 4 and 8 slices (FP64)."""
+    import torch
+    import paper_1405_3521_amd as S
+    import workloads as W
+    dev = "cuda:0"
+
+    def timed(fn, k=steps):
+        fn()
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            out = fn()
+        _sync()
+        return out, (time.perf_counter() - t0) / k * 1e3
+
+    def ra_for(p, nK, autotune=1):
+        return S.RaOpts(coarse_n=(nK, nK), C=p.ra_C, M=p.ra_M, q=p.ra_q, tol=0.0,
+                        autotune=autotune, local_iters=8)
+
+    out = {}
+    # Table 1
+    p = W.box_distance_problem(1025, split=4).with_(ra_C=0.25, ra_M=0.25)
+    dp = S.to_device(p, torch.float32, dev)
+    rows = []
+    for N in (5, 7, 10, 15, 20, 30, 40, 50):
+        ra = ra_for(p, N + 1)
+        (mem, lab, st, mK, lK), ms = timed(lambda: S.reconstruct(dp, ra, want_coarse=True))
+        fK = max(float(((mK >> i) & 1).float().mean()) for i in range(4))
+        ff = max(float(((mem >> i) & 1).float().mean()) for i in range(4))
+        rows.append({"N": N, "dx_K": 2.0 / N, "ms": ms, "set_fraction_max_coarse": fK,
+                     "set_fraction_max_fine": ff})
+    out["tab1_distance_ra"] = rows
+    # Table 2
+    rows = []
+    for n in (25, 51, 75, 101, 201, 301, 1025):
+        p = W.box_distance_problem(n, split=4).with_(ra_C=0.25, ra_M=0.25)
+        dp = S.to_device(p, torch.float32, dev)
+        opts = S.SolveOpts(tol=1e-6, autotune=1, local_iters=li)
+        (_, _, stn), ms_nd = timed(lambda: S.solve(dp, opts))
+        ra = ra_for(p, 21)
+        (_, _, _, _, _, _, sti), ms_isa = timed(lambda: S.isa(dp, ra, opts))
+        rows.append({"n": n, "nd_ms": ms_nd, "isa_ms": ms_isa,
+                     "isa_set_fraction_max": sti["set_fraction_max"]})
+    out["tab2_distance_nd_vs_isa"] = rows
+    # Table 3: with the exponential discount and h = dx the scheme is exact at the
+    # nodes for this problem (an axis control lands on a node and no other control
+    # does better), so the errors of the discount printed with the scheme
+    # (1/(1 + h), w = h) are reported beside it
+    rows = []
+    for n in (51, 101, 201):
+        X = W.node_coords((n, n), (-1.0, -1.0), (1.0, 1.0))
+        exact = 1.0 - np.exp(-(1.0 - np.abs(X).max(axis=1)))
+        for split in (1, 2, 4, 8):
+            row = {"n": n, "subsets": split}
+            for disc, vg in (("exp", 1.0), ("paper", 2.0)):
+                p = W.box_distance_problem(n, split=split).with_(ra_C=0.25, ra_M=0.25,
+                                                                 disc=disc, v_ghost=vg)
+                dp = S.to_device(p, torch.float64, dev)
+                opts = S.SolveOpts(tol=0.0, autotune=1, local_iters=li)
+                if split == 1:
+                    V = S.solve(dp, opts)[0]
+                else:
+                    V = S.isa(dp, ra_for(p, 21), opts)[0]
+                e = np.abs(V.cpu().numpy() - exact)
+                row[f"sup_{disc}"] = float(e.max())
+                row[f"mean_{disc}"] = float(e.mean())
+            rows.append(row)
+    out["tab3_distance_error"] = rows
+    # Table 4
+    p = W.vdp_problem(401, split=4)
+    dp = S.to_device(p, torch.float32, dev)
+    rows = []
+    for N in (5, 10, 20, 30, 40, 50):
+        ra = ra_for(p, N + 1)
+        (mem, lab, st, mK, lK), ms = timed(lambda: S.reconstruct(dp, ra, want_coarse=True))
+        fK = max(float(((mK >> i) & 1).float().mean()) for i in range(4))
+        ff = max(float(((mem >> i) & 1).float().mean()) for i in range(4))
+        rows.append({"N": N, "dx_K": 2.0 / N, "ms": ms, "set_fraction_max_coarse": fK,
+                     "set_fraction_max_fine": ff})
+    out["tab4_vdp_ra"] = rows
+    # Table 5
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "vdp_401.npz"))
+    Vr = ref["V"].astype(np.float64).reshape(401, 401)
+    rows = []
+    for n in (51, 101, 201):
+        step = 400 // (n - 1)
+        R = Vr[::step, ::step].reshape(-1)
+        for split in (1, 2, 4, 8):
+            p = W.vdp_problem(n, split=split)
+            dp = S.to_device(p, torch.float64, dev)
+            opts = S.SolveOpts(tol=0.0, autotune=1, local_iters=li)
+            if split == 1:
+                V, _, st = S.solve(dp, opts)
+            else:
+                V, _, _, _, _, _, st = S.isa(dp, ra_for(p, 21), opts)
+            ok = (np.asarray(p.target) < 0) & (R < float(ref["v_ghost"]))
+            e = np.abs(V.cpu().numpy() - R)[ok]
+            rows.append({"n": n, "subsets": split, "sup": float(e.max()), "mean": float(e.mean()),
+                         "n_unreachable": int(st["n_unreachable"])})
+    out["tab5_vdp_error"] = rows
+    out["workload"] = ("distance function and Van der Pol examples of Sec. 4.1: RA set sizes, "
+                       "ND vs ISA time, errors against the closed form / the oracle's 401^2 "
+                       "reference")
+    return out
+
+
 def leg_balance(steps: int, li: int):
     """Recursive refinement of the target split (balance) on Van der Pol 1025^2
     (RA on 129^2, C = M = 0.05, q = 1): from the whole capture disk as one
@@ -404,6 +530,9 @@ def leg_c4(steps: int, li: int):
             "node_control_updates_per_s": tot["node_control_updates"] / (ms_b / 1e3)}
 
 
+ADJ_LOCAL_ITERS = 16         # set from --adj-local-iters
+
+
 def leg_c5(steps: int, li: int):
     """Adjoint 513^2: loss sum (V - V_obs)^2 on 2000 nodes, l = exp(theta); ISA
     forward with the policy exported, then the adjoint (sets frozen)."""
@@ -416,14 +545,15 @@ def leg_c5(steps: int, li: int):
     member, label, _ = S.reconstruct(dp, ra)
     th_true = torch.as_tensor(p.meta["theta_true"], dtype=torch.float32, device="cuda:0")
     fwd_opts = S.SolveOpts(tol=1e-6, autotune=1, local_iters=li)
-    V_obs = S.HJBSolve.apply(torch.exp(th_true), dp, member, ra, fwd_opts, 1e-7, li)
+    ali = li if ADJ_LOCAL_ITERS < 0 else ADJ_LOCAL_ITERS
+    V_obs = S.HJBSolve.apply(torch.exp(th_true), dp, member, ra, fwd_opts, 1e-7, ali)
     obs = torch.as_tensor(p.meta["obs"], device="cuda:0")
     V_obs = V_obs[obs].detach()
     theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device="cuda:0")
 
     def fwd_bwd():
         th = theta.clone().requires_grad_(True)
-        V = S.HJBSolve.apply(torch.exp(th), dp, member, ra, fwd_opts, 1e-7, li)
+        V = S.HJBSolve.apply(torch.exp(th), dp, member, ra, fwd_opts, 1e-7, ali)
         loss = ((V[obs] - V_obs) ** 2).sum()
         _sync()
         t1 = time.perf_counter()
@@ -548,6 +678,8 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
         return
 
+    global ADJ_LOCAL_ITERS
+    ADJ_LOCAL_ITERS = args.adj_local_iters
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
     ra = ra_opts(prob, autotune=-args.ra_config if args.ra_config > 0 else 1,
@@ -625,10 +757,12 @@ def main():
     for leg in [x for x in args.legs.split(",") if x]:
         fn = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "vdp": leg_vdp, "pe": leg_pe,
               "study": leg_study, "balance": leg_balance, "kruzkov": leg_kruzkov, "c1": leg_c1,
+              "tables": leg_tables,
               "p1": leg_p1, "p1_3d": leg_p1_3d}[leg]
         t0 = time.perf_counter()
-        legs[leg] = fn(max(1, min(args.steps, 3)),
-                       LEG_LOCAL_ITERS.get(leg, LEG_LOCAL_ITERS_DEFAULT))
+        over = dict(kv.split("=") for kv in args.leg_local_iters.split(",") if kv)
+        li_leg = int(over[leg]) if leg in over else LEG_LOCAL_ITERS.get(leg, LEG_LOCAL_ITERS_DEFAULT)
+        legs[leg] = fn(max(1, min(args.steps, 3)), li_leg)
         print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if legs:
         res["legs"] = legs

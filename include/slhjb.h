@@ -204,7 +204,10 @@ typedef struct sl_stats {
     double node_control_updates; /* node*control evaluations actually computed        */
     double ms_ra, ms_fine, ms_total; /* wall times of the phases (HIP events)         */
     int n_subdomains;         /* sub-domains solved                                   */
-    int n_unreachable;        /* reserved (0)                                         */
+    int n_unreachable;        /* sl_solve, sl_solve_isa: free nodes whose final value is
+                                 still v_ghost up to rounding, |V - v_ghost| <= 8 eps
+                                 v_ghost / (1 - beta) (they never read a reached value:
+                                 no target is reachable from them); else 0 */
     double set_fraction_max;  /* max_i |Sigma_i| / N on the fine grid (ISA calls)     */
     double ms_sweeps;         /* profile: HIP-event time spanning the sweep launches  */
     long sweep_launches;      /* profile: number of sweep launches timed              */

@@ -681,6 +681,7 @@ struct Exec {
         return run(tol, max_sweeps, check_every, want_policy, s, sweeps_done, profile);
     }
 
+    unsigned long long unreached = 0;   // from the last read_stats
     int read_stats(hipStream_t s, std::vector<SdState> &out, unsigned long long *nc) {
         out.resize(n_sd);
         ExecCounters c{};
@@ -688,6 +689,7 @@ struct Exec {
         HIPCHK(hipMemcpyAsync(&c, cnt, sizeof(ExecCounters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         *nc = c.nc_updates;
+        unreached = c.n_unreached;
         return SL_OK;
     }
 };
@@ -796,6 +798,19 @@ int check_fields(const FieldStats &fs) {
     return SL_OK;
 }
 
+// A free node that never reads a reached value keeps v_ghost up to rounding: the
+// iteration V = beta V + w l settles within about eps G / (1 - beta) of G (the
+// rounding of one step, amplified by the contraction).  Values within eight
+// times that count as unreached.
+template <typename T>
+T unreached_level(const sl_problem *p) {
+    const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+    double beta, w;
+    scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
+    const double G = p->v_ghost;
+    return (T)(G - 8.0 * eps * std::fabs(G) / std::max(1.0 - beta, 1e-12));
+}
+
 // ------------------------------------------------------------ global solve
 template <typename T>
 int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **ctrl,
@@ -898,11 +913,14 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
                                       o->want_policy && policy, s, &S, o->profile);
     if (status < 0) return status;
     HIPCHK(launch_copy_final<T>(ex.sds, ex.st, 0, V, N, s));
+    HIPCHK(launch_count_unreached<T>(V, p->target, N, unreached_level<T>(p),
+                                     &ex.cnt->n_unreached, s));
     tm.mark(2, s);
     std::vector<SdState> hs;
     unsigned long long nc = 0;
     if ((rc = ex.read_stats(s, hs, &nc))) return rc;
     fill_stats(stats, hs, nc, S);
+    if (stats) stats->n_unreachable = (int)ex.unreached;
     if (stats) {
         stats->ms_ra = 0.0;
         stats->ms_fine = tm.ms(1, 2);
@@ -1229,6 +1247,8 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
             HIPCHK(launch_copy_final<T>(P.ex.sds, P.ex.st, i, V_sets + (size_t)i * N, N, s));
     HIPCHK(hipMemsetAsync(P.counts, 0, sizeof(unsigned long long) * 8, s));
     HIPCHK(launch_member_counts(member, N, P.counts, s));
+    HIPCHK(launch_count_unreached<T>(V, p->target, N, unreached_level<T>(p),
+                                     &P.ex.cnt->n_unreached, s));
     unsigned long long counts[8];
     HIPCHK(hipMemcpyAsync(counts, P.counts, sizeof(counts), hipMemcpyDeviceToHost, s));
     tm.mark(3, s);
@@ -1237,6 +1257,7 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     if ((rc = P.ex.read_stats(s, hs, &ncu))) return rc;
     fill_stats(stats, hs, ncu, S);
     if (stats) {
+        stats->n_unreachable = (int)P.ex.unreached;
         double fr = 0.0;
         for (int i = 0; i < nc; ++i) fr = std::max(fr, (double)counts[i] / (double)N);
         stats->set_fraction_max = fr;

@@ -84,6 +84,7 @@ struct ExecCounters {
     int class_items[kMaxClasses];      // work items per halo class
     int class_queue[kMaxClasses][3];   // per-class, per-sweep work-queue heads
     int class_count[kMaxClasses][3];   // per-class, per-sweep active-list lengths
+    unsigned long long n_unreached;    // free nodes left at the ghost value (after the solve)
 };
 
 // Input statistics gathered on the device in one pass (see launch_field_stats).
@@ -269,6 +270,11 @@ template <typename T>
 hipError_t launch_copy_final(const SdDesc<T> *sds_dev, const SdState *st, int i, T *dst,
                              size_t N, hipStream_t s);
 // member popcounts per bit (for set fractions)
+// Free nodes whose value is still the ghost value G (no target reached), added
+// to *count.
+template <typename T>
+hipError_t launch_count_unreached(const T *V, const int8_t *target, size_t N, T G,
+                                  unsigned long long *count, hipStream_t s);
 hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long long *counts8,
                                 hipStream_t s);
 

@@ -379,6 +379,17 @@ __global__ void k_copy_final(const SdDesc<T> *sds, const SdState *st, int i, T *
         dst[j] = src[j];
 }
 
+template <typename T>
+__global__ void k_count_unreached(const T *V, const int8_t *target, size_t N, T G,
+                                  unsigned long long *count) {
+    unsigned c = 0;
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N;
+         j += (size_t)gridDim.x * blockDim.x)
+        c += target[j] < 0 && V[j] >= G;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
 __global__ void k_member_counts(const uint8_t *member, size_t N, unsigned long long *counts) {
     __shared__ unsigned c[8];
     if (threadIdx.x < 8) c[threadIdx.x] = 0;
@@ -566,5 +577,15 @@ hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long l
                        dim3(kOpThreads), 0, s, member, N, counts8);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_count_unreached(const T *V, const int8_t *target, size_t N, T G,
+                                  unsigned long long *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_unreached<T>, dim3(grid_for(N) < 1024 ? grid_for(N) : 1024),
+                       dim3(kOpThreads), 0, s, V, target, N, G, count);
+    return hipGetLastError();
+}
+template hipError_t launch_count_unreached<float>(const float *, const int8_t *, size_t, float, unsigned long long *, hipStream_t);
+template hipError_t launch_count_unreached<double>(const double *, const int8_t *, size_t, double, unsigned long long *, hipStream_t);
 
 }  // namespace slhjb

@@ -365,7 +365,8 @@ def strip_problem(n: int, delta: float, m: int = 32) -> Problem:
 
 def box_distance_problem(n: int, split: int = 4, m: int = 32) -> Problem:
     """Distance to the boundary of (-1,1)^2 with lam = 1: the whole grid boundary is
-    the target, split into ``split`` components (1, 2, 4 edge groups)."""
+    the target, split into ``split`` components (1, 2, 4 edge groups, or 8 half
+    edges)."""
     N = n * n
     tid = np.full(N, -1, dtype=np.int8)
     T = tid.reshape(n, n)           # T[i1, i0]
@@ -379,8 +380,14 @@ def box_distance_problem(n: int, split: int = 4, m: int = 32) -> Problem:
         T[-1, :] = 2                   # top    (x2 = +1)
         T[:, -1] = 1                   # right  (x1 = +1)
         T[0, :] = 0                    # bottom (x2 = -1), corners go to the last writer
+    elif split == 8:
+        h = n // 2                     # each edge in two halves, the middle node to the upper
+        T[:h, 0] = 6; T[h:, 0] = 7     # left
+        T[-1, :h] = 4; T[-1, h:] = 5   # top
+        T[:h, -1] = 2; T[h:, -1] = 3   # right
+        T[0, :h] = 0; T[0, h:] = 1     # bottom, corners go to the last writer
     else:
-        raise ValueError("split must be 1, 2 or 4")
+        raise ValueError("split must be 1, 2, 4 or 8")
     return Problem(name=f"boxdist_{n}_{split}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                    velocity=controls_2d(m), target=tid, n_comp=split, v_ghost=1.0,
                    coarse_stride=1)
@@ -389,7 +396,7 @@ def box_distance_problem(n: int, split: int = 4, m: int = 32) -> Problem:
 def vdp_problem(n: int, split: int = 4, n_a: int = 21, rho: float = 0.2) -> Problem:
     """Van der Pol target problem: f = (x2, (1 - x1^2) x2 - x1) + (0, a), a in [-1,1]
     (``n_a`` values), l = |x|, target = nodes of the ball |x| <= rho split in
-    ``split`` quadrant-shaped slices."""
+    ``split`` slices (halves, quadrants, or octants by angle)."""
     X = node_coords((n, n), (-1.0, -1.0), (1.0, 1.0))
     x1, x2 = X[:, 0], X[:, 1]
     drift = np.stack([x2, (1.0 - x1 * x1) * x2 - x1], axis=1)
@@ -404,8 +411,11 @@ def vdp_problem(n: int, split: int = 4, n_a: int = 21, rho: float = 0.2) -> Prob
     elif split == 4:
         comp = np.select([(x1 >= 0) & (x2 >= 0), (x1 >= 0) & (x2 < 0), (x1 < 0) & (x2 < 0)],
                          [0, 1, 2], 3).astype(np.int8)
+    elif split == 8:
+        ang = np.arctan2(x2, x1)                     # (-pi, pi]
+        comp = np.clip(np.floor((ang + np.pi) / (np.pi / 4)), 0, 7).astype(np.int8)
     else:
-        raise ValueError("split must be 1, 2 or 4")
+        raise ValueError("split must be 1, 2, 4 or 8")
     tid[inside] = comp[inside]
     return Problem(name=f"vdp_{n}_{split}", dim=2, n=(n, n), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                    velocity=vel, target=tid, n_comp=split, speed=None,
