@@ -20,7 +20,8 @@ import numpy as np
 __all__ = [
     "DeviceProblem", "RaOpts", "SolveOpts", "lib", "lib_path", "to_device", "solve",
     "solve_noalloc",
-    "reconstruct", "solve_isa", "isa", "adjoint", "solve_batched", "refine_split", "SlError",
+    "reconstruct", "solve_isa", "isa", "adjoint", "solve_batched", "BatchedSolver",
+    "refine_split", "SlError",
     "HJBSolve",
 ]
 
@@ -493,43 +494,69 @@ def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float 
     return out, d
 
 
+class BatchedSolver:
+    """A batch marshalled once for repeated calls of sl_solve_batched: the problem
+    and option structs, the output tensors (V, member, label, owner per problem),
+    their pointer arrays and the workspace are built here; ``solve`` only makes
+    the call.  The problems' device fields must stay alive and unchanged in shape
+    while the solver is used (their values may change between calls)."""
+
+    def __init__(self, problems, ras, want_owner: bool = True, workspace=None):
+        import torch
+        L = lib()
+        n = len(problems)
+        if n == 0 or len(ras) != n:
+            raise ValueError("need one RaOpts per problem")
+        cps, self._keep = [], []
+        for p in problems:
+            cp, k = _cproblem(p)
+            cps.append(cp)
+            self._keep.append(k)
+        self.n = n
+        self.arr = (SlProblem * n)(*cps)
+        self.rarr = (SlRaOpts * n)(*[_ra(r) for r in ras])
+        dev = problems[0].target.device
+        ws_bytes = L.sl_batched_workspace_size(n, self.arr, self.rarr)
+        if ws_bytes == 0:
+            raise ValueError("invalid batch (problems must share dim and dtype)")
+        self.ws = (workspace if workspace is not None and workspace.numel() >= ws_bytes
+                   else _workspace(ws_bytes, dev))
+        self.V = [torch.empty(p.N, dtype=p.dtype, device=dev) for p in problems]
+        self.member = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
+        self.label = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
+        self.owner = ([torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
+                      if want_owner else None)
+        ptrs = lambda ts: (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+        self._pV, self._pm, self._pl = ptrs(self.V), ptrs(self.member), ptrs(self.label)
+        self._po = ptrs(self.owner) if self.owner else None
+        self.per = (SlStats * n)()
+        self.tot = SlStats()
+
+    def solve(self, opts: SolveOpts = SolveOpts()):
+        """One batched solve into the solver's output tensors.  Returns (V list,
+        member list, label list, owner list, total stats); per-problem stats are
+        in ``per_problem()``."""
+        rc = lib().sl_solve_batched(self.n, self.arr, self.rarr, C.byref(_so(opts)),
+                                    _ptr(self.ws), self.ws.numel(), self._pV, self._pm,
+                                    self._pl, self._po, self.per, C.byref(self.tot), _stream())
+        if rc < 0:
+            raise SlError("sl_solve_batched", rc)
+        t = self.tot.as_dict()
+        t["converged"] = rc == SL_OK
+        return self.V, self.member, self.label, self.owner, t
+
+    def per_problem(self):
+        return [x.as_dict() for x in self.per]
+
+
 def solve_batched(problems, ras, opts: SolveOpts = SolveOpts(), want_owner: bool = True,
                   workspace=None):
     """The independent-sets algorithm for many problems at once (one launch per
     step for all of them).  Returns (V list, member list, label list, owner list,
     per-problem stats list, total stats)."""
-    import torch
-    L = lib()
-    np_ = len(problems)
-    if np_ == 0 or len(ras) != np_:
-        raise ValueError("need one RaOpts per problem")
-    cps, keep = [], []
-    for p in problems:
-        cp, k = _cproblem(p)
-        cps.append(cp)
-        keep.append(k)
-    arr = (SlProblem * np_)(*cps)
-    rarr = (SlRaOpts * np_)(*[_ra(r) for r in ras])
-    dev = problems[0].target.device
-    ws_bytes = L.sl_batched_workspace_size(np_, arr, rarr)
-    if ws_bytes == 0:
-        raise ValueError("invalid batch (problems must share dim and dtype)")
-    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
-    Vs = [torch.empty(p.N, dtype=p.dtype, device=dev) for p in problems]
-    mem = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
-    lab = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems]
-    own = [torch.empty(p.N, dtype=torch.uint8, device=dev) for p in problems] if want_owner else None
-    ptrs = lambda ts: (C.c_void_p * np_)(*[t.data_ptr() for t in ts])
-    per = (SlStats * np_)()
-    tot = SlStats()
-    rc = L.sl_solve_batched(np_, arr, rarr, C.byref(_so(opts)), _ptr(ws), ws.numel(), ptrs(Vs),
-                            ptrs(mem), ptrs(lab), ptrs(own) if own else None, per,
-                            C.byref(tot), _stream())
-    if rc < 0:
-        raise SlError("sl_solve_batched", rc)
-    t = tot.as_dict()
-    t["converged"] = rc == SL_OK
-    return Vs, mem, lab, own, [x.as_dict() for x in per], t
+    b = BatchedSolver(problems, ras, want_owner, workspace)
+    Vs, mem, lab, own, t = b.solve(opts)
+    return Vs, mem, lab, own, b.per_problem(), t
 
 
 from .autograd import HJBSolve  # noqa: E402

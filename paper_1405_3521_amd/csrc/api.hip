@@ -460,6 +460,18 @@ struct Exec {
         // halo classes (ascending halo)
         std::vector<int> halos;
         for (const auto &d : host_sds) halos.push_back(d.halo > 0 ? d.halo : cfg.halo);
+        // in 2D a launch per class costs more than the wider staging of one class
+        // at the largest halo while the staged region grows by at most 3x (the
+        // region is loaded once per launch, the local iterations reuse it), so the
+        // classes merge into one
+        if (cfg.dim == 2 && kind == 0 && !halos.empty()) {
+            const int hmin = *std::min_element(halos.begin(), halos.end());
+            const int hmax = *std::max_element(halos.begin(), halos.end());
+            const double rmin = (double)(cfg.tile[0] + 2 * hmin) * (cfg.tile[1] + 2 * hmin);
+            const double rmax = (double)(cfg.tile[0] + 2 * hmax) * (cfg.tile[1] + 2 * hmax);
+            if (rmax <= 3.0 * rmin)
+                for (auto &h : halos) h = hmax;
+        }
         std::vector<int> uniq = halos;
         std::sort(uniq.begin(), uniq.end());
         uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
