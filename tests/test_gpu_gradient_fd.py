@@ -10,13 +10,17 @@ argmin differs from the base policy in either solve.  The bars:
 
 * single-node directions (eps = 1e-4, no switch): the GPU gradient agrees with the
   central difference to 1e-3 relative;
-* dense random directions: the GPU directional derivative agrees with the
-  central difference at eps = 1e-6 (one or a few switches) to 1e-2 relative; the
-  eps = 1e-4 difference crosses tens to hundreds of kinks and is reported only,
-  as is the distance to the oracle adjoint's directional derivative: the FP32
-  forward's argmin can differ from the FP64 oracle's at near-tied nodes, so the
-  two gradients are derivatives of neighbouring pieces of L (the adjoint itself
-  is compared with the oracle's on the same policy in test_gpu_adjoint.py).
+* dense random directions, FP64 forward (its argmin is the oracle's bit for bit,
+  so the GPU differentiates the same piece of L): the GPU directional derivative
+  agrees with the oracle adjoint's to 1e-6 of the size of its terms (the l2
+  norm of grad_i d_i), and with the central difference at eps = 1e-6 (a few
+  switches) to 1e-2 relative;
+* dense random directions, FP32 forward: its argmin can differ from the FP64
+  oracle's at near-tied nodes (a gap below the FP32 rounding), so the GPU
+  differentiates a neighbouring piece of L; the directional derivative agrees
+  with the central difference at eps = 1e-6 to 3e-2 relative (measured: up to
+  1.2e-2 at 513^2);
+* the eps = 1e-4 difference crosses tens to hundreds of kinks and is reported.
 
 Both adjoint modes run: block-asynchronous tiles (16 local iterations, as the
 benchmark) and the deterministic Jacobi mode."""
@@ -33,21 +37,21 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 DEV = "cuda:0"
-CASES = {"c5_129": dict(n=129, n_obs=1500)}
+CASES = {"c5_129": dict(n=129, n_obs=1500), "c5_513": dict()}
 
 
 def say(*a):
     print(*a, flush=True)
 
 
-def _gradient(p, g, adj_local):
-    dp = S.to_device(p, torch.float32, DEV)
+def _gradient(p, g, adj_local, dtype):
+    dp = S.to_device(p, dtype, DEV)
     ra = S.RaOpts(coarse_stride=p.coarse_stride, coarse_n=p.coarse_n, C=p.ra_C, M=p.ra_M,
                   q=p.ra_q, tol=p.ra_tol)
     member = torch.as_tensor(g["member"], device=DEV)
     obs = torch.as_tensor(p.meta["obs"], device=DEV)
-    V_obs = torch.as_tensor(g["V_obs"], dtype=torch.float32, device=DEV)
-    theta = torch.as_tensor(p.meta["theta"], dtype=torch.float32, device=DEV).requires_grad_(True)
+    V_obs = torch.as_tensor(g["V_obs"], dtype=dtype, device=DEV)
+    theta = torch.as_tensor(p.meta["theta"], dtype=dtype, device=DEV).requires_grad_(True)
     opts = S.SolveOpts(tol=0.0, max_sweeps=50_000, local_iters=8)
     V = S.HJBSolve.apply(torch.exp(theta), dp, member, ra, opts, 1e-7, adj_local)
     loss = ((V[obs] - V_obs) ** 2).sum()
@@ -55,15 +59,20 @@ def _gradient(p, g, adj_local):
     return theta.grad.detach().cpu().numpy().astype(np.float64), float(loss)
 
 
-@pytest.mark.parametrize("adj_local", [16, 0])
-@pytest.mark.parametrize("case", list(CASES))
-def test_gradient_against_oracle_differences(case, adj_local):
+RUNS = [("c5_129", torch.float32, 16), ("c5_129", torch.float32, 0),
+        ("c5_129", torch.float64, 16), ("c5_129", torch.float64, 0),
+        ("c5_513", torch.float32, 16), ("c5_513", torch.float64, 16)]
+
+
+@pytest.mark.parametrize("case,dtype,adj_local", RUNS,
+                         ids=[f"{c}-{str(d)[6:]}-{a}" for c, d, a in RUNS])
+def test_gradient_against_oracle_differences(case, dtype, adj_local):
     path = os.path.join(GOLDEN, f"{case}.npz")
     assert os.path.exists(path), f"{path} missing: run tests/golden/make_full_size.py {case}"
     g = np.load(path)
     p = W.c5_adjoint(**CASES[case])
-    say("case: gradient vs differences", case, "adjoint local iterations", adj_local)
-    grad, loss = _gradient(p, g, adj_local)
+    say("case: gradient vs differences", case, dtype, "adjoint local iterations", adj_local)
+    grad, loss = _gradient(p, g, adj_local, dtype)
     say(f"  loss gpu {loss:.9e} oracle {float(g['loss']):.9e}")
     assert abs(loss - float(g["loss"])) <= 1e-3 * float(g["loss"])
     # single nodes
@@ -86,4 +95,8 @@ def test_gradient_against_oracle_differences(case, adj_local):
             f"[{int(g['switched_dir_small'][k])} switched] fd(1e-4) {fd4:.6e} "
             f"[{int(g['switched_dir'][k])} switched]")
         say(f"    |gpu - oracle adjoint| / |terms| {abs(an - ref) / scale:.2e}")
-        assert abs(an - fd6) <= 1e-2 * abs(fd6)
+        if dtype == torch.float64:
+            assert abs(an - ref) <= 1e-6 * scale
+            assert abs(an - fd6) <= 1e-2 * abs(fd6)
+        else:
+            assert abs(an - fd6) <= 3e-2 * abs(fd6)

@@ -177,12 +177,12 @@ def test_isa_gradient_against_fd():
         assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
 
 
-@pytest.mark.parametrize("case", ["c5_129"])
+@pytest.mark.parametrize("case", ["c5_129", "c5_513"])
 def test_stored_gradient_against_stored_differences(case):
     """The oracle's ISA gradient of the learnable-cost workload against the oracle's
     own central differences, both stored by tests/golden/make_full_size.py
-    (eps = 1e-4 along 32 single nodes and 8 dense directions, eps = 1e-6 along
-    the same directions).  Where no argmin switches inside +-eps the two agree to
+    (eps = 1e-4 along single nodes (32 at 129^2, 8 at 513^2) and 8 dense
+    directions, eps = 1e-6 along the same directions).  Where no argmin switches inside +-eps the two agree to
     1e-6 relative; a dense direction at eps = 1e-4 moves the near-tied candidates
     of tens of nodes past each other (L has kinks there), so it is only counted,
     and at eps = 1e-6 (one or two switches) it agrees to 1e-2."""
