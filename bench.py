@@ -9,7 +9,7 @@ Prints ONE JSON line (see the fields below).  `value` is node*control updates
 per second over the whole step (updates actually computed / step wall time);
 `time_to_converge_ms` is the step time.  The `roofline` object reports the
 dominant kernel (the sweep) against the FP32 VALU peak: it is bound by vector
-ALU work, not by HBM (20 VALU lane-operations per node*control against 13
+ALU work, not by HBM (18 VALU lane-operations per node*control against 13
 bytes per node per sweep).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -32,24 +32,26 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # FP32 vector ALU without packed math: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.3 T lane-ops/s
-# Lane operations per node*control, the hot-path scope's count for the scheme's
-# arithmetic with the cell index: 2D Q1 -> 20, 3D Q1 -> 40.  Our evaluation order
-# needs fewer: 2D foot 2 fma, cell index 2, fraction 2, LDS address 2, Q1 as
-# nested one-axis interpolations 8 (1-tau 2, 3 mul, 3 fma), candidate 1 fma,
-# min 1 = 18, and the built loop issues 17.5 VALU instructions per node*control
-# (two controls share one v_min3); so `frac` at 20 ops can exceed the kernel's
-# VALU issue fraction by up to 20/17.5, and the issue fraction measured with
-# SQ counters is stored beside it in profiles/.
-OPS_PER_NC_2D = 20
+# Lane operations per node*control: the instructions the scheme needs in the
+# evaluation order the kernels use, the cell index and its LDS address included.
+# 2D Q1: foot 2 fma, cell index 2 (cvt), fraction 2 (fract), LDS address 2,
+# Q1 as nested one-axis interpolations 8 (1-tau 2, 3 mul, 3 fma), candidate 1
+# fma, min 1 -> 18.  The hot-path scope estimated "about 20" for a tensor-product
+# weight form (4 weights, then a dot product); counting 20 against kernels that
+# issue 17.5 VALU instructions per node*control (two controls share one v_min3)
+# would let the fraction exceed 1 (the 288-candidate game reads 1.06 at 20), so
+# the count is the one of the order actually evaluated.
+OPS_PER_NC_2D = 18
 # P1 on the Kuhn simplex: the 8 lane-ops of the nested Q1 become simplex order 3
 # (compare, 2 selects), ratio t1/t0 3 (reciprocal, mul, clamp) and the nested
-# P1 6 (1-s 2, 2 mul, 2 fma) -> 20 - 8 + 12 = 24
-OPS_PER_NC_2D_P1 = 24
-# 3D Q1 -> 40 (ours: foot 3, index 3, fraction 3, address 3, Q1 17 (1-tau 3,
-# 7 mul, 7 fma), candidate 1, min 1 = 31; the built loop issues 33.5)
-OPS_PER_NC_3D = 40
-# 3D P1: Q1's 17 become sort 9 (3 compare-swaps), ratios 6, nested 9 -> 40 - 17 + 24
-OPS_PER_NC_3D_P1 = 47
+# P1 6 (1-s 2, 2 mul, 2 fma) -> 18 - 8 + 12 = 22
+OPS_PER_NC_2D_P1 = 22
+# 3D Q1: foot 3, index 3, fraction 3, address 3, Q1 17 (1-tau 3, 7 mul, 7 fma),
+# candidate 1, min 1 -> 31 (the scope's estimate: about 40); the built loop
+# issues 33.5 (unrolled by two)
+OPS_PER_NC_3D = 31
+# 3D P1: Q1's 17 become sort 9 (3 compare-swaps), ratios 6, nested 9 -> 31 - 17 + 24
+OPS_PER_NC_3D_P1 = 38
 # Revision of the headline sweep kernel whose HBM counters are stored in
 # profiles/ (the traffic figure is reported only while the kernel is unchanged)
 SWEEP_KERNEL_REV = 2

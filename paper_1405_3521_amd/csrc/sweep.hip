@@ -65,8 +65,6 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
     const int n_items = list.n;
     const int grp = S > 1 ? (int)threadIdx.x / GT : 0;
     const int lt = S > 1 ? (int)threadIdx.x % GT : (int)threadIdx.x;
-    const int tx = lt % TX;
-    const int ty0 = lt / TX;
     unsigned nact = 0;
     const int slot = sweep % 3;
     // mode 0: one item per work-group, scheduled by the hardware;
@@ -103,47 +101,89 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
         }
         __syncthreads();
 
-        const int gx = x0 + tx;
+        // Compaction (one node per thread): the tile's active nodes (free
+        // members) take the first threads, in node order, so the threads past
+        // the last active node form whole waves that skip the control loop: the
+        // inactive lanes of a tile cut by a set's boundary or holding targets
+        // become idle waves instead of inactive lanes inside busy ones.  With
+        // several nodes per thread every thread keeps its own nodes (rows r of
+        // the tile), which keeps neighbouring lanes on neighbouring nodes.
+        constexpr bool COMPACT = NPT == 1;
+        constexpr int NW = GT / 64;                  // waves of one control group
+        __shared__ short cidx[COMPACT ? TX * TY : 1];
+        __shared__ int ccnt[COMPACT ? NW : 1];
+        int n_act = 0;
+        if (COMPACT) {
+            bool fl = false;
+            unsigned long long mk = 0;
+            if (grp == 0) {
+                const int gxn = x0 + lt % TX, gyn = y0 + lt / TX;
+                if (gxn < n0 && gyn < n1) {
+                    const size_t j = (size_t)gyn * n0 + gxn;
+                    fl = (!mem || ((mem[j] >> bit) & 1)) && d.target[j] < 0;
+                }
+                mk = __ballot(fl);
+                if ((lt & 63) == 0) ccnt[lt >> 6] = (int)__popcll(mk);
+            }
+            __syncthreads();
+            if (grp == 0 && fl) {
+                int base = 0;
+                for (int p = 0; p < (lt >> 6); ++p) base += ccnt[p];
+                cidx[base + (int)__popcll(mk & ((1ull << (lt & 63)) - 1ull))] = (short)lt;
+            }
+#pragma unroll
+            for (int p = 0; p < NW; ++p) n_act += ccnt[p];
+            __syncthreads();             // cidx complete
+        }
+
         T cx[NPT], cy[NPT], ux0[NPT], uy0[NPT], qx[NPT], qy[NPT], wl[NPT], bt[NPT], best[NPT];
-        int arg[NPT];
+        int arg[NPT], nx[NPT], ny[NPT];
         bool act[NPT];
         int any = 0;
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            const int ty = ty0 + r * RSTEP;
-            const int gy = y0 + ty;
-            act[r] = false;
+            int n = lt + r * GT;
+            if (COMPACT) {
+                act[r] = lt < n_act;
+                n = act[r] ? (int)cidx[lt] : 0;
+            }
+            nx[r] = n % TX;
+            ny[r] = n / TX;
+            const int gx = x0 + nx[r], gy = y0 + ny[r];
+            if (!COMPACT) {
+                act[r] = false;
+                if (gx < n0 && gy < n1) {
+                    const size_t j = (size_t)gy * n0 + gx;
+                    act[r] = (!mem || ((mem[j] >> bit) & 1)) && d.target[j] < 0;
+                }
+            }
             cx[r] = T(0);                       // inactive lanes: foot = own node
             cy[r] = T(0);
             wl[r] = d.wl_const;
             bt[r] = d.beta;
             T qxv = T(0), qyv = T(0);           // drift in index units
-            if (gx < n0 && gy < n1) {
+            if (act[r]) {
                 const size_t j = (size_t)gy * n0 + gx;
-                const bool inset = !mem || ((mem[j] >> bit) & 1);
-                act[r] = inset && d.target[j] < 0;
-                if (act[r]) {
-                    if (!d.speed) {
-                        cx[r] = cy[r] = T(1);
-                    } else if (d.speed_axes) {
-                        cx[r] = d.speed[2 * j];
-                        cy[r] = d.speed[2 * j + 1];
-                    } else {
-                        cx[r] = cy[r] = d.speed[j];
-                    }
-                    if (d.wl) wl[r] = d.wl[j];
-                    if (d.beta_n) bt[r] = d.beta_n[j];
-                    if (d.drift) {
-                        qxv = d.drift[2 * j];
-                        qyv = d.drift[2 * j + 1];
-                    }
+                if (!d.speed) {
+                    cx[r] = cy[r] = T(1);
+                } else if (d.speed_axes) {
+                    cx[r] = d.speed[2 * j];
+                    cy[r] = d.speed[2 * j + 1];
+                } else {
+                    cx[r] = cy[r] = d.speed[j];
+                }
+                if (d.wl) wl[r] = d.wl[j];
+                if (d.beta_n) bt[r] = d.beta_n[j];
+                if (d.drift) {
+                    qxv = d.drift[2 * j];
+                    qyv = d.drift[2 * j + 1];
                 }
             }
             any |= act[r];
             if (sizeof(T) == 4) {
                 // FP32: the drift folds into the node's tile-local origin
-                ux0[r] = (T)(tx + H) + qxv;
-                uy0[r] = (T)(ty + H) + qyv;
+                ux0[r] = (T)(nx[r] + H) + qxv;
+                uy0[r] = (T)(ny[r] + H) + qyv;
             } else {
                 // FP64: u = i + (e c + q), the reproducible operation order
                 ux0[r] = (T)gx;
@@ -245,7 +285,7 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
             if (grp > 0) {
 #pragma unroll
                 for (int r = 0; r < NPT; ++r) {
-                    const int node = (ty0 + r * RSTEP) * TX + tx;
+                    const int node = lt + r * GT;           // thread slot
                     part[(grp - 1) * TX * TY + node] = best[r];
                     if (POLICY) parg[(grp - 1) * TX * TY + node] = arg[r];
                 }
@@ -254,7 +294,7 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
             if (grp == 0) {
 #pragma unroll
                 for (int r = 0; r < NPT; ++r) {
-                    const int node = (ty0 + r * RSTEP) * TX + tx;
+                    const int node = lt + r * GT;           // thread slot
                     for (int g = 1; g < S; ++g) {
                         const T v = part[(g - 1) * TX * TY + node];
                         if (POLICY) {
@@ -275,8 +315,7 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
                 if (!act[r] || grp > 0) continue;
-                const int ty = ty0 + r * RSTEP;
-                const T old = lds[(ty + H) * LW + tx + H];
+                const T old = lds[(ny[r] + H) * LW + nx[r] + H];
                 const double dv = __builtin_fabs((double)best[r] - (double)old);
                 rmax = dv > rmax ? dv : rmax;
                 chg |= best[r] != old;
@@ -286,7 +325,7 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
                 if (!act[r] || grp > 0) continue;
-                lds[(ty0 + r * RSTEP + H) * LW + tx + H] = best[r];
+                lds[(ny[r] + H) * LW + nx[r] + H] = best[r];
             }
             if (!__syncthreads_or(chg)) break;
             tile_changed = true;
@@ -294,14 +333,13 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
                 if (!act[r] || grp > 0) continue;
-                const int ty = ty0 + r * RSTEP;
-                const size_t j = (size_t)(y0 + ty) * n0 + gx;
+                const size_t j = (size_t)(y0 + ny[r]) * n0 + x0 + nx[r];
                 // a policy pass over in-place (block-asynchronous) values only
                 // records the argmin, so that it belongs to the returned values
                 if (!POLICY || Vout != Vin) Vout[j] = best[r];
                 if (POLICY) d.policy[j] = (uint8_t)arg[r];
                 const double dv =
-                    __builtin_fabs((double)best[r] - (double)lds[(ty + H) * LW + tx + H]);
+                    __builtin_fabs((double)best[r] - (double)lds[(ny[r] + H) * LW + nx[r] + H]);
                 rmax = dv > rmax ? dv : rmax;
                 ++na;
             }
@@ -311,8 +349,7 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
                 if (!act[r] || grp > 0) continue;
-                const int ty = ty0 + r * RSTEP;
-                Vout[(size_t)(y0 + ty) * n0 + gx] = lds[(ty + H) * LW + tx + H];
+                Vout[(size_t)(y0 + ny[r]) * n0 + x0 + nx[r]] = lds[(ny[r] + H) * LW + nx[r] + H];
             }
         }
         nact += na * (unsigned)m;

@@ -56,7 +56,7 @@ def _gradient(p, g, adj_local, dtype):
     V = S.HJBSolve.apply(torch.exp(theta), dp, member, ra, opts, 1e-7, adj_local)
     loss = ((V[obs] - V_obs) ** 2).sum()
     loss.backward()
-    return theta.grad.detach().cpu().numpy().astype(np.float64), float(loss)
+    return theta.grad.detach().cpu().numpy().astype(np.float64), float(loss.detach())
 
 
 RUNS = [("c5_129", torch.float32, 16), ("c5_129", torch.float32, 0),
