@@ -54,7 +54,7 @@ OPS_PER_NC_3D = 31
 OPS_PER_NC_3D_P1 = 38
 # Revision of the headline sweep kernel whose HBM counters are stored in
 # profiles/ (the traffic figure is reported only while the kernel is unchanged)
-SWEEP_KERNEL_REV = 2
+SWEEP_KERNEL_REV = 3
 # Headline sweep configuration: autotuner candidate 24 of the 2D FP32 kernels
 # (32x8 tiles, one node per thread, a resident grid walking the sweep's active
 # list with a grid stride) with block-asynchronous sweeps of up to 8 local
@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--ra-config", type=int, default=0,
                     help="coarse FP64 pass of the headline: k > 0 forces coarse candidate k-1 "
                          "(sl_tune_candidates order), 0 lets the autotuner pick")
+    ap.add_argument("--leg-config", default="",
+                    help="force fine-sweep candidates of 3D legs, e.g. c3=5 (no tuner trials)")
     ap.add_argument("--leg-local-iters", default="",
                     help="override the fine local iterations of legs, e.g. c5=16,c3=8")
     ap.add_argument("--adj-local-iters", type=int, default=16,
@@ -181,16 +183,23 @@ def leg_p1_3d(steps: int, li: int):
     return _isa_leg_3d(W.c3_aniso3d().with_(interp="p1"), steps, li,
                        "aniso3d 257^3 with P1 (Kuhn simplices), 8 balls r=0.04, 128 "
                        "Fibonacci controls, ISA (RA on 65^3) to sup-res<1e-6",
-                       OPS_PER_NC_3D_P1)
+                       OPS_PER_NC_3D_P1, name="p1_3d")
 
 
-def _isa_leg_3d(p, steps: int, li: int, workload: str, ops_per_nc: int = OPS_PER_NC_3D):
+# --leg-config name=k: force fine-sweep candidate k-1 on a leg instead of the
+# tuner's pick (profiles taken that way hold no tuner trials)
+LEG_CONFIG = {}
+
+
+def _isa_leg_3d(p, steps: int, li: int, workload: str, ops_per_nc: int = OPS_PER_NC_3D,
+                name: str = "c3"):
     """ISA to sup-res<1e-6 of a 3D problem in FP32 (tuned kernels)."""
     import torch
     import paper_1405_3521_amd as S
     dp = S.to_device(p, torch.float32, "cuda:0")
     ra = ra_opts(p, local=4)
-    opts = S.SolveOpts(tol=1e-6, profile=True, autotune=1, local_iters=li)
+    opts = S.SolveOpts(tol=1e-6, profile=True, autotune=-LEG_CONFIG[name] if name in LEG_CONFIG
+                       else 1, local_iters=li)
     S.isa(dp, ra, opts)
     _sync()
     t0 = time.perf_counter()
@@ -698,6 +707,8 @@ def main():
 
     global ADJ_LOCAL_ITERS
     ADJ_LOCAL_ITERS = args.adj_local_iters
+    LEG_CONFIG.update({k: int(v) for k, v in (kv.split("=") for kv in args.leg_config.split(",")
+                                              if kv)})
     prob = W.c2_multitarget(n=args.n)
     dp = S.to_device(prob, torch.float32, "cuda:0")
     ra = ra_opts(prob, autotune=-args.ra_config if args.ra_config > 0 else 1,
