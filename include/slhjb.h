@@ -255,7 +255,7 @@ int sl_solve(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t ws_by
 int sl_solve_noalloc(const sl_problem *p, const sl_solve_opts *o, void *V, uint8_t *policy,
                      sl_stats *stats, void *stream);
 
-/* Workspace bytes needed by sl_reconstruct / sl_solve_isa. */
+/* Workspace bytes needed by sl_reconstruct / sl_solve_isa / sl_isa. */
 size_t sl_isa_workspace_size(const sl_problem *p, const sl_ra_opts *ra);
 
 /* Reconstruction of the independent sub-domains (paper Sec. 3, RA steps 1-3, on
@@ -309,6 +309,17 @@ int sl_refine_split(const sl_problem *p, const sl_ra_opts *ra, int max_comp, dou
 int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
                  const sl_solve_opts *o, void *ws, size_t ws_bytes, void *V, uint8_t *owner,
                  uint8_t *policy, void *V_sets, sl_stats *stats, void *stream);
+
+/* The whole independent-sets algorithm in one call (paper Sec. 4, ISA steps 1-4):
+ * sl_reconstruct, then sl_solve_isa on its sets, with the field statistics
+ * gathered once.  Same arguments and outputs as the two calls: member and label
+ * (DEVICE, N uint8 each, outputs), V, owner, policy, V_sets as sl_solve_isa; ws
+ * of sl_isa_workspace_size bytes.  stats: those of the sets' solves, with ms_ra
+ * and ra_sweeps_max of the reconstruction and ms_total of the whole call.
+ * Returns SL_NOT_CONVERGED if either stage stopped at its sweep limit. */
+int sl_isa(const sl_problem *p, const sl_ra_opts *ra, const sl_solve_opts *o, void *ws,
+           size_t ws_bytes, void *V, uint8_t *owner, uint8_t *member, uint8_t *label,
+           uint8_t *policy, void *V_sets, sl_stats *stats, void *stream);
 
 /* Workspace bytes needed by sl_solve_batched (0 if any input is invalid). */
 size_t sl_batched_workspace_size(int nprob, const sl_problem *probs, const sl_ra_opts *ras);

@@ -126,6 +126,10 @@ def lib():
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, P(SlStats), C.c_void_p]
         L.sl_solve_isa.restype = C.c_int
+        L.sl_isa.argtypes = [P(SlProblem), P(SlRaOpts), P(SlSolveOpts), C.c_void_p, C.c_size_t,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p, P(SlStats), C.c_void_p]
+        L.sl_isa.restype = C.c_int
         L.sl_batched_workspace_size.argtypes = [C.c_int, P(SlProblem), P(SlRaOpts)]
         L.sl_batched_workspace_size.restype = C.c_size_t
         L.sl_solve_batched.argtypes = [C.c_int, P(SlProblem), P(SlRaOpts), P(SlSolveOpts),
@@ -445,13 +449,37 @@ def solve_isa(p: DeviceProblem, ra: RaOpts, member, opts: SolveOpts = SolveOpts(
     return V, owner, pol, Vs, d
 
 
-def isa(p: DeviceProblem, ra: RaOpts, opts: SolveOpts = SolveOpts(), want_sets: bool = False):
-    """The whole independent-sets algorithm: reconstruct, then solve the sets."""
-    member, label, st_ra = reconstruct(p, ra)
-    V, owner, pol, Vs, st = solve_isa(p, ra, member, opts, want_sets=want_sets)
-    st["ms_ra"] = st_ra["ms_total"]
-    st["ra_sweeps_max"] = st_ra["sweeps_max"]
-    return V, owner, member, label, pol, Vs, st
+def isa(p: DeviceProblem, ra: RaOpts, opts: SolveOpts = SolveOpts(), want_sets: bool = False,
+        workspace=None):
+    """The whole independent-sets algorithm in one library call (sl_isa):
+    reconstruct, then solve the sets.  Returns (V, owner, member, label, policy,
+    V_sets, stats); stats are the sets' solves' with ``ms_ra`` and
+    ``ra_sweeps_max`` of the reconstruction."""
+    import torch
+    L = lib()
+    cp, keep = _cproblem(p)
+    dev = p.target.device
+    cra = _ra(ra)
+    ws_bytes = L.sl_isa_workspace_size(C.byref(cp), C.byref(cra))
+    if ws_bytes == 0:
+        raise ValueError("invalid problem or RA options")
+    ws = workspace if workspace is not None and workspace.numel() >= ws_bytes else _workspace(ws_bytes, dev)
+    V = torch.empty(p.N, dtype=p.dtype, device=dev)
+    owner = torch.empty(p.N, dtype=torch.uint8, device=dev)
+    member = torch.empty(p.N, dtype=torch.uint8, device=dev)
+    label = torch.empty(p.N, dtype=torch.uint8, device=dev)
+    pol = (torch.full((p.n_comp * p.N,), 255, dtype=torch.uint8, device=dev)
+           if opts.want_policy else None)
+    Vs = torch.empty(p.n_comp * p.N, dtype=p.dtype, device=dev) if want_sets else None
+    st = SlStats()
+    rc = L.sl_isa(C.byref(cp), C.byref(cra), C.byref(_so(opts)), _ptr(ws), ws.numel(), _ptr(V),
+                  _ptr(owner), _ptr(member), _ptr(label), _ptr(pol), _ptr(Vs), C.byref(st),
+                  _stream())
+    if rc < 0:
+        raise SlError("sl_isa", rc)
+    d = st.as_dict()
+    d["converged"] = rc == SL_OK
+    return V, owner, member, label, pol, Vs, d
 
 
 def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float = None,

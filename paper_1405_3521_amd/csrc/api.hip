@@ -761,7 +761,9 @@ struct Timer {
     }
     double ms(int a, int b) {
         float v = 0.f;
-        if (ok && hipEventElapsedTime(&v, e[a], e[b]) == hipSuccess) return v;
+        if (ok && hipEventSynchronize(e[b]) == hipSuccess &&
+            hipEventElapsedTime(&v, e[a], e[b]) == hipSuccess)
+            return v;
         return 0.0;
     }
 };
@@ -830,8 +832,8 @@ int plan_global(const sl_problem *p, Arena &a, Exec<T> &ex, T **Vb, T **wl, T **
     const size_t N = nodes_of(p);
     (void)variant;
     const int tiles = max_tiles(p->dim, p->dtype, p->n);
-    Vb[0] = a.take<T>(N);
-    Vb[1] = a.take<T>(N);
+    Vb[0] = a.take<T>(2 * N);       // both buffers back to back (one init launch)
+    Vb[1] = Vb[0] ? Vb[0] + N : nullptr;
     *wl = p->cost ? a.take<T>(N) : nullptr;
     T *bb = uses_node_discount(p) ? a.take<T>(N) : nullptr;
     if (bn) *bn = bb;
@@ -888,13 +890,10 @@ int solve_global(const sl_problem *p, const sl_solve_opts *o, void *ws, size_t w
     } else if (p->cost) {
         HIPCHK((launch_scale_field<T, T>((const T *)p->cost, wl, N, w, s)));
     }
+    // both buffers (Vb[1] follows Vb[0]) in one launch
     auto reinit = [&](hipStream_t q) -> hipError_t {
-        for (int b = 0; b < 2; ++b) {
-            const hipError_t e = launch_init_values<T>(Vb[b], p->target, (const T *)p->g,
-                                                       (T)p->v_ghost, -1, N, q);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        return launch_init_values<T>(Vb[0], p->target, (const T *)p->g, (T)p->v_ghost, -1, N, q,
+                                     2);
     };
     SdDesc<T> d{};
     d.V[0] = Vb[0];
@@ -980,7 +979,6 @@ struct IsaPlan {
     T *gK_t = nullptr;
     int8_t *tK = nullptr;
     double *Vaux = nullptr;        // n_comp * 2 * NK
-    double *Vpack = nullptr;       // n_comp * NK final auxiliary values
     uint8_t *mK = nullptr, *lbK = nullptr;
     FieldStats *fsK = nullptr;
     Exec<double> exK;
@@ -1009,7 +1007,6 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
     P.ctrlK = a.take<double>((size_t)table_rows(p) * p->dim);
     P.tK = a.take<int8_t>(cg.NK);
     P.Vaux = a.take<double>((size_t)nc * 2 * cg.NK);
-    P.Vpack = a.take<double>((size_t)nc * cg.NK);
     P.mK = a.take<uint8_t>(cg.NK);
     P.lbK = a.take<uint8_t>(cg.NK);
     P.fsK = a.take<FieldStats>(1);
@@ -1028,7 +1025,7 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
 template <typename T>
 int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t ws_bytes,
                      uint8_t *member, uint8_t *label, uint8_t *member_K, uint8_t *label_K,
-                     sl_stats *stats, hipStream_t s) {
+                     sl_stats *stats, hipStream_t s, FieldStats *fs_out = nullptr) {
     Timer tm;
     tm.mark(0, s);
     const size_t N = nodes_of(p);
@@ -1045,6 +1042,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
                                    P.fs, &fs, s);
     if (rc) return rc;
     if ((rc = check_fields(fs))) return rc;
+    if (fs_out) *fs_out = fs;
 
     // coarse problem data: speed and cost by Q1 interpolation in FP64 (exact copies
     // at coincident nodes), target ids and g from the nearest fine node
@@ -1097,15 +1095,10 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     P.exK.cfg = make_cfg(p->dim, SL_F64, HK, default_variant(p->dim, SL_F64));
     P.exK.cfg.interp = p->interp;
     P.exK.cfg.local_iters = ra->local_iters;
+    // the two buffers of every auxiliary problem i (component i keeps g) in one launch
     auto reinit = [&](hipStream_t q) -> hipError_t {
-        for (int i = 0; i < nc; ++i)
-            for (int b = 0; b < 2; ++b) {
-                const hipError_t e = launch_init_values<double>(
-                    P.Vaux + (size_t)i * 2 * cg.NK + b * cg.NK, P.tK, p->g ? P.gK : nullptr,
-                    p->v_ghost, i, cg.NK, q);
-                if (e != hipSuccess) return e;
-            }
-        return hipSuccess;
+        return launch_init_values<double>(P.Vaux, P.tK, p->g ? P.gK : nullptr, p->v_ghost, -1,
+                                          cg.NK, q, 2 * nc, 1);
     };
     for (int i = 0; i < nc; ++i) {
         double *V0 = P.Vaux + (size_t)i * 2 * cg.NK;
@@ -1138,9 +1131,6 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     if (status < 0) return status;
 
     // RA steps 2-3: min, threshold, label on the final auxiliary iterates.
-    for (int i = 0; i < nc; ++i)
-        HIPCHK(launch_copy_final<double>(P.exK.sds, P.exK.st, i, P.Vpack + (size_t)i * cg.NK,
-                                         cg.NK, s));
     double dxK = 0.0;
     for (int d = 0; d < p->dim; ++d)
         dxK = std::max(dxK, (p->hi[d] - p->lo[d]) / (double)(cg.nK[d] - 1));
@@ -1149,7 +1139,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
                              : 2.0 * (ra->C * std::pow(dxK, ra->q) + ra->M * dxK);
     uint8_t *mK = member_K ? member_K : P.mK;
     uint8_t *lbK = label_K ? label_K : P.lbK;
-    HIPCHK(launch_ra_combine(P.Vpack, nc, cg.NK, P.tK, delta, mK, lbK, s));
+    HIPCHK(launch_ra_combine(P.exK.sds, P.exK.st, nc, cg.NK, P.tK, delta, mK, lbK, s));
     // ISA step 2: projection to the fine grid
     HIPCHK(launch_project(mK, lbK, cg.nK, p->n, p->dim, member, label, s));
     tm.mark(1, s);
@@ -1172,7 +1162,8 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
 template <typename T>
 int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
              const sl_solve_opts *o, void *ws, size_t ws_bytes, T *V, uint8_t *owner,
-             uint8_t *policy, T *V_sets, sl_stats *stats, hipStream_t s) {
+             uint8_t *policy, T *V_sets, sl_stats *stats, hipStream_t s,
+             const FieldStats *fs_in = nullptr) {
     Timer tm;
     tm.mark(0, s);
     const size_t N = nodes_of(p);
@@ -1181,11 +1172,17 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     plan_isa<T>(p, ra, a, P);
     if (!a.fits()) return SL_ERR_WORKSPACE;
     const int nc = p->n_comp;
+    // fs_in: the statistics the reconstruction of the same call gathered
     FieldStats fs{};
-    int rc = gather_field_stats<T>(p, p->target, (const T *)p->speed, (const T *)p->cost, N, nc,
+    int rc = SL_OK;
+    if (fs_in) {
+        fs = *fs_in;
+    } else {
+        rc = gather_field_stats<T>(p, p->target, (const T *)p->speed, (const T *)p->cost, N, nc,
                                    P.fs, &fs, s);
-    if (rc) return rc;
-    if ((rc = check_fields(fs))) return rc;
+        if (rc) return rc;
+        if ((rc = check_fields(fs))) return rc;
+    }
 
     double beta, w, emax;
     scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
@@ -1210,15 +1207,10 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     } else if (p->cost) {
         HIPCHK((launch_scale_field<T, T>((const T *)p->cost, P.wl, N, w, s)));
     }
+    // the two buffers of every set in one launch
     auto reinit = [&](hipStream_t q) -> hipError_t {
-        for (int i = 0; i < nc; ++i)
-            for (int b = 0; b < 2; ++b) {
-                const hipError_t e =
-                    launch_init_values<T>(P.Vf + (size_t)i * 2 * N + b * N, p->target,
-                                          (const T *)p->g, (T)p->v_ghost, -1, N, q);
-                if (e != hipSuccess) return e;
-            }
-        return hipSuccess;
+        return launch_init_values<T>(P.Vf, p->target, (const T *)p->g, (T)p->v_ghost, -1, N, q,
+                                     2 * nc);
     };
     for (int i = 0; i < nc; ++i) {
         T *V0 = P.Vf + (size_t)i * 2 * N;
@@ -1281,6 +1273,31 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     }
     fill_cfg(stats, P.ex.cfg);
     return status;
+}
+
+// The whole ISA in one call: reconstruction, then the sets' solves and the
+// assembly, sharing the field statistics (one host round trip fewer).
+template <typename T>
+int isa_all_impl(const sl_problem *p, const sl_ra_opts *ra, const sl_solve_opts *o, void *ws,
+                 size_t ws_bytes, T *V, uint8_t *owner, uint8_t *member, uint8_t *label,
+                 uint8_t *policy, T *V_sets, sl_stats *stats, hipStream_t s) {
+    Timer tm;
+    tm.mark(0, s);
+    sl_stats sra{};
+    FieldStats fs{};
+    const int ra_status = reconstruct_impl<T>(p, ra, ws, ws_bytes, member, label, nullptr,
+                                              nullptr, &sra, s, &fs);
+    if (ra_status < 0) return ra_status;
+    const int status = isa_impl<T>(p, ra, member, o, ws, ws_bytes, V, owner, policy, V_sets,
+                                   stats, s, &fs);
+    if (status < 0) return status;
+    tm.mark(1, s);
+    if (stats) {
+        stats->ms_ra = sra.ms_ra;
+        stats->ra_sweeps_max = sra.ra_sweeps_max;
+        stats->ms_total = tm.ms(0, 1);
+    }
+    return status != SL_OK ? status : ra_status;
 }
 
 // ------------------------------------------------------------------- adjoint
@@ -2059,6 +2076,25 @@ int sl_solve_isa(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *membe
                                (float *)V_sets, stats, s);
     return isa_impl<double>(p, ra, member, o, ws, ws_bytes, (double *)V, owner, policy,
                             (double *)V_sets, stats, s);
+}
+
+int sl_isa(const sl_problem *p, const sl_ra_opts *ra, const sl_solve_opts *o, void *ws,
+           size_t ws_bytes, void *V, uint8_t *owner, uint8_t *member, uint8_t *label,
+           uint8_t *policy, void *V_sets, sl_stats *stats, void *stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if ((rc = validate_ra(p, ra))) return rc;
+    if ((rc = validate_solve_opts(o))) return rc;
+    if (!member || !label || !V || !ws) return SL_ERR_INVALID_ARG;
+    if (is_game(p) && o->want_policy && policy) return SL_ERR_UNSUPPORTED;
+    if (o->want_policy && policy && p->m > SL_MAX_POLICY_CONTROLS) return SL_ERR_UNSUPPORTED;
+    if (ws_bytes < sl_isa_workspace_size(p, ra)) return SL_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->dtype == SL_F32)
+        return isa_all_impl<float>(p, ra, o, ws, ws_bytes, (float *)V, owner, member, label,
+                                   policy, (float *)V_sets, stats, s);
+    return isa_all_impl<double>(p, ra, o, ws, ws_bytes, (double *)V, owner, member, label,
+                                policy, (double *)V_sets, stats, s);
 }
 
 size_t sl_batched_workspace_size(int nprob, const sl_problem *probs, const sl_ra_opts *ras) {

@@ -217,11 +217,12 @@ hipError_t launch_absmax(const T *src, size_t n, unsigned long long *out, hipStr
 // count of nodes with target >= 0 (int atomic) and per-component presence bits
 hipError_t launch_target_scan(const int8_t *target, size_t n, int n_comp, int *count,
                               int *first_node, hipStream_t s);
-// V init for a solve: fixed (target) nodes -> g (or G if comp >= 0 and id != comp),
-// others -> G.  member/bit: non-members -> G.
+// V init for a solve, `reps` consecutive grids of n nodes: target nodes -> g (only
+// those of component comp when comp >= 0; of component r / 2 in grid r with
+// comp_by_pair), others -> G.
 template <typename T>
 hipError_t launch_init_values(T *V, const int8_t *target, const T *g, T G, int comp,
-                              size_t n, hipStream_t s);
+                              size_t n, hipStream_t s, int reps = 1, int comp_by_pair = 0);
 // Build work items for sds whose grids are tiled with cfg.tile; sds with member
 // masks only get tiles that contain a member node.
 // Items of an sd go to the segment of its halo class (class_off[cls] onward).
@@ -254,8 +255,9 @@ hipError_t launch_field_stats(const T *speed, int speed_comps, const T *cost, co
 // Flip final_buf of every sd (after a policy pass).
 hipError_t launch_flip(SdState *st, int n_sd, hipStream_t s);
 // RA steps 2-3 on K: V = min_i V_i, member bits, argmin label.
-hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
-                             double delta, uint8_t *memberK, uint8_t *labelK, hipStream_t s);
+hipError_t launch_ra_combine(const SdDesc<double> *sds, const SdState *st, int n_comp, size_t NK,
+                             const int8_t *tK, double delta, uint8_t *memberK, uint8_t *labelK,
+                             hipStream_t s);
 // ISA step 2: Con(.) projection + orphan repair + nearest-node label.
 hipError_t launch_project(const uint8_t *memberK, const uint8_t *labelK, const int *nK,
                           const int *n, int dim, uint8_t *member, uint8_t *label,

@@ -164,15 +164,21 @@ __global__ void k_target_scan(const int8_t *target, size_t n, int n_comp, int *c
     if (local) atomicAdd(count, local);
 }
 
+// Initial iterate of gridDim.y consecutive grids of n nodes (grid r at V + r n):
+// g on the target nodes of component c (of every component when c < 0), v_ghost
+// elsewhere; c = comp, or c = r / 2 with comp_by_pair (the two buffers of
+// auxiliary problem r / 2).
 template <typename T>
 __global__ void k_init_values(T *V, const int8_t *target, const T *g, T G, int comp,
-                              size_t n) {
+                              int comp_by_pair, size_t n) {
+    const int c = comp_by_pair ? (int)(blockIdx.y >> 1) : comp;
+    T *__restrict__ Vr = V + (size_t)blockIdx.y * n;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const int t = target[i];
         T v = G;
-        if (t >= 0 && (comp < 0 || t == comp)) v = g ? g[i] : T(0);
-        V[i] = v;
+        if (t >= 0 && (c < 0 || t == c)) v = g ? g[i] : T(0);
+        Vr[i] = v;
     }
 }
 
@@ -295,22 +301,33 @@ __global__ void k_place_missing(int8_t *tK, T *gK, const T *g, const int *first_
     }
 }
 
-__global__ void k_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
-                             double delta, uint8_t *memberK, uint8_t *labelK) {
+// RA steps 2-3 on the final auxiliary iterates (sds[i].V[st[i].final_buf]).
+__global__ void k_ra_combine(const SdDesc<double> *sds, const SdState *st, int n_comp,
+                             size_t NK, const int8_t *tK, double delta, uint8_t *memberK,
+                             uint8_t *labelK) {
+    const double *Va[SL_MAX_COMP];
+#pragma unroll
+    for (int i = 0; i < SL_MAX_COMP; ++i) Va[i] = i < n_comp ? sds[i].V[st[i].final_buf] : nullptr;
     for (size_t z = blockIdx.x * (size_t)blockDim.x + threadIdx.x; z < NK;
          z += (size_t)gridDim.x * blockDim.x) {
-        double V = Vaux[z];
-        for (int i = 1; i < n_comp; ++i) {
-            const double v = Vaux[(size_t)i * NK + z];
-            V = v < V ? v : V;
+        double V = Va[0][z];
+#pragma unroll
+        for (int i = 1; i < SL_MAX_COMP; ++i) {
+            if (i < n_comp) {
+                const double v = Va[i][z];
+                V = v < V ? v : V;
+            }
         }
         const int t = tK[z];
         unsigned bits = 0;
         int label = 255;
-        for (int i = n_comp - 1; i >= 0; --i) {
-            const double v = Vaux[(size_t)i * NK + z];
-            if (t == i || __builtin_fabs(v - V) <= delta) bits |= 1u << i;
-            if (v == V) label = i;
+#pragma unroll
+        for (int i = SL_MAX_COMP - 1; i >= 0; --i) {
+            if (i < n_comp) {
+                const double v = Va[i][z];
+                if (t == i || __builtin_fabs(v - V) <= delta) bits |= 1u << i;
+                if (v == V) label = i;
+            }
         }
         memberK[z] = (uint8_t)bits;
         labelK[z] = (uint8_t)label;
@@ -453,13 +470,14 @@ hipError_t launch_target_scan(const int8_t *target, size_t n, int n_comp, int *c
 
 template <typename T>
 hipError_t launch_init_values(T *V, const int8_t *target, const T *g, T G, int comp, size_t n,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_init_values<T>, dim3(grid_for(n)), dim3(kOpThreads), 0, s, V, target, g,
-                       G, comp, n);
+                              hipStream_t s, int reps, int comp_by_pair) {
+    if (reps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_values<T>, dim3(grid_for(n), reps), dim3(kOpThreads), 0, s, V,
+                       target, g, G, comp, comp_by_pair, n);
     return hipGetLastError();
 }
-template hipError_t launch_init_values<float>(float *, const int8_t *, const float *, float, int, size_t, hipStream_t);
-template hipError_t launch_init_values<double>(double *, const int8_t *, const double *, double, int, size_t, hipStream_t);
+template hipError_t launch_init_values<float>(float *, const int8_t *, const float *, float, int, size_t, hipStream_t, int, int);
+template hipError_t launch_init_values<double>(double *, const int8_t *, const double *, double, int, size_t, hipStream_t, int, int);
 
 template <typename T>
 hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, int n_sd,
@@ -533,9 +551,10 @@ hipError_t launch_field_stats(const T *speed, int speed_comps, const T *cost, co
 template hipError_t launch_field_stats<float>(const float *, int, const float *, const float *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
 template hipError_t launch_field_stats<double>(const double *, int, const double *, const double *, int, const int8_t *, size_t, int, FieldStats *, hipStream_t);
 
-hipError_t launch_ra_combine(const double *Vaux, int n_comp, size_t NK, const int8_t *tK,
-                             double delta, uint8_t *memberK, uint8_t *labelK, hipStream_t s) {
-    hipLaunchKernelGGL(k_ra_combine, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, Vaux, n_comp,
+hipError_t launch_ra_combine(const SdDesc<double> *sds, const SdState *st, int n_comp, size_t NK,
+                             const int8_t *tK, double delta, uint8_t *memberK, uint8_t *labelK,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_ra_combine, dim3(grid_for(NK)), dim3(kOpThreads), 0, s, sds, st, n_comp,
                        NK, tK, delta, memberK, labelK);
     return hipGetLastError();
 }

@@ -172,6 +172,32 @@ def test_isa_fp64_bit_exact_non_nested_with_cost():
     assert np.array_equal(host(owner), own_o)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_isa_single_call_equals_two_calls(dtype):
+    """sl_isa (one call) against sl_reconstruct followed by sl_solve_isa: the same
+    kernels on the same data, so sets, labels, values, owners and per-set values
+    are equal bit for bit (Jacobi sweeps; FP64 also equals the oracle)."""
+    p = W.c2_multitarget(n=97, m=32)
+    say("case: isa single call vs two calls", dtype)
+    dp = S.to_device(p, dtype)
+    ra = ra_of(p)
+    opts = S.SolveOpts(tol=0.0, max_sweeps=CAP)
+    V, owner, member, label, _, Vs, st = S.isa(dp, ra, opts, want_sets=True)
+    m2, l2, st_ra = S.reconstruct(dp, ra)
+    V2, o2, _, Vs2, st2 = S.solve_isa(dp, ra, m2, opts, want_sets=True)
+    assert st["converged"] and st2["converged"]
+    for a, b in ((member, m2), (label, l2), (V, V2), (owner, o2), (Vs, Vs2)):
+        assert np.array_equal(host(a), host(b))
+    assert st["sweeps_max"] == st2["sweeps_max"]
+    assert st["ra_sweeps_max"] == st_ra["ra_sweeps_max"]
+    assert st["ms_ra"] > 0.0 and st["ms_total"] >= st["ms_ra"]
+    if dtype == torch.float64:
+        Vbar, _, rec, _, _ = I.isa(p)
+        assert np.array_equal(host(member), rec.member)
+        assert np.array_equal(host(label), rec.label)
+        assert np.array_equal(host(V), Vbar)
+
+
 def test_full_size_c2_every_configuration():
     """The benchmark's problem (1025^2, 64 controls, 4 disks), every sweep
     configuration of the autotuner: candidates of one tile shape give the same
