@@ -54,7 +54,7 @@ OPS_PER_NC_3D = 31
 OPS_PER_NC_3D_P1 = 38
 # Revision of the headline sweep kernel whose HBM counters are stored in
 # profiles/ (the traffic figure is reported only while the kernel is unchanged)
-SWEEP_KERNEL_REV = 3
+SWEEP_KERNEL_REV = 4
 # Headline sweep configuration: autotuner candidate 24 of the 2D FP32 kernels
 # (32x8 tiles, one node per thread, a resident grid walking the sweep's active
 # list with a grid stride) with block-asynchronous sweeps of up to 8 local

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
         // several nodes per thread every thread keeps its own nodes (rows r of
         // the tile), which keeps neighbouring lanes on neighbouring nodes.
         constexpr bool COMPACT = NPT == 1;
+        constexpr int CU = NPT == 1 ? 4 : 2;
         constexpr int NW = GT / 64;                  // waves of one control group
         __shared__ short cidx[COMPACT ? TX * TY : 1];
         __shared__ int ccnt[COMPACT ? NW : 1];
@@ -218,7 +219,9 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
             T inner[NPT];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) inner[r] = (T)INFINITY;
-#pragma unroll 2
+            // controls unrolled by 4 with one node per thread, by 2 when each
+            // thread carries several nodes (their registers already give ILP)
+#pragma unroll CU
             for (int k = kb + grp; k < kb + ma; k += S) {
                 const T ex = ctrl[2 * k], ey = ctrl[2 * k + 1];
 #pragma unroll

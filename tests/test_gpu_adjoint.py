@@ -124,12 +124,17 @@ def test_adjoint_nonnegative_for_nonnegative_g(li):
     assert float(dLdl.min()) >= 0.0
 
 
+@pytest.mark.parametrize("interp", ["q1", "p1"])
 @pytest.mark.parametrize("li", LOCAL)
 @pytest.mark.parametrize("mode", ["global", "isa"])
-def test_autograd_gradient_against_fd(mode, li):
+def test_autograd_gradient_against_fd(mode, li, interp):
     """theta -> l = exp(theta) -> V (GPU, FP32) -> loss; theta.grad against central
-    differences of the oracle's FP64 loss (eps = 1e-6 along dense directions)."""
+    differences of the oracle's FP64 loss (eps = 1e-6 along dense directions), with
+    Q1 and with P1 interpolation (the adjoint then sums over the feet's Kuhn
+    simplices)."""
     p = W.c5_adjoint(n=65, n_obs=300)
+    if interp == "p1":
+        p = p.with_(interp="p1")
     obs = p.meta["obs"]
     member = None
     if mode == "isa":
@@ -166,7 +171,8 @@ def test_autograd_gradient_against_fd(mode, li):
         d = rng.normal(size=p.N)
         fd = (loss_o(th + eps * d) - loss_o(th - eps * d)) / (2 * eps)
         an = float(grad @ d)
-        say(f"  {mode} local {li}: fd {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+        say(f"  {mode} {interp} local {li}: fd {fd:.6e} adjoint {an:.6e} "
+            f"rel {abs(fd - an) / abs(fd):.2e}")
         assert abs(fd - an) <= 1e-3 * abs(fd)
 
 
