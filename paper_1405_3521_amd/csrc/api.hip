@@ -262,10 +262,39 @@ GraphCache &graph_cache() {
     return c;
 }
 
+// Converged sweep counts of earlier calls, keyed like the graph cache: a call
+// that repeats an earlier call's launches polls first near that call's count
+// instead of every 32 sweeps (the results do not depend on where the host
+// polls: sweeps of converged sets change nothing).  The key holds the launch
+// arguments, not the field values, so a call on new data in the same workspace
+// inherits the count; if it converges sooner, the launches up to the first
+// poll find nothing to do (a few microseconds each).  Bounded: cleared when
+// full.
+struct SweepHints {
+    static constexpr size_t kMax = 64;
+    std::map<std::vector<unsigned long long>, long> m;
+    std::mutex mu;
+    long find(const std::vector<unsigned long long> &key) {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = m.find(key);
+        return it == m.end() ? 0 : it->second;
+    }
+    void put(const std::vector<unsigned long long> &key, long v) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (m.size() >= kMax && !m.count(key)) m.clear();
+        m[key] = v;
+    }
+};
+SweepHints &sweep_hints() {
+    static SweepHints h;
+    return h;
+}
+
 // Runs `enqueue(stream, todo)` -- `todo` iterations, then a bookkeeping launch
 // that advances the device-side iteration base, then a copy of the active-set
 // counter to pinned host memory -- in chunks until the counter is zero or
-// max_steps iterations are done.  Full chunks are captured as a hipGraph and
+// max_steps iterations are done.  The first chunk has `first` iterations, the
+// others `chunk`.  Full chunks are captured as hipGraphs (one per length) and
 // replayed on the caller's stream (from the graph cache when `key` is given);
 // a short last chunk is launched directly.
 struct ChunkLoop {
@@ -273,46 +302,67 @@ struct ChunkLoop {
     long launches = 0;
     // `active`: host int the enqueued copy writes the active-set counter to
     template <class F>
-    int run(F enqueue, long max_steps, int chunk, hipStream_t s, int use_graph, int profile,
-            long *done, int *status, int *active,
+    int run(F enqueue, long max_steps, int first, int chunk, hipStream_t s, int use_graph,
+            int profile, long *done, int *status, int *active,
             const std::vector<unsigned long long> *key = nullptr) {
         if (!active) return SL_ERR_HIP;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        bool cached = false;
-        if (use_graph && key) {
-            exec = graph_cache().find(*key);
-            cached = exec != nullptr;
-        }
+        struct Slot {
+            int len = 0;
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            bool cached = false;
+        } slots[2];
+        // the replayable graph of a full chunk of `len` iterations (nullptr on error)
+        auto graph_of = [&](int len) -> hipGraphExec_t {
+            Slot *g = nullptr;
+            for (auto &x : slots)
+                if (x.len == len) g = &x;
+            if (!g) {
+                for (auto &x : slots)
+                    if (!g && x.len == 0) g = &x;
+                if (!g) return nullptr;
+                g->len = len;
+            }
+            if (g->exec) return g->exec;
+            std::vector<unsigned long long> k2;
+            if (key) {
+                k2 = *key;
+                k2.push_back((unsigned long long)len);
+                g->exec = graph_cache().find(k2);
+                if (g->exec) {
+                    g->cached = true;
+                    return g->exec;
+                }
+            }
+            hipStream_t cs = capture_stream();
+            if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return nullptr;
+            const hipError_t e1 = enqueue(cs, len);
+            const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+            if (e1 != hipSuccess || e2 != hipSuccess ||
+                hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+                g->exec = nullptr;
+                return nullptr;
+            }
+            if (key) {
+                graph_cache().insert(k2, g->exec);
+                g->cached = true;
+            }
+            return g->exec;
+        };
         hipEvent_t ev[2] = {nullptr, nullptr};
         int rc = SL_OK;
         long S = 0;
         *status = SL_NOT_CONVERGED;
         if (profile && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess))
             rc = SL_ERR_HIP;
-        while (rc == SL_OK && S < max_steps) {
-            const int todo = (int)std::min<long>(chunk, max_steps - S);
+        for (long c = 0; rc == SL_OK && S < max_steps; ++c) {
+            const int len = c == 0 && first > 0 ? first : chunk;
+            const int todo = (int)std::min<long>(len, max_steps - S);
             if (profile && hipEventRecord(ev[0], s) != hipSuccess) { rc = SL_ERR_HIP; break; }
-            if (use_graph && todo == chunk) {
-                if (!exec) {
-                    hipStream_t cs = capture_stream();
-                    if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-                        rc = SL_ERR_HIP;
-                        break;
-                    }
-                    const hipError_t e1 = enqueue(cs, todo);
-                    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
-                    if (e1 != hipSuccess || e2 != hipSuccess ||
-                        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-                        rc = SL_ERR_HIP;
-                        break;
-                    }
-                    if (key) {
-                        graph_cache().insert(*key, exec);
-                        cached = true;
-                    }
-                }
-                if (hipGraphLaunch(exec, s) != hipSuccess) { rc = SL_ERR_HIP; break; }
+            if (use_graph && todo == len) {
+                const hipGraphExec_t exec = graph_of(len);
+                if (!exec || hipGraphLaunch(exec, s) != hipSuccess) { rc = SL_ERR_HIP; break; }
             } else if (enqueue(s, todo) != hipSuccess) {
                 rc = SL_ERR_HIP;
                 break;
@@ -330,8 +380,10 @@ struct ChunkLoop {
                 break;
             }
         }
-        if (exec && !cached) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (auto &g : slots) {
+            if (g.exec && !g.cached) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         *done = S;
@@ -545,12 +597,13 @@ struct Exec {
     // plain host int (no pinned allocation) -- the path of sl_solve_noalloc
     int no_alloc = 0;
     int poll_host = 0;
+    std::vector<unsigned long long> last_key;   // key of the last default-schedule run
 
     int run(double tol, long max_sweeps, int check_every, int want_policy, hipStream_t s,
             long *sweeps_done, int profile = 0) {
         int *active = no_alloc ? &poll_host : pinned().active;
         if (!active) return SL_ERR_HIP;
-        const int chunk = check_every > 0 ? check_every : 32;
+        int chunk = check_every > 0 ? check_every : 32;
         auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
             for (int i = 0; i < todo; ++i) {
                 const hipError_t e = launch_classes(i, tol, 0, q);
@@ -582,10 +635,24 @@ struct Exec {
                           class_cap[c]})
                 key.push_back((unsigned long long)(long long)v);
         }
+        // default schedule: a repeat of an earlier call's launches polls first at
+        // that call's converged count rounded up to a multiple of 8 (one poll and
+        // at most 7 launches past convergence when it converges alike), then
+        // every 8 sweeps
+        int first = chunk;
+        last_key.clear();
+        if (check_every == 0 && !no_alloc) {
+            last_key = key;
+            const long h = sweep_hints().find(key);
+            if (h > 0) {
+                chunk = 8;
+                first = (int)std::min<long>((h + 7) / 8 * 8, 1 << 20);
+            }
+        }
         ChunkLoop loop;
         long S = 0;
         int status = SL_NOT_CONVERGED;
-        int rc = loop.run(enqueue, max_sweeps, chunk, s, no_alloc ? 0 : use_graph,
+        int rc = loop.run(enqueue, max_sweeps, first, chunk, s, no_alloc ? 0 : use_graph,
                           no_alloc ? 0 : profile, &S, &status, active, &key);
         if (rc) return rc;
         ms_sweeps += loop.ms;
@@ -702,6 +769,17 @@ struct Exec {
         HIPCHK(hipStreamSynchronize(s));
         *nc = c.nc_updates;
         unreached = c.n_unreached;
+        // the poll hint of the last default-schedule run: the number of sweeps
+        // after which the bookkeeping sees every set converged
+        if (!last_key.empty()) {
+            long smax = 0;
+            bool all = true;
+            for (const auto &x : out) {
+                all = all && x.conv_at >= 0;
+                smax = std::max<long>(smax, (long)x.conv_at + 1);
+            }
+            if (all && smax > 0) sweep_hints().put(last_key, smax);
+        }
         return SL_OK;
     }
 };
@@ -1127,7 +1205,7 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     }
     long S = 0;
     const int status =
-        P.exK.solve_tuned(ra->autotune, reinit, ra->tol, ra->max_sweeps, 32, 0, s, &S, 0);
+        P.exK.solve_tuned(ra->autotune, reinit, ra->tol, ra->max_sweeps, 0, 0, s, &S, 0);
     if (status < 0) return status;
 
     // RA steps 2-3: min, threshold, label on the final auxiliary iterates.
@@ -1449,7 +1527,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         tm.mark(1, s);
         if ((rc = P.ex.prepare(s))) return rc;
         long it = 0;
-        const int status = P.ex.run(tol, max_iters, 32, 0, s, &it, 0);
+        const int status = P.ex.run(tol, max_iters, 0, 0, s, &it, 0);
         if (status < 0) return status;
         HIPCHK(launch_adjoint_combine<T>(P.ads, P.ex.st, n_sets, p->target, N, (T)w, dLdl, s));
         tm.mark(2, s);
@@ -1481,7 +1559,7 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     ChunkLoop loop;
     long it = 0;
     int status = SL_NOT_CONVERGED;
-    if ((rc = loop.run(enqueue, max_iters, 32, s, 1, 0, &it, &status, active))) return rc;
+    if ((rc = loop.run(enqueue, max_iters, 32, 32, s, 1, 0, &it, &status, active))) return rc;
     HIPCHK(launch_bookkeep(P.st, n_sets, 0, tol, P.cnt, 1, s, scale_rel));
     HIPCHK(launch_adjoint_combine<T>(P.ads, P.st, n_sets, p->target, N, (T)w, dLdl, s));
     tm.mark(2, s);
@@ -1724,7 +1802,7 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     }
     int rc = SL_OK;
     long SK = 0;
-    int stK = B.exK.solve_tuned(ras[0].autotune, reinitK, ras[0].tol, ras[0].max_sweeps, 32, 0,
+    int stK = B.exK.solve_tuned(ras[0].autotune, reinitK, ras[0].tol, ras[0].max_sweeps, 0, 0,
                                 s, &SK, 0);
     if (stK < 0) return stK;
     // 4. RA steps 2-3, projection, fine initial values
