@@ -173,7 +173,13 @@ typedef struct sl_solve_opts {
     double tol;               /* stop when max|V_new - V| <= tol over the sub-domain (0: no change) */
     long max_sweeps;          /* sweep cap (>= 1)                                     */
     int want_policy;          /* write the first minimising control index per node   */
-    int check_every;          /* sweeps between host convergence polls (0 = default 32) */
+    int check_every;          /* sweeps between host convergence polls.  0 = default:
+                                 32, or, when a call repeats the launch arguments
+                                 of an earlier call (same shapes, workspace and
+                                 options), a first poll at that call's converged
+                                 sweep count rounded up to 8 and then every 8.
+                                 The results do not depend on it: sweeps after a
+                                 set converged change nothing.                  */
     int profile;              /* 1: time the sweep launches with HIP events (stats.ms_sweeps) */
     int autotune;             /* 0: default kernel; 1: on the first call with a new shape,
                                  time the first 96 sweeps of every (tile shape, schedule)

@@ -167,6 +167,7 @@ struct LaunchCfg {
     int halo;                   // H
     int variant;                // kernel variant id (autotuner)
     int grid_cap;               // resident work-groups (persistent grid), 0 = unset
+    int grid_cap_pol;           // the same for the policy-pass kernel
     int mode;                   // 0: one work-group per item; 1: resident grid + atomic
                                 // work queue; 2: resident grid + static grid stride
     int threads;                // work-group size of the variant
@@ -196,7 +197,8 @@ hipError_t launch_bookkeep(SdState *st, int n_sd, int sweep_rel, double tol,
                            ExecCounters *cnt, int final_pass, hipStream_t s,
                            double scale_rel = 0.0, int advance = 0);
 // Dynamic-LDS attributes of the kernels of `cfg` (call before graph capture);
-// sets cfg.grid_cap to the number of resident work-groups.
+// sets cfg.grid_cap (cfg.grid_cap_pol) to the number of resident work-groups of
+// the sweep (policy-pass) kernel.
 hipError_t sweep_set_attributes(LaunchCfg &cfg);
 // Supported tile shapes per (dim) for the autotuner; returns count.
 int sweep_variants(int dim, LaunchCfg *out, int cap);

@@ -799,7 +799,7 @@ hipError_t sweep_set_attributes(LaunchCfg &cfg) {
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             n_cu = 256;
     }
-    int cap = 1 << 30;
+    int caps[2] = {1, 1};
     for (int pol = 0; pol < 2; ++pol) {
         size_t lds = 0;
         const void *fn = sweep_fn(cfg, pol, &lds);
@@ -813,9 +813,12 @@ hipError_t sweep_set_attributes(LaunchCfg &cfg) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cfg.threads, lds) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        cap = std::min(cap, per_cu * n_cu);
+        caps[pol] = per_cu * n_cu;
     }
-    cfg.grid_cap = cap;
+    // each kernel's own occupancy: the policy pass keeps more registers (the
+    // argmin) and would otherwise hold the sweeps to fewer resident work-groups
+    cfg.grid_cap = caps[0];
+    cfg.grid_cap_pol = caps[1];
     return hipSuccess;
 }
 
@@ -828,7 +831,8 @@ hipError_t launch_sweep(const LaunchCfg &cfg, const void *sds, SdState *st, int 
     if (!fn) return hipErrorInvalidValue;
     int grid = max_items > 0 ? max_items : 1;
     int persistent = cfg.mode;
-    if (persistent && cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
+    const int cap = want_policy ? cfg.grid_cap_pol : cfg.grid_cap;
+    if (persistent && cap > 0 && grid > cap) grid = cap;
     int local_iters = want_policy ? 0 : cfg.local_iters;
     void *args[] = {(void *)&sds, (void *)&st, (void *)&n_sd, (void *)&items, (void *)&lists,
                     (void *)&cnt, (void *)&sweep, (void *)&tol, (void *)&stamp, (void *)&stamp_stride,
