@@ -182,13 +182,16 @@ __global__ void k_init_values(T *V, const int8_t *target, const T *g, T G, int c
     }
 }
 
-// One work-group per (sd, tile): OR-reduce the member bit over the tile's nodes.
+// One wave per (sd, tile): OR-reduce the member bit over the tile's nodes and
+// append the tile to its halo class's items when any node is a member (every
+// tile of an sd without a member mask).  No work-group barrier: each wave
+// decides and appends on its own.
 template <typename T>
 __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
                               const int *tile_prefix, int tx, int ty, int tz,
                               WorkItem *items, ExecCounters *cnt, const int *class_off) {
-    __shared__ int hit;
-    const int g = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int g = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (g >= total_tiles) return;
     // binary search the sd owning tile g
     int lo = 0, hi = n_sd - 1;
@@ -202,12 +205,11 @@ __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
     const int t0 = local % d.tiles[0];
     const int t1 = (local / d.tiles[0]) % d.tiles[1];
     const int t2 = local / (d.tiles[0] * d.tiles[1]);
-    if (threadIdx.x == 0) hit = d.member ? 0 : 1;
-    __syncthreads();
+    bool hit = true;
     if (d.member) {
         const int cnt_nodes = tx * ty * tz;
         int mine = 0;
-        for (int q = threadIdx.x; q < cnt_nodes; q += blockDim.x) {
+        for (int q = lane; q < cnt_nodes; q += 64) {
             const int lx = q % tx, ly = (q / tx) % ty, lz = q / (tx * ty);
             const int gx = t0 * tx + lx, gy = t1 * ty + ly, gz = t2 * tz + lz;
             if (gx < d.n[0] && gy < d.n[1] && gz < d.n[2]) {
@@ -215,10 +217,9 @@ __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
                 mine |= (d.member[j] >> d.bit) & 1;
             }
         }
-        if (__any(mine) && (threadIdx.x & 63) == 0) hit = 1;
+        hit = __any(mine);
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && hit) {
+    if (lane == 0 && hit) {
         const int slot = atomicAdd(&cnt->class_items[d.cls], 1);
         WorkItem w;
         w.sd = sd;
@@ -484,7 +485,9 @@ hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, in
                               int total_tiles, const int *tile_prefix_dev, WorkItem *items,
                               ExecCounters *cnt, const int *class_off, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_items<T>, dim3(total_tiles), dim3(kOpThreads), 0, s, sds_dev,
+    const int per_block = kOpThreads / 64;          // one wave per tile
+    hipLaunchKernelGGL(k_build_items<T>, dim3((total_tiles + per_block - 1) / per_block),
+                       dim3(kOpThreads), 0, s, sds_dev,
                        n_sd, total_tiles, tile_prefix_dev, cfg.tile[0], cfg.tile[1],
                        cfg.tile[2], items, cnt, class_off);
     return hipGetLastError();
