@@ -378,7 +378,9 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
  *   The iteration has nonnegative coefficients and spectral radius <= beta < 1,
  *   so every order converges to the same lambda (up to rounding).  Stop: the
  *   largest change of one evaluation <= tol + 16 eps max|lambda| (eps of
- *   p->dtype, the rounding level of the sums), or max_iters launches.
+ *   p->dtype, the rounding level of the sums), or max_iters launches.  tol >= 0
+ *   is absolute; tol < 0 is relative: |tol| * max_j |dLdV_j|, the maximum taken
+ *   on the device with the input checks (no extra host round trip).
  * Output: dLdl (DEVICE, N in p->dtype; 0 on target nodes). */
 int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
                const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,

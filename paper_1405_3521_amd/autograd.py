@@ -41,9 +41,9 @@ class HJBSolve(torch.autograd.Function):
     def backward(ctx, dV):
         from . import adjoint
         g = dV.detach().to(ctx.problem.dtype).contiguous()
-        scale = float(g.abs().max())
-        tol = ctx.adj_rtol * scale
-        dLdl, st = adjoint(ctx.problem, ctx.policy, g, ctx.member, ctx.owner, tol=tol,
-                           local_iters=ctx.adj_local_iters)
+        # a negative tolerance is relative to max |g|, which the library takes on
+        # the device (no host round trip here)
+        dLdl, st = adjoint(ctx.problem, ctx.policy, g, ctx.member, ctx.owner,
+                           tol=-ctx.adj_rtol, local_iters=ctx.adj_local_iters)
         ctx.adjoint_stats = st
         return dLdl, None, None, None, None, None, None

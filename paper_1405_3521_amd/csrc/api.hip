@@ -850,12 +850,13 @@ struct Timer {
 template <typename T>
 int gather_field_stats(const sl_problem *p, const int8_t *target, const T *speed,
                        const T *cost, size_t N, int n_comp, FieldStats *fs_dev,
-                       FieldStats *host, hipStream_t s) {
+                       FieldStats *host, hipStream_t s, const T *g_abs = nullptr) {
     FieldStats init{};
     for (int i = 0; i < SL_MAX_COMP; ++i) init.first_node[i] = INT_MAX;
     HIPCHK(hipMemcpyAsync(fs_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
     HIPCHK(launch_field_stats<T>(speed, speed_comps(p), cost, (const T *)p->drift, p->dim,
                                  target, N, n_comp, fs_dev, s));
+    if (g_abs) HIPCHK(launch_abs_max<T>(g_abs, N, &fs_dev->g_absmax, s));
     HIPCHK(hipMemcpyAsync(host, fs_dev, sizeof(FieldStats), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return SL_OK;
@@ -1422,9 +1423,10 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     if (!a.fits()) return SL_ERR_WORKSPACE;
     FieldStats fs{};
     int rc = gather_field_stats<T>(p, p->target, (const T *)p->speed, (const T *)p->cost, N,
-                                   p->n_comp, P.fs, &fs, s);
+                                   p->n_comp, P.fs, &fs, s, dLdV);
     if (rc) return rc;
     if ((rc = check_fields(fs))) return rc;
+    if (tol < 0.0) tol = -tol * bits_to_double(fs.g_absmax);   // relative to max |dL/dV|
     double beta, w, emax;
     scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
     std::vector<double> e;
@@ -2228,7 +2230,7 @@ int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
     int rc = validate(p);
     if (rc) return rc;
     if (!policy || !dLdV || !dLdl || !ws) return SL_ERR_INVALID_ARG;
-    if (!(tol >= 0.0) || !std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
+    if (!std::isfinite(tol) || max_iters < 1) return SL_ERR_INVALID_ARG;
     if (local_iters < 0 || local_iters > 1024) return SL_ERR_INVALID_ARG;
     if (is_game(p) || p->disc == SL_DISC_KRUZKOV) return SL_ERR_UNSUPPORTED;
     if (p->m > SL_MAX_POLICY_CONTROLS) return SL_ERR_UNSUPPORTED;

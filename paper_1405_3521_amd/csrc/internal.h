@@ -92,6 +92,7 @@ struct FieldStats {
     unsigned long long speed_max;   // FP64 bit patterns of non-negative maxima
     unsigned long long cost_max;
     unsigned long long drift_max;
+    unsigned long long g_absmax;    // max |dL/dV| (adjoint calls)
     int bad_speed;                  // speed < 0 or non-finite, drift non-finite
     int bad_cost;                   // cost <= 0 or non-finite
     int n_target;                   // nodes with target id >= 0
@@ -219,6 +220,9 @@ hipError_t launch_absmax(const T *src, size_t n, unsigned long long *out, hipStr
 // count of nodes with target >= 0 (int atomic) and per-component presence bits
 hipError_t launch_target_scan(const int8_t *target, size_t n, int n_comp, int *count,
                               int *first_node, hipStream_t s);
+// Fold max_j |x_j| (FP64 bit pattern) into *dst with atomicMax.
+template <typename T>
+hipError_t launch_abs_max(const T *x, size_t n, unsigned long long *dst, hipStream_t s);
 // V init for a solve, `reps` consecutive grids of n nodes: target nodes -> g (only
 // those of component comp when comp >= 0; of component r / 2 in grid r with
 // comp_by_pair), others -> G.

@@ -164,6 +164,17 @@ __global__ void k_target_scan(const int8_t *target, size_t n, int n_comp, int *c
     if (local) atomicAdd(count, local);
 }
 
+template <typename T>
+__global__ void k_abs_max(const T *x, size_t n, unsigned long long *dst) {
+    double m = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double a = __builtin_fabs((double)x[i]);
+        m = a > m ? a : m;
+    }
+    block_max_to<kOpThreads>(m, dst);
+}
+
 // Initial iterate of gridDim.y consecutive grids of n nodes (grid r at V + r n):
 // g on the target nodes of component c (of every component when c < 0), v_ghost
 // elsewhere; c = comp, or c = r / 2 with comp_by_pair (the two buffers of
@@ -468,6 +479,15 @@ hipError_t launch_target_scan(const int8_t *target, size_t n, int n_comp, int *c
                        dim3(kOpThreads), 0, s, target, n, n_comp, count, first_node);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_abs_max(const T *x, size_t n, unsigned long long *dst, hipStream_t s) {
+    const int g = grid_for(n) < 1024 ? grid_for(n) : 1024;
+    hipLaunchKernelGGL(k_abs_max<T>, dim3(g), dim3(kOpThreads), 0, s, x, n, dst);
+    return hipGetLastError();
+}
+template hipError_t launch_abs_max<float>(const float *, size_t, unsigned long long *, hipStream_t);
+template hipError_t launch_abs_max<double>(const double *, size_t, unsigned long long *, hipStream_t);
 
 template <typename T>
 hipError_t launch_init_values(T *V, const int8_t *target, const T *g, T G, int comp, size_t n,

@@ -295,6 +295,27 @@ def test_adjoint_jacobi_mode_is_deterministic(dtype, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_adjoint_relative_tolerance(dtype):
+    """A negative tol is relative to max |dL/dV|, taken on the device: the same
+    stopping threshold as the absolute tol computed on the host, so the Jacobi
+    iterates (deterministic mode) stop at the same launch with the same bits."""
+    p = W.c5_adjoint(n=65, n_obs=300)
+    say("case: relative adjoint tolerance", dtype)
+    V, pol = O.solve(p)[:2]
+    gV = np.random.Generator(np.random.PCG64(23)).normal(size=p.N)
+    dp = S.to_device(p, dtype)
+    g_t = torch.as_tensor(gV, dtype=dtype, device=DEV)
+    pol_t = torch.as_tensor(pol_u8(pol), device=DEV)
+    rtol = 1e-5
+    scale = float(np.abs(g_t.cpu().numpy().astype(np.float64)).max())
+    a, sa = S.adjoint(dp, pol_t, g_t, tol=-rtol, local_iters=0)
+    b, sb = S.adjoint(dp, pol_t, g_t, tol=rtol * scale, local_iters=0)
+    assert sa["converged"] and sb["converged"]
+    assert sa["sweeps_max"] == sb["sweeps_max"]
+    assert torch.equal(a, b)
+
+
 def _adjoint_3d(n=25, seed=3):
     p = W.c3_aniso3d(n=n, m=32, n_balls=3, r=0.15)
     th = np.random.Generator(np.random.PCG64(seed)).normal(0.0, 0.1, p.N)
