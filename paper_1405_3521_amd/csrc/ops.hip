@@ -193,53 +193,80 @@ __global__ void k_init_values(T *V, const int8_t *target, const T *g, T G, int c
     }
 }
 
-// One wave per (sd, tile): OR-reduce the member bit over the tile's nodes and
-// append the tile to its halo class's items when any node is a member (every
-// tile of an sd without a member mask).  No work-group barrier: each wave
-// decides and appends on its own.
+// Work items of the tiled sds.  Each wave takes kBuildTilesPerWave consecutive
+// (sd, tile) pairs and OR-reduces the member bit over each tile's nodes; a tile
+// with a member node (every tile of an sd without a member mask) becomes an item
+// of its sd's halo class.  The work-group reserves the slots of all its items
+// with one global atomic per class (a single counter per class takes every
+// append, so one atomic per tile would serialize the whole build on it).
+constexpr int kBuildTilesPerWave = 4;
+constexpr int kBuildTilesPerBlock = kBuildTilesPerWave * (kOpThreads / 64);
+
 template <typename T>
 __global__ void k_build_items(const SdDesc<T> *sds, int n_sd, int total_tiles,
                               const int *tile_prefix, int tx, int ty, int tz,
                               WorkItem *items, ExecCounters *cnt, const int *class_off) {
+    __shared__ int s_count[kMaxClasses], s_base[kMaxClasses];
+    __shared__ int s_slot[kBuildTilesPerBlock];        // class slot, -1: not an item
+    __shared__ WorkItem s_item[kBuildTilesPerBlock];
+    __shared__ int s_cls[kBuildTilesPerBlock];
+    if (threadIdx.x < kMaxClasses) s_count[threadIdx.x] = 0;
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int g = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    if (g >= total_tiles) return;
-    // binary search the sd owning tile g
-    int lo = 0, hi = n_sd - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    const int sd = lo;
-    const SdDesc<T> &d = sds[sd];
-    const int local = g - tile_prefix[sd];
-    const int t0 = local % d.tiles[0];
-    const int t1 = (local / d.tiles[0]) % d.tiles[1];
-    const int t2 = local / (d.tiles[0] * d.tiles[1]);
-    bool hit = true;
-    if (d.member) {
-        const int cnt_nodes = tx * ty * tz;
-        int mine = 0;
-        for (int q = lane; q < cnt_nodes; q += 64) {
-            const int lx = q % tx, ly = (q / tx) % ty, lz = q / (tx * ty);
-            const int gx = t0 * tx + lx, gy = t1 * ty + ly, gz = t2 * tz + lz;
-            if (gx < d.n[0] && gy < d.n[1] && gz < d.n[2]) {
-                const size_t j = ((size_t)gz * d.n[1] + gy) * d.n[0] + gx;
-                mine |= (d.member[j] >> d.bit) & 1;
-            }
+    const int wave = threadIdx.x >> 6;
+    for (int t = 0; t < kBuildTilesPerWave; ++t) {
+        const int k = wave * kBuildTilesPerWave + t;          // tile of this block
+        const int g = blockIdx.x * kBuildTilesPerBlock + k;
+        if (g >= total_tiles) {
+            if (lane == 0) s_slot[k] = -1;
+            continue;
         }
-        hit = __any(mine);
+        // binary search the sd owning tile g
+        int lo = 0, hi = n_sd - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const int sd = lo;
+        const SdDesc<T> &d = sds[sd];
+        const int local = g - tile_prefix[sd];
+        const int t0 = local % d.tiles[0];
+        const int t1 = (local / d.tiles[0]) % d.tiles[1];
+        const int t2 = local / (d.tiles[0] * d.tiles[1]);
+        bool hit = true;
+        if (d.member) {
+            const int cnt_nodes = tx * ty * tz;
+            int mine = 0;
+            for (int q = lane; q < cnt_nodes; q += 64) {
+                const int lx = q % tx, ly = (q / tx) % ty, lz = q / (tx * ty);
+                const int gx = t0 * tx + lx, gy = t1 * ty + ly, gz = t2 * tz + lz;
+                if (gx < d.n[0] && gy < d.n[1] && gz < d.n[2]) {
+                    const size_t j = ((size_t)gz * d.n[1] + gy) * d.n[0] + gx;
+                    mine |= (d.member[j] >> d.bit) & 1;
+                }
+            }
+            hit = __any(mine);
+        }
+        if (lane == 0) {
+            s_slot[k] = hit ? atomicAdd(&s_count[d.cls], 1) : -1;
+            s_cls[k] = d.cls;
+            WorkItem w;
+            w.sd = sd;
+            w.t[0] = t0;
+            w.t[1] = t1;
+            w.t[2] = t2;
+            w.tflat = g;
+            w.pad[0] = w.pad[1] = w.pad[2] = 0;
+            s_item[k] = w;
+        }
     }
-    if (lane == 0 && hit) {
-        const int slot = atomicAdd(&cnt->class_items[d.cls], 1);
-        WorkItem w;
-        w.sd = sd;
-        w.t[0] = t0;
-        w.t[1] = t1;
-        w.t[2] = t2;
-        w.tflat = g;
-        w.pad[0] = w.pad[1] = w.pad[2] = 0;
-        items[class_off[d.cls] + slot] = w;
+    __syncthreads();
+    if (threadIdx.x < kMaxClasses && s_count[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&cnt->class_items[threadIdx.x], s_count[threadIdx.x]);
+    __syncthreads();
+    if (threadIdx.x < kBuildTilesPerBlock && s_slot[threadIdx.x] >= 0) {
+        const int c = s_cls[threadIdx.x];
+        items[class_off[c] + s_base[c] + s_slot[threadIdx.x]] = s_item[threadIdx.x];
     }
 }
 
@@ -505,8 +532,8 @@ hipError_t launch_build_items(const LaunchCfg &cfg, const SdDesc<T> *sds_dev, in
                               int total_tiles, const int *tile_prefix_dev, WorkItem *items,
                               ExecCounters *cnt, const int *class_off, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
-    const int per_block = kOpThreads / 64;          // one wave per tile
-    hipLaunchKernelGGL(k_build_items<T>, dim3((total_tiles + per_block - 1) / per_block),
+    hipLaunchKernelGGL(k_build_items<T>,
+                       dim3((total_tiles + kBuildTilesPerBlock - 1) / kBuildTilesPerBlock),
                        dim3(kOpThreads), 0, s, sds_dev,
                        n_sd, total_tiles, tile_prefix_dev, cfg.tile[0], cfg.tile[1],
                        cfg.tile[2], items, cnt, class_off);
@@ -615,7 +642,7 @@ template hipError_t launch_copy_final<double>(const SdDesc<double> *, const SdSt
 
 hipError_t launch_member_counts(const uint8_t *member, size_t N, unsigned long long *counts8,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_member_counts, dim3(grid_for(N) < 1024 ? grid_for(N) : 1024),
+    hipLaunchKernelGGL(k_member_counts, dim3(grid_for(N) < 128 ? grid_for(N) : 128),
                        dim3(kOpThreads), 0, s, member, N, counts8);
     return hipGetLastError();
 }
