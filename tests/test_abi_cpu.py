@@ -182,6 +182,37 @@ def test_reconstruction_argument_errors():
                             C.byref(st), None) == -1
 
 
+def test_single_call_isa_argument_errors():
+    """sl_isa refuses on the host what sl_reconstruct and sl_solve_isa refuse:
+    missing outputs, an invalid RA grid, bad solve options, a too small
+    workspace; a negative adjoint tolerance is a relative one, not an error."""
+    L = S.lib()
+    p, keep = _problem()
+    st = S.SlStats()
+    buf = C.create_string_buffer(64)
+    opts = S.SlSolveOpts(0.0, 100, 0, 0, 0, 0, 0)
+    ra = S.SlRaOpts(2, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    args = lambda **kw: [C.byref(kw.get("p", p)), C.byref(kw.get("ra", ra)),
+                         C.byref(kw.get("o", opts)), buf, kw.get("ws", 64),
+                         kw.get("V", buf), None, kw.get("member", buf), kw.get("label", buf),
+                         None, None, C.byref(st), None]
+    assert L.sl_isa(*args()) == -5                                  # workspace too small
+    assert L.sl_isa(*args(member=None)) == -1
+    assert L.sl_isa(*args(label=None)) == -1
+    assert L.sl_isa(*args(V=None)) == -1
+    bad_ra = S.SlRaOpts(3, (C.c_int * 3)(0, 0, 0), 0.5, 0.5, 1.0, 0.0, 0.0, 1000)
+    assert L.sl_isa(*args(ra=bad_ra)) == -1
+    assert L.sl_isa(*args(o=S.SlSolveOpts(-1.0, 100, 0, 0, 0, 0, 0))) == -1
+    q, keep2 = _problem(dim=1)
+    assert L.sl_isa(*args(p=q)) == -3
+    # sl_adjoint: a negative (relative) tolerance passes the checks, a non-finite
+    # one does not (both then meet the too-small workspace or the argument error)
+    assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, -1e-6, 10, 0, buf, 64,
+                        C.byref(st), None) == -5
+    assert L.sl_adjoint(C.byref(p), None, None, buf, buf, buf, float("nan"), 10, 0, buf, 64,
+                        C.byref(st), None) == -1
+
+
 def test_binding_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "_LIB", None)
     monkeypatch.setattr(S, "_LIB_PATH", str(tmp_path / "missing.so"))
