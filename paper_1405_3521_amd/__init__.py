@@ -343,6 +343,24 @@ def _workspace(nbytes: int, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
+def solve_workspace_bytes(p: DeviceProblem) -> int:
+    """Workspace bytes of ``solve`` (sl_solve_workspace_size)."""
+    cp, keep = _cproblem(p)
+    return int(lib().sl_solve_workspace_size(C.byref(cp)))
+
+
+def isa_workspace_bytes(p: DeviceProblem, ra: RaOpts) -> int:
+    """Workspace bytes of ``reconstruct`` / ``solve_isa`` / ``isa``."""
+    cp, keep = _cproblem(p)
+    return int(lib().sl_isa_workspace_size(C.byref(cp), C.byref(_ra(ra))))
+
+
+def adjoint_workspace_bytes(p: DeviceProblem, n_sets: int) -> int:
+    """Workspace bytes of ``adjoint`` over n_sets sets (1 for the global solve)."""
+    cp, keep = _cproblem(p)
+    return int(lib().sl_adjoint_workspace_size(C.byref(cp), int(n_sets)))
+
+
 def solve(p: DeviceProblem, opts: SolveOpts = SolveOpts(), out=None, policy=None,
           workspace=None):
     """Global value iteration (no decomposition).  Returns (V, policy or None, stats)."""
