@@ -167,3 +167,31 @@ def test_block_async_batched_coarse_and_fine():
         assert np.array_equal(host(m), rec.member), p.name
         assert np.array_equal(host(l), rec.label), p.name
         assert torch.equal(V, Vr), p.name
+
+
+def test_repeat_calls_poll_on_the_previous_schedule_with_the_same_values():
+    """A call that repeats an earlier call's launch arguments (same shapes and
+    workspace) polls at that call's converged sweep count instead of every 32
+    sweeps.  The values cannot depend on where the host polls (sweeps of
+    converged sets change nothing): calls in one workspace give the same bits as
+    a call in a fresh workspace (the greatest floating-point fixed point below the
+    initial values), also for a second problem of the same shapes that needs more
+    sweeps than the count it inherits."""
+    a = W.c2_multitarget(n=257, m=32)
+    sp = a.speed.copy()
+    slow = sp < np.median(sp)
+    sp[slow] = W.f32(sp[slow] * 0.6)          # slower where slow, same maximum (same halo)
+    b = a.with_(speed=sp)
+    say("case: repeated calls, adaptive poll schedule")
+    da, db = S.to_device(a, torch.float32), S.to_device(b, torch.float32)
+    ra = ra_of(a)
+    ws = torch.empty(S.isa_workspace_bytes(da, ra), dtype=torch.uint8, device=da.target.device)
+    opts = S.SolveOpts(tol=0.0, max_sweeps=CAP, local_iters=8)
+    ref_a, ref_b = S.isa(da, ra, opts), S.isa(db, ra, opts)
+    say("  launches to stagnation", ref_a[-1]["sweeps_max"], ref_b[-1]["sweeps_max"])
+    for dp, ref in ((da, ref_a), (da, ref_a), (db, ref_b), (da, ref_a), (db, ref_b)):
+        V, own, mem, lab, _, _, st = S.isa(dp, ra, opts, workspace=ws)
+        assert st["converged"]
+        assert np.array_equal(host(V), host(ref[0]))
+        assert np.array_equal(host(mem), host(ref[2]))
+    assert np.array_equal(host(ref_b[2]), I.reconstruct(b).member)
