@@ -9,7 +9,7 @@ Prints ONE JSON line (see the fields below).  `value` is node*control updates
 per second over the whole step (updates actually computed / step wall time);
 `time_to_converge_ms` is the step time.  The `roofline` object reports the
 dominant kernel (the sweep) against the FP32 VALU peak: it is bound by vector
-ALU work, not by HBM (18 VALU lane-operations per node*control against 13
+ALU work, not by HBM (16 VALU lane-operations per node*control against 13
 bytes per node per sweep).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -33,28 +33,30 @@ PEAK_HBM_GBS = 8000.0
 # FP32 vector ALU without packed math: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.3 T lane-ops/s
 # Lane operations per node*control: the instructions the scheme needs in the
-# evaluation order the kernels use, the cell index and its LDS address included.
-# 2D Q1: foot 2 fma, cell index 2 (cvt), fraction 2 (fract), LDS address 2,
-# Q1 as nested one-axis interpolations 8 (1-tau 2, 3 mul, 3 fma), candidate 1
-# fma, min 1 -> 18.  The hot-path scope estimated "about 20" for a tensor-product
-# weight form (4 weights, then a dot product); counting 20 against kernels that
-# issue 17.5 VALU instructions per node*control (two controls share one v_min3)
-# would let the fraction exceed 1 (the 288-candidate game reads 1.06 at 20), so
-# the count is the one of the order actually evaluated.
-OPS_PER_NC_2D = 18
-# P1 on the Kuhn simplex: the 8 lane-ops of the nested Q1 become simplex order 3
+# evaluation order the FP32 kernels use, the cell index and its LDS address
+# included.  2D Q1: foot 2 fma, cell index 2 (cvt), fraction 2 (fract), LDS
+# address 2, Q1 as nested one-axis interpolations 6 (fma(f, v1, fma(-f, v0, v0))
+# per lerp, 3 lerps), candidate 1 fma, min 1 -> 16.  The hot-path scope estimated
+# "about 20" for a tensor-product weight form (4 weights, then a dot product);
+# the count here is the one of the order actually evaluated, so the fraction
+# says how close the kernel runs to the issue rate of the work it must do.
+OPS_PER_NC_2D = 16
+# FP64 kernels (the eikonal workload) keep the order the labels' reproducibility
+# fixes: (1 - f) v0 rounded, then the fma: Q1 8 instead of 6 -> 18
+OPS_PER_NC_2D_F64 = 18
+# P1 on the Kuhn simplex: the 6 lane-ops of the nested Q1 become simplex order 3
 # (compare, 2 selects), ratio t1/t0 3 (reciprocal, mul, clamp) and the nested
-# P1 6 (1-s 2, 2 mul, 2 fma) -> 18 - 8 + 12 = 22
-OPS_PER_NC_2D_P1 = 22
-# 3D Q1: foot 3, index 3, fraction 3, address 3, Q1 17 (1-tau 3, 7 mul, 7 fma),
-# candidate 1, min 1 -> 31 (the scope's estimate: about 40); the built loop
-# issues 33.5 (unrolled by two)
-OPS_PER_NC_3D = 31
-# 3D P1: Q1's 17 become sort 9 (3 compare-swaps), ratios 6, nested 9 -> 31 - 17 + 24
-OPS_PER_NC_3D_P1 = 38
+# P1 4 (2 lerps of 2 fma) -> 16 - 6 + 10 = 20
+OPS_PER_NC_2D_P1 = 20
+# 3D Q1: foot 3, index 3, fraction 3, address 3, Q1 14 (7 lerps of 2 fma),
+# candidate 1, min 1 -> 28 (the scope's estimate: about 40)
+OPS_PER_NC_3D = 28
+# 3D P1: Q1's 14 become sort 9 (3 compare-swaps), ratios 6, nested 6 (3 lerps)
+# -> 28 - 14 + 21 = 35
+OPS_PER_NC_3D_P1 = 35
 # Revision of the headline sweep kernel whose HBM counters are stored in
 # profiles/ (the traffic figure is reported only while the kernel is unchanged)
-SWEEP_KERNEL_REV = 4
+SWEEP_KERNEL_REV = 5
 # Headline sweep configuration: autotuner candidate 24 of the 2D FP32 kernels
 # (32x8 tiles, one node per thread, a resident grid walking the sweep's active
 # list with a grid stride) with block-asynchronous sweeps of up to 8 local
@@ -161,7 +163,7 @@ def leg_c1(steps: int, li: int):
         nc = np.mean([x["node_control_updates"] for x in sts])
         launches = np.mean([x["sweep_launches"] for x in sts])
         ms_launch = np.sum([x["ms_sweeps"] for x in sts]) / np.sum([x["sweep_launches"] for x in sts])
-        ach = OPS_PER_NC_2D * nc / launches / (ms_launch / 1e3) / 1e12
+        ach = OPS_PER_NC_2D_F64 * nc / launches / (ms_launch / 1e3) / 1e12
         out[name] = {"time_to_converge_ms": ms, "sweeps": int(np.mean([x["sweeps_max"] for x in sts])),
                      "node_control_updates_per_s": nc / (ms / 1e3),
                      "sweep_ms_per_launch": ms_launch, "valu_tops": ach,

@@ -15,6 +15,24 @@ __device__ __forceinline__ float fma_<float>(float a, float b, float c) { return
 template <>
 __device__ __forceinline__ double fma_<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// One-axis interpolation (1 - f) v0 + f v1 for 0 <= f <= 1, each rounding step
+// monotone in v0 and v1 and a power-of-two constant reproduced exactly (so
+// iterates from the ghost value decrease to a bitwise fixed point in any update
+// order).  FP64, the order the labels' reproducibility fixes:
+// fma(f, v1, RN(1 - f) v0).  FP32: fma(f, v1, fma(-f, v0, v0)), where v0 (1 - f)
+// is formed exactly and rounded once: two operations instead of three.  On a
+// constant G = 2^k both give G RN(f + RN(1 - f)) = G.
+template <typename T>
+__device__ __forceinline__ T lerp_m(T f, T v0, T v1);
+template <>
+__device__ __forceinline__ float lerp_m<float>(float f, float v0, float v1) {
+    return __builtin_fmaf(f, v1, __builtin_fmaf(-f, v0, v0));
+}
+template <>
+__device__ __forceinline__ double lerp_m<double>(double f, double v0, double v1) {
+    return __builtin_fma(f, v1, (1.0 - f) * v0);
+}
+
 template <typename T>
 __device__ __forceinline__ T min_(T a, T b) { return a < b ? a : b; }
 

@@ -251,23 +251,22 @@ __global__ __launch_bounds__(GT * S) void k_sweep2d(const SdDesc<T> *__restrict_
                         const T v00 = lds[base], vm = lds[base + (xf ? 1 : LW)];
                         const T v11 = lds[base + LW + 1];
                         const T sr = simplex_ratio(t1, t0);
-                        const T in = fma_(sr, v11, (T(1) - sr) * vm);
-                        acc = fma_(t0, in, (T(1) - t0) * v00);
+                        const T in = lerp_m(sr, vm, v11);
+                        acc = lerp_m(t0, v00, in);
                     } else {
                     const T v00 = lds[base], v10 = lds[base + 1];
                     const T v01 = lds[base + LW], v11 = lds[base + LW + 1];
-                    // Q1 as nested one-axis interpolations fma(f, v1, (1-f) v0), x then
-                    // y.  Every rounding step is monotone in the node values (so the
+                    // Q1 as nested one-axis interpolations (lerp_m), x then y.
+                    // Every rounding step is monotone in the node values (so the
                     // iterates from the ghost value decrease to a bitwise fixed point,
                     // in any update order), and a field equal to a power of two (the
                     // ghost value) is reproduced exactly: the unreached region keeps
                     // its value bit for bit, so its tiles are skipped instead of
                     // drifting.  In FP64 (global index coordinates) this is also the
                     // fixed operation order the reproducible labels rely on.
-                    const T ax = T(1) - fx, ay = T(1) - fy;
-                    const T a = fma_(fx, v10, ax * v00);
-                    const T b = fma_(fx, v11, ax * v01);
-                    acc = fma_(fy, b, ay * a);
+                    const T a = lerp_m(fx, v00, v10);
+                    const T b = lerp_m(fx, v01, v11);
+                    acc = lerp_m(fy, a, b);
                     }
                     const T cand = fma_(bt[r], acc, wl[r]);
                     if (POLICY) {
@@ -549,25 +548,24 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const SdDesc<T> *__restric
                         const T v0 = lds[base], v1 = lds[base + o0], v2 = lds[base + o0 + o1];
                         const T v3 = lds[base + 1 + LW + PL];
                         const T s2 = simplex_ratio(t2, t1), s1 = simplex_ratio(t1, t0);
-                        const T i2 = fma_(s2, v3, (T(1) - s2) * v2);
-                        const T i1 = fma_(s1, i2, (T(1) - s1) * v1);
-                        acc = fma_(t0, i1, (T(1) - t0) * v0);
+                        const T i2 = lerp_m(s2, v2, v3);
+                        const T i1 = lerp_m(s1, v1, i2);
+                        acc = lerp_m(t0, v0, i1);
                         (void)o2;
                     } else {
                     // nested one-axis interpolations, x, then y, then z (as in 2D)
-                    const T ax = T(1) - fx, ay = T(1) - fy, az = T(1) - fz;
                     const T v000 = lds[base], v100 = lds[base + 1];
                     const T v010 = lds[base + LW], v110 = lds[base + LW + 1];
                     const T *__restrict__ up = lds + base + PL;   // the z + 1 plane
                     const T v001 = up[0], v101 = up[1];
                     const T v011 = up[LW], v111 = up[LW + 1];
-                    const T a0 = fma_(fx, v100, ax * v000);
-                    const T b0 = fma_(fx, v110, ax * v010);
-                    const T a1 = fma_(fx, v101, ax * v001);
-                    const T b1 = fma_(fx, v111, ax * v011);
-                    const T c0 = fma_(fy, b0, ay * a0);
-                    const T c1 = fma_(fy, b1, ay * a1);
-                    acc = fma_(fz, c1, az * c0);
+                    const T a0 = lerp_m(fx, v000, v100);
+                    const T b0 = lerp_m(fx, v010, v110);
+                    const T a1 = lerp_m(fx, v001, v101);
+                    const T b1 = lerp_m(fx, v011, v111);
+                    const T c0 = lerp_m(fy, a0, b0);
+                    const T c1 = lerp_m(fy, a1, b1);
+                    acc = lerp_m(fz, c0, c1);
                     }
                     const T cand = fma_(bt[r], acc, wl[r]);
                     if (POLICY) {
