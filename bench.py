@@ -218,7 +218,14 @@ def _isa_leg_3d(p, steps: int, li: int, workload: str, ops_per_nc: int = OPS_PER
             "ms_reconstruct": float(np.mean([x["ms_ra"] for x in sts])),
             "set_fraction_max": float(np.mean([x["set_fraction_max"] for x in sts])),
             "sweep_ms_per_launch": ms_launch, "valu_tops": ach, "valu_frac": ach / PEAK_VALU_TOPS,
-            "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"]}
+            "tile": list(sts[0]["tile"]), "schedule": sts[0]["mode"],
+            # the leg's dominant kernel against the same roof as the headline's
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
+                         "unit": "T VALU lane-ops/s", "frac": ach / PEAK_VALU_TOPS,
+                         "traffic": None, "kernel": f"k_sweep3d<float,{sts[0]['tile'][0]},"
+                                                    f"{sts[0]['tile'][1]},{sts[0]['tile'][2]},H>",
+                         "ops_per_node_control": ops_per_nc, "ms_per_launch": ms_launch,
+                         "node_controls_per_launch": nc / launches}}
 
 
 def _isa_leg_2d(p, steps: int, li: int, workload: str, ra_local: int = 4,
