@@ -210,12 +210,17 @@ LaunchCfg make_cfg(int dim, int dtype, int halo, int variant) {
     return c;
 }
 
-// Pinned host scratch for the per-chunk convergence poll.
+// Pinned host scratch for the per-chunk convergence poll, and for statistics
+// read back after a later synchronisation (kPinnedStats bytes).
+constexpr size_t kPinnedStats = 16384;
 struct Pinned {
     int *active = nullptr;
+    char *stats = nullptr;
     Pinned() {
         if (hipHostMalloc((void **)&active, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess)
             active = nullptr;
+        if (hipHostMalloc((void **)&stats, kPinnedStats, hipHostMallocDefault) != hipSuccess)
+            stats = nullptr;
     }
 };
 Pinned &pinned() {
@@ -769,19 +774,53 @@ struct Exec {
         HIPCHK(hipStreamSynchronize(s));
         *nc = c.nc_updates;
         unreached = c.n_unreached;
-        // the poll hint of the last default-schedule run: the number of sweeps
-        // after which the bookkeeping sees every set converged
-        if (!last_key.empty()) {
-            long smax = 0;
-            bool all = true;
-            for (const auto &x : out) {
-                all = all && x.conv_at >= 0;
-                smax = std::max<long>(smax, (long)x.conv_at + 1);
-            }
-            if (all && smax > 0) sweep_hints().put(last_key, smax);
-        }
+        remember(out, last_key);
         return SL_OK;
     }
+
+    // The states and counters copied to pinned `host` in stream order, to be read
+    // after a later synchronisation of the stream (read_copied).
+    static size_t copied_bytes(int n) { return sizeof(SdState) * n + sizeof(ExecCounters); }
+    int copy_stats(hipStream_t s, char *host) const {
+        if (!host || copied_bytes(n_sd) > kPinnedStats) return SL_ERR_HIP;
+        HIPCHK(hipMemcpyAsync(host, st, sizeof(SdState) * n_sd, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(host + sizeof(SdState) * n_sd, cnt, sizeof(ExecCounters),
+                              hipMemcpyDeviceToHost, s));
+        return SL_OK;
+    }
+    static void read_copied(const char *host, int n, std::vector<SdState> &out,
+                            unsigned long long *nc) {
+        out.resize(n);
+        std::memcpy(out.data(), host, sizeof(SdState) * n);
+        ExecCounters c;
+        std::memcpy(&c, host + sizeof(SdState) * n, sizeof(c));
+        *nc = c.nc_updates;
+    }
+
+    // the poll hint of a default-schedule run: the number of sweeps after which
+    // the bookkeeping sees every set converged
+    static void remember(const std::vector<SdState> &out,
+                         const std::vector<unsigned long long> &key) {
+        if (key.empty()) return;
+        long smax = 0;
+        bool all = true;
+        for (const auto &x : out) {
+            all = all && x.conv_at >= 0;
+            smax = std::max<long>(smax, (long)x.conv_at + 1);
+        }
+        if (all && smax > 0) sweep_hints().put(key, smax);
+    }
+};
+
+// Statistics of a reconstruction whose read-back waits for the next
+// synchronisation of the stream (the whole-ISA call): the coarse states are
+// copied to pinned memory in stream order, so the host enqueues the fine solve
+// without waiting for the reconstruction to finish.
+struct DeferredRaStats {
+    char *host = nullptr;
+    int n_sd = 0;
+    long launches = 0;
+    std::vector<unsigned long long> key;
 };
 
 void fill_stats(sl_stats *stats, const std::vector<SdState> &hs, unsigned long long nc,
@@ -1104,8 +1143,9 @@ void plan_isa(const sl_problem *p, const sl_ra_opts *ra, Arena &a, IsaPlan<T> &P
 template <typename T>
 int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t ws_bytes,
                      uint8_t *member, uint8_t *label, uint8_t *member_K, uint8_t *label_K,
-                     sl_stats *stats, hipStream_t s, FieldStats *fs_out = nullptr) {
-    Timer tm;
+                     sl_stats *stats, hipStream_t s, FieldStats *fs_out = nullptr,
+                     DeferredRaStats *defer = nullptr) {
+    Timer tm(defer == nullptr);
     tm.mark(0, s);
     const size_t N = nodes_of(p);
     Arena a{(char *)ws, ws_bytes};
@@ -1221,6 +1261,14 @@ int reconstruct_impl(const sl_problem *p, const sl_ra_opts *ra, void *ws, size_t
     HIPCHK(launch_ra_combine(P.exK.sds, P.exK.st, nc, cg.NK, P.tK, delta, mK, lbK, s));
     // ISA step 2: projection to the fine grid
     HIPCHK(launch_project(mK, lbK, cg.nK, p->n, p->dim, member, label, s));
+    if (defer) {
+        defer->host = pinned().stats;
+        defer->n_sd = P.exK.n_sd;
+        defer->launches = S;
+        defer->key = P.exK.last_key;
+        if (P.exK.copy_stats(s, defer->host) != SL_OK) return SL_ERR_HIP;
+        return status;
+    }
     tm.mark(1, s);
     std::vector<SdState> hs;
     unsigned long long ncu = 0;
@@ -1362,19 +1410,25 @@ int isa_all_impl(const sl_problem *p, const sl_ra_opts *ra, const sl_solve_opts 
                  uint8_t *policy, T *V_sets, sl_stats *stats, hipStream_t s) {
     Timer tm;
     tm.mark(0, s);
-    sl_stats sra{};
     FieldStats fs{};
+    DeferredRaStats dra;
     const int ra_status = reconstruct_impl<T>(p, ra, ws, ws_bytes, member, label, nullptr,
-                                              nullptr, &sra, s, &fs);
+                                              nullptr, nullptr, s, &fs, &dra);
     if (ra_status < 0) return ra_status;
+    tm.mark(1, s);
     const int status = isa_impl<T>(p, ra, member, o, ws, ws_bytes, V, owner, policy, V_sets,
                                    stats, s, &fs);
     if (status < 0) return status;
-    tm.mark(1, s);
+    tm.mark(2, s);
+    // isa_impl ended with a stream synchronisation: the coarse states are in
+    std::vector<SdState> hs;
+    unsigned long long ncK = 0;
+    Exec<double>::read_copied(dra.host, dra.n_sd, hs, &ncK);
+    Exec<double>::remember(hs, dra.key);
     if (stats) {
-        stats->ms_ra = sra.ms_ra;
-        stats->ra_sweeps_max = sra.ra_sweeps_max;
-        stats->ms_total = tm.ms(0, 1);
+        stats->ms_ra = tm.ms(0, 1);
+        stats->ra_sweeps_max = sweeps_of(hs, 0, hs.size(), dra.launches);
+        stats->ms_total = tm.ms(0, 2);
     }
     return status != SL_OK ? status : ra_status;
 }
