@@ -728,8 +728,11 @@ def main():
                        autotune=-args.sweep_config if args.sweep_config > 0 else 2,
                        local_iters=args.local_iters)
 
+    # a prepared solver: arguments marshalled once, outputs and workspace kept
+    solver = S.IsaSolver(dp, ra)
+
     def step():
-        return S.isa(dp, ra, opts)
+        return solver.solve(opts)
 
     for _ in range(args.warmup):
         step()

@@ -500,6 +500,48 @@ def isa(p: DeviceProblem, ra: RaOpts, opts: SolveOpts = SolveOpts(), want_sets: 
     return V, owner, member, label, pol, Vs, d
 
 
+class IsaSolver:
+    """``isa`` on one problem with its arguments marshalled once and its outputs
+    and workspace kept across calls: a loop that solves the same problem (or new
+    values in the same field tensors) pays only the library call.  ``solve``
+    returns (V, owner, member, label, policy, V_sets, stats) like ``isa``; the
+    tensors are this object's and are overwritten by the next call."""
+
+    def __init__(self, p: DeviceProblem, ra: RaOpts, want_sets: bool = False,
+                 want_policy: bool = False):
+        import torch
+        L = lib()
+        self.p = p
+        self.cp, self._keep = _cproblem(p)
+        self.cra = _ra(ra)
+        dev = p.target.device
+        ws_bytes = L.sl_isa_workspace_size(C.byref(self.cp), C.byref(self.cra))
+        if ws_bytes == 0:
+            raise ValueError("invalid problem or RA options")
+        self.ws = _workspace(ws_bytes, dev)
+        self.V = torch.empty(p.N, dtype=p.dtype, device=dev)
+        self.owner = torch.empty(p.N, dtype=torch.uint8, device=dev)
+        self.member = torch.empty(p.N, dtype=torch.uint8, device=dev)
+        self.label = torch.empty(p.N, dtype=torch.uint8, device=dev)
+        self.pol = (torch.full((p.n_comp * p.N,), 255, dtype=torch.uint8, device=dev)
+                    if want_policy else None)
+        self.Vs = torch.empty(p.n_comp * p.N, dtype=p.dtype, device=dev) if want_sets else None
+        self._args = [_ptr(self.ws), self.ws.numel(), _ptr(self.V), _ptr(self.owner),
+                      _ptr(self.member), _ptr(self.label), _ptr(self.pol), _ptr(self.Vs)]
+        self.st = SlStats()
+
+    def solve(self, opts: SolveOpts = SolveOpts()):
+        if opts.want_policy and self.pol is None:
+            raise ValueError("IsaSolver built without want_policy")
+        rc = lib().sl_isa(C.byref(self.cp), C.byref(self.cra), C.byref(_so(opts)), *self._args,
+                          C.byref(self.st), _stream())
+        if rc < 0:
+            raise SlError("sl_isa", rc)
+        d = self.st.as_dict()
+        d["converged"] = rc == SL_OK
+        return self.V, self.owner, self.member, self.label, self.pol, self.Vs, d
+
+
 def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float = None,
             max_iters: int = 100_000, local_iters: int = 0, workspace=None):
     """dL/dl of a loss with gradient dL/dV, the forward's controls frozen.

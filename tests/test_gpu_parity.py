@@ -198,6 +198,26 @@ def test_isa_single_call_equals_two_calls(dtype):
         assert np.array_equal(host(V), Vbar)
 
 
+def test_prepared_isa_solver_equals_isa():
+    """IsaSolver (arguments marshalled once, outputs kept) gives what isa gives,
+    call after call; FP64 equals the oracle bit for bit."""
+    p = W.c2_multitarget(n=97, m=32)
+    say("case: prepared isa solver")
+    dp = S.to_device(p, torch.float64)
+    ra = ra_of(p)
+    opts = S.SolveOpts(tol=0.0, max_sweeps=CAP)
+    solver = S.IsaSolver(dp, ra, want_sets=True)
+    ref = S.isa(dp, ra, opts, want_sets=True)
+    Vbar, own_o, rec, _, _ = I.isa(p)
+    for _ in range(2):
+        V, owner, member, label, _, Vs, st = solver.solve(opts)
+        assert st["converged"]
+        for a, b in ((V, ref[0]), (owner, ref[1]), (member, ref[2]), (label, ref[3]), (Vs, ref[5])):
+            assert np.array_equal(host(a), host(b))
+        assert np.array_equal(host(V), Vbar)
+        assert np.array_equal(host(member), rec.member)
+
+
 def test_full_size_c2_every_configuration():
     """The benchmark's problem (1025^2, 64 controls, 4 disks), every sweep
     configuration of the autotuner: candidates of one tile shape give the same
