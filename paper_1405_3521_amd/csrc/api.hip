@@ -465,6 +465,9 @@ struct Exec {
     int *prefix = nullptr;          // device
     int *stamp = nullptr;           // device, 2 x tiles: sweep each tile must be computed in
     int *class_off_dev = nullptr;   // device, kMaxClasses: item segment of each halo class
+    // class_off_dev, prefix, st, sds and cnt share one block (one upload per prepare)
+    char *hdr = nullptr;
+    size_t hdr_bytes = 0, o_class = 0, o_prefix = 0, o_st = 0, o_sds = 0, o_cnt = 0;
     int n_sd = 0;
     int total_tiles = 0;
     int stamp_stride = 1;           // tiles reserved (stride of the two stamp arrays)
@@ -478,15 +481,28 @@ struct Exec {
     double scale_rel = 0.0;         // rounding-aware stopping term (adjoint)
 
     void reserve(Arena &a, int nsd, int tiles_total) {
-        sds = a.take<SdDesc<T>>(nsd);
-        st = a.take<SdState>(nsd);
+        size_t off = 0;
+        auto put = [&off](size_t bytes) {
+            const size_t o = off;
+            off = (off + bytes + 255) & ~size_t(255);
+            return o;
+        };
+        o_class = put(sizeof(int) * kMaxClasses);
+        o_prefix = put(sizeof(int) * (size_t)nsd);
+        o_st = put(sizeof(SdState) * (size_t)nsd);
+        o_sds = put(sizeof(SdDesc<T>) * (size_t)nsd);
+        o_cnt = put(sizeof(ExecCounters));
+        hdr_bytes = off;
+        hdr = a.take<char>(hdr_bytes);
+        class_off_dev = hdr ? reinterpret_cast<int *>(hdr + o_class) : nullptr;
+        prefix = hdr ? reinterpret_cast<int *>(hdr + o_prefix) : nullptr;
+        st = hdr ? reinterpret_cast<SdState *>(hdr + o_st) : nullptr;
+        sds = hdr ? reinterpret_cast<SdDesc<T> *>(hdr + o_sds) : nullptr;
+        cnt = hdr ? reinterpret_cast<ExecCounters *>(hdr + o_cnt) : nullptr;
         items = a.take<WorkItem>(tiles_total > 0 ? tiles_total : 1);
         lists = a.take<WorkItem>(2 * (size_t)(tiles_total > 0 ? tiles_total : 1));
-        cnt = a.take<ExecCounters>(1);
-        prefix = a.take<int>(nsd);
         stamp_stride = tiles_total > 0 ? tiles_total : 1;
         stamp = a.take<int>(2 * (size_t)stamp_stride);
-        class_off_dev = a.take<int>(kMaxClasses);
     }
 
     static int tiles_of(const LaunchCfg &cfg, const int *n, int dim, int *t) {
@@ -546,8 +562,6 @@ struct Exec {
             if (c > 0) class_off[c] = class_off[c - 1] + class_cap[c - 1];
             HIPCHK(kind == 1 ? adjoint_tiles_set_attributes(ccfg[c]) : sweep_set_attributes(ccfg[c]));
         }
-        HIPCHK(hipMemcpyAsync(class_off_dev, class_off.data(), sizeof(int) * kMaxClasses,
-                              hipMemcpyHostToDevice, s));
         std::vector<SdState> hs(n_sd);
         for (auto &x : hs) {
             x.res[0] = x.res[1] = x.res[2] = 0ull;
@@ -558,12 +572,16 @@ struct Exec {
             x.final_res = 0ull;
             x.scale[0] = x.scale[1] = x.scale[2] = 0ull;
         }
-        HIPCHK(hipMemcpyAsync(sds, host_sds.data(), sizeof(SdDesc<T>) * n_sd,
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(st, hs.data(), sizeof(SdState) * n_sd, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(prefix, host_prefix.data(), sizeof(int) * n_sd,
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(ExecCounters), s));
+        // class offsets, prefix, states, descriptors and zeroed counters in one copy
+        if (!hdr || o_cnt + sizeof(ExecCounters) > hdr_bytes ||
+            o_sds + sizeof(SdDesc<T>) * (size_t)n_sd > o_cnt)
+            return SL_ERR_WORKSPACE;
+        std::vector<char> h(hdr_bytes, 0);
+        std::memcpy(h.data() + o_class, class_off.data(), sizeof(int) * kMaxClasses);
+        std::memcpy(h.data() + o_prefix, host_prefix.data(), sizeof(int) * (size_t)n_sd);
+        std::memcpy(h.data() + o_st, hs.data(), sizeof(SdState) * (size_t)n_sd);
+        std::memcpy(h.data() + o_sds, host_sds.data(), sizeof(SdDesc<T>) * (size_t)n_sd);
+        HIPCHK(hipMemcpyAsync(hdr, h.data(), hdr_bytes, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemsetAsync(stamp, 0xFF, sizeof(int) * 2 * (size_t)stamp_stride, s));
         HIPCHK(launch_build_items(cfg, sds, n_sd, total_tiles, prefix, items, cnt, class_off_dev, s));
         return SL_OK;
