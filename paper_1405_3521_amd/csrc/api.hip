@@ -210,23 +210,66 @@ LaunchCfg make_cfg(int dim, int dtype, int halo, int variant) {
     return c;
 }
 
-// Pinned host scratch for the per-chunk convergence poll, and for statistics
-// read back after a later synchronisation (kPinnedStats bytes).
+// Pinned host scratch for the per-chunk convergence poll, for statistics read
+// back after a later synchronisation (kPinnedStats bytes), and for the read-backs
+// that end a call (kPinnedReadback bytes, see Readback).
 constexpr size_t kPinnedStats = 16384;
+constexpr size_t kPinnedReadback = 262144;
 struct Pinned {
     int *active = nullptr;
     char *stats = nullptr;
+    char *readback = nullptr;
     Pinned() {
         if (hipHostMalloc((void **)&active, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess)
             active = nullptr;
         if (hipHostMalloc((void **)&stats, kPinnedStats, hipHostMallocDefault) != hipSuccess)
             stats = nullptr;
+        if (hipHostMalloc((void **)&readback, kPinnedReadback, hipHostMallocDefault) != hipSuccess)
+            readback = nullptr;
     }
 };
 Pinned &pinned() {
     static thread_local Pinned p;
     return p;
 }
+
+// Device-to-host copies that end a call, completed by one synchronisation of
+// the stream.  A copy into pageable memory waits for the stream by itself, so
+// several of them cost one round trip each; here they land in the pinned
+// read-back buffer in stream order and are moved to their destinations after
+// finish().  Without that buffer (the no-allocation path) or when it is full,
+// a copy goes to its destination directly.  Destinations must stay valid and
+// untouched until finish().  One Readback at a time per thread: every call
+// that uses the buffer ends with finish().
+struct Readback {
+    hipStream_t s;
+    char *buf;
+    size_t used = 0;
+    struct Item {
+        void *dst;
+        size_t off, n;
+    };
+    std::vector<Item> items;
+    Readback(hipStream_t s_, bool use_pinned) : s(s_), buf(use_pinned ? pinned().readback : nullptr) {}
+    hipError_t add(void *dst, const void *src, size_t n) {
+        const size_t off = (used + 63) & ~(size_t)63;
+        if (!buf || n > kPinnedReadback || off > kPinnedReadback - n)
+            return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s);
+        const hipError_t e = hipMemcpyAsync(buf + off, src, n, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        items.push_back({dst, off, n});
+        used = off + n;
+        return hipSuccess;
+    }
+    hipError_t finish() {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        for (const Item &it : items) std::memcpy(it.dst, buf + it.off, it.n);
+        items.clear();
+        used = 0;
+        return hipSuccess;
+    }
+};
 
 // A private stream for graph capture (captured graphs are launched on the
 // caller's stream; capture itself needs a non-default stream).  Default priority.
@@ -784,15 +827,24 @@ struct Exec {
     }
 
     unsigned long long unreached = 0;   // from the last read_stats
-    int read_stats(hipStream_t s, std::vector<SdState> &out, unsigned long long *nc) {
+    // The states and counters queued on rb; take_stats after rb.finish().
+    hipError_t queue_stats(Readback &rb, std::vector<SdState> &out, ExecCounters &c) const {
         out.resize(n_sd);
-        ExecCounters c{};
-        HIPCHK(hipMemcpyAsync(out.data(), st, sizeof(SdState) * n_sd, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&c, cnt, sizeof(ExecCounters), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        const hipError_t e = rb.add(out.data(), st, sizeof(SdState) * n_sd);
+        return e != hipSuccess ? e : rb.add(&c, cnt, sizeof(ExecCounters));
+    }
+    void take_stats(const std::vector<SdState> &out, const ExecCounters &c,
+                    unsigned long long *nc) {
         *nc = c.nc_updates;
         unreached = c.n_unreached;
         remember(out, last_key);
+    }
+    int read_stats(hipStream_t s, std::vector<SdState> &out, unsigned long long *nc) {
+        Readback rb(s, !no_alloc);
+        ExecCounters c{};
+        HIPCHK(queue_stats(rb, out, c));
+        HIPCHK(rb.finish());
+        take_stats(out, c, nc);
         return SL_OK;
     }
 
@@ -1399,11 +1451,15 @@ int isa_impl(const sl_problem *p, const sl_ra_opts *ra, const uint8_t *member,
     HIPCHK(launch_count_unreached<T>(V, p->target, N, unreached_level<T>(p),
                                      &P.ex.cnt->n_unreached, s));
     unsigned long long counts[8];
-    HIPCHK(hipMemcpyAsync(counts, P.counts, sizeof(counts), hipMemcpyDeviceToHost, s));
+    Readback rb(s, true);
+    HIPCHK(rb.add(counts, P.counts, sizeof(counts)));
     tm.mark(3, s);
     std::vector<SdState> hs;
+    ExecCounters c{};
     unsigned long long ncu = 0;
-    if ((rc = P.ex.read_stats(s, hs, &ncu))) return rc;
+    HIPCHK(P.ex.queue_stats(rb, hs, c));
+    HIPCHK(rb.finish());
+    P.ex.take_stats(hs, c, &ncu);
     fill_stats(stats, hs, ncu, S);
     if (stats) {
         stats->n_unreachable = (int)P.ex.unreached;
@@ -1512,7 +1568,6 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         HIPCHK(launch_scale_drift<T>((const T *)p->drift, P.q, N, p->dim, t, s));
     }
     HIPCHK(hipMemsetAsync(P.lam, 0, sizeof(T) * (size_t)n_sets * N, s));
-    HIPCHK(hipMemsetAsync(P.acc, 0, sizeof(T) * (size_t)n_sets * 2 * N, s));
     std::vector<AdjDesc<T>> hd(n_sets);
     for (int i = 0; i < n_sets; ++i) {
         AdjDesc<T> &d = hd[i];
@@ -1543,14 +1598,11 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     const bool tiles = H <= adjoint_tiles_max_halo(p->dim);
     if (tiles && local_iters == 0)          // Jacobi: the second buffer is the acc area
         for (int i = 0; i < n_sets; ++i) hd[i].lam2 = hd[i].acc[0];
+    // the scatter and the Jacobi tiles start from zero in the acc area too; the
+    // block-asynchronous tiles iterate in place and never read it
+    if (!tiles || local_iters == 0)
+        HIPCHK(hipMemsetAsync(P.acc, 0, sizeof(T) * (size_t)n_sets * 2 * N, s));
     HIPCHK(hipMemcpyAsync(P.ads, hd.data(), sizeof(AdjDesc<T>) * n_sets, hipMemcpyHostToDevice, s));
-    std::vector<SdState> hs(n_sets);
-    for (auto &x : hs) {
-        x = SdState{};
-        x.conv_at = -1;
-    }
-    HIPCHK(hipMemcpyAsync(P.st, hs.data(), sizeof(SdState) * n_sets, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(P.cnt, 0, sizeof(ExecCounters), s));
     // rounding-level stop: atomics reorder the sums, so the state settles to
     // within a few ulps of its largest entry
     const double scale_rel = 16.0 * (sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
@@ -1619,6 +1671,14 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
         }
         return status;
     }
+    // scatter: its own states and counters
+    std::vector<SdState> hs(n_sets);
+    for (auto &x : hs) {
+        x = SdState{};
+        x.conv_at = -1;
+    }
+    HIPCHK(hipMemcpyAsync(P.st, hs.data(), sizeof(SdState) * n_sets, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(P.cnt, 0, sizeof(ExecCounters), s));
     tm.mark(1, s);
     auto enqueue = [&](hipStream_t q, int todo) -> hipError_t {
         for (int i = 0; i < todo; ++i) {
@@ -1638,9 +1698,10 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
     HIPCHK(launch_adjoint_combine<T>(P.ads, P.st, n_sets, p->target, N, (T)w, dLdl, s));
     tm.mark(2, s);
     ExecCounters c{};
-    HIPCHK(hipMemcpyAsync(hs.data(), P.st, sizeof(SdState) * n_sets, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&c, P.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    Readback rb(s, true);
+    HIPCHK(rb.add(hs.data(), P.st, sizeof(SdState) * n_sets));
+    HIPCHK(rb.add(&c, P.cnt, sizeof(c)));
+    HIPCHK(rb.finish());
     fill_stats(stats, hs, c.nc_updates, it);
     if (stats) {
         stats->ms_ra = 0.0;
@@ -1931,8 +1992,15 @@ int batched_impl(int np, const sl_problem *probs, const sl_ra_opts *ras, const s
     tm.mark(3, s);
     std::vector<SdState> hsK, hs;
     unsigned long long ncK = 0, nc = 0;
-    if ((rc = B.exK.read_stats(s, hsK, &ncK))) return rc;
-    if ((rc = B.ex.read_stats(s, hs, &nc))) return rc;
+    {
+        Readback rb(s, true);
+        ExecCounters cK{}, c{};
+        HIPCHK(B.exK.queue_stats(rb, hsK, cK));
+        HIPCHK(B.ex.queue_stats(rb, hs, c));
+        HIPCHK(rb.finish());
+        B.exK.take_stats(hsK, cK, &ncK);
+        B.ex.take_stats(hs, c, &nc);
+    }
     if (per_problem) {
         for (int q = 0; q < np; ++q) {
             const ProbDesc<T> &d = B.hp[q];
