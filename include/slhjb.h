@@ -363,7 +363,7 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
  * p->dtype).  The feet are those of the forward scheme: per-axis speed factors
  * and drift (index units, e c + q) are taken; games and the Kruzkov discount (the
  * discount then depends on l, so V is not linear in l) return SL_ERR_UNSUPPORTED.
- * Iteration (tiles of 32x16 nodes in 2D, 8x8x4 in 3D, when the feet reach at
+ * Iteration (tiles of 32x8 nodes in 2D, 8x8x4 in 3D, when the feet reach at
  * most 8 cells in 2D and 5 in 3D):
  *   local_iters = 0: Jacobi: every launch evaluates each active tile once from
  *     one buffer into the other; a tile is revisited when a node of its

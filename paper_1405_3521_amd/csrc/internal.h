@@ -311,8 +311,8 @@ hipError_t launch_adjoint_tiles(const LaunchCfg &cfg, const SdDesc<T> *sds, SdSt
                                 hipStream_t s);
 hipError_t adjoint_tiles_set_attributes(LaunchCfg &cfg);
 int adjoint_tiles_max_halo(int dim);
-// Tile shapes of the gather adjoint: 2D 32x16, 3D 8x8x4.
-constexpr int kAdjTX = 32, kAdjTY = 16;
+// Tile shapes of the gather adjoint: 2D 32x8 (one node per thread), 3D 8x8x4.
+constexpr int kAdjTX = 32, kAdjTY = 8;
 constexpr int kAdjTX3 = 8, kAdjTY3 = 8, kAdjTZ3 = 4;
 template <typename T>
 hipError_t launch_adjoint_combine(const AdjDesc<T> *ads, const SdState *st, int n_sets,
