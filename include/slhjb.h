@@ -379,8 +379,11 @@ size_t sl_adjoint_workspace_size(const sl_problem *p, int n_sets);
  *   so every order converges to the same lambda (up to rounding).  Stop: the
  *   largest change of one evaluation <= tol + 16 eps max|lambda| (eps of
  *   p->dtype, the rounding level of the sums), or max_iters launches.  tol >= 0
- *   is absolute; tol < 0 is relative: |tol| * max_j |dLdV_j|, the maximum taken
- *   on the device with the input checks (no extra host round trip).
+ *   is absolute; tol < 0 is relative: |tol| * max_j |dLdV_j| rounded down to a
+ *   power of two, the maximum taken on the device with the input checks (no
+ *   extra host round trip); the rounding keeps the tolerance, and with it the
+ *   captured launch graphs, unchanged while the gradient's scale moves within a
+ *   factor of two.
  * Output: dLdl (DEVICE, N in p->dtype; 0 on target nodes). */
 int sl_adjoint(const sl_problem *p, const uint8_t *member, const uint8_t *owner,
                const uint8_t *policy, const void *dLdV, void *dLdl, double tol, long max_iters,

@@ -548,7 +548,7 @@ def adjoint(p: DeviceProblem, policy, dLdV, member=None, owner=None, tol: float 
 
     ``tol``: stop when the adjoint state changes by at most tol (plus the
     library's rounding allowance, 16 eps max|lambda|) in one iteration; default 0.
-    A negative tol is relative: |tol| * max |dLdV|.
+    A negative tol is relative: |tol| * max |dLdV|, rounded down to a power of two.
     ``local_iters``: 0 Jacobi iteration; k > 0 block-asynchronous tiles (2D).
 
     ``policy``: from the forward call (``solve``: N entries; ``solve_isa``:

@@ -284,16 +284,22 @@ hipStream_t capture_stream() {
 // a call that repeats an earlier call's launches -- the same problem shape in the
 // same workspace -- replays the earlier graph without capturing it again.  The
 // node fields themselves are not in the key: kernels read them through the
-// descriptors, which every call uploads.  Bounded: the oldest entry is destroyed
-// when the cache is full.
+// descriptors, which every call uploads.  Bounded: when the cache is full the
+// least recently used entry is destroyed (a hit moves its entry to the back), so
+// the graphs that a loop replays every step outlive those of one-off calls.
+// The chunk loop waits for every chunk before it enqueues the next (or captures
+// a new graph), so on one host thread an evicted graph is never in flight.
 struct GraphCache {
-    static constexpr size_t kMax = 16;
+    static constexpr size_t kMax = 32;
     std::vector<std::pair<std::vector<unsigned long long>, hipGraphExec_t>> entries;
     std::mutex mu;
     hipGraphExec_t find(const std::vector<unsigned long long> &key) {
         std::lock_guard<std::mutex> lk(mu);
-        for (auto &e : entries)
-            if (e.first == key) return e.second;
+        for (size_t i = 0; i < entries.size(); ++i)
+            if (entries[i].first == key) {
+                std::rotate(entries.begin() + i, entries.begin() + i + 1, entries.end());
+                return entries.back().second;
+            }
         return nullptr;
     }
     void insert(std::vector<unsigned long long> key, hipGraphExec_t exec) {
@@ -1554,7 +1560,17 @@ int adjoint_impl(const sl_problem *p, const uint8_t *member, const uint8_t *owne
                                    p->n_comp, P.fs, &fs, s, dLdV);
     if (rc) return rc;
     if ((rc = check_fields(fs))) return rc;
-    if (tol < 0.0) tol = -tol * bits_to_double(fs.g_absmax);   // relative to max |dL/dV|
+    if (tol < 0.0) {
+        // relative to max |dL/dV|, rounded down to a power of two: the stop is at
+        // least as strict as asked, and the tolerance (a launch argument, so part
+        // of the captured chunk graphs' key) stays the same from one call to the
+        // next while the gradient's scale moves within a factor of two, so a
+        // training loop replays its adjoint graphs instead of capturing them anew
+        const double t = -tol * bits_to_double(fs.g_absmax);
+        int ex = 0;
+        (void)std::frexp(t, &ex);
+        tol = t > 0.0 && std::isfinite(t) ? std::ldexp(0.5, ex) : t;
+    }
     double beta, w, emax;
     scheme_constants(p->lambda, p->h, p->disc, &beta, &w);
     std::vector<double> e;

@@ -5,6 +5,8 @@ must reproduce the oracle's dL/dl (FP32: relative l2 <= 1e-4; FP64: <= 1e-12; th
 atomics only change the summation order).  End to end, the autograd gradient of
 sum (V[obs] - V_obs)^2 with respect to theta (l = exp(theta)) is checked against
 central differences of the oracle's FP64 forward solve."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -297,9 +299,10 @@ def test_adjoint_jacobi_mode_is_deterministic(dtype, tol):
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_adjoint_relative_tolerance(dtype):
-    """A negative tol is relative to max |dL/dV|, taken on the device: the same
-    stopping threshold as the absolute tol computed on the host, so the Jacobi
-    iterates (deterministic mode) stop at the same launch with the same bits."""
+    """A negative tol is relative to max |dL/dV|, taken on the device and rounded
+    down to a power of two: the same stopping threshold as that absolute tol
+    computed on the host, so the Jacobi iterates (deterministic mode) stop at the
+    same launch with the same bits."""
     p = W.c5_adjoint(n=65, n_obs=300)
     say("case: relative adjoint tolerance", dtype)
     V, pol = O.solve(p)[:2]
@@ -309,8 +312,11 @@ def test_adjoint_relative_tolerance(dtype):
     pol_t = torch.as_tensor(pol_u8(pol), device=DEV)
     rtol = 1e-5
     scale = float(np.abs(g_t.cpu().numpy().astype(np.float64)).max())
+    m, ex = math.frexp(rtol * scale)
+    tol_abs = math.ldexp(0.5, ex)
+    assert tol_abs <= rtol * scale < 2 * tol_abs
     a, sa = S.adjoint(dp, pol_t, g_t, tol=-rtol, local_iters=0)
-    b, sb = S.adjoint(dp, pol_t, g_t, tol=rtol * scale, local_iters=0)
+    b, sb = S.adjoint(dp, pol_t, g_t, tol=tol_abs, local_iters=0)
     assert sa["converged"] and sb["converged"]
     assert sa["sweeps_max"] == sb["sweeps_max"]
     assert torch.equal(a, b)
