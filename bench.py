@@ -571,7 +571,8 @@ ADJ_LOCAL_ITERS = 16         # set from --adj-local-iters
 
 def leg_c5(steps: int, li: int):
     """Adjoint 513^2: loss sum (V - V_obs)^2 on 2000 nodes, l = exp(theta); ISA
-    forward with the policy exported, then the adjoint (sets frozen)."""
+    forward with the policy exported, then the adjoint (sets frozen).  A step
+    takes a few milliseconds, so the leg times at least 30 of them."""
     import torch
     import paper_1405_3521_amd as S
     import workloads as W
@@ -598,6 +599,7 @@ def leg_c5(steps: int, li: int):
         return time.perf_counter() - t1, th.grad
 
     fwd_bwd()
+    steps = max(steps, 30)
     t0 = time.perf_counter()
     t_bwd = 0.0
     for _ in range(steps):
